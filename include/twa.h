@@ -1,0 +1,157 @@
+/*
+ * twa.h -- C ABI of the MI355X three-weight message-passing trajectory
+ * planner (Bento, Derbinsky, Alonso-Mora, Yedidia, "A message-passing
+ * algorithm for multi-agent trajectory planning", NIPS 2013).
+ *
+ * One call of twa_iterate(s, k) runs k full iterations of the algorithm of
+ * App. B over the factor graph of Sec. 3.3 on the solver's HIP stream:
+ *   fixed start/goal factors, energy factors (App. E), agent-agent collision
+ *   factors over every pair of agents and every segment (Sec. 3.3.1, App. C),
+ *   agent-wall factors (Sec. 3.3.2, App. D), each emitting x and a weight
+ *   0 / rho0 / infinity; the weighted-consensus z update and the <-rho weight
+ *   of every break-point node; the u (dual) update of every edge.
+ *
+ * Conventions for every entry point
+ *   - Array arguments are DEVICE pointers (e.g. a torch CUDA tensor's
+ *     data_ptr()) that must be valid on the solver's stream.  The caller owns
+ *     them; the solver copies what it needs and never keeps a pointer.
+ *   - float is IEEE binary32; arrays are dense and row-major as documented.
+ *   - Break-point positions ("trajectories") have layout [p][eta+1][dim]:
+ *     agent i, break-point s (0 = start x_i(0), eta = goal x_i(T)).
+ *   - Every call returns a twa_status; no C++ exception crosses the ABI.
+ *     On failure twa_last_error() describes the cause.  A device error
+ *     (TWA_E_DEVICE) latches: every later call on that solver fails with it.
+ *   - Calls are asynchronous on the stream unless stated; calls on one
+ *     solver must not overlap (one host thread at a time).
+ *
+ * Canonical edge order (used by state get/set and the per-edge debug output;
+ * factor order is the same with one entry per factor):
+ *   1. fixed factors, for i = 0..p-1: start(i), goal(i)          1 edge each
+ *   2. energy factors, for i, for s = 0..eta-1: [(i,s), (i,s+1)]
+ *   3. collision factors, for s, for i < j (row-major):
+ *        [(i,s), (i,s+1), (j,s), (j,s+1)]
+ *   4. wall factors, for s, for i, for w = 0..n_walls-1: [(i,s), (i,s+1)]
+ *   E = 2p + 2 eta p + 4 eta p(p-1)/2 + 2 eta p n_walls edges.
+ * Weight codes: 0 = zero (inactive), 1 = rho0 (standard), 2 = infinity.
+ */
+#ifndef TWA_H_
+#define TWA_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct twa_solver twa_solver;
+
+typedef enum {
+    TWA_OK = 0,
+    TWA_E_INVALID = 1,    /* bad argument (size, null pointer, NaN, flag) */
+    TWA_E_INFEASIBLE = 2, /* start or goal positions overlap, or touch a wall */
+    TWA_E_NOMEM = 3,      /* device allocation failed */
+    TWA_E_DEVICE = 4,     /* a HIP call failed; latched */
+    TWA_E_NUMERIC = 5,    /* non-finite value found by twa_check_finite */
+    TWA_E_STATE = 6       /* call not valid in the solver's current state */
+} twa_status;
+
+enum { TWA_W_ZERO = 0, TWA_W_STD = 1, TWA_W_INF = 2 };
+
+/* twa_create flags */
+enum {
+    /* Read and write u of every edge every iteration, the literal dense form
+     * of App. B step 7.  Without it an edge whose factor sent weight 0 keeps
+     * no u (it is zero by the update rule), and a bit per factor records
+     * which factors carry one.  Results are identical. */
+    TWA_F_DENSE = 1u << 0
+};
+
+typedef struct {
+    long long iter;          /* iterations run so far */
+    long long active_coll;   /* collision factors with weight rho0, last iteration */
+    long long active_wall;   /* wall factors with weight rho0, last iteration */
+    long long queued;        /* factors that went through a full minimiser, last iteration */
+} twa_stats;
+
+/*
+ * Create a solver for one planning problem (Sec. 1 problem statement,
+ * Sec. 3.1-3.2 formulation).
+ *   p >= 1 agents, eta >= 1 segments (eta+1 break-points), dim 2 or 3.
+ *   radii [p]          agent radii r_i > 0.
+ *   x0, xT [p][dim]    start and goal positions (constants, Sec. 3).
+ *   n_walls >= 0, walls [n_walls][2][dim] segment end points (x_L, x_R),
+ *                      planar only (Sec. 3.2): n_walls > 0 needs dim == 2.
+ *                      May be NULL when n_walls == 0.
+ *   C [p][eta]         energy coefficient C_{i,s} >= 0 of segment (i, s)
+ *                      (eq. velo_cost_pair_wise, prefactor folded in).
+ *   rho0 > 0           standard weight; alpha > 0 step (App. B step 7 uses
+ *                      alpha/rho0).
+ *   flags              TWA_F_* above.
+ *   hip_stream         hipStream_t on which every call runs (NULL = default).
+ * Starts must be pairwise >= r_i + r_j apart, and so must goals; no start or
+ * goal may lie within r_i of a wall (TWA_E_INFEASIBLE otherwise).
+ * Initial state: straight lines from start to goal, u = 0, <-rho = infinity
+ * at start and goal, rho0 elsewhere.  Synchronises the stream.
+ * On success *out owns all device memory it allocated (twa_destroy frees it).
+ */
+twa_status twa_create(int p, int eta, int dim, const float *radii, const float *x0, const float *xT,
+                      int n_walls, const float *walls, const float *C, float rho0, float alpha,
+                      unsigned flags, void *hip_stream, twa_solver **out);
+
+/* Initial break-points z [p][eta+1][dim] (break-points 0 and eta are
+ * replaced by the start and goal); resets u to 0 and <-rho to the default. */
+twa_status twa_set_init(twa_solver *s, const float *z);
+
+/* rho0 = rho0_init for the first n_warm iterations counted from 0, then the
+ * create-time rho0 (Sec. 4 uses a small rho0 for 20 iterations). */
+twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm);
+
+/* Run k >= 0 iterations (App. B steps 1-7), asynchronously. */
+twa_status twa_iterate(twa_solver *s, int k);
+
+/* As twa_iterate, and records HIP events around every launch on the
+ * solver's stream; synchronises and writes the summed device time in
+ * milliseconds of each kernel to kernel_ms (host array of 3: factor stream,
+ * queued minimisers, node consensus). */
+twa_status twa_iterate_timed(twa_solver *s, int k, double *kernel_ms);
+
+/* Current consensus positions z [p][eta+1][dim]. */
+twa_status twa_get_trajectories(twa_solver *s, float *z_out);
+
+/* Full state after the last iteration: z [p][eta+1][dim], u [E][dim] in
+ * canonical edge order, <-rho [p][eta+1] (codes above), iteration count
+ * (host pointer, may be NULL).  Any device pointer may be NULL to skip it. */
+twa_status twa_get_state(twa_solver *s, float *z, float *u, unsigned char *lrho, long long *iter);
+
+/* Replace the state (same layouts as twa_get_state); iter is host memory. */
+twa_status twa_set_state(twa_solver *s, const float *z, const float *u, const unsigned char *lrho,
+                         long long iter);
+
+/* Debug output of the NEXT twa_iterate(s, 1): x [E][dim] (canonical edge
+ * order) and ->rho per factor [F] (canonical factor order), written during
+ * that iteration.  Pass NULLs to switch it off.  The buffers must stay valid
+ * until that iteration has run. */
+twa_status twa_capture_next(twa_solver *s, float *x_out, unsigned char *rho_out);
+
+/* Counters of the last iteration (host struct; synchronises the stream). */
+twa_status twa_get_stats(twa_solver *s, twa_stats *out);
+
+/* Sizes: factors and edges in canonical order (host pointers). */
+twa_status twa_sizes(const twa_solver *s, long long *n_factors, long long *n_edges);
+
+/* Scan z and u for NaN/Inf (synchronises): TWA_E_NUMERIC if any. */
+twa_status twa_check_finite(twa_solver *s);
+
+/* Text of the last error on this solver ("" if none). */
+const char *twa_last_error(const twa_solver *s);
+
+/* Release every device buffer (synchronises the stream).  NULL is a no-op. */
+void twa_destroy(twa_solver *s);
+
+/* Library version string. */
+const char *twa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TWA_H_ */

@@ -61,6 +61,8 @@ def _load():
     lib.tor_get_last.argtypes = [ct.c_void_p, _dp, _u8]
     lib.tor_iterate.restype = None
     lib.tor_iterate.argtypes = [ct.c_void_p, ct.c_long]
+    lib.tor_get_margins.restype = None
+    lib.tor_get_margins.argtypes = [ct.c_void_p, _dp, _dp]
     lib.tor_objective.restype = ct.c_double
     lib.tor_objective.argtypes = [ct.c_void_p]
     lib.tor_min_clearance.restype = ct.c_double
@@ -201,6 +203,15 @@ class Planner:
         rf = np.zeros(self.F, dtype=np.uint8)
         _load().tor_get_last(self.h, x.ctypes.data_as(_dp), rf.ctypes.data_as(_u8))
         return x, rf
+
+    def margins(self):
+        """Per-factor near-tie diagnostics of the last iteration:
+        |closest approach - R|/R of the activity test, and the relative energy
+        gap between the chosen candidate and the best distinct runner-up."""
+        a = np.zeros(self.F)
+        t = np.zeros(self.F)
+        _load().tor_get_margins(self.h, a.ctypes.data_as(_dp), t.ctypes.data_as(_dp))
+        return a, t
 
     def iterate(self, k: int):
         _load().tor_iterate(self.h, int(k))

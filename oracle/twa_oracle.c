@@ -475,8 +475,36 @@ static int tangents_through(const capsule *R, const double *q, double th[2]) {
  * Capsule minimiser: returns 1 if the constraint was active (x moved or was
  * solved), 0 if scenario 1 (x = n).  w = INFINITY marks a certain weight.
  */
+/* relative energy gap between the chosen configuration and the best other
+ * (distinct) candidate; a diagnostic for near-ties, not part of the method */
+static double tie_gap(const cand *all, int na, const cand *best) {
+    double second = INFINITY;
+    double scale = fabs(best->x0[0]) + fabs(best->x0[1]) + fabs(best->x1[0]) + fabs(best->x1[1]) + 1e-300;
+    for (int k = 0; k < na; k++) {
+        double d = fabs(all[k].x0[0] - best->x0[0]) + fabs(all[k].x0[1] - best->x0[1]) +
+                   fabs(all[k].x1[0] - best->x1[0]) + fabs(all[k].x1[1] - best->x1[1]);
+        if (d <= 1e-9 * scale) continue;
+        if (all[k].E < second) second = all[k].E;
+    }
+    if (!(second < INFINITY)) return INFINITY;
+    return (second - best->E) / fmax(fabs(best->E), 1e-300);
+}
+
+int tor_prox_capsule_gap(const double *xa, const double *xb, double r, const double *n0, const double *n1,
+                         double w0, double w1, double *x0, double *x1, int *kind_out, double *theta_out,
+                         double *gap_out);
+
 int tor_prox_capsule(const double *xa, const double *xb, double r, const double *n0, const double *n1,
                      double w0, double w1, double *x0, double *x1, int *kind_out, double *theta_out) {
+    return tor_prox_capsule_gap(xa, xb, r, n0, n1, w0, w1, x0, x1, kind_out, theta_out, NULL);
+}
+
+int tor_prox_capsule_gap(const double *xa, const double *xb, double r, const double *n0, const double *n1,
+                         double w0, double w1, double *x0, double *x1, int *kind_out, double *theta_out,
+                         double *gap_out) {
+    cand all[40];
+    int na = 0;
+    if (gap_out) *gap_out = INFINITY;
     capsule R = {{xa[0], xa[1]}, {xb[0], xb[1]}, r};
     if (tor_segseg(n0, n1, xa, xb) >= r) {
         x0[0] = n0[0], x0[1] = n0[1], x1[0] = n1[0], x1[1] = n1[1];
@@ -517,6 +545,7 @@ int tor_prox_capsule(const double *xa, const double *xb, double r, const double 
         }
         for (int k = 0; k < nt; k++) {
             tangent_config(&R, n0, n1, w0, w1, ths[k], &c);
+            all[na++] = c;
             if (better(&c, &best)) best = c;
         }
         /* (b) one spring relaxed, the other end on the visible boundary */
@@ -527,7 +556,8 @@ int tor_prox_capsule(const double *xa, const double *xb, double r, const double 
                 c.kind = 1, c.th = th;
                 c.x0[0] = p[0], c.x0[1] = p[1], c.x1[0] = n1[0], c.x1[1] = n1[1];
                 c.E = 0.5 * w0 * ((p[0] - n0[0]) * (p[0] - n0[0]) + (p[1] - n0[1]) * (p[1] - n0[1]));
-                if (better(&c, &best)) best = c;
+                all[na++] = c;
+            if (better(&c, &best)) best = c;
             }
         } else if (in1 && !in0) {
             double p[2], th;
@@ -535,7 +565,8 @@ int tor_prox_capsule(const double *xa, const double *xb, double r, const double 
                 c.kind = 2, c.th = th;
                 c.x0[0] = n0[0], c.x0[1] = n0[1], c.x1[0] = p[0], c.x1[1] = p[1];
                 c.E = 0.5 * w1 * ((p[0] - n1[0]) * (p[0] - n1[0]) + (p[1] - n1[1]) * (p[1] - n1[1]));
-                if (better(&c, &best)) best = c;
+                all[na++] = c;
+            if (better(&c, &best)) best = c;
             }
         } else if (!in0 && !in1) {
             double p[2], th;
@@ -543,13 +574,15 @@ int tor_prox_capsule(const double *xa, const double *xb, double r, const double 
                 c.kind = 1, c.th = th;
                 c.x0[0] = p[0], c.x0[1] = p[1], c.x1[0] = n1[0], c.x1[1] = n1[1];
                 c.E = 0.5 * w0 * ((p[0] - n0[0]) * (p[0] - n0[0]) + (p[1] - n0[1]) * (p[1] - n0[1]));
-                if (better(&c, &best)) best = c;
+                all[na++] = c;
+            if (better(&c, &best)) best = c;
             }
             if (nearest_visible(&R, n0, n1, p, &th)) {
                 c.kind = 2, c.th = th;
                 c.x0[0] = n0[0], c.x0[1] = n0[1], c.x1[0] = p[0], c.x1[1] = p[1];
                 c.E = 0.5 * w1 * ((p[0] - n1[0]) * (p[0] - n1[0]) + (p[1] - n1[1]) * (p[1] - n1[1]));
-                if (better(&c, &best)) best = c;
+                all[na++] = c;
+            if (better(&c, &best)) best = c;
             }
         }
     } else {
@@ -572,6 +605,7 @@ int tor_prox_capsule(const double *xa, const double *xb, double r, const double 
             } else {
                 c.x1[0] = nf[0], c.x1[1] = nf[1], c.x0[0] = xv[0], c.x0[1] = xv[1];
             }
+            all[na++] = c;
             if (better(&c, &best)) best = c;
         }
         double p[2], th;
@@ -583,6 +617,7 @@ int tor_prox_capsule(const double *xa, const double *xb, double r, const double 
             } else {
                 c.x1[0] = nf[0], c.x1[1] = nf[1], c.x0[0] = p[0], c.x0[1] = p[1];
             }
+            all[na++] = c;
             if (better(&c, &best)) best = c;
         }
     }
@@ -594,6 +629,7 @@ int tor_prox_capsule(const double *xa, const double *xb, double r, const double 
         return 1;
     }
     x0[0] = best.x0[0], x0[1] = best.x0[1], x1[0] = best.x1[0], x1[1] = best.x1[1];
+    if (gap_out) *gap_out = tie_gap(all, na, &best);
     if (kind_out) *kind_out = best.kind;
     if (theta_out) *theta_out = best.th;
     return 1;
@@ -669,9 +705,21 @@ static void plane_basis(const double *a, const double *b, double *e1, double *e2
  * nhp), their weights (INFINITY = certain) and the radius sum R.  Returns 1
  * if the pair collides (weights rho0 out), 0 otherwise (x = n, weights 0).
  */
+int tor_prox_coll_gap(const double *nl, const double *nh, const double *nlp, const double *nhp, double wl,
+                      double wh, double wlp, double whp, double R, int dim, double *xl, double *xh, double *xlp,
+                      double *xhp, int *kind_out, double *theta_out, double *gap_out);
+
 int tor_prox_coll(const double *nl, const double *nh, const double *nlp, const double *nhp, double wl,
                   double wh, double wlp, double whp, double R, int dim, double *xl, double *xh, double *xlp,
                   double *xhp, int *kind_out, double *theta_out) {
+    return tor_prox_coll_gap(nl, nh, nlp, nhp, wl, wh, wlp, whp, R, dim, xl, xh, xlp, xhp, kind_out, theta_out,
+                             NULL);
+}
+
+int tor_prox_coll_gap(const double *nl, const double *nh, const double *nlp, const double *nhp, double wl,
+                      double wh, double wlp, double whp, double R, int dim, double *xl, double *xh, double *xlp,
+                      double *xhp, int *kind_out, double *theta_out, double *gap_out) {
+    if (gap_out) *gap_out = INFINITY;
     double ml[3], mh[3];
     for (int k = 0; k < dim; k++) {
         ml[k] = nlp[k] - nl[k];
@@ -690,14 +738,14 @@ int tor_prox_coll(const double *nl, const double *nh, const double *nlp, const d
     double zero[2] = {0, 0};
     double vl[3], vh[3];
     if (dim == 2) {
-        tor_prox_capsule(zero, zero, R, ml, mh, om_l, om_h, vl, vh, kind_out, theta_out);
+        tor_prox_capsule_gap(zero, zero, R, ml, mh, om_l, om_h, vl, vh, kind_out, theta_out, gap_out);
     } else {
         double e1[3], e2[3];
         plane_basis(ml, mh, e1, e2);
         double a[2] = {ml[0] * e1[0] + ml[1] * e1[1] + ml[2] * e1[2], ml[0] * e2[0] + ml[1] * e2[1] + ml[2] * e2[2]};
         double b[2] = {mh[0] * e1[0] + mh[1] * e1[1] + mh[2] * e1[2], mh[0] * e2[0] + mh[1] * e2[1] + mh[2] * e2[2]};
         double va[2], vb[2];
-        tor_prox_capsule(zero, zero, R, a, b, om_l, om_h, va, vb, kind_out, theta_out);
+        tor_prox_capsule_gap(zero, zero, R, a, b, om_l, om_h, va, vb, kind_out, theta_out, gap_out);
         /* the component of m orthogonal to the plane is zero by construction */
         for (int k = 0; k < 3; k++) {
             vl[k] = va[0] * e1[k] + va[1] * e2[k];
@@ -729,6 +777,8 @@ typedef struct {
     double *z, *u, *x, *n, *m; /* z: [N][dim]; others [E][dim] */
     unsigned char *rout;  /* ->rho per edge */
     unsigned char *rin;   /* <-rho per edge */
+    double *act_margin;   /* |closest approach - R| / R of the last activity test, per factor */
+    double *tie_margin;   /* relative energy gap to the runner-up candidate, per factor */
 } tor_t;
 
 static long node_id(const tor_t *T, int i, int s) { return (long)i * (T->eta + 1) + s; }
@@ -813,6 +863,9 @@ void *tor_create(int p, int eta, int dim, const double *radii, const double *x0,
     T->m = (double *)calloc(T->E * dim, sizeof(double));
     T->rout = (unsigned char *)calloc(T->E, 1);
     T->rin = (unsigned char *)calloc(T->E, 1);
+    T->act_margin = (double *)malloc(sizeof(double) * T->F);
+    T->tie_margin = (double *)malloc(sizeof(double) * T->F);
+    for (long q = 0; q < T->F; q++) T->act_margin[q] = T->tie_margin[q] = INFINITY;
     /* default state: straight lines, u = 0, <-rho INF at end points, STD inside */
     for (int i = 0; i < p; i++)
         for (int s = 0; s <= eta; s++)
@@ -833,6 +886,7 @@ void tor_destroy(void *h) {
     free(T->ftype), free(T->fe0), free(T->fa), free(T->fb), free(T->fs), free(T->fw);
     free(T->enode), free(T->adj_off), free(T->adj);
     free(T->z), free(T->u), free(T->x), free(T->n), free(T->m), free(T->rout), free(T->rin);
+    free(T->act_margin), free(T->tie_margin);
     free(T);
 }
 
@@ -872,6 +926,13 @@ void tor_get_last(void *h, double *x, unsigned char *rho_f) {
         for (long f = 0; f < T->F; f++) rho_f[f] = T->rout[T->fe0[f]];
 }
 
+/* near-tie diagnostics of the last iteration, per factor (test use) */
+void tor_get_margins(void *h, double *act_margin, double *tie_margin) {
+    tor_t *T = (tor_t *)h;
+    if (act_margin) memcpy(act_margin, T->act_margin, sizeof(double) * T->F);
+    if (tie_margin) memcpy(tie_margin, T->tie_margin, sizeof(double) * T->F);
+}
+
 static double weight_value(const tor_t *T, unsigned char w, double rho) {
     (void)T;
     if (w == TOR_INF) return INFINITY;
@@ -901,16 +962,23 @@ static void run_factor(tor_t *T, long f, double rho) {
         double R = T->radii[T->fa[f]] + T->radii[T->fb[f]];
         double w[4];
         for (int q = 0; q < 4; q++) w[q] = weight_value(T, T->rin[e + q], rho);
-        int act = tor_prox_coll(n + e * dim, n + (e + 1) * dim, n + (e + 2) * dim, n + (e + 3) * dim, w[0], w[1],
-                                w[2], w[3], R, dim, x + e * dim, x + (e + 1) * dim, x + (e + 2) * dim,
-                                x + (e + 3) * dim, NULL, NULL);
+        double d0[3], d1[3];
+        for (int k = 0; k < dim; k++) {
+            d0[k] = n[(e + 2) * dim + k] - n[e * dim + k];
+            d1[k] = n[(e + 3) * dim + k] - n[(e + 1) * dim + k];
+        }
+        T->act_margin[f] = fabs(tor_cpa(d0, d1, dim) - R) / R;
+        int act = tor_prox_coll_gap(n + e * dim, n + (e + 1) * dim, n + (e + 2) * dim, n + (e + 3) * dim, w[0],
+                                    w[1], w[2], w[3], R, dim, x + e * dim, x + (e + 1) * dim, x + (e + 2) * dim,
+                                    x + (e + 3) * dim, NULL, NULL, &T->tie_margin[f]);
         out = act ? TOR_STD : TOR_ZERO;
     } else {
         const double *wa = T->walls + T->fw[f] * 4, *wb = wa + 2;
         double r = T->radii[T->fa[f]];
         double wl = weight_value(T, T->rin[e], rho), wh = weight_value(T, T->rin[e + 1], rho);
-        int act = tor_prox_capsule(wa, wb, r, n + e * dim, n + (e + 1) * dim, wl, wh, x + e * dim,
-                                   x + (e + 1) * dim, NULL, NULL);
+        T->act_margin[f] = fabs(tor_segseg(n + e * dim, n + (e + 1) * dim, wa, wb) - r) / r;
+        int act = tor_prox_capsule_gap(wa, wb, r, n + e * dim, n + (e + 1) * dim, wl, wh, x + e * dim,
+                                       x + (e + 1) * dim, NULL, NULL, &T->tie_margin[f]);
         out = act ? TOR_STD : TOR_ZERO;
     }
     if (T->mode == TOR_MODE_ADMM) out = TOR_STD;

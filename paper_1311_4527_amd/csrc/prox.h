@@ -1,0 +1,456 @@
+// prox.h -- FP32 device minimisers of the three-weight planner for gfx950.
+//
+// Every minimiser returns the argmin of  f_b(x) + sum_k (w_k/2)|x_k - n_k|^2
+// (eq. general_minimizer_definition).  The collision and wall minimisers use
+// the separating-line form of the non-convex constraint: a segment avoids
+// the open capsule R (all points within r of [x_L, x_R]) iff some unit
+// normal u has both segment ends in {y : <y, u> >= h(u)}, h the support
+// function of R.  For a fixed u the best ends are the projections of n onto
+// that half-plane, so the minimiser is
+//     min_u F(u),  F(u) = sum_k (w_k/2) max(0, h(u) - <n_k, u>)^2 .
+// F is C^1 on the circle away from the two kinks of h, so its minimum is at
+// (a) a stationary point of a smooth piece where both ends are pushed (the
+// paper's tangent-slab family, App. I), (b) the outward normal of the point
+// of R nearest to one end while the other end is already clear (the
+// paper's "one spring relaxed" configuration), or (c) a kink of h (slab
+// resting on a flat side of the wall).  Candidates of each kind are
+// enumerated in closed form or by a bracketed 1-D root solve, and the one
+// of least F wins.  The stationary points of a piece are Lagrange points of
+// a quadratic on the unit circle; the global one is the root below the
+// smallest eigenvalue of the secular equation (trust-region theory), found
+// by safeguarded Newton.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace twa {
+
+enum : int { W_ZERO = 0, W_STD = 1, W_INF = 2 };
+
+struct f2 {
+    float x, y;
+};
+__device__ __forceinline__ f2 mk(float x, float y) { return f2{x, y}; }
+__device__ __forceinline__ f2 add(f2 a, f2 b) { return f2{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ f2 sub(f2 a, f2 b) { return f2{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ f2 scl(f2 a, float s) { return f2{a.x * s, a.y * s}; }
+__device__ __forceinline__ float dot(f2 a, f2 b) { return a.x * b.x + a.y * b.y; }
+__device__ __forceinline__ f2 perp(f2 a) { return f2{-a.y, a.x}; }
+__device__ __forceinline__ float pos(float v) { return v > 0.f ? v : 0.f; }
+
+struct f3 {
+    float x, y, z;
+};
+__device__ __forceinline__ f3 sub3(f3 a, f3 b) { return f3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ float dot3(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// Squared closest approach of (1-a) d0 + a d1 over a in [0, 1]
+// (the constraint of eq. basic_opt_prob on the relative positions).
+__device__ __forceinline__ float cpa_sq(f3 d0, f3 d1) {
+    f3 e = sub3(d1, d0);
+    float ee = dot3(e, e);
+    float a = 0.f;
+    if (ee > 0.f) a = fminf(fmaxf(-dot3(d0, e) / ee, 0.f), 1.f);
+    f3 v{d0.x + a * e.x, d0.y + a * e.y, d0.z + a * e.z};
+    return dot3(v, v);
+}
+
+__device__ __forceinline__ float point_seg_sq(f2 q, f2 a, f2 b) {
+    f2 d = sub(b, a);
+    float L2 = dot(d, d);
+    float t = 0.f;
+    if (L2 > 0.f) t = fminf(fmaxf(dot(sub(q, a), d) / L2, 0.f), 1.f);
+    f2 v = sub(add(a, scl(d, t)), q);
+    return dot(v, v);
+}
+
+__device__ __forceinline__ float orient(f2 a, f2 b, f2 c) {
+    return (b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x);
+}
+
+// Squared distance between planar segments [p0,p1] and [q0,q1]
+// (the constraint of eq. wall_minimizer over all alpha, beta).
+__device__ __forceinline__ float segseg_sq(f2 p0, f2 p1, f2 q0, f2 q1) {
+    float o1 = orient(p0, p1, q0), o2 = orient(p0, p1, q1);
+    float o3 = orient(q0, q1, p0), o4 = orient(q0, q1, p1);
+    if (((o1 > 0.f && o2 < 0.f) || (o1 < 0.f && o2 > 0.f)) && ((o3 > 0.f && o4 < 0.f) || (o3 < 0.f && o4 > 0.f)))
+        return 0.f;
+    float m = point_seg_sq(p0, q0, q1);
+    m = fminf(m, point_seg_sq(p1, q0, q1));
+    m = fminf(m, point_seg_sq(q0, p0, p1));
+    m = fminf(m, point_seg_sq(q1, p0, p1));
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// Energy minimiser, App. E (eq. energy_minimizer_output) with the limits of
+// infinite weights and of two equal weights tending to zero.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void energy_prox(float nl, float nh, float wl, float wh, int kl, int kh, float C,
+                                            float &xl, float &xh) {
+    if (C <= 0.f || (kl == W_INF && kh == W_INF)) {
+        xl = nl;
+        xh = nh;
+    } else if (kl == W_INF) {
+        xl = nl;
+        xh = (wh * nh + 2.f * C * nl) / (2.f * C + wh);
+    } else if (kh == W_INF) {
+        xh = nh;
+        xl = (wl * nl + 2.f * C * nh) / (2.f * C + wl);
+    } else if (kl == W_ZERO && kh == W_ZERO) {
+        xl = xh = 0.5f * (nl + nh);
+    } else {
+        float den = 2.f * C * (wl + wh) + wl * wh;
+        float cm = 2.f * C * (wl * nl + wh * nh);
+        xl = (wl * wh * nl + cm) / den;
+        xh = (wl * wh * nh + cm) / den;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Quadratic on the unit circle: E(u) = 1/2 u^T Q u - <b, u>,
+// Q = [[a, c], [c, e]] positive semi-definite.
+// ---------------------------------------------------------------------------
+struct Eig2 {
+    f2 v1, v2;       // eigenvectors of q1 <= q2
+    float gap;       // q2 - q1
+    float b1, b2;    // coordinates of b
+};
+
+__device__ __forceinline__ Eig2 eig2(float a, float c, float e, f2 b) {
+    Eig2 r;
+    float d = 0.5f * (a - e);
+    float rad = sqrtf(d * d + c * c);
+    f2 v;
+    if (rad <= 1e-30f) v = mk(1.f, 0.f);
+    else if (d >= 0.f) v = mk(-c, d + rad);
+    else v = mk(rad - d, -c);
+    float inv = rsqrtf(dot(v, v));
+    r.v1 = scl(v, inv);
+    r.v2 = perp(r.v1);
+    r.gap = 2.f * rad;
+    r.b1 = dot(b, r.v1);
+    r.b2 = dot(b, r.v2);
+    return r;
+}
+
+// Global minimiser of E on the circle.  Writes a second candidate (the
+// mirror point of the degenerate "hard case", where two minimisers tie)
+// into *alt and returns 2, else returns 1.
+__device__ __forceinline__ int trs_global(const Eig2 &g, f2 *out, f2 *alt) {
+    float b1 = g.b1, b2 = g.b2, gap = g.gap;
+    float bn = sqrtf(b1 * b1 + b2 * b2);
+    if (!(bn > 0.f)) {
+        // E = 1/2 u^T Q u: minimised along v1 (both signs)
+        out[0] = g.v1;
+        *alt = scl(g.v1, -1.f);
+        return 2;
+    }
+    // t = q1 - lambda > 0 solves b1^2/t^2 + b2^2/(t+gap)^2 = 1
+    float lo = fmaxf(fabsf(b1), bn - gap), hi = bn;
+    float t = hi;
+    for (int it = 0; it < 24; ++it) {
+        float y1 = b1 / t, y2 = b2 / (t + gap);
+        float S = y1 * y1 + y2 * y2;
+        float rs = rsqrtf(S);
+        float h = rs - 1.f; // increasing in t; root where h == 0
+        if (h > 0.f) hi = t;
+        else lo = t;
+        float dS = y1 * y1 / t + y2 * y2 / (t + gap); // = -S'/2
+        float hp = rs * rs * rs * dS;
+        float tn = t - h / hp;
+        if (!(tn > lo && tn < hi)) tn = 0.5f * (lo + hi);
+        if (tn == t) break;
+        t = tn;
+    }
+    float y1, y2;
+    bool hard = t <= 1e-6f * (bn + gap);
+    if (hard) {
+        y2 = fminf(fmaxf(b2 / (t + gap), -1.f), 1.f);
+        y1 = sqrtf(fmaxf(0.f, 1.f - y2 * y2));
+        if (b1 < 0.f) y1 = -y1;
+    } else {
+        y1 = b1 / t;
+        y2 = b2 / (t + gap);
+    }
+    float inv = rsqrtf(y1 * y1 + y2 * y2);
+    y1 *= inv;
+    y2 *= inv;
+    out[0] = add(scl(g.v1, y1), scl(g.v2, y2));
+    if (hard) {
+        *alt = add(scl(g.v1, -y1), scl(g.v2, y2));
+        return 2;
+    }
+    return 1;
+}
+
+// The two stationary points between the eigenvalues (a local minimum and a
+// local maximum), when they exist.  Returns how many were written.
+__device__ __forceinline__ int trs_middle(const Eig2 &g, f2 *out) {
+    float b1 = g.b1, b2 = g.b2, gap = g.gap;
+    if (!(gap > 0.f) || b1 == 0.f || b2 == 0.f) return 0;
+    float c1 = cbrtf(b1 * b1), c2 = cbrtf(b2 * b2);
+    float tm = gap * c1 / (c1 + c2); // t = lambda - q1 in (0, gap)
+    float y1 = b1 / tm, y2 = b2 / (gap - tm);
+    if (y1 * y1 + y2 * y2 >= 1.f) return 0;
+    int n = 0;
+    for (int side = 0; side < 2; ++side) {
+        float lo = side ? tm : 0.f, hi = side ? gap : tm;
+        for (int it = 0; it < 40; ++it) {
+            float mid = 0.5f * (lo + hi);
+            float a1 = b1 / mid, a2 = b2 / (gap - mid);
+            bool above = a1 * a1 + a2 * a2 > 1.f; // f > 0
+            // f decreases on (0, tm) and increases on (tm, gap)
+            if (side == 0) {
+                if (above) lo = mid;
+                else hi = mid;
+            } else {
+                if (above) hi = mid;
+                else lo = mid;
+            }
+        }
+        float t = 0.5f * (lo + hi);
+        float z1 = -b1 / t, z2 = b2 / (gap - t); // (q1 - lambda) = -t, (q2 - lambda) = gap - t
+        float inv = rsqrtf(z1 * z1 + z2 * z2);
+        out[n++] = add(scl(g.v1, z1 * inv), scl(g.v2, z2 * inv));
+    }
+    return n;
+}
+
+// Q and b of E_c(u) = sum_k (w_k/2)(r - <m_k, u>)^2 up to a constant
+__device__ __forceinline__ Eig2 piece_quadratic(f2 m0, f2 m1, float w0, float w1, float r) {
+    float a = w0 * m0.x * m0.x + w1 * m1.x * m1.x;
+    float c = w0 * m0.x * m0.y + w1 * m1.x * m1.y;
+    float e = w0 * m0.y * m0.y + w1 * m1.y * m1.y;
+    f2 b = scl(add(scl(m0, w0), scl(m1, w1)), r);
+    return eig2(a, c, e, b);
+}
+
+// ---------------------------------------------------------------------------
+// Disk (collision) minimiser on the difference variables (App. C, I):
+// min (w0/2)|v0 - m0|^2 + (w1/2)|v1 - m1|^2  s.t.  dist(0, [v0, v1]) >= R.
+// k0/k1: W_INF marks a certain end that must stay.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float disk_F(f2 u, f2 m0, f2 m1, float w0, float w1, float R) {
+    float g0 = pos(R - dot(m0, u)), g1 = pos(R - dot(m1, u));
+    return 0.5f * (w0 * g0 * g0 + w1 * g1 * g1);
+}
+
+// tangent normals from point q (|q| >= r) to the circle of radius r at c
+__device__ __forceinline__ int tangent_normals(f2 q, f2 c, float r, f2 *out) {
+    f2 w = sub(q, c);
+    float L2 = dot(w, w);
+    float s2 = L2 - r * r;
+    if (!(L2 > 0.f) || s2 < 0.f) return 0;
+    float s = sqrtf(s2);
+    f2 wp = perp(w);
+    float inv = 1.f / L2;
+    out[0] = scl(add(scl(w, r), scl(wp, s)), inv);
+    out[1] = scl(sub(scl(w, r), scl(wp, s)), inv);
+    return 2;
+}
+
+__device__ __forceinline__ void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R, f2 &v0,
+                                          f2 &v1) {
+    bool i0 = k0 == W_INF, i1 = k1 == W_INF;
+    if (i0 && i1) {
+        v0 = m0;
+        v1 = m1;
+        return;
+    }
+    if (i0 || i1) {
+        f2 q = i0 ? m0 : m1, m = i0 ? m1 : m0;
+        f2 cand[3];
+        int nc = tangent_normals(q, mk(0.f, 0.f), R, cand);
+        float mm = dot(m, m);
+        if (mm > 0.f) {
+            f2 u = scl(m, rsqrtf(mm));
+            if (dot(q, u) >= R) cand[nc++] = u;
+        }
+        f2 best = mk(1.f, 0.f);
+        float bg = INFINITY;
+        for (int k = 0; k < nc; ++k) {
+            float g = pos(R - dot(m, cand[k]));
+            if (g < bg) {
+                bg = g;
+                best = cand[k];
+            }
+        }
+        f2 vm = (bg < INFINITY) ? add(m, scl(best, bg)) : m;
+        if (i0) {
+            v0 = m0;
+            v1 = vm;
+        } else {
+            v1 = m1;
+            v0 = vm;
+        }
+        return;
+    }
+    Eig2 g = piece_quadratic(m0, m1, w0, w1, R);
+    f2 cand[4];
+    f2 alt;
+    int nc = trs_global(g, cand, &alt);
+    if (nc == 2) cand[1] = alt;
+    float q0 = dot(m0, m0), q1 = dot(m1, m1);
+    if (q0 > 0.f && q0 < R * R) cand[nc++] = scl(m0, rsqrtf(q0));
+    if (q1 > 0.f && q1 < R * R) cand[nc++] = scl(m1, rsqrtf(q1));
+    f2 best = cand[0];
+    float bF = disk_F(cand[0], m0, m1, w0, w1, R);
+    for (int k = 1; k < nc; ++k) {
+        float Fk = disk_F(cand[k], m0, m1, w0, w1, R);
+        if (Fk < bF) {
+            bF = Fk;
+            best = cand[k];
+        }
+    }
+    v0 = add(m0, scl(best, pos(R - dot(m0, best))));
+    v1 = add(m1, scl(best, pos(R - dot(m1, best))));
+}
+
+// ---------------------------------------------------------------------------
+// Capsule (wall) minimiser, App. D and I.
+// ---------------------------------------------------------------------------
+struct Capsule {
+    f2 a, b;
+    float r;
+};
+__device__ __forceinline__ float cap_h(const Capsule &C, f2 u) { return fmaxf(dot(C.a, u), dot(C.b, u)) + C.r; }
+__device__ __forceinline__ float cap_F(const Capsule &C, f2 u, f2 n0, f2 n1, float w0, float w1) {
+    float h = cap_h(C, u);
+    float g0 = pos(h - dot(n0, u)), g1 = pos(h - dot(n1, u));
+    return 0.5f * (w0 * g0 * g0 + w1 * g1 * g1);
+}
+__device__ __forceinline__ f2 closest_on_seg(f2 q, f2 a, f2 b) {
+    f2 d = sub(b, a);
+    float L2 = dot(d, d);
+    float t = 0.f;
+    if (L2 > 0.f) t = fminf(fmaxf(dot(sub(q, a), d) / L2, 0.f), 1.f);
+    return add(a, scl(d, t));
+}
+
+__device__ __forceinline__ void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int k0, int k1, f2 &x0,
+                                          f2 &x1) {
+    bool i0 = k0 == W_INF, i1 = k1 == W_INF;
+    if (i0 && i1) {
+        x0 = n0;
+        x1 = n1;
+        return;
+    }
+    f2 d = sub(C.b, C.a);
+    float L2 = dot(d, d);
+    bool seg = L2 > 0.f;
+    f2 sw = seg ? scl(perp(d), rsqrtf(L2)) : mk(0.f, 1.f);
+    f2 cand[16];
+    int nc = 0;
+    if (i0 || i1) {
+        // one end certain: the other moves along normals u visible from it
+        f2 q = i0 ? n0 : n1, m = i0 ? n1 : n0;
+        nc += tangent_normals(q, C.a, C.r, cand + nc);
+        if (seg) nc += tangent_normals(q, C.b, C.r, cand + nc);
+        f2 t0 = sub(m, C.a);
+        if (dot(t0, t0) > 0.f) cand[nc++] = scl(t0, rsqrtf(dot(t0, t0)));
+        if (seg) {
+            f2 t1 = sub(m, C.b);
+            if (dot(t1, t1) > 0.f) cand[nc++] = scl(t1, rsqrtf(dot(t1, t1)));
+            cand[nc++] = sw;
+            cand[nc++] = scl(sw, -1.f);
+        }
+        float tol = 1e-5f * (fabsf(q.x) + fabsf(q.y) + C.r);
+        f2 best = mk(1.f, 0.f);
+        float bg = INFINITY;
+        for (int k = 0; k < nc; ++k) {
+            float h = cap_h(C, cand[k]);
+            if (dot(q, cand[k]) < h - tol) continue; // not visible from the certain end
+            float g = pos(h - dot(m, cand[k]));
+            if (g < bg) {
+                bg = g;
+                best = cand[k];
+            }
+        }
+        f2 xm = (bg < INFINITY) ? add(m, scl(best, bg)) : m;
+        if (i0) {
+            x0 = n0;
+            x1 = xm;
+        } else {
+            x1 = n1;
+            x0 = xm;
+        }
+        return;
+    }
+    // (a) stationary points of each smooth piece
+    for (int pc = 0; pc < (seg ? 2 : 1); ++pc) {
+        f2 c = pc ? C.b : C.a;
+        Eig2 g = piece_quadratic(sub(n0, c), sub(n1, c), w0, w1, C.r);
+        f2 alt;
+        int k = trs_global(g, cand + nc, &alt);
+        nc += 1;
+        if (k == 2) cand[nc++] = alt;
+        nc += trs_middle(g, cand + nc);
+    }
+    // (c) kinks: slab against a flat side
+    if (seg) {
+        cand[nc++] = sw;
+        cand[nc++] = scl(sw, -1.f);
+    }
+    // (b) nearest boundary point of one end
+    for (int e = 0; e < 2; ++e) {
+        f2 n = e ? n1 : n0;
+        f2 c = closest_on_seg(n, C.a, C.b);
+        f2 t = sub(n, c);
+        float tt = dot(t, t);
+        if (tt > 0.f && tt < C.r * C.r) cand[nc++] = scl(t, rsqrtf(tt));
+    }
+    f2 best = cand[0];
+    float bF = cap_F(C, cand[0], n0, n1, w0, w1);
+    for (int k = 1; k < nc; ++k) {
+        float Fk = cap_F(C, cand[k], n0, n1, w0, w1);
+        if (Fk < bF) {
+            bF = Fk;
+            best = cand[k];
+        }
+    }
+    float h = cap_h(C, best);
+    x0 = add(n0, scl(best, pos(h - dot(n0, best))));
+    x1 = add(n1, scl(best, pos(h - dot(n1, best))));
+}
+
+// ---------------------------------------------------------------------------
+// Agent-agent minimiser through the difference variables v = x' - x of each
+// break-point (App. C).  At fixed v the best x is
+//   x = (rho n + rho' (n' - v)) / (rho + rho'),
+// leaving (omega/2)|v - (n' - n)|^2 with omega = rho rho'/(rho + rho').
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pair_weight(float r, float rp, int k, int kp, float &om, int &kom) {
+    if (k == W_INF && kp == W_INF) {
+        om = 0.f;
+        kom = W_INF;
+    } else if (k == W_INF) {
+        om = rp;
+        kom = W_STD;
+    } else if (kp == W_INF) {
+        om = r;
+        kom = W_STD;
+    } else {
+        om = r * rp / (r + rp);
+        kom = W_STD;
+    }
+}
+
+// rebuild one break-point pair from v (component-wise)
+__device__ __forceinline__ void pair_rebuild(float r, float rp, int k, int kp, float n, float np, float v, float &x,
+                                             float &xp) {
+    if (k == W_INF && kp == W_INF) {
+        x = n;
+        xp = np;
+    } else if (k == W_INF) {
+        x = n;
+        xp = n + v;
+    } else if (kp == W_INF) {
+        xp = np;
+        x = np - v;
+    } else {
+        x = (r * n + rp * (np - v)) / (r + rp);
+        xp = x + v;
+    }
+}
+
+} // namespace twa

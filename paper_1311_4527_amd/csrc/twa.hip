@@ -1,0 +1,1189 @@
+// twa.hip -- gfx950 kernels and host runtime of the three-weight
+// message-passing trajectory planner behind the C ABI of include/twa.h.
+//
+// One iteration (App. B, steps 1-7) is three launches on the solver stream:
+//   k_stream  one lane per factor, coalesced streams.  Collision and wall
+//             factors: closest-approach / segment-distance activity test on
+//             n = z - u (Sec. 3.3.1-3.3.2 weight rule); factors that are
+//             active, or were active last iteration, are appended to a
+//             work queue with one wave-aggregated atomic.  Energy and fixed
+//             factors are always active and are finished here.
+//   k_queue   one lane per queued factor: the full non-convex minimiser
+//             (App. C, D, I), the u update of the previous iteration
+//             (fused, see below), m = x + u, and the consensus sums.
+//   k_nodes   one lane per break-point node: z = weighted mean (step 5),
+//             <-rho (step 6), clear the sums.
+// The u update (step 7) of iteration k needs z^{k+1}, so it is deferred
+// into the next iteration's k_stream/k_queue: they recompute x^{k} from the
+// saved (z^{k-1}, u^{k-1}) -- bitwise the same arithmetic -- and update u
+// in registers, so u is read once and written once per iteration.
+// Consensus sums are accumulated as exact 64-bit fixed-point integers with
+// atomics, so the result does not depend on the order of the additions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/twa.h"
+#include "prox.h"
+
+using namespace twa;
+
+#define TWA_VERSION "twa-mi355x 0.1"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr float kZeroWeight = 1e-9f; // a zero weight is replaced by a small equal value (App. C-E)
+
+enum Mode : int { M_FIRST = 0, M_FUSED = 1, M_FINAL = 2 };
+
+// queue entry flags
+constexpr unsigned kPrev = 0x80000000u; // factor was active last iteration: recompute and update u
+constexpr unsigned kIdx = 0x7fffffffu;
+
+struct Params {
+    int p, eta, W;
+    long long Fc, Fw, Fe, Ff;
+    long long nbc, nbw, nbe, nbf; // blocks per factor kind in k_stream
+    // node records, time-major (s * p + i): x, y, z, <-rho code
+    float4 *zr_prev, *zr_cur;
+    const float *radii;  // [p]
+    const float4 *walls; // [W] (xL.x, xL.y, xR.x, xR.y)
+    const float *C;      // [p][eta]
+    const float4 *xfix;  // [2p] start(i), goal(i)
+    float4 *u_coll;      // [dim planes][Fc]
+    float4 *u_wall;      // [Fw]
+    float *u_energy;     // [Fe][2*dim]
+    float *u_fixed;      // [2p][dim]
+    unsigned *bits_coll, *bits_wall;
+    unsigned *qc, *qw;
+    int *counters; // [0] qc length, [1] qw length, [2] active coll, [3] active wall
+    unsigned long long *acc; // [2 kinds][dim][N]  kind 0 = std, 1 = inf
+    int *cnt;                // [2][N]
+    long long N;
+    double scale;
+    float scalef;
+    float rho, step;      // this iteration: weight value of rho0, alpha/rho0
+    float rho_prev, step_prev;
+    int dense;
+    // debug capture of this iteration
+    float *dbg_x;
+    unsigned char *dbg_rho;
+    long long e_energy, e_coll, e_wall; // canonical edge offsets
+    long long f_energy, f_coll, f_wall; // canonical factor offsets
+};
+
+__device__ __forceinline__ float wval(int code, float rho) {
+    return code == W_STD ? rho : (code == W_ZERO ? kZeroWeight * rho : 0.f);
+}
+
+__device__ __forceinline__ int wcode(float4 r) { return (int)r.w; }
+
+// wave-aggregated append of `val` where pred holds; all lanes must call
+__device__ __forceinline__ void push(unsigned *q, int *len, bool pred, unsigned val) {
+    unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return;
+    int lane = __lane_id();
+    int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(len, __popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) q[base + __popcll(mask & ((1ull << lane) - 1ull))] = val;
+}
+
+__device__ __forceinline__ void count_wave(int *ctr, bool pred) {
+    unsigned long long mask = __ballot(pred);
+    if (mask && __lane_id() == __ffsll((long long)mask) - 1) atomicAdd(ctr, __popcll(mask));
+}
+
+__device__ __forceinline__ void contribute(const Params &P, long long node, int kind, const float *m, int D) {
+    for (int k = 0; k < D; ++k) {
+        float v = fminf(fmaxf(m[k] * P.scalef, -4.0e18f), 4.0e18f);
+        long long q = __float2ll_rn(v);
+        atomicAdd(&P.acc[((long long)kind * D + k) * P.N + node], (unsigned long long)q);
+    }
+    atomicAdd(&P.cnt[(long long)kind * P.N + node], 1);
+}
+
+// (s, i, j) of collision factor f: s-major, then i < j row-major
+__device__ __forceinline__ void decode_pair(long long f, int p, int &s, int &i, int &j) {
+    long long P2 = (long long)p * (p - 1) / 2;
+    s = (int)(f / P2);
+    long long t = f - (long long)s * P2;
+    // rows i hold p-1-i pairs; first pair of row i is at T(i) = i(2p-i-1)/2
+    double B = 2.0 * p - 1.0;
+    int r = (int)((B - sqrt(B * B - 8.0 * (double)t)) * 0.5);
+    if (r < 0) r = 0;
+    if (r > p - 2) r = p - 2;
+    while (r > 0 && (long long)r * (2LL * p - r - 1) / 2 > t) --r;
+    while (r < p - 2 && (long long)(r + 1) * (2LL * p - r - 2) / 2 <= t) ++r;
+    i = r;
+    j = (int)(t - (long long)r * (2LL * p - r - 1) / 2) + r + 1;
+}
+
+template <int D>
+__device__ __forceinline__ void load_u_coll(const Params &P, long long f, float *u) {
+    float4 a = P.u_coll[f];
+    float4 b = P.u_coll[P.Fc + f];
+    u[0] = a.x, u[1] = a.y, u[2] = a.z, u[3] = a.w;
+    u[4] = b.x, u[5] = b.y, u[6] = b.z, u[7] = b.w;
+    if constexpr (D == 3) {
+        float4 c = P.u_coll[2 * P.Fc + f];
+        u[8] = c.x, u[9] = c.y, u[10] = c.z, u[11] = c.w;
+    }
+}
+template <int D>
+__device__ __forceinline__ void store_u_coll(const Params &P, long long f, const float *u) {
+    P.u_coll[f] = make_float4(u[0], u[1], u[2], u[3]);
+    P.u_coll[P.Fc + f] = make_float4(u[4], u[5], u[6], u[7]);
+    if constexpr (D == 3) P.u_coll[2 * P.Fc + f] = make_float4(u[8], u[9], u[10], u[11]);
+}
+
+// four node records of a collision factor: (i,s), (i,s+1), (j,s), (j,s+1)
+__device__ __forceinline__ void coll_nodes(const Params &P, int s, int i, int j, long long *nd) {
+    nd[0] = (long long)s * P.p + i;
+    nd[1] = (long long)(s + 1) * P.p + i;
+    nd[2] = (long long)s * P.p + j;
+    nd[3] = (long long)(s + 1) * P.p + j;
+}
+
+template <int D>
+__device__ __forceinline__ bool coll_active(const float *n, float R) {
+    // n: 4 edges x D; relative positions agent j - agent i at s and s+1
+    f3 d0{n[2 * D + 0] - n[0], n[2 * D + 1] - n[1], D == 3 ? n[2 * D + 2] - n[2] : 0.f};
+    f3 d1{n[3 * D + 0] - n[D + 0], n[3 * D + 1] - n[D + 1], D == 3 ? n[3 * D + 2] - n[D + 2] : 0.f};
+    return cpa_sq(d0, d1) < R * R;
+}
+
+// Full collision minimiser (App. C): n, weights -> x.  D == 3 solves in the
+// plane spanned by the two difference vectors (the optimum lies there).
+template <int D>
+__device__ __forceinline__ void coll_prox(const float *n, const float *w, const int *k, float R, float *x) {
+    float om_l, om_h;
+    int ko_l, ko_h;
+    pair_weight(w[0], w[2], k[0], k[2], om_l, ko_l);
+    pair_weight(w[1], w[3], k[1], k[3], om_h, ko_h);
+    float vl[3], vh[3];
+    if constexpr (D == 2) {
+        f2 ml = mk(n[4] - n[0], n[5] - n[1]);
+        f2 mh = mk(n[6] - n[2], n[7] - n[3]);
+        f2 a, b;
+        disk_prox(ml, mh, om_l, om_h, ko_l, ko_h, R, a, b);
+        vl[0] = a.x, vl[1] = a.y, vh[0] = b.x, vh[1] = b.y;
+    } else {
+        float ml[3] = {n[6] - n[0], n[7] - n[1], n[8] - n[2]};
+        float mh[3] = {n[9] - n[3], n[10] - n[4], n[11] - n[5]};
+        float nl = sqrtf(ml[0] * ml[0] + ml[1] * ml[1] + ml[2] * ml[2]);
+        float nh = sqrtf(mh[0] * mh[0] + mh[1] * mh[1] + mh[2] * mh[2]);
+        const float *f = nl > 0.f ? ml : mh;
+        float nf = nl > 0.f ? nl : nh;
+        float e1[3] = {1.f, 0.f, 0.f}, e2[3];
+        if (nf > 0.f) e1[0] = f[0] / nf, e1[1] = f[1] / nf, e1[2] = f[2] / nf;
+        const float *g = nl > 0.f ? mh : ml;
+        float pr = g[0] * e1[0] + g[1] * e1[1] + g[2] * e1[2];
+        float w3[3] = {g[0] - pr * e1[0], g[1] - pr * e1[1], g[2] - pr * e1[2]};
+        float nw = sqrtf(w3[0] * w3[0] + w3[1] * w3[1] + w3[2] * w3[2]);
+        if (!(nw > 1e-6f * (nf + nh))) {
+            int ax = 0;
+            if (fabsf(e1[1]) < fabsf(e1[ax])) ax = 1;
+            if (fabsf(e1[2]) < fabsf(e1[ax])) ax = 2;
+            float t[3] = {0.f, 0.f, 0.f};
+            t[ax] = 1.f;
+            float p2 = e1[ax];
+            w3[0] = t[0] - p2 * e1[0], w3[1] = t[1] - p2 * e1[1], w3[2] = t[2] - p2 * e1[2];
+            nw = sqrtf(w3[0] * w3[0] + w3[1] * w3[1] + w3[2] * w3[2]);
+        }
+        for (int q = 0; q < 3; ++q) e2[q] = w3[q] / nw;
+        f2 a2 = mk(ml[0] * e1[0] + ml[1] * e1[1] + ml[2] * e1[2], ml[0] * e2[0] + ml[1] * e2[1] + ml[2] * e2[2]);
+        f2 b2 = mk(mh[0] * e1[0] + mh[1] * e1[1] + mh[2] * e1[2], mh[0] * e2[0] + mh[1] * e2[1] + mh[2] * e2[2]);
+        f2 a, b;
+        disk_prox(a2, b2, om_l, om_h, ko_l, ko_h, R, a, b);
+        for (int q = 0; q < 3; ++q) {
+            vl[q] = a.x * e1[q] + a.y * e2[q];
+            vh[q] = b.x * e1[q] + b.y * e2[q];
+        }
+    }
+    for (int c = 0; c < D; ++c) {
+        pair_rebuild(w[0], w[2], k[0], k[2], n[c], n[2 * D + c], vl[c], x[c], x[2 * D + c]);
+        pair_rebuild(w[1], w[3], k[1], k[3], n[D + c], n[3 * D + c], vh[c], x[D + c], x[3 * D + c]);
+    }
+}
+
+__device__ __forceinline__ void node_xyz(float4 r, float *z, int D) {
+    z[0] = r.x, z[1] = r.y;
+    if (D == 3) z[2] = r.z;
+}
+
+// ------------------------------------------------------------------ k_stream
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stream(Params P) {
+    long long b = blockIdx.x;
+    const bool dense = P.dense != 0;
+    if (b < P.nbc) {
+        // ---------------- collision factors: activity only
+        long long f = b * kBlock + threadIdx.x;
+        bool valid = f < P.Fc;
+        bool push_prev = false, push_new = false;
+        int s = 0, i = 0, j = 1;
+        if (valid) {
+            decode_pair(f, P.p, s, i, j);
+            long long nd[4];
+            coll_nodes(P, s, i, j, nd);
+            float R = P.radii[i] + P.radii[j];
+            float n[4 * D];
+            bool check_cur = true;
+            float u[4 * D];
+            if (MODE == M_FIRST) {
+                load_u_coll<D>(P, f, u);
+            } else if (dense) {
+                load_u_coll<D>(P, f, u);
+                float zz[3];
+                for (int e = 0; e < 4; ++e) {
+                    node_xyz(P.zr_prev[nd[e]], zz, D);
+                    for (int c = 0; c < D; ++c) n[e * D + c] = zz[c] - u[e * D + c];
+                }
+                if (coll_active<D>(n, R)) {
+                    push_prev = true;
+                    check_cur = false;
+                } else {
+                    for (int q = 0; q < 4 * D; ++q) u[q] = 0.f;
+                    store_u_coll<D>(P, f, u);
+                }
+            } else {
+                unsigned w = P.bits_coll[f >> 5];
+                if ((w >> (f & 31)) & 1u) {
+                    push_prev = true;
+                    check_cur = false;
+                } else {
+                    for (int q = 0; q < 4 * D; ++q) u[q] = 0.f;
+                }
+            }
+            if (MODE == M_FINAL) {
+                check_cur = false;
+                if (!dense && !push_prev) store_u_coll<D>(P, f, u); // zero
+            }
+            if (check_cur) {
+                float zz[3];
+                for (int e = 0; e < 4; ++e) {
+                    node_xyz(P.zr_cur[nd[e]], zz, D);
+                    for (int c = 0; c < D; ++c) n[e * D + c] = zz[c] - u[e * D + c];
+                }
+                push_new = coll_active<D>(n, R);
+                if (!push_new && P.dbg_x) {
+                    long long e0 = P.e_coll + 4 * f;
+                    for (int q = 0; q < 4 * D; ++q) P.dbg_x[e0 * D + q] = n[q];
+                    P.dbg_rho[P.f_coll + f] = W_ZERO;
+                }
+            }
+        }
+        if (MODE != M_FINAL && !dense) {
+            // bits of this iteration are set by k_queue; clear this wave's words
+            __syncthreads();
+            if (valid && (f & 31) == 0) P.bits_coll[f >> 5] = 0u;
+        }
+        push(P.qc, &P.counters[0], push_prev || push_new, (unsigned)f | (push_prev ? kPrev : 0u));
+    } else if (b < P.nbc + P.nbw) {
+        // ---------------- wall factors: activity only (planar)
+        long long f = (b - P.nbc) * kBlock + threadIdx.x;
+        bool valid = f < P.Fw;
+        bool push_prev = false, push_new = false;
+        if (valid) {
+            int w = (int)(f % P.W);
+            long long si = f / P.W;
+            int i = (int)(si % P.p), s = (int)(si / P.p);
+            long long na = (long long)s * P.p + i, nb = na + P.p;
+            float4 wl = P.walls[w];
+            f2 xa = mk(wl.x, wl.y), xb = mk(wl.z, wl.w);
+            float r = P.radii[i];
+            float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+            bool check_cur = true;
+            if (MODE == M_FIRST) {
+                u = P.u_wall[f];
+            } else if (dense) {
+                u = P.u_wall[f];
+                float4 za = P.zr_prev[na], zb = P.zr_prev[nb];
+                f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
+                if (segseg_sq(n0, n1, xa, xb) < r * r) {
+                    push_prev = true;
+                    check_cur = false;
+                } else {
+                    u = make_float4(0.f, 0.f, 0.f, 0.f);
+                    P.u_wall[f] = u;
+                }
+            } else {
+                unsigned wd = P.bits_wall[f >> 5];
+                if ((wd >> (f & 31)) & 1u) {
+                    push_prev = true;
+                    check_cur = false;
+                }
+            }
+            if (MODE == M_FINAL) {
+                check_cur = false;
+                if (!dense && !push_prev) P.u_wall[f] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            if (check_cur) {
+                float4 za = P.zr_cur[na], zb = P.zr_cur[nb];
+                f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
+                push_new = segseg_sq(n0, n1, xa, xb) < r * r;
+                if (!push_new && P.dbg_x) {
+                    long long e0 = P.e_wall + 2 * f;
+                    P.dbg_x[e0 * 2 + 0] = n0.x, P.dbg_x[e0 * 2 + 1] = n0.y;
+                    P.dbg_x[e0 * 2 + 2] = n1.x, P.dbg_x[e0 * 2 + 3] = n1.y;
+                    P.dbg_rho[P.f_wall + f] = W_ZERO;
+                }
+            }
+        }
+        if (MODE != M_FINAL && !dense) {
+            __syncthreads();
+            if (valid && (f & 31) == 0) P.bits_wall[f >> 5] = 0u;
+        }
+        push(P.qw, &P.counters[1], push_prev || push_new, (unsigned)f | (push_prev ? kPrev : 0u));
+    } else if (b < P.nbc + P.nbw + P.nbe) {
+        // ---------------- energy factors: always weight rho0
+        long long f = (b - P.nbc - P.nbw) * kBlock + threadIdx.x;
+        if (f >= P.Fe) return;
+        int i = (int)(f / P.eta), s = (int)(f % P.eta);
+        long long na = (long long)s * P.p + i, nb = na + P.p;
+        float C = P.C[f];
+        float *up = P.u_energy + f * 2 * D;
+        float u[6];
+        for (int q = 0; q < 2 * D; ++q) u[q] = up[q];
+        float4 ca = P.zr_cur[na], cb = P.zr_cur[nb];
+        float zc[6];
+        node_xyz(ca, zc, D);
+        node_xyz(cb, zc + D, D);
+        int ka = wcode(ca), kb = wcode(cb);
+        if (MODE != M_FIRST) {
+            // recompute x^k from (z^{k-1}, u^{k-1}), then u^k
+            float4 pa = P.zr_prev[na], pb = P.zr_prev[nb];
+            float zp[6];
+            node_xyz(pa, zp, D);
+            node_xyz(pb, zp + D, D);
+            int pka = wcode(pa), pkb = wcode(pb);
+            float xk[6];
+            for (int c = 0; c < D; ++c)
+                energy_prox(zp[c] - u[c], zp[D + c] - u[D + c], wval(pka, P.rho_prev), wval(pkb, P.rho_prev), pka,
+                            pkb, C, xk[c], xk[D + c]);
+            for (int c = 0; c < D; ++c) {
+                u[c] = (ka == W_STD) ? u[c] + P.step_prev * (xk[c] - zc[c]) : 0.f;
+                u[D + c] = (kb == W_STD) ? u[D + c] + P.step_prev * (xk[D + c] - zc[D + c]) : 0.f;
+            }
+            for (int q = 0; q < 2 * D; ++q) up[q] = u[q];
+            if (MODE == M_FINAL) return;
+        }
+        float x[6], m[6];
+        for (int c = 0; c < D; ++c)
+            energy_prox(zc[c] - u[c], zc[D + c] - u[D + c], wval(ka, P.rho), wval(kb, P.rho), ka, kb, C, x[c],
+                        x[D + c]);
+        for (int q = 0; q < 2 * D; ++q) m[q] = x[q] + u[q];
+        contribute(P, na, 0, m, D);
+        contribute(P, nb, 0, m + D, D);
+        if (P.dbg_x) {
+            long long e0 = P.e_energy + 2 * f;
+            for (int q = 0; q < 2 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
+            P.dbg_rho[P.f_energy + f] = W_STD;
+        }
+    } else {
+        // ---------------- fixed start/goal factors: x = const, weight infinity
+        long long f = (b - P.nbc - P.nbw - P.nbe) * kBlock + threadIdx.x;
+        if (f >= P.Ff) return;
+        int i = (int)(f >> 1);
+        int s = (f & 1) ? P.eta : 0;
+        long long nd = (long long)s * P.p + i;
+        float *up = P.u_fixed + f * D;
+        float u[3];
+        for (int c = 0; c < D; ++c) u[c] = up[c];
+        if (MODE != M_FIRST) {
+            // ->rho^{k-1} = infinity, so u^k = 0
+            for (int c = 0; c < D; ++c) u[c] = 0.f, up[c] = 0.f;
+            if (MODE == M_FINAL) return;
+        }
+        float4 xf = P.xfix[f];
+        float x[3] = {xf.x, xf.y, xf.z}, m[3];
+        for (int c = 0; c < D; ++c) m[c] = x[c] + u[c];
+        contribute(P, nd, 1, m, D);
+        if (P.dbg_x) {
+            for (int c = 0; c < D; ++c) P.dbg_x[f * D + c] = x[c];
+            P.dbg_rho[f] = W_INF;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ k_queue
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_queue(Params P) {
+    const int nqc = P.counters[0], nqw = P.counters[1];
+    const long long total = (long long)nqc + nqw;
+    const bool dense = P.dense != 0;
+    for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < total; t += (long long)gridDim.x * kBlock) {
+        if (t < nqc) {
+            unsigned e = P.qc[t];
+            long long f = e & kIdx;
+            bool prev = (e & kPrev) != 0;
+            int s, i, j;
+            decode_pair(f, P.p, s, i, j);
+            long long nd[4];
+            coll_nodes(P, s, i, j, nd);
+            float R = P.radii[i] + P.radii[j];
+            float u[4 * D], zc[4 * D], n[4 * D], x[4 * D], w[4];
+            int k[4];
+            float4 rc[4];
+            for (int q = 0; q < 4; ++q) {
+                rc[q] = P.zr_cur[nd[q]];
+                node_xyz(rc[q], zc + q * D, D);
+                k[q] = wcode(rc[q]);
+            }
+            if (prev) {
+                load_u_coll<D>(P, f, u);
+                float wp[4];
+                int kp[4];
+                for (int q = 0; q < 4; ++q) {
+                    float4 rp = P.zr_prev[nd[q]];
+                    float zp[3];
+                    node_xyz(rp, zp, D);
+                    kp[q] = wcode(rp);
+                    wp[q] = wval(kp[q], P.rho_prev);
+                    for (int c = 0; c < D; ++c) n[q * D + c] = zp[c] - u[q * D + c];
+                }
+                coll_prox<D>(n, wp, kp, R, x); // x^k; its weight was rho0 on all four edges
+                for (int q = 0; q < 4; ++q)
+                    for (int c = 0; c < D; ++c)
+                        u[q * D + c] =
+                            (k[q] == W_STD) ? u[q * D + c] + P.step_prev * (x[q * D + c] - zc[q * D + c]) : 0.f;
+                if (MODE == M_FINAL) {
+                    store_u_coll<D>(P, f, u);
+                    continue;
+                }
+            } else if (MODE == M_FIRST) {
+                load_u_coll<D>(P, f, u);
+            } else {
+                for (int q = 0; q < 4 * D; ++q) u[q] = 0.f;
+            }
+            for (int q = 0; q < 4 * D; ++q) n[q] = zc[q] - u[q];
+            bool act = coll_active<D>(n, R);
+            if (act) {
+                for (int q = 0; q < 4; ++q) w[q] = wval(k[q], P.rho);
+                coll_prox<D>(n, w, k, R, x);
+                float m[3];
+                for (int q = 0; q < 4; ++q) {
+                    for (int c = 0; c < D; ++c) m[c] = x[q * D + c] + u[q * D + c];
+                    contribute(P, nd[q], 0, m, D);
+                }
+                atomicOr(&P.bits_coll[f >> 5], 1u << (f & 31));
+                atomicAdd(&P.counters[2], 1);
+            } else {
+                for (int q = 0; q < 4 * D; ++q) x[q] = n[q];
+            }
+            if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) store_u_coll<D>(P, f, u);
+            if (P.dbg_x) {
+                long long e0 = P.e_coll + 4 * f;
+                for (int q = 0; q < 4 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
+                P.dbg_rho[P.f_coll + f] = act ? W_STD : W_ZERO;
+            }
+        } else {
+            unsigned e = P.qw[t - nqc];
+            long long f = e & kIdx;
+            bool prev = (e & kPrev) != 0;
+            int wi = (int)(f % P.W);
+            long long si = f / P.W;
+            int i = (int)(si % P.p), s = (int)(si / P.p);
+            long long na = (long long)s * P.p + i, nb = na + P.p;
+            float4 wl = P.walls[wi];
+            Capsule Cw{mk(wl.x, wl.y), mk(wl.z, wl.w), P.radii[i]};
+            float4 ca = P.zr_cur[na], cb = P.zr_cur[nb];
+            int ka = wcode(ca), kb = wcode(cb);
+            float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (prev) {
+                u = P.u_wall[f];
+                float4 pa = P.zr_prev[na], pb = P.zr_prev[nb];
+                int pka = wcode(pa), pkb = wcode(pb);
+                f2 x0, x1;
+                capsule_prox(Cw, mk(pa.x - u.x, pa.y - u.y), mk(pb.x - u.z, pb.y - u.w), wval(pka, P.rho_prev),
+                             wval(pkb, P.rho_prev), pka, pkb, x0, x1);
+                u.x = (ka == W_STD) ? u.x + P.step_prev * (x0.x - ca.x) : 0.f;
+                u.y = (ka == W_STD) ? u.y + P.step_prev * (x0.y - ca.y) : 0.f;
+                u.z = (kb == W_STD) ? u.z + P.step_prev * (x1.x - cb.x) : 0.f;
+                u.w = (kb == W_STD) ? u.w + P.step_prev * (x1.y - cb.y) : 0.f;
+                if (MODE == M_FINAL) {
+                    P.u_wall[f] = u;
+                    continue;
+                }
+            } else if (MODE == M_FIRST) {
+                u = P.u_wall[f];
+            }
+            f2 n0 = mk(ca.x - u.x, ca.y - u.y), n1 = mk(cb.x - u.z, cb.y - u.w);
+            bool act = segseg_sq(n0, n1, Cw.a, Cw.b) < Cw.r * Cw.r;
+            f2 x0 = n0, x1 = n1;
+            if (act) {
+                capsule_prox(Cw, n0, n1, wval(ka, P.rho), wval(kb, P.rho), ka, kb, x0, x1);
+                float m0[2] = {x0.x + u.x, x0.y + u.y}, m1[2] = {x1.x + u.z, x1.y + u.w};
+                contribute(P, na, 0, m0, 2);
+                contribute(P, nb, 0, m1, 2);
+                atomicOr(&P.bits_wall[f >> 5], 1u << (f & 31));
+                atomicAdd(&P.counters[3], 1);
+            }
+            if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) P.u_wall[f] = u;
+            if (P.dbg_x) {
+                long long e0 = P.e_wall + 2 * f;
+                P.dbg_x[e0 * 2 + 0] = x0.x, P.dbg_x[e0 * 2 + 1] = x0.y;
+                P.dbg_x[e0 * 2 + 2] = x1.x, P.dbg_x[e0 * 2 + 3] = x1.y;
+                P.dbg_rho[P.f_wall + f] = act ? W_STD : W_ZERO;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ k_nodes
+// z^{k+1} and <-rho^{k+1} per node; shift the node records; clear the sums.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_nodes(Params P, int *stats_out) {
+    long long nd = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (nd == 0) {
+        // counters of this iteration -> stats, then reset for the next one
+        stats_out[0] = P.counters[2];
+        stats_out[1] = P.counters[3];
+        stats_out[2] = P.counters[0] + P.counters[1];
+        P.counters[0] = P.counters[1] = P.counters[2] = P.counters[3] = 0;
+    }
+    if (nd >= P.N) return;
+    int ci = P.cnt[P.N + nd], cs = P.cnt[nd];
+    float4 cur = P.zr_cur[nd];
+    float4 nw = cur;
+    if (ci > 0 || cs > 0) {
+        int kind = ci > 0 ? 1 : 0;
+        double den = (double)(ci > 0 ? ci : cs) * P.scale;
+        float z[3];
+        for (int c = 0; c < D; ++c) {
+            long long a = (long long)P.acc[((long long)kind * D + c) * P.N + nd];
+            z[c] = (float)((double)a / den);
+        }
+        nw.x = z[0];
+        nw.y = z[1];
+        if (D == 3) nw.z = z[2];
+        nw.w = (float)(ci > 0 ? W_INF : W_STD);
+    } else {
+        // every incoming weight zero: each m equals z (x = n for an inactive
+        // factor), so the mean of step 5 is z itself
+        nw.w = (float)W_ZERO;
+    }
+    P.zr_prev[nd] = cur;
+    P.zr_cur[nd] = nw;
+    for (int kind = 0; kind < 2; ++kind) {
+        for (int c = 0; c < D; ++c) P.acc[((long long)kind * D + c) * P.N + nd] = 0ull;
+        P.cnt[(long long)kind * P.N + nd] = 0;
+    }
+}
+
+__global__ void k_reset_counters(int *counters) {
+    if (threadIdx.x < 4) counters[threadIdx.x] = 0;
+}
+
+// ------------------------------------------------------------------ layout conversion
+// canonical [p][eta+1][dim] <-> time-major node records
+__global__ void k_z_import(float4 *zr, const float *z, int p, int eta, int D, const unsigned char *lrho, int keep_w) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long N = (long long)p * (eta + 1);
+    if (t >= N) return;
+    int i = (int)(t / (eta + 1)), s = (int)(t % (eta + 1));
+    long long nd = (long long)s * p + i;
+    float4 r = zr[nd];
+    r.x = z[t * D + 0];
+    r.y = z[t * D + 1];
+    r.z = D == 3 ? z[t * D + 2] : 0.f;
+    if (lrho) r.w = (float)lrho[t];
+    else if (!keep_w) r.w = (float)((s == 0 || s == eta) ? W_INF : W_STD);
+    zr[nd] = r;
+}
+__global__ void k_z_export(const float4 *zr, float *z, unsigned char *lrho, int p, int eta, int D) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long N = (long long)p * (eta + 1);
+    if (t >= N) return;
+    int i = (int)(t / (eta + 1)), s = (int)(t % (eta + 1));
+    float4 r = zr[(long long)s * p + i];
+    if (z) {
+        z[t * D + 0] = r.x;
+        z[t * D + 1] = r.y;
+        if (D == 3) z[t * D + 2] = r.z;
+    }
+    if (lrho) lrho[t] = (unsigned char)(int)r.w;
+}
+// u: canonical [E][dim] <-> per-kind layouts.  dir 0: import, 1: export
+__global__ void k_u_convert(Params P, float *u, int D, int dir) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long E = P.e_wall + 2 * P.Fw;
+    if (t >= E) return;
+    for (int c = 0; c < D; ++c) {
+        float *dst = nullptr;
+        float *src = u + t * D + c;
+        if (t < P.e_energy) {
+            dst = P.u_fixed + t * D + c;
+        } else if (t < P.e_coll) {
+            dst = P.u_energy + (t - P.e_energy) * D + c;
+        } else if (t < P.e_wall) {
+            long long r = t - P.e_coll;
+            long long f = r >> 2;
+            int slot = (int)(r & 3);
+            int q = slot * D + c;          // position inside the factor's 4*D vector
+            int plane = q >> 2, lane = q & 3;
+            dst = reinterpret_cast<float *>(P.u_coll + plane * P.Fc + f) + lane;
+        } else {
+            long long r = t - P.e_wall;
+            long long f = r >> 1;
+            int slot = (int)(r & 1);
+            dst = reinterpret_cast<float *>(P.u_wall + f) + slot * 2 + c;
+        }
+        if (dir == 0) *dst = *src;
+        else *src = *dst;
+    }
+}
+__global__ void k_fix_ends(float4 *zr, const float4 *xfix, int p, int eta) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p) return;
+    float4 a = xfix[2 * i], b = xfix[2 * i + 1];
+    a.w = (float)W_INF;
+    b.w = (float)W_INF;
+    zr[i] = a;
+    zr[(long long)eta * p + i] = b;
+}
+__global__ void k_fill_bits(unsigned *bits, long long nwords, unsigned v) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nwords) bits[t] = v;
+}
+__global__ void k_finite(const float4 *zr, long long N, const float *u, long long nu, int *bad) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < N) {
+        float4 r = zr[t];
+        if (!isfinite(r.x) || !isfinite(r.y) || !isfinite(r.z)) atomicOr(bad, 1);
+    }
+    for (long long q = t; q < nu; q += (long long)gridDim.x * blockDim.x)
+        if (!isfinite(u[q])) atomicOr(bad, 1);
+}
+
+} // namespace
+
+// ============================================================================
+// host runtime
+// ============================================================================
+
+struct twa_solver {
+    int p = 0, eta = 0, dim = 0, W = 0;
+    float rho0 = 1.f, alpha = 1.f, rho0_init = 1.f;
+    int n_warm = 0;
+    unsigned flags = 0;
+    long long iter = 0;
+    bool pending = false;
+    hipStream_t stream = nullptr;
+    Params P{};
+    int *stats_dev = nullptr;
+    int *bad_dev = nullptr;
+    std::vector<void *> allocs;
+    std::string err;
+    twa_status latched = TWA_OK;
+    float *dbg_x = nullptr;
+    unsigned char *dbg_rho = nullptr;
+    long long nblocks_stream = 0;
+    int nblocks_queue = 0;
+    // event timing (twa_iterate_timed)
+    std::vector<hipEvent_t> events;
+    int timing = 0;
+};
+
+namespace {
+
+void mark(twa_solver *s, int slot) {
+    if (!s->timing) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, s->stream);
+    s->events.push_back(e);
+    (void)slot;
+}
+
+twa_status fail(twa_solver *s, twa_status st, const std::string &msg) {
+    if (s) {
+        s->err = msg;
+        if (st == TWA_E_DEVICE) s->latched = TWA_E_DEVICE;
+    }
+    return st;
+}
+
+#define HIP_TRY(s, call)                                                                                       \
+    do {                                                                                                       \
+        hipError_t e_ = (call);                                                                                \
+        if (e_ != hipSuccess)                                                                                  \
+            return fail((s), TWA_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+template <class T>
+twa_status dev_alloc(twa_solver *s, T **ptr, size_t count) {
+    void *p = nullptr;
+    size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(s, TWA_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    s->allocs.push_back(p);
+    *ptr = static_cast<T *>(p);
+    return TWA_OK;
+}
+
+template <class T>
+twa_status to_host(twa_solver *s, std::vector<T> &dst, const T *src, size_t count) {
+    dst.resize(count);
+    if (count == 0) return TWA_OK;
+    HIP_TRY(s, hipMemcpyAsync(dst.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    return TWA_OK;
+}
+
+#define TRY(x)                                                                                                 \
+    do {                                                                                                       \
+        twa_status st_ = (x);                                                                                  \
+        if (st_ != TWA_OK) return st_;                                                                         \
+    } while (0)
+
+twa_status check_alive(twa_solver *s) {
+    if (!s) return TWA_E_INVALID;
+    if (s->latched != TWA_OK) return s->latched;
+    return TWA_OK;
+}
+
+void mark(twa_solver *s, int slot);
+
+template <int D>
+twa_status launch_iteration(twa_solver *s, int mode) {
+    Params P = s->P;
+    long long g = s->nblocks_stream;
+    int gq = s->nblocks_queue;
+    if (mode == M_FIRST) {
+        mark(s, 0);
+        hipLaunchKernelGGL((k_stream<D, M_FIRST>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
+        mark(s, 1);
+        hipLaunchKernelGGL((k_queue<D, M_FIRST>), dim3(gq), dim3(kBlock), 0, s->stream, P);
+        mark(s, 2);
+    } else if (mode == M_FUSED) {
+        mark(s, 0);
+        hipLaunchKernelGGL((k_stream<D, M_FUSED>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
+        mark(s, 1);
+        hipLaunchKernelGGL((k_queue<D, M_FUSED>), dim3(gq), dim3(kBlock), 0, s->stream, P);
+        mark(s, 2);
+    } else {
+        hipLaunchKernelGGL((k_stream<D, M_FINAL>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
+        hipLaunchKernelGGL((k_queue<D, M_FINAL>), dim3(gq), dim3(kBlock), 0, s->stream, P);
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s->stream, P.counters);
+        HIP_TRY(s, hipGetLastError());
+        return TWA_OK;
+    }
+    unsigned nb = (unsigned)((P.N + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_nodes<D>), dim3(nb), dim3(kBlock), 0, s->stream, P, s->stats_dev);
+    mark(s, 3);
+    HIP_TRY(s, hipGetLastError());
+    return TWA_OK;
+}
+
+twa_status run_iteration(twa_solver *s, int mode, float rho, float rho_prev) {
+    s->P.rho = rho;
+    s->P.step = s->alpha / rho;
+    s->P.rho_prev = rho_prev;
+    s->P.step_prev = s->alpha / rho_prev;
+    s->P.dbg_x = (mode == M_FINAL) ? nullptr : s->dbg_x;
+    s->P.dbg_rho = (mode == M_FINAL) ? nullptr : s->dbg_rho;
+    twa_status st = s->dim == 2 ? launch_iteration<2>(s, mode) : launch_iteration<3>(s, mode);
+    s->P.dbg_x = nullptr;
+    s->P.dbg_rho = nullptr;
+    return st;
+}
+
+float rho_at(const twa_solver *s, long long k) { return k < s->n_warm ? s->rho0_init : s->rho0; }
+
+// pending -> canonical: materialise u^k
+twa_status finalize(twa_solver *s) {
+    if (!s->pending) return TWA_OK;
+    TRY(run_iteration(s, M_FINAL, rho_at(s, s->iter), rho_at(s, s->iter - 1)));
+    s->pending = false;
+    return TWA_OK;
+}
+
+twa_status reset_state_buffers(twa_solver *s) {
+    const Params &P = s->P;
+    long long D = s->dim;
+    HIP_TRY(s, hipMemsetAsync(P.u_coll, 0, sizeof(float4) * std::max<long long>(1, D * P.Fc), s->stream));
+    HIP_TRY(s, hipMemsetAsync(P.u_wall, 0, sizeof(float4) * std::max<long long>(1, P.Fw), s->stream));
+    HIP_TRY(s, hipMemsetAsync(P.u_energy, 0, sizeof(float) * std::max<long long>(1, P.Fe * 2 * D), s->stream));
+    HIP_TRY(s, hipMemsetAsync(P.u_fixed, 0, sizeof(float) * std::max<long long>(1, P.Ff * D), s->stream));
+    HIP_TRY(s, hipMemsetAsync(P.bits_coll, 0, sizeof(unsigned) * std::max<long long>(1, (P.Fc + 31) / 32), s->stream));
+    HIP_TRY(s, hipMemsetAsync(P.bits_wall, 0, sizeof(unsigned) * std::max<long long>(1, (P.Fw + 31) / 32), s->stream));
+    HIP_TRY(s, hipMemsetAsync(P.acc, 0, sizeof(unsigned long long) * 2 * D * P.N, s->stream));
+    HIP_TRY(s, hipMemsetAsync(P.cnt, 0, sizeof(int) * 2 * P.N, s->stream));
+    HIP_TRY(s, hipMemsetAsync(P.counters, 0, sizeof(int) * 8, s->stream));
+    HIP_TRY(s, hipMemsetAsync(s->stats_dev, 0, sizeof(int) * 4, s->stream));
+    s->pending = false;
+    return TWA_OK;
+}
+
+bool finite_all(const std::vector<float> &v) {
+    for (float x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *twa_version(void) { return TWA_VERSION; }
+
+const char *twa_last_error(const twa_solver *s) { return s ? s->err.c_str() : "null solver"; }
+
+void twa_destroy(twa_solver *s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (void *p : s->allocs) (void)hipFree(p);
+    delete s;
+}
+
+twa_status twa_create(int p, int eta, int dim, const float *radii, const float *x0, const float *xT, int n_walls,
+                      const float *walls, const float *C, float rho0, float alpha, unsigned flags,
+                      void *hip_stream, twa_solver **out) {
+    if (!out) return TWA_E_INVALID;
+    *out = nullptr;
+    twa_solver *s = new (std::nothrow) twa_solver();
+    if (!s) return TWA_E_NOMEM;
+    auto bail = [&](twa_status st) {
+        std::string e = s->err;
+        twa_destroy(s);
+        (void)e;
+        return st;
+    };
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    if (p < 1 || eta < 1 || (dim != 2 && dim != 3) || n_walls < 0) {
+        fail(s, TWA_E_INVALID, "need p >= 1, eta >= 1, dim in {2,3}, n_walls >= 0");
+        return bail(TWA_E_INVALID);
+    }
+    if (n_walls > 0 && dim != 2) {
+        fail(s, TWA_E_INVALID, "walls are planar only (dim == 2)");
+        return bail(TWA_E_INVALID);
+    }
+    if (!radii || !x0 || !xT || !C || (n_walls > 0 && !walls)) {
+        fail(s, TWA_E_INVALID, "null array argument");
+        return bail(TWA_E_INVALID);
+    }
+    if (!(rho0 > 0.f) || !(alpha > 0.f) || !std::isfinite(rho0) || !std::isfinite(alpha)) {
+        fail(s, TWA_E_INVALID, "rho0 and alpha must be finite and > 0");
+        return bail(TWA_E_INVALID);
+    }
+    if (flags & ~(unsigned)(TWA_F_DENSE)) {
+        fail(s, TWA_E_INVALID, "unsupported flag");
+        return bail(TWA_E_INVALID);
+    }
+    long long P2 = (long long)p * (p - 1) / 2;
+    long long Fc = (long long)eta * P2, Fw = (long long)eta * p * n_walls, Fe = (long long)eta * p, Ff = 2LL * p;
+    if (Fc >= (long long)kIdx || Fw >= (long long)kIdx) {
+        fail(s, TWA_E_INVALID, "too many factors for one solver");
+        return bail(TWA_E_INVALID);
+    }
+    s->p = p, s->eta = eta, s->dim = dim, s->W = n_walls;
+    s->rho0 = s->rho0_init = rho0, s->alpha = alpha, s->flags = flags;
+    // --- host copies for validation
+    std::vector<float> hr, h0, hT, hw, hC;
+    if (to_host(s, hr, radii, p) || to_host(s, h0, x0, (size_t)p * dim) || to_host(s, hT, xT, (size_t)p * dim) ||
+        to_host(s, hw, walls, (size_t)n_walls * 2 * dim) || to_host(s, hC, C, (size_t)p * eta))
+        return bail(TWA_E_DEVICE);
+    if (!finite_all(hr) || !finite_all(h0) || !finite_all(hT) || !finite_all(hw) || !finite_all(hC)) {
+        fail(s, TWA_E_INVALID, "non-finite input");
+        return bail(TWA_E_INVALID);
+    }
+    for (float r : hr)
+        if (!(r > 0.f)) {
+            fail(s, TWA_E_INVALID, "radii must be > 0");
+            return bail(TWA_E_INVALID);
+        }
+    for (float c : hC)
+        if (c < 0.f) {
+            fail(s, TWA_E_INVALID, "energy coefficients must be >= 0");
+            return bail(TWA_E_INVALID);
+        }
+    double Lmax = 1.0;
+    for (float v : h0) Lmax = std::max(Lmax, (double)std::fabs(v));
+    for (float v : hT) Lmax = std::max(Lmax, (double)std::fabs(v));
+    for (float v : hw) Lmax = std::max(Lmax, (double)std::fabs(v));
+    // feasibility of the fixed end points (Sec. 1: non-strict separation)
+    for (int which = 0; which < 2; ++which) {
+        const std::vector<float> &X = which ? hT : h0;
+        for (int i = 0; i < p; ++i)
+            for (int j = i + 1; j < p; ++j) {
+                double d2 = 0;
+                for (int c = 0; c < dim; ++c) {
+                    double d = (double)X[i * dim + c] - X[j * dim + c];
+                    d2 += d * d;
+                }
+                double R = (double)hr[i] + hr[j];
+                if (d2 < R * R) {
+                    fail(s, TWA_E_INFEASIBLE, std::string(which ? "goals " : "starts ") + std::to_string(i) + " and " +
+                                                  std::to_string(j) + " overlap");
+                    return bail(TWA_E_INFEASIBLE);
+                }
+            }
+        for (int i = 0; i < p && n_walls > 0; ++i)
+            for (int w = 0; w < n_walls; ++w) {
+                double ax = hw[w * 4 + 0], ay = hw[w * 4 + 1], bx = hw[w * 4 + 2], by = hw[w * 4 + 3];
+                double qx = X[i * 2 + 0], qy = X[i * 2 + 1];
+                double dx = bx - ax, dy = by - ay, L2 = dx * dx + dy * dy, t = 0;
+                if (L2 > 0) t = std::min(1.0, std::max(0.0, ((qx - ax) * dx + (qy - ay) * dy) / L2));
+                double ex = ax + t * dx - qx, ey = ay + t * dy - qy;
+                if (ex * ex + ey * ey < (double)hr[i] * hr[i]) {
+                    fail(s, TWA_E_INFEASIBLE, std::string(which ? "goal " : "start ") + std::to_string(i) +
+                                                  " touches wall " + std::to_string(w));
+                    return bail(TWA_E_INFEASIBLE);
+                }
+            }
+    }
+    // --- device buffers
+    Params &P = s->P;
+    P.p = p, P.eta = eta, P.W = n_walls;
+    P.Fc = Fc, P.Fw = Fw, P.Fe = Fe, P.Ff = Ff;
+    P.N = (long long)p * (eta + 1);
+    P.nbc = (Fc + kBlock - 1) / kBlock;
+    P.nbw = (Fw + kBlock - 1) / kBlock;
+    P.nbe = (Fe + kBlock - 1) / kBlock;
+    P.nbf = (Ff + kBlock - 1) / kBlock;
+    s->nblocks_stream = P.nbc + P.nbw + P.nbe + P.nbf;
+    s->nblocks_queue = 1024;
+    P.e_energy = Ff;
+    P.e_coll = Ff + 2 * Fe;
+    P.e_wall = P.e_coll + 4 * Fc;
+    P.f_energy = Ff;
+    P.f_coll = Ff + Fe;
+    P.f_wall = Ff + Fe + Fc;
+    P.dense = (flags & TWA_F_DENSE) ? 1 : 0;
+    // fixed-point scale: |m| * scale * (degree + 1) stays below 2^62
+    long long deg = 2LL * (p - 1) + 2 + 2LL * n_walls + 1;
+    double lim = std::ldexp(1.0, 62) / (8.0 * Lmax * (double)deg);
+    int S = (int)std::floor(std::log2(lim));
+    S = std::min(S, 44);
+    P.scale = std::ldexp(1.0, S);
+    P.scalef = (float)P.scale;
+    float *radii_d, *C_d;
+    float4 *walls_d, *xfix_d;
+    if (dev_alloc(s, &P.zr_prev, P.N) || dev_alloc(s, &P.zr_cur, P.N) || dev_alloc(s, &radii_d, p) ||
+        dev_alloc(s, &walls_d, std::max(1, n_walls)) || dev_alloc(s, &C_d, (size_t)p * eta) ||
+        dev_alloc(s, &xfix_d, Ff) || dev_alloc(s, &P.u_coll, (size_t)std::max<long long>(1, dim * Fc)) ||
+        dev_alloc(s, &P.u_wall, (size_t)std::max<long long>(1, Fw)) ||
+        dev_alloc(s, &P.u_energy, (size_t)Fe * 2 * dim) || dev_alloc(s, &P.u_fixed, (size_t)Ff * dim) ||
+        dev_alloc(s, &P.bits_coll, (size_t)std::max<long long>(1, (Fc + 31) / 32)) ||
+        dev_alloc(s, &P.bits_wall, (size_t)std::max<long long>(1, (Fw + 31) / 32)) ||
+        dev_alloc(s, &P.qc, (size_t)std::max<long long>(1, Fc)) ||
+        dev_alloc(s, &P.qw, (size_t)std::max<long long>(1, Fw)) || dev_alloc(s, &P.counters, 8) ||
+        dev_alloc(s, &P.acc, (size_t)2 * dim * P.N) || dev_alloc(s, &P.cnt, (size_t)2 * P.N) ||
+        dev_alloc(s, &s->stats_dev, 4) || dev_alloc(s, &s->bad_dev, 1))
+        return bail(TWA_E_NOMEM);
+    P.radii = radii_d, P.C = C_d, P.walls = walls_d, P.xfix = xfix_d;
+    // constants
+    std::vector<float4> hwall(std::max(1, n_walls)), hfix(Ff);
+    for (int w = 0; w < n_walls; ++w) hwall[w] = make_float4(hw[w * 4 + 0], hw[w * 4 + 1], hw[w * 4 + 2], hw[w * 4 + 3]);
+    for (int i = 0; i < p; ++i) {
+        hfix[2 * i] = make_float4(h0[i * dim], h0[i * dim + 1], dim == 3 ? h0[i * dim + 2] : 0.f, 0.f);
+        hfix[2 * i + 1] = make_float4(hT[i * dim], hT[i * dim + 1], dim == 3 ? hT[i * dim + 2] : 0.f, 0.f);
+    }
+    // initial state: straight lines, <-rho INF at the ends and STD inside
+    std::vector<float4> hz(P.N);
+    for (int i = 0; i < p; ++i)
+        for (int s2 = 0; s2 <= eta; ++s2) {
+            float v[3] = {0.f, 0.f, 0.f};
+            for (int c = 0; c < dim; ++c) {
+                double a = h0[i * dim + c], b = hT[i * dim + c];
+                v[c] = (s2 == 0) ? (float)a : (s2 == eta) ? (float)b : (float)(a + (double)s2 / eta * (b - a));
+            }
+            hz[(size_t)s2 * p + i] = make_float4(v[0], v[1], v[2], (float)((s2 == 0 || s2 == eta) ? W_INF : W_STD));
+        }
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(radii_d, hr.data(), sizeof(float) * p, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(walls_d, hwall.data(), sizeof(float4) * hwall.size(), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(C_d, hC.data(), sizeof(float) * hC.size(), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(xfix_d, hfix.data(), sizeof(float4) * Ff, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(P.zr_cur, hz.data(), sizeof(float4) * P.N, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(P.zr_prev, hz.data(), sizeof(float4) * P.N, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        fail(s, TWA_E_DEVICE, std::string("upload: ") + hipGetErrorString(e));
+        return bail(TWA_E_DEVICE);
+    }
+    if (reset_state_buffers(s) != TWA_OK) return bail(TWA_E_DEVICE);
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(TWA_E_DEVICE);
+    *out = s;
+    return TWA_OK;
+}
+
+twa_status twa_set_init(twa_solver *s, const float *z) {
+    TRY(check_alive(s));
+    if (!z) return fail(s, TWA_E_INVALID, "null z");
+    long long N = s->P.N;
+    unsigned nb = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL(k_z_import, dim3(nb), dim3(256), 0, s->stream, s->P.zr_cur, z, s->p, s->eta, s->dim,
+                       (const unsigned char *)nullptr, 0);
+    HIP_TRY(s, hipGetLastError());
+    // the end points are the constants x(0), x(T)
+    hipLaunchKernelGGL(k_fix_ends, dim3((unsigned)((s->p + 255) / 256)), dim3(256), 0, s->stream, s->P.zr_cur,
+                       (const float4 *)s->P.xfix, s->p, s->eta);
+    HIP_TRY(s, hipGetLastError());
+    HIP_TRY(s, hipMemcpyAsync(s->P.zr_prev, s->P.zr_cur, sizeof(float4) * N, hipMemcpyDeviceToDevice, s->stream));
+    TRY(reset_state_buffers(s));
+    s->iter = 0;
+    return TWA_OK;
+}
+
+twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm) {
+    TRY(check_alive(s));
+    if (!(rho0_init > 0.f) || n_warm < 0) return fail(s, TWA_E_INVALID, "rho0_init > 0 and n_warm >= 0 required");
+    s->rho0_init = rho0_init;
+    s->n_warm = n_warm;
+    return TWA_OK;
+}
+
+twa_status twa_iterate(twa_solver *s, int k) {
+    TRY(check_alive(s));
+    if (k < 0) return fail(s, TWA_E_INVALID, "k must be >= 0");
+    for (int it = 0; it < k; ++it) {
+        float rho = rho_at(s, s->iter);
+        if (!s->pending) {
+            TRY(run_iteration(s, M_FIRST, rho, rho));
+        } else {
+            TRY(run_iteration(s, M_FUSED, rho, rho_at(s, s->iter - 1)));
+        }
+        s->pending = true;
+        s->iter++;
+        s->dbg_x = nullptr;
+        s->dbg_rho = nullptr;
+    }
+    return TWA_OK;
+}
+
+twa_status twa_iterate_timed(twa_solver *s, int k, double *kernel_ms) {
+    TRY(check_alive(s));
+    if (!kernel_ms) return fail(s, TWA_E_INVALID, "null kernel_ms");
+    s->events.clear();
+    s->timing = 1;
+    twa_status st = twa_iterate(s, k);
+    s->timing = 0;
+    double acc[3] = {0, 0, 0};
+    hipError_t e = hipStreamSynchronize(s->stream);
+    // four marks per iteration: before stream, before queue, before nodes, after nodes
+    for (size_t q = 0; q + 3 < s->events.size() && e == hipSuccess; q += 4) {
+        for (int kk = 0; kk < 3; ++kk) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, s->events[q + kk], s->events[q + kk + 1]) == hipSuccess) acc[kk] += ms;
+        }
+    }
+    for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
+    s->events.clear();
+    for (int kk = 0; kk < 3; ++kk) kernel_ms[kk] = acc[kk];
+    if (st != TWA_OK) return st;
+    if (e != hipSuccess) return fail(s, TWA_E_DEVICE, std::string("timed iterate: ") + hipGetErrorString(e));
+    return TWA_OK;
+}
+
+twa_status twa_capture_next(twa_solver *s, float *x_out, unsigned char *rho_out) {
+    TRY(check_alive(s));
+    if ((x_out == nullptr) != (rho_out == nullptr)) return fail(s, TWA_E_INVALID, "pass both buffers or neither");
+    s->dbg_x = x_out;
+    s->dbg_rho = rho_out;
+    return TWA_OK;
+}
+
+twa_status twa_get_trajectories(twa_solver *s, float *z_out) {
+    TRY(check_alive(s));
+    if (!z_out) return fail(s, TWA_E_INVALID, "null z_out");
+    unsigned nb = (unsigned)((s->P.N + 255) / 256);
+    hipLaunchKernelGGL(k_z_export, dim3(nb), dim3(256), 0, s->stream, (const float4 *)s->P.zr_cur, z_out,
+                       (unsigned char *)nullptr, s->p, s->eta, s->dim);
+    HIP_TRY(s, hipGetLastError());
+    return TWA_OK;
+}
+
+twa_status twa_get_state(twa_solver *s, float *z, float *u, unsigned char *lrho, long long *iter) {
+    TRY(check_alive(s));
+    TRY(finalize(s));
+    unsigned nb = (unsigned)((s->P.N + 255) / 256);
+    if (z || lrho)
+        hipLaunchKernelGGL(k_z_export, dim3(nb), dim3(256), 0, s->stream, (const float4 *)s->P.zr_cur, z, lrho, s->p,
+                           s->eta, s->dim);
+    if (u) {
+        long long E = s->P.e_wall + 2 * s->P.Fw;
+        hipLaunchKernelGGL(k_u_convert, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s->stream, s->P, u, s->dim,
+                           1);
+    }
+    HIP_TRY(s, hipGetLastError());
+    if (iter) *iter = s->iter;
+    return TWA_OK;
+}
+
+twa_status twa_set_state(twa_solver *s, const float *z, const float *u, const unsigned char *lrho, long long iter) {
+    TRY(check_alive(s));
+    if (!z || !u || !lrho) return fail(s, TWA_E_INVALID, "null state array");
+    if (iter < 0) return fail(s, TWA_E_INVALID, "iter must be >= 0");
+    TRY(reset_state_buffers(s));
+    unsigned nb = (unsigned)((s->P.N + 255) / 256);
+    hipLaunchKernelGGL(k_z_import, dim3(nb), dim3(256), 0, s->stream, s->P.zr_cur, z, s->p, s->eta, s->dim, lrho, 1);
+    long long E = s->P.e_wall + 2 * s->P.Fw;
+    hipLaunchKernelGGL(k_u_convert, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s->stream, s->P,
+                       const_cast<float *>(u), s->dim, 0);
+    HIP_TRY(s, hipGetLastError());
+    HIP_TRY(s, hipMemcpyAsync(s->P.zr_prev, s->P.zr_cur, sizeof(float4) * s->P.N, hipMemcpyDeviceToDevice, s->stream));
+    s->iter = iter;
+    s->pending = false;
+    return TWA_OK;
+}
+
+twa_status twa_get_stats(twa_solver *s, twa_stats *out) {
+    TRY(check_alive(s));
+    if (!out) return fail(s, TWA_E_INVALID, "null stats");
+    int h[4] = {0, 0, 0, 0};
+    HIP_TRY(s, hipMemcpyAsync(h, s->stats_dev, sizeof(int) * 3, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    out->iter = s->iter;
+    out->active_coll = h[0];
+    out->active_wall = h[1];
+    out->queued = h[2];
+    return TWA_OK;
+}
+
+twa_status twa_sizes(const twa_solver *s, long long *n_factors, long long *n_edges) {
+    if (!s) return TWA_E_INVALID;
+    const Params &P = s->P;
+    if (n_factors) *n_factors = P.Ff + P.Fe + P.Fc + P.Fw;
+    if (n_edges) *n_edges = P.e_wall + 2 * P.Fw;
+    return TWA_OK;
+}
+
+twa_status twa_check_finite(twa_solver *s) {
+    TRY(check_alive(s));
+    TRY(finalize(s));
+    HIP_TRY(s, hipMemsetAsync(s->bad_dev, 0, sizeof(int), s->stream));
+    unsigned nb = (unsigned)((s->P.N + 255) / 256);
+    hipLaunchKernelGGL(k_finite, dim3(nb), dim3(256), 0, s->stream, (const float4 *)s->P.zr_cur, s->P.N,
+                       (const float *)s->P.u_coll, (long long)(4 * s->dim * s->P.Fc), s->bad_dev);
+    hipLaunchKernelGGL(k_finite, dim3(1), dim3(256), 0, s->stream, (const float4 *)s->P.zr_cur, 0LL,
+                       (const float *)s->P.u_wall, (long long)(4 * s->P.Fw), s->bad_dev);
+    hipLaunchKernelGGL(k_finite, dim3(1), dim3(256), 0, s->stream, (const float4 *)s->P.zr_cur, 0LL,
+                       (const float *)s->P.u_energy, (long long)(2 * s->dim * s->P.Fe), s->bad_dev);
+    HIP_TRY(s, hipGetLastError());
+    int bad = 0;
+    HIP_TRY(s, hipMemcpyAsync(&bad, s->bad_dev, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    if (bad) return fail(s, TWA_E_NUMERIC, "non-finite value in z or u");
+    return TWA_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,220 @@
+"""Python binding of the C ABI in ``include/twa.h`` (argument marshalling only).
+
+Every function of the library is exposed under the same name; ``Solver``
+wraps a ``twa_solver*`` and owns it.  PyTorch provides the device memory
+(CUDA tensors on the HIP device) and the stream.  Every step of the planner
+runs in the HIP kernels of ``libtwa.so``: if the library is missing this
+module raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtwa.so")
+
+TWA_OK, TWA_E_INVALID, TWA_E_INFEASIBLE, TWA_E_NOMEM, TWA_E_DEVICE, TWA_E_NUMERIC, TWA_E_STATE = range(7)
+TWA_W_ZERO, TWA_W_STD, TWA_W_INF = 0, 1, 2
+TWA_F_DENSE = 1
+_STATUS = {0: "TWA_OK", 1: "TWA_E_INVALID", 2: "TWA_E_INFEASIBLE", 3: "TWA_E_NOMEM", 4: "TWA_E_DEVICE",
+           5: "TWA_E_NUMERIC", 6: "TWA_E_STATE"}
+
+
+class TWAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Stats(ct.Structure):
+    _fields_ = [("iter", ct.c_longlong), ("active_coll", ct.c_longlong), ("active_wall", ct.c_longlong),
+                ("queued", ct.c_longlong)]
+
+
+_lib = None
+_vp = ct.c_void_p
+
+
+def load_library():
+    """Load ``libtwa.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1311_4527_amd/build.py")
+    lib = ct.CDLL(LIB_PATH)
+    lib.twa_create.restype = ct.c_int
+    lib.twa_create.argtypes = [ct.c_int, ct.c_int, ct.c_int, _vp, _vp, _vp, ct.c_int, _vp, _vp, ct.c_float,
+                               ct.c_float, ct.c_uint, _vp, ct.POINTER(_vp)]
+    lib.twa_set_init.restype = ct.c_int
+    lib.twa_set_init.argtypes = [_vp, _vp]
+    lib.twa_set_schedule.restype = ct.c_int
+    lib.twa_set_schedule.argtypes = [_vp, ct.c_float, ct.c_int]
+    lib.twa_iterate.restype = ct.c_int
+    lib.twa_iterate.argtypes = [_vp, ct.c_int]
+    lib.twa_iterate_timed.restype = ct.c_int
+    lib.twa_iterate_timed.argtypes = [_vp, ct.c_int, ct.POINTER(ct.c_double)]
+    lib.twa_get_trajectories.restype = ct.c_int
+    lib.twa_get_trajectories.argtypes = [_vp, _vp]
+    lib.twa_get_state.restype = ct.c_int
+    lib.twa_get_state.argtypes = [_vp, _vp, _vp, _vp, ct.POINTER(ct.c_longlong)]
+    lib.twa_set_state.restype = ct.c_int
+    lib.twa_set_state.argtypes = [_vp, _vp, _vp, _vp, ct.c_longlong]
+    lib.twa_capture_next.restype = ct.c_int
+    lib.twa_capture_next.argtypes = [_vp, _vp, _vp]
+    lib.twa_get_stats.restype = ct.c_int
+    lib.twa_get_stats.argtypes = [_vp, ct.POINTER(_Stats)]
+    lib.twa_sizes.restype = ct.c_int
+    lib.twa_sizes.argtypes = [_vp, ct.POINTER(ct.c_longlong), ct.POINTER(ct.c_longlong)]
+    lib.twa_check_finite.restype = ct.c_int
+    lib.twa_check_finite.argtypes = [_vp]
+    lib.twa_last_error.restype = ct.c_char_p
+    lib.twa_last_error.argtypes = [_vp]
+    lib.twa_destroy.restype = None
+    lib.twa_destroy.argtypes = [_vp]
+    lib.twa_version.restype = ct.c_char_p
+    lib.twa_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _dev(a, dtype=torch.float32, device="cuda") -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=dtype)
+    else:
+        t = torch.as_tensor(np.asarray(a), dtype=dtype, device=device)
+    return t.contiguous()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One planning problem on the GPU (twa_create ... twa_destroy)."""
+
+    def __init__(self, p, eta, dim, radii, x0, xT, walls=None, C=None, rho0=1.0, alpha=1.0, flags=0,
+                 stream: Optional[torch.cuda.Stream] = None, device="cuda"):
+        lib = load_library()
+        self.p, self.eta, self.dim = int(p), int(eta), int(dim)
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        nw = 0 if walls is None else int(np.asarray(walls).reshape(-1, 2, dim).shape[0]) if not isinstance(
+            walls, torch.Tensor) else int(walls.reshape(-1, 2, dim).shape[0])
+        if C is None:
+            C = np.ones((p, eta))
+        self._radii = _dev(radii, device=device)
+        self._x0 = _dev(x0, device=device).reshape(p, dim)
+        self._xT = _dev(xT, device=device).reshape(p, dim)
+        self._walls = _dev(walls, device=device).reshape(nw, 2, dim) if nw else None
+        self._C = _dev(C, device=device).reshape(p, eta)
+        h = ct.c_void_p()
+        with torch.cuda.stream(self.stream):
+            st = lib.twa_create(self.p, self.eta, self.dim, _ptr(self._radii), _ptr(self._x0), _ptr(self._xT), nw,
+                                _ptr(self._walls), _ptr(self._C), float(rho0), float(alpha), int(flags),
+                                ct.c_void_p(self.stream.cuda_stream), ct.byref(h))
+        if st != TWA_OK:
+            raise TWAError(st, "twa_create failed")
+        self.h = h
+        self.n_walls = nw
+        nf, ne = ct.c_longlong(), ct.c_longlong()
+        lib.twa_sizes(self.h, ct.byref(nf), ct.byref(ne))
+        self.n_factors, self.n_edges = nf.value, ne.value
+
+    @classmethod
+    def from_instance(cls, inst, flags=0, stream=None, device="cuda", set_init=True):
+        s = cls(inst.p, inst.eta, inst.dim, inst.radii, inst.x0, inst.xT,
+                walls=inst.walls if inst.n_walls else None, C=inst.C, rho0=inst.rho0, alpha=inst.alpha,
+                flags=flags, stream=stream, device=device)
+        if set_init:
+            s.twa_set_init(inst.z0)
+        return s
+
+    # -- error handling
+    def _check(self, st):
+        if st != TWA_OK:
+            msg = load_library().twa_last_error(self.h)
+            raise TWAError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().twa_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the C ABI, same names
+    def twa_set_init(self, z):
+        zt = _dev(z, device=self.device).reshape(self.p, self.eta + 1, self.dim)
+        self._check(load_library().twa_set_init(self.h, _ptr(zt)))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def twa_set_schedule(self, rho0_init: float, n_warm: int):
+        self._check(load_library().twa_set_schedule(self.h, float(rho0_init), int(n_warm)))
+
+    def twa_iterate(self, k: int):
+        self._check(load_library().twa_iterate(self.h, int(k)))
+
+    def twa_iterate_timed(self, k: int):
+        """k iterations with HIP events around each launch; returns the summed
+        device milliseconds of (factor stream, queued minimisers, consensus)."""
+        ms = (ct.c_double * 3)()
+        self._check(load_library().twa_iterate_timed(self.h, int(k), ms))
+        return list(ms)
+
+    def twa_get_trajectories(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((self.p, self.eta + 1, self.dim), dtype=torch.float32, device=self.device)
+        self._check(load_library().twa_get_trajectories(self.h, _ptr(out)))
+        return out
+
+    def twa_get_state(self):
+        z = torch.empty((self.p, self.eta + 1, self.dim), dtype=torch.float32, device=self.device)
+        u = torch.empty((self.n_edges, self.dim), dtype=torch.float32, device=self.device)
+        lr = torch.empty((self.p, self.eta + 1), dtype=torch.uint8, device=self.device)
+        it = ct.c_longlong()
+        self._check(load_library().twa_get_state(self.h, _ptr(z), _ptr(u), _ptr(lr), ct.byref(it)))
+        return z, u, lr, it.value
+
+    def twa_set_state(self, z, u, lrho, iteration: int = 0):
+        zt = _dev(z, device=self.device).reshape(self.p, self.eta + 1, self.dim)
+        ut = _dev(u, device=self.device).reshape(self.n_edges, self.dim)
+        lt = _dev(lrho, dtype=torch.uint8, device=self.device).reshape(self.p, self.eta + 1)
+        self._check(load_library().twa_set_state(self.h, _ptr(zt), _ptr(ut), _ptr(lt), int(iteration)))
+        self.stream.synchronize()
+
+    def twa_capture_next(self, x_out: Optional[torch.Tensor], rho_out: Optional[torch.Tensor]):
+        self._keep_dbg = (x_out, rho_out)
+        self._check(load_library().twa_capture_next(self.h, _ptr(x_out), _ptr(rho_out)))
+
+    def twa_get_stats(self) -> dict:
+        s = _Stats()
+        self._check(load_library().twa_get_stats(self.h, ct.byref(s)))
+        return dict(iter=s.iter, active_coll=s.active_coll, active_wall=s.active_wall, queued=s.queued)
+
+    def twa_check_finite(self):
+        self._check(load_library().twa_check_finite(self.h))
+
+    # -- convenience
+    def step_debug(self):
+        """One iteration that also returns x [E][dim] and ->rho per factor."""
+        x = torch.empty((self.n_edges, self.dim), dtype=torch.float32, device=self.device)
+        r = torch.empty((self.n_factors,), dtype=torch.uint8, device=self.device)
+        self.twa_capture_next(x, r)
+        self.twa_iterate(1)
+        self.stream.synchronize()
+        self._keep_dbg = None
+        return x, r
+
+
+def twa_version() -> str:
+    return load_library().twa_version().decode()

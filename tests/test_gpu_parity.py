@@ -1,0 +1,219 @@
+"""Parity of the HIP planner (through the C ABI) with the FP64 reference.
+
+Single-iteration protocol: take a reference state, round it to FP32, run one
+iteration on both sides from that same state and compare x per edge, the
+outgoing weight per factor, z per node and u per edge with
+|gpu - ref| <= 1e-5 * max(|ref|, 1) (1 = scene scale).  Factors whose
+activity test is within 1e-5 (relative) of the radius, or whose best two
+candidate configurations are within 1e-5 in energy, may legitimately differ
+between FP32 and FP64; they are excluded together with the nodes and edges
+they touch, and counted.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1311_4527_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _solver(inst, flags=0):
+    from paper_1311_4527_amd.twa import Solver
+    return Solver.from_instance(inst, flags=flags)
+
+
+def _exclusions(inst, P, nodes, fac):
+    act, tie = P.margins()
+    bad_f = (act < TOL) | (tie < TOL)
+    bad_e = bad_f[fac]
+    bad_nodes = np.zeros(inst.p * (inst.eta + 1), dtype=bool)
+    bad_nodes[nodes[bad_e]] = True
+    bad_u = bad_e | bad_nodes[nodes]
+    return bad_f, bad_e, bad_nodes, bad_u
+
+
+def _close(a, b):
+    return np.abs(a - b) <= TOL * np.maximum(np.abs(b), 1.0)
+
+
+def one_iteration_parity(inst, z, u, lrho, k=0, flags=0, solver=None, report=None):
+    """Run one iteration from (z, u, lrho) on both sides and compare."""
+    import torch
+    z32 = np.asarray(z, np.float32)
+    u32 = np.asarray(u, np.float32)
+    P = O.Planner(inst)
+    P.set_state(z32.astype(np.float64), u32.astype(np.float64), lrho, k)
+    P.iterate(1)
+    zr, ur, lr = P.get_state()
+    xr, rfr = P.last()
+    S = solver if solver is not None else _solver(inst, flags)
+    S.twa_set_state(torch.from_numpy(z32), torch.from_numpy(u32), torch.from_numpy(np.asarray(lrho, np.uint8)), k)
+    xg, rfg = S.step_debug()
+    zg, ug, lg, _ = S.twa_get_state()
+    xg, rfg, zg, ug, lg = (t.cpu().numpy() for t in (xg, rfg, zg, ug, lg))
+    nodes = I.canonical_edge_nodes(inst)
+    fac = I.canonical_edge_factor(inst)
+    bad_f, bad_e, bad_nodes, bad_u = _exclusions(inst, P, nodes, fac)
+    ok_x = _close(xg, xr).all(axis=1) | bad_e
+    ok_r = (rfg == rfr) | bad_f
+    ok_z = _close(zg.reshape(-1, inst.dim), zr.reshape(-1, inst.dim)).all(axis=1) | bad_nodes
+    ok_u = _close(ug, ur).all(axis=1) | bad_u
+    ok_l = (lg.reshape(-1) == lr.reshape(-1)) | bad_nodes
+    info = dict(excluded_factors=int(bad_f.sum()), factors=len(bad_f),
+                active=int((rfr == O.STD).sum()), bad_x=int((~ok_x).sum()), bad_rho=int((~ok_r).sum()),
+                bad_z=int((~ok_z).sum()), bad_u=int((~ok_u).sum()), bad_lrho=int((~ok_l).sum()))
+    if report is not None:
+        report.append(info)
+    assert ok_r.all(), info
+    assert ok_x.all(), (info, np.argwhere(~ok_x)[:5].ravel(), xg[~ok_x][:3], xr[~ok_x][:3])
+    assert ok_z.all(), info
+    assert ok_u.all(), info
+    assert ok_l.all(), info
+    # the excluded share must stay tiny
+    assert bad_f.sum() <= max(2, 0.01 * max(1, info["active"])), info
+    return info
+
+
+def _reference_states(inst, ks):
+    P = O.Planner(inst)
+    out = []
+    done = 0
+    for k in ks:
+        P.iterate(k - done)
+        done = k
+        z, u, lr = P.get_state()
+        out.append((k, z, u, lr))
+    return out
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_parity_small_swap(seed, flags):
+    inst = I.conf_small(seed)
+    for k, z, u, lr in _reference_states(inst, [0, 1, 10, 100, 400]):
+        one_iteration_parity(inst, z, u, lr, k, flags)
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_parity_box_with_walls(flags):
+    inst = I.random_box(24, 0.03, 5, n_walls=6, sigma=1e-2, seed=11, alpha=0.1, C=1 / 120)
+    rep = []
+    for k, z, u, lr in _reference_states(inst, [0, 3, 30, 150]):
+        one_iteration_parity(inst, z, u, lr, k, flags, report=rep)
+    assert sum(r["active"] for r in rep) > 0
+
+
+@pytest.mark.parametrize("dim", [3])
+def test_parity_3d(dim):
+    inst = I.circle_swap(10, 0.08, 4, dim=3, sigma=2e-2, seed=3, alpha=0.1, C=1 / 40)
+    for k, z, u, lr in _reference_states(inst, [0, 5, 60]):
+        one_iteration_parity(inst, z, u, lr, k, 0)
+    box = I.random_box(14, 0.05, 4, dim=3, sigma=1e-2, seed=9, alpha=0.1, C=1 / 56)
+    for k, z, u, lr in _reference_states(box, [0, 20]):
+        one_iteration_parity(box, z, u, lr, k, 1)
+
+
+def test_parity_random_states():
+    """Synthetic states (random u on random factors) exercise minimiser
+    branches the trajectories above may not reach."""
+    inst = I.random_box(16, 0.06, 4, n_walls=5, sigma=3e-2, seed=21, alpha=0.5, C=0.3)
+    for seed in range(4):
+        z, u, lr = I.random_state(inst, seed, u_scale=2e-2, active_frac=0.5)
+        one_iteration_parity(inst, z, u, lr, 0, flags=seed % 2)
+
+
+def test_parity_ragged_tail_sizes():
+    """Factor counts that are not multiples of the block size or the wave."""
+    for p, eta, W in [(2, 1, 1), (3, 2, 0), (37, 3, 2), (65, 2, 1)]:
+        inst = I.random_box(p, 0.04, eta, n_walls=W, sigma=1e-2, seed=p, alpha=0.1, C=1.0 / (p * eta))
+        for k, z, u, lr in _reference_states(inst, [0, 4]):
+            one_iteration_parity(inst, z, u, lr, k, flags=p % 2)
+
+
+def test_fused_matches_stepwise():
+    """k iterations in a row (u update fused into the next iteration) equal k
+    single iterations with the state exported and re-imported in between."""
+    import torch
+    inst = I.random_box(20, 0.04, 4, n_walls=3, sigma=1e-2, seed=5, alpha=0.1, C=1 / 80)
+    A = _solver(inst)
+    A.twa_iterate(12)
+    za, ua, la, _ = A.twa_get_state()
+    B = _solver(inst)
+    for _ in range(12):
+        B.twa_iterate(1)
+        z, u, l, it = B.twa_get_state()
+        B.twa_set_state(z, u, l, it)
+    zb, ub, lb, _ = B.twa_get_state()
+    assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb)
+
+
+def test_dense_equals_skip():
+    import torch
+    inst = I.conf_small(3)
+    A = _solver(inst, flags=0)
+    B = _solver(inst, flags=1)
+    A.twa_iterate(300)
+    B.twa_iterate(300)
+    za, ua, la, _ = A.twa_get_state()
+    zb, ub, lb, _ = B.twa_get_state()
+    assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb)
+
+
+def test_deterministic_replay():
+    import torch
+    inst = I.conf_swap100(0)
+    A = _solver(inst)
+    B = _solver(inst)
+    A.twa_iterate(200)
+    B.twa_iterate(200)
+    assert torch.equal(A.twa_get_trajectories(), B.twa_get_trajectories())
+
+
+def test_full_solve_small_swap():
+    """Collision-free and objective within 1e-3 of the reference after the
+    same number of iterations (p=8 circle swap)."""
+    inst = I.conf_small(0)
+    S = _solver(inst)
+    S.twa_iterate(4000)
+    zg = S.twa_get_trajectories().cpu().numpy().astype(np.float64)
+    P = O.Planner(inst)
+    P.iterate(4000)
+    zr = P.trajectories()
+    assert O.min_clearance(inst.radii, zg) > -1e-5
+    Jg = float(np.sum(inst.C * np.sum(np.diff(zg, axis=1) ** 2, axis=2)))
+    Jr = P.objective()
+    assert abs(Jg - Jr) <= 1e-3 * Jr
+    assert np.array_equal(zg[:, 0], inst.x0.astype(np.float32).astype(np.float64))
+
+
+def test_full_solve_swap100():
+    inst = I.conf_swap100(0)
+    S = _solver(inst)
+    S.twa_iterate(5000)
+    zg = S.twa_get_trajectories().cpu().numpy().astype(np.float64)
+    P = O.Planner(inst)
+    P.iterate(5000)
+    cg = O.min_clearance(inst.radii, zg)
+    cr = P.min_clearance()
+    Jg = float(np.sum(inst.C * np.sum(np.diff(zg, axis=1) ** 2, axis=2)))
+    Jr = P.objective()
+    assert abs(Jg - Jr) <= 1e-3 * Jr, (Jg, Jr)
+    # the GPU run is as clear as the reference run (both converge slowly to contact)
+    assert cg > min(cr, 0.0) - 5e-5, (cg, cr)
+
+
+def test_parity_large_box_one_iteration():
+    """The p=1024, eta=16, 32-wall workload (8.4 M collision factors) in the
+    launch configuration of the benchmark: one iteration from the straight-
+    line state and one from an advanced reference state, element-wise."""
+    inst = I.conf_box1024()
+    P = O.Planner(inst)
+    z, u, lr = P.get_state()
+    S = _solver(inst, flags=0)
+    one_iteration_parity(inst, z, u, lr, 0, solver=S)
+    P.iterate(8)
+    z, u, lr = P.get_state()
+    one_iteration_parity(inst, z, u, lr, 8, solver=S)

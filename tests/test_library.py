@@ -1,0 +1,83 @@
+"""The C-ABI library loads and exports every symbol its header declares;
+argument validation that needs no device (no GPU)."""
+import ctypes as ct
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "twa.h")
+LIB = os.path.join(ROOT, "paper_1311_4527_amd", "libtwa.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(twa_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1311_4527_amd.build import build
+        build()
+    return ct.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("twa_create", "twa_iterate", "twa_get_trajectories", "twa_get_state", "twa_set_state",
+                 "twa_destroy", "twa_last_error"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    for n in _declared():
+        getattr(lib, n)
+
+
+def test_version(lib):
+    lib.twa_version.restype = ct.c_char_p
+    assert lib.twa_version().decode().startswith("twa-mi355x")
+
+
+@pytest.mark.parametrize("p,eta,dim,nw", [(0, 4, 2, 0), (4, 0, 2, 0), (4, 4, 4, 0), (4, 4, 3, 2), (4, 4, 2, -1)])
+def test_create_rejects_bad_sizes_without_touching_the_device(lib, p, eta, dim, nw):
+    lib.twa_create.restype = ct.c_int
+    out = ct.c_void_p()
+    dummy = ct.c_void_p(16)
+    st = lib.twa_create(p, eta, dim, dummy, dummy, dummy, nw, dummy, dummy, ct.c_float(1.0), ct.c_float(1.0), 0,
+                        None, ct.byref(out))
+    assert st == 1 and not out.value
+
+
+def test_create_rejects_bad_scalars(lib):
+    lib.twa_create.restype = ct.c_int
+    out = ct.c_void_p()
+    dummy = ct.c_void_p(16)
+    for rho, alpha, flags in [(0.0, 1.0, 0), (1.0, -1.0, 0), (float("nan"), 1.0, 0), (1.0, 1.0, 1 << 7)]:
+        st = lib.twa_create(4, 4, 2, dummy, dummy, dummy, 0, None, dummy, ct.c_float(rho), ct.c_float(alpha), flags,
+                            None, ct.byref(out))
+        assert st == 1
+
+
+def test_null_solver_calls(lib):
+    lib.twa_iterate.restype = ct.c_int
+    lib.twa_last_error.restype = ct.c_char_p
+    assert lib.twa_iterate(None, 1) == 1
+    lib.twa_destroy(None)
+    assert lib.twa_last_error(None)
+
+
+def test_binding_exposes_the_abi_names():
+    from paper_1311_4527_amd import twa
+    for n in _declared():
+        if n in ("twa_create", "twa_destroy", "twa_last_error", "twa_sizes"):
+            continue
+        assert hasattr(twa.Solver, n) or hasattr(twa, n), n
