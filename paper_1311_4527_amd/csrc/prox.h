@@ -24,28 +24,33 @@
 
 namespace twa {
 
+// host and device: the minimisers are plain arithmetic
+#define TWA_HD __host__ __device__ __forceinline__
+
+TWA_HD float inv_sqrt(float x) { return 1.0f / sqrtf(x); }
+
 enum : int { W_ZERO = 0, W_STD = 1, W_INF = 2 };
 
 struct f2 {
     float x, y;
 };
-__device__ __forceinline__ f2 mk(float x, float y) { return f2{x, y}; }
-__device__ __forceinline__ f2 add(f2 a, f2 b) { return f2{a.x + b.x, a.y + b.y}; }
-__device__ __forceinline__ f2 sub(f2 a, f2 b) { return f2{a.x - b.x, a.y - b.y}; }
-__device__ __forceinline__ f2 scl(f2 a, float s) { return f2{a.x * s, a.y * s}; }
-__device__ __forceinline__ float dot(f2 a, f2 b) { return a.x * b.x + a.y * b.y; }
-__device__ __forceinline__ f2 perp(f2 a) { return f2{-a.y, a.x}; }
-__device__ __forceinline__ float pos(float v) { return v > 0.f ? v : 0.f; }
+TWA_HD f2 mk(float x, float y) { return f2{x, y}; }
+TWA_HD f2 add(f2 a, f2 b) { return f2{a.x + b.x, a.y + b.y}; }
+TWA_HD f2 sub(f2 a, f2 b) { return f2{a.x - b.x, a.y - b.y}; }
+TWA_HD f2 scl(f2 a, float s) { return f2{a.x * s, a.y * s}; }
+TWA_HD float dot(f2 a, f2 b) { return a.x * b.x + a.y * b.y; }
+TWA_HD f2 perp(f2 a) { return f2{-a.y, a.x}; }
+TWA_HD float pos(float v) { return v > 0.f ? v : 0.f; }
 
 struct f3 {
     float x, y, z;
 };
-__device__ __forceinline__ f3 sub3(f3 a, f3 b) { return f3{a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ float dot3(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+TWA_HD f3 sub3(f3 a, f3 b) { return f3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+TWA_HD float dot3(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
 // Squared closest approach of (1-a) d0 + a d1 over a in [0, 1]
 // (the constraint of eq. basic_opt_prob on the relative positions).
-__device__ __forceinline__ float cpa_sq(f3 d0, f3 d1) {
+TWA_HD float cpa_sq(f3 d0, f3 d1) {
     f3 e = sub3(d1, d0);
     float ee = dot3(e, e);
     float a = 0.f;
@@ -54,7 +59,7 @@ __device__ __forceinline__ float cpa_sq(f3 d0, f3 d1) {
     return dot3(v, v);
 }
 
-__device__ __forceinline__ float point_seg_sq(f2 q, f2 a, f2 b) {
+TWA_HD float point_seg_sq(f2 q, f2 a, f2 b) {
     f2 d = sub(b, a);
     float L2 = dot(d, d);
     float t = 0.f;
@@ -63,13 +68,13 @@ __device__ __forceinline__ float point_seg_sq(f2 q, f2 a, f2 b) {
     return dot(v, v);
 }
 
-__device__ __forceinline__ float orient(f2 a, f2 b, f2 c) {
+TWA_HD float orient(f2 a, f2 b, f2 c) {
     return (b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x);
 }
 
 // Squared distance between planar segments [p0,p1] and [q0,q1]
 // (the constraint of eq. wall_minimizer over all alpha, beta).
-__device__ __forceinline__ float segseg_sq(f2 p0, f2 p1, f2 q0, f2 q1) {
+TWA_HD float segseg_sq(f2 p0, f2 p1, f2 q0, f2 q1) {
     float o1 = orient(p0, p1, q0), o2 = orient(p0, p1, q1);
     float o3 = orient(q0, q1, p0), o4 = orient(q0, q1, p1);
     if (((o1 > 0.f && o2 < 0.f) || (o1 < 0.f && o2 > 0.f)) && ((o3 > 0.f && o4 < 0.f) || (o3 < 0.f && o4 > 0.f)))
@@ -85,7 +90,7 @@ __device__ __forceinline__ float segseg_sq(f2 p0, f2 p1, f2 q0, f2 q1) {
 // Energy minimiser, App. E (eq. energy_minimizer_output) with the limits of
 // infinite weights and of two equal weights tending to zero.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void energy_prox(float nl, float nh, float wl, float wh, int kl, int kh, float C,
+TWA_HD void energy_prox(float nl, float nh, float wl, float wh, int kl, int kh, float C,
                                             float &xl, float &xh) {
     if (C <= 0.f || (kl == W_INF && kh == W_INF)) {
         xl = nl;
@@ -116,7 +121,7 @@ struct Eig2 {
     float b1, b2;    // coordinates of b
 };
 
-__device__ __forceinline__ Eig2 eig2(float a, float c, float e, f2 b) {
+TWA_HD Eig2 eig2(float a, float c, float e, f2 b) {
     Eig2 r;
     float d = 0.5f * (a - e);
     float rad = sqrtf(d * d + c * c);
@@ -124,7 +129,7 @@ __device__ __forceinline__ Eig2 eig2(float a, float c, float e, f2 b) {
     if (rad <= 1e-30f) v = mk(1.f, 0.f);
     else if (d >= 0.f) v = mk(-c, d + rad);
     else v = mk(rad - d, -c);
-    float inv = rsqrtf(dot(v, v));
+    float inv = inv_sqrt(dot(v, v));
     r.v1 = scl(v, inv);
     r.v2 = perp(r.v1);
     r.gap = 2.f * rad;
@@ -136,7 +141,7 @@ __device__ __forceinline__ Eig2 eig2(float a, float c, float e, f2 b) {
 // Global minimiser of E on the circle.  Writes a second candidate (the
 // mirror point of the degenerate "hard case", where two minimisers tie)
 // into *alt and returns 2, else returns 1.
-__device__ __forceinline__ int trs_global(const Eig2 &g, f2 *out, f2 *alt) {
+TWA_HD int trs_global(const Eig2 &g, f2 *out, f2 *alt) {
     float b1 = g.b1, b2 = g.b2, gap = g.gap;
     float bn = sqrtf(b1 * b1 + b2 * b2);
     if (!(bn > 0.f)) {
@@ -145,20 +150,30 @@ __device__ __forceinline__ int trs_global(const Eig2 &g, f2 *out, f2 *alt) {
         *alt = scl(g.v1, -1.f);
         return 2;
     }
-    // t = q1 - lambda > 0 solves b1^2/t^2 + b2^2/(t+gap)^2 = 1
+    // t = q1 - lambda > 0 solves b1^2/t^2 + b2^2/(t+gap)^2 = 1.  The root
+    // lies in [lo, hi]; when |b2| < gap and t << gap it is close to
+    // |b1| / sqrt(1 - (b2/gap)^2), a good first guess.  Newton on
+    // 1/sqrt(S) - 1 (nearly linear in t at both ends), with geometric
+    // bisection whenever a step leaves the bracket.
     float lo = fmaxf(fabsf(b1), bn - gap), hi = bn;
     float t = hi;
-    for (int it = 0; it < 24; ++it) {
+    float q = b2 / fmaxf(gap, 1e-30f);
+    if (q * q < 1.f) {
+        float ta = fabsf(b1) * inv_sqrt(1.f - q * q);
+        if (ta > lo && ta < hi) t = ta;
+    }
+    for (int it = 0; it < 60; ++it) {
         float y1 = b1 / t, y2 = b2 / (t + gap);
         float S = y1 * y1 + y2 * y2;
-        float rs = rsqrtf(S);
+        float rs = inv_sqrt(S);
         float h = rs - 1.f; // increasing in t; root where h == 0
         if (h > 0.f) hi = t;
         else lo = t;
+        if (fabsf(h) <= 2.4e-7f) break;
         float dS = y1 * y1 / t + y2 * y2 / (t + gap); // = -S'/2
         float hp = rs * rs * rs * dS;
         float tn = t - h / hp;
-        if (!(tn > lo && tn < hi)) tn = 0.5f * (lo + hi);
+        if (!(tn > lo && tn < hi)) tn = lo > 0.f ? sqrtf(lo * hi) : 0.5f * hi;
         if (tn == t) break;
         t = tn;
     }
@@ -172,7 +187,7 @@ __device__ __forceinline__ int trs_global(const Eig2 &g, f2 *out, f2 *alt) {
         y1 = b1 / t;
         y2 = b2 / (t + gap);
     }
-    float inv = rsqrtf(y1 * y1 + y2 * y2);
+    float inv = inv_sqrt(y1 * y1 + y2 * y2);
     y1 *= inv;
     y2 *= inv;
     out[0] = add(scl(g.v1, y1), scl(g.v2, y2));
@@ -185,7 +200,7 @@ __device__ __forceinline__ int trs_global(const Eig2 &g, f2 *out, f2 *alt) {
 
 // The two stationary points between the eigenvalues (a local minimum and a
 // local maximum), when they exist.  Returns how many were written.
-__device__ __forceinline__ int trs_middle(const Eig2 &g, f2 *out) {
+TWA_HD int trs_middle(const Eig2 &g, f2 *out) {
     float b1 = g.b1, b2 = g.b2, gap = g.gap;
     if (!(gap > 0.f) || b1 == 0.f || b2 == 0.f) return 0;
     float c1 = cbrtf(b1 * b1), c2 = cbrtf(b2 * b2);
@@ -210,14 +225,14 @@ __device__ __forceinline__ int trs_middle(const Eig2 &g, f2 *out) {
         }
         float t = 0.5f * (lo + hi);
         float z1 = -b1 / t, z2 = b2 / (gap - t); // (q1 - lambda) = -t, (q2 - lambda) = gap - t
-        float inv = rsqrtf(z1 * z1 + z2 * z2);
+        float inv = inv_sqrt(z1 * z1 + z2 * z2);
         out[n++] = add(scl(g.v1, z1 * inv), scl(g.v2, z2 * inv));
     }
     return n;
 }
 
 // Q and b of E_c(u) = sum_k (w_k/2)(r - <m_k, u>)^2 up to a constant
-__device__ __forceinline__ Eig2 piece_quadratic(f2 m0, f2 m1, float w0, float w1, float r) {
+TWA_HD Eig2 piece_quadratic(f2 m0, f2 m1, float w0, float w1, float r) {
     float a = w0 * m0.x * m0.x + w1 * m1.x * m1.x;
     float c = w0 * m0.x * m0.y + w1 * m1.x * m1.y;
     float e = w0 * m0.y * m0.y + w1 * m1.y * m1.y;
@@ -230,13 +245,13 @@ __device__ __forceinline__ Eig2 piece_quadratic(f2 m0, f2 m1, float w0, float w1
 // min (w0/2)|v0 - m0|^2 + (w1/2)|v1 - m1|^2  s.t.  dist(0, [v0, v1]) >= R.
 // k0/k1: W_INF marks a certain end that must stay.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float disk_F(f2 u, f2 m0, f2 m1, float w0, float w1, float R) {
+TWA_HD float disk_F(f2 u, f2 m0, f2 m1, float w0, float w1, float R) {
     float g0 = pos(R - dot(m0, u)), g1 = pos(R - dot(m1, u));
     return 0.5f * (w0 * g0 * g0 + w1 * g1 * g1);
 }
 
 // tangent normals from point q (|q| >= r) to the circle of radius r at c
-__device__ __forceinline__ int tangent_normals(f2 q, f2 c, float r, f2 *out) {
+TWA_HD int tangent_normals(f2 q, f2 c, float r, f2 *out) {
     f2 w = sub(q, c);
     float L2 = dot(w, w);
     float s2 = L2 - r * r;
@@ -249,7 +264,7 @@ __device__ __forceinline__ int tangent_normals(f2 q, f2 c, float r, f2 *out) {
     return 2;
 }
 
-__device__ __forceinline__ void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R, f2 &v0,
+TWA_HD void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R, f2 &v0,
                                           f2 &v1) {
     bool i0 = k0 == W_INF, i1 = k1 == W_INF;
     if (i0 && i1) {
@@ -263,7 +278,7 @@ __device__ __forceinline__ void disk_prox(f2 m0, f2 m1, float w0, float w1, int 
         int nc = tangent_normals(q, mk(0.f, 0.f), R, cand);
         float mm = dot(m, m);
         if (mm > 0.f) {
-            f2 u = scl(m, rsqrtf(mm));
+            f2 u = scl(m, inv_sqrt(mm));
             if (dot(q, u) >= R) cand[nc++] = u;
         }
         f2 best = mk(1.f, 0.f);
@@ -291,8 +306,8 @@ __device__ __forceinline__ void disk_prox(f2 m0, f2 m1, float w0, float w1, int 
     int nc = trs_global(g, cand, &alt);
     if (nc == 2) cand[1] = alt;
     float q0 = dot(m0, m0), q1 = dot(m1, m1);
-    if (q0 > 0.f && q0 < R * R) cand[nc++] = scl(m0, rsqrtf(q0));
-    if (q1 > 0.f && q1 < R * R) cand[nc++] = scl(m1, rsqrtf(q1));
+    if (q0 > 0.f && q0 < R * R) cand[nc++] = scl(m0, inv_sqrt(q0));
+    if (q1 > 0.f && q1 < R * R) cand[nc++] = scl(m1, inv_sqrt(q1));
     f2 best = cand[0];
     float bF = disk_F(cand[0], m0, m1, w0, w1, R);
     for (int k = 1; k < nc; ++k) {
@@ -313,13 +328,13 @@ struct Capsule {
     f2 a, b;
     float r;
 };
-__device__ __forceinline__ float cap_h(const Capsule &C, f2 u) { return fmaxf(dot(C.a, u), dot(C.b, u)) + C.r; }
-__device__ __forceinline__ float cap_F(const Capsule &C, f2 u, f2 n0, f2 n1, float w0, float w1) {
+TWA_HD float cap_h(const Capsule &C, f2 u) { return fmaxf(dot(C.a, u), dot(C.b, u)) + C.r; }
+TWA_HD float cap_F(const Capsule &C, f2 u, f2 n0, f2 n1, float w0, float w1) {
     float h = cap_h(C, u);
     float g0 = pos(h - dot(n0, u)), g1 = pos(h - dot(n1, u));
     return 0.5f * (w0 * g0 * g0 + w1 * g1 * g1);
 }
-__device__ __forceinline__ f2 closest_on_seg(f2 q, f2 a, f2 b) {
+TWA_HD f2 closest_on_seg(f2 q, f2 a, f2 b) {
     f2 d = sub(b, a);
     float L2 = dot(d, d);
     float t = 0.f;
@@ -327,7 +342,7 @@ __device__ __forceinline__ f2 closest_on_seg(f2 q, f2 a, f2 b) {
     return add(a, scl(d, t));
 }
 
-__device__ __forceinline__ void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int k0, int k1, f2 &x0,
+TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int k0, int k1, f2 &x0,
                                           f2 &x1) {
     bool i0 = k0 == W_INF, i1 = k1 == W_INF;
     if (i0 && i1) {
@@ -338,7 +353,7 @@ __device__ __forceinline__ void capsule_prox(const Capsule C, f2 n0, f2 n1, floa
     f2 d = sub(C.b, C.a);
     float L2 = dot(d, d);
     bool seg = L2 > 0.f;
-    f2 sw = seg ? scl(perp(d), rsqrtf(L2)) : mk(0.f, 1.f);
+    f2 sw = seg ? scl(perp(d), inv_sqrt(L2)) : mk(0.f, 1.f);
     f2 cand[16];
     int nc = 0;
     if (i0 || i1) {
@@ -347,10 +362,10 @@ __device__ __forceinline__ void capsule_prox(const Capsule C, f2 n0, f2 n1, floa
         nc += tangent_normals(q, C.a, C.r, cand + nc);
         if (seg) nc += tangent_normals(q, C.b, C.r, cand + nc);
         f2 t0 = sub(m, C.a);
-        if (dot(t0, t0) > 0.f) cand[nc++] = scl(t0, rsqrtf(dot(t0, t0)));
+        if (dot(t0, t0) > 0.f) cand[nc++] = scl(t0, inv_sqrt(dot(t0, t0)));
         if (seg) {
             f2 t1 = sub(m, C.b);
-            if (dot(t1, t1) > 0.f) cand[nc++] = scl(t1, rsqrtf(dot(t1, t1)));
+            if (dot(t1, t1) > 0.f) cand[nc++] = scl(t1, inv_sqrt(dot(t1, t1)));
             cand[nc++] = sw;
             cand[nc++] = scl(sw, -1.f);
         }
@@ -397,7 +412,7 @@ __device__ __forceinline__ void capsule_prox(const Capsule C, f2 n0, f2 n1, floa
         f2 c = closest_on_seg(n, C.a, C.b);
         f2 t = sub(n, c);
         float tt = dot(t, t);
-        if (tt > 0.f && tt < C.r * C.r) cand[nc++] = scl(t, rsqrtf(tt));
+        if (tt > 0.f && tt < C.r * C.r) cand[nc++] = scl(t, inv_sqrt(tt));
     }
     f2 best = cand[0];
     float bF = cap_F(C, cand[0], n0, n1, w0, w1);
@@ -419,7 +434,7 @@ __device__ __forceinline__ void capsule_prox(const Capsule C, f2 n0, f2 n1, floa
 //   x = (rho n + rho' (n' - v)) / (rho + rho'),
 // leaving (omega/2)|v - (n' - n)|^2 with omega = rho rho'/(rho + rho').
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void pair_weight(float r, float rp, int k, int kp, float &om, int &kom) {
+TWA_HD void pair_weight(float r, float rp, int k, int kp, float &om, int &kom) {
     if (k == W_INF && kp == W_INF) {
         om = 0.f;
         kom = W_INF;
@@ -436,7 +451,7 @@ __device__ __forceinline__ void pair_weight(float r, float rp, int k, int kp, fl
 }
 
 // rebuild one break-point pair from v (component-wise)
-__device__ __forceinline__ void pair_rebuild(float r, float rp, int k, int kp, float n, float np, float v, float &x,
+TWA_HD void pair_rebuild(float r, float rp, int k, int kp, float n, float np, float v, float &x,
                                              float &xp) {
     if (k == W_INF && kp == W_INF) {
         x = n;
@@ -450,6 +465,60 @@ __device__ __forceinline__ void pair_rebuild(float r, float rp, int k, int kp, f
     } else {
         x = (r * n + rp * (np - v)) / (r + rp);
         xp = x + v;
+    }
+}
+
+// Full collision minimiser (App. C): n, weights -> x.  D == 3 solves in the
+// plane spanned by the two difference vectors (the optimum lies there).
+template <int D>
+TWA_HD void coll_prox(const float *n, const float *w, const int *k, float R, float *x) {
+    float om_l, om_h;
+    int ko_l, ko_h;
+    pair_weight(w[0], w[2], k[0], k[2], om_l, ko_l);
+    pair_weight(w[1], w[3], k[1], k[3], om_h, ko_h);
+    float vl[3], vh[3];
+    if constexpr (D == 2) {
+        f2 ml = mk(n[4] - n[0], n[5] - n[1]);
+        f2 mh = mk(n[6] - n[2], n[7] - n[3]);
+        f2 a, b;
+        disk_prox(ml, mh, om_l, om_h, ko_l, ko_h, R, a, b);
+        vl[0] = a.x, vl[1] = a.y, vh[0] = b.x, vh[1] = b.y;
+    } else {
+        float ml[3] = {n[6] - n[0], n[7] - n[1], n[8] - n[2]};
+        float mh[3] = {n[9] - n[3], n[10] - n[4], n[11] - n[5]};
+        float nl = sqrtf(ml[0] * ml[0] + ml[1] * ml[1] + ml[2] * ml[2]);
+        float nh = sqrtf(mh[0] * mh[0] + mh[1] * mh[1] + mh[2] * mh[2]);
+        const float *f = nl > 0.f ? ml : mh;
+        float nf = nl > 0.f ? nl : nh;
+        float e1[3] = {1.f, 0.f, 0.f}, e2[3];
+        if (nf > 0.f) e1[0] = f[0] / nf, e1[1] = f[1] / nf, e1[2] = f[2] / nf;
+        const float *g = nl > 0.f ? mh : ml;
+        float pr = g[0] * e1[0] + g[1] * e1[1] + g[2] * e1[2];
+        float w3[3] = {g[0] - pr * e1[0], g[1] - pr * e1[1], g[2] - pr * e1[2]};
+        float nw = sqrtf(w3[0] * w3[0] + w3[1] * w3[1] + w3[2] * w3[2]);
+        if (!(nw > 1e-6f * (nf + nh))) {
+            int ax = 0;
+            if (fabsf(e1[1]) < fabsf(e1[ax])) ax = 1;
+            if (fabsf(e1[2]) < fabsf(e1[ax])) ax = 2;
+            float t[3] = {0.f, 0.f, 0.f};
+            t[ax] = 1.f;
+            float p2 = e1[ax];
+            w3[0] = t[0] - p2 * e1[0], w3[1] = t[1] - p2 * e1[1], w3[2] = t[2] - p2 * e1[2];
+            nw = sqrtf(w3[0] * w3[0] + w3[1] * w3[1] + w3[2] * w3[2]);
+        }
+        for (int q = 0; q < 3; ++q) e2[q] = w3[q] / nw;
+        f2 a2 = mk(ml[0] * e1[0] + ml[1] * e1[1] + ml[2] * e1[2], ml[0] * e2[0] + ml[1] * e2[1] + ml[2] * e2[2]);
+        f2 b2 = mk(mh[0] * e1[0] + mh[1] * e1[1] + mh[2] * e1[2], mh[0] * e2[0] + mh[1] * e2[1] + mh[2] * e2[2]);
+        f2 a, b;
+        disk_prox(a2, b2, om_l, om_h, ko_l, ko_h, R, a, b);
+        for (int q = 0; q < 3; ++q) {
+            vl[q] = a.x * e1[q] + a.y * e2[q];
+            vh[q] = b.x * e1[q] + b.y * e2[q];
+        }
+    }
+    for (int c = 0; c < D; ++c) {
+        pair_rebuild(w[0], w[2], k[0], k[2], n[c], n[2 * D + c], vl[c], x[c], x[2 * D + c]);
+        pair_rebuild(w[1], w[3], k[1], k[3], n[D + c], n[3 * D + c], vh[c], x[D + c], x[3 * D + c]);
     }
 }
 

@@ -161,60 +161,6 @@ __device__ __forceinline__ bool coll_active(const float *n, float R) {
     return cpa_sq(d0, d1) < R * R;
 }
 
-// Full collision minimiser (App. C): n, weights -> x.  D == 3 solves in the
-// plane spanned by the two difference vectors (the optimum lies there).
-template <int D>
-__device__ __forceinline__ void coll_prox(const float *n, const float *w, const int *k, float R, float *x) {
-    float om_l, om_h;
-    int ko_l, ko_h;
-    pair_weight(w[0], w[2], k[0], k[2], om_l, ko_l);
-    pair_weight(w[1], w[3], k[1], k[3], om_h, ko_h);
-    float vl[3], vh[3];
-    if constexpr (D == 2) {
-        f2 ml = mk(n[4] - n[0], n[5] - n[1]);
-        f2 mh = mk(n[6] - n[2], n[7] - n[3]);
-        f2 a, b;
-        disk_prox(ml, mh, om_l, om_h, ko_l, ko_h, R, a, b);
-        vl[0] = a.x, vl[1] = a.y, vh[0] = b.x, vh[1] = b.y;
-    } else {
-        float ml[3] = {n[6] - n[0], n[7] - n[1], n[8] - n[2]};
-        float mh[3] = {n[9] - n[3], n[10] - n[4], n[11] - n[5]};
-        float nl = sqrtf(ml[0] * ml[0] + ml[1] * ml[1] + ml[2] * ml[2]);
-        float nh = sqrtf(mh[0] * mh[0] + mh[1] * mh[1] + mh[2] * mh[2]);
-        const float *f = nl > 0.f ? ml : mh;
-        float nf = nl > 0.f ? nl : nh;
-        float e1[3] = {1.f, 0.f, 0.f}, e2[3];
-        if (nf > 0.f) e1[0] = f[0] / nf, e1[1] = f[1] / nf, e1[2] = f[2] / nf;
-        const float *g = nl > 0.f ? mh : ml;
-        float pr = g[0] * e1[0] + g[1] * e1[1] + g[2] * e1[2];
-        float w3[3] = {g[0] - pr * e1[0], g[1] - pr * e1[1], g[2] - pr * e1[2]};
-        float nw = sqrtf(w3[0] * w3[0] + w3[1] * w3[1] + w3[2] * w3[2]);
-        if (!(nw > 1e-6f * (nf + nh))) {
-            int ax = 0;
-            if (fabsf(e1[1]) < fabsf(e1[ax])) ax = 1;
-            if (fabsf(e1[2]) < fabsf(e1[ax])) ax = 2;
-            float t[3] = {0.f, 0.f, 0.f};
-            t[ax] = 1.f;
-            float p2 = e1[ax];
-            w3[0] = t[0] - p2 * e1[0], w3[1] = t[1] - p2 * e1[1], w3[2] = t[2] - p2 * e1[2];
-            nw = sqrtf(w3[0] * w3[0] + w3[1] * w3[1] + w3[2] * w3[2]);
-        }
-        for (int q = 0; q < 3; ++q) e2[q] = w3[q] / nw;
-        f2 a2 = mk(ml[0] * e1[0] + ml[1] * e1[1] + ml[2] * e1[2], ml[0] * e2[0] + ml[1] * e2[1] + ml[2] * e2[2]);
-        f2 b2 = mk(mh[0] * e1[0] + mh[1] * e1[1] + mh[2] * e1[2], mh[0] * e2[0] + mh[1] * e2[1] + mh[2] * e2[2]);
-        f2 a, b;
-        disk_prox(a2, b2, om_l, om_h, ko_l, ko_h, R, a, b);
-        for (int q = 0; q < 3; ++q) {
-            vl[q] = a.x * e1[q] + a.y * e2[q];
-            vh[q] = b.x * e1[q] + b.y * e2[q];
-        }
-    }
-    for (int c = 0; c < D; ++c) {
-        pair_rebuild(w[0], w[2], k[0], k[2], n[c], n[2 * D + c], vl[c], x[c], x[2 * D + c]);
-        pair_rebuild(w[1], w[3], k[1], k[3], n[D + c], n[3 * D + c], vh[c], x[D + c], x[3 * D + c]);
-    }
-}
-
 __device__ __forceinline__ void node_xyz(float4 r, float *z, int D) {
     z[0] = r.x, z[1] = r.y;
     if (D == 3) z[2] = r.z;

@@ -1,0 +1,21 @@
+// Host build of the HIP library's FP32 minimisers (prox.h), so the CPU test
+// suite can compare them case by case with the FP64 reference.
+#include "../paper_1311_4527_amd/csrc/prox.h"
+using namespace twa;
+extern "C" {
+// collision minimiser on the four n-messages of one factor (dim 2 or 3)
+void h_coll(int dim, const float *n, const float *w, const int *k, float R, float *x) {
+    if (dim == 2) coll_prox<2>(n, w, k, R, x);
+    else coll_prox<3>(n, w, k, R, x);
+}
+void h_capsule(const float *ab, float r, const float *n, float w0, float w1, int k0, int k1, float *x) {
+    Capsule C{mk(ab[0], ab[1]), mk(ab[2], ab[3]), r};
+    f2 a, b;
+    capsule_prox(C, mk(n[0], n[1]), mk(n[2], n[3]), w0, w1, k0, k1, a, b);
+    x[0] = a.x, x[1] = a.y, x[2] = b.x, x[3] = b.y;
+}
+void h_energy(const float *nl, const float *nh, int dim, float wl, float wh, int kl, int kh, float C, float *xl,
+              float *xh) {
+    for (int c = 0; c < dim; ++c) energy_prox(nl[c], nh[c], wl, wh, kl, kh, C, xl[c], xh[c]);
+}
+}

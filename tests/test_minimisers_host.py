@@ -1,0 +1,168 @@
+"""The HIP library's FP32 minimisers (prox.h), compiled for the host, agree
+case by case with the FP64 reference minimisers (no GPU).
+
+Inputs are rounded to FP32 first; cases whose two best candidate
+configurations are within 1e-5 in energy (near-ties, where FP32 and FP64
+may choose differently) are counted and skipped.
+"""
+import ctypes as ct
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.ref import _dp, _ip, _load
+from tests import bruteforce as bf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TOL = 1e-5
+_fp = ct.POINTER(ct.c_float)
+_i32 = ct.POINTER(ct.c_int)
+
+
+@pytest.fixture(scope="module")
+def H():
+    d = tempfile.mkdtemp(prefix="twa_host_")
+    so = os.path.join(d, "libhost_prox.so")
+    subprocess.run(["hipcc", "-O2", "-fPIC", "-shared", "-std=c++17", "-o", so,
+                    os.path.join(ROOT, "tests", "host_prox.cpp")], check=True)
+    lib = ct.CDLL(so)
+    lib.h_coll.argtypes = [ct.c_int, _fp, _fp, _i32, ct.c_float, _fp]
+    lib.h_capsule.argtypes = [_fp, ct.c_float, _fp, ct.c_float, ct.c_float, ct.c_int, ct.c_int, _fp]
+    lib.h_energy.argtypes = [_fp, _fp, ct.c_int, ct.c_float, ct.c_float, ct.c_int, ct.c_int, ct.c_float, _fp, _fp]
+    return lib
+
+
+def _ref_lib():
+    L = _load()
+    L.tor_prox_capsule_gap.restype = ct.c_int
+    L.tor_prox_capsule_gap.argtypes = [_dp, _dp, ct.c_double, _dp, _dp, ct.c_double, ct.c_double, _dp, _dp, _ip,
+                                       _dp, _dp]
+    L.tor_prox_coll_gap.restype = ct.c_int
+    L.tor_prox_coll_gap.argtypes = [_dp, _dp, _dp, _dp, ct.c_double, ct.c_double, ct.c_double, ct.c_double,
+                                    ct.c_double, ct.c_int, _dp, _dp, _dp, _dp, _ip, _dp, _dp]
+    return L
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, np.float32))
+
+
+def _d(a):
+    return np.ascontiguousarray(np.asarray(a, np.float64))
+
+
+def ref_coll(n, w, R):
+    L = _ref_lib()
+    dim = n.shape[1]
+    nn = [_d(v) for v in n]
+    xs = [np.zeros(dim) for _ in range(4)]
+    k, th, g = ct.c_int(), ct.c_double(), ct.c_double()
+    act = L.tor_prox_coll_gap(*[v.ctypes.data_as(_dp) for v in nn], *[float(x) for x in w], float(R), dim,
+                              *[x.ctypes.data_as(_dp) for x in xs], ct.byref(k), ct.byref(th), ct.byref(g))
+    return bool(act), np.concatenate(xs), g.value
+
+
+def ref_capsule(a, b, r, n0, n1, w0, w1):
+    L = _ref_lib()
+    arrs = [_d(v) for v in (a, b, n0, n1)]
+    x0, x1 = np.zeros(2), np.zeros(2)
+    k, th, g = ct.c_int(), ct.c_double(), ct.c_double()
+    act = L.tor_prox_capsule_gap(arrs[0].ctypes.data_as(_dp), arrs[1].ctypes.data_as(_dp), float(r),
+                                 arrs[2].ctypes.data_as(_dp), arrs[3].ctypes.data_as(_dp), float(w0), float(w1),
+                                 x0.ctypes.data_as(_dp), x1.ctypes.data_as(_dp), ct.byref(k), ct.byref(th),
+                                 ct.byref(g))
+    return bool(act), np.concatenate([x0, x1]), g.value
+
+
+def _close(a, b):
+    return np.all(np.abs(a - b) <= TOL * np.maximum(np.abs(b), 1.0))
+
+
+WEIGHTS = {"std": ([1.0] * 4, [1] * 4), "inf_lo": ([0.0, 1.0, 0.0, 1.0], [2, 1, 2, 1]),
+           "inf_hi": ([1.0, 0.0, 1.0, 0.0], [1, 2, 1, 2]), "unequal": (None, [1] * 4)}
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("wmode", list(WEIGHTS))
+@pytest.mark.parametrize("scale", [1.0, 0.01])
+def test_coll_matches_reference(H, dim, wmode, scale):
+    rng = np.random.default_rng(hash((dim, wmode, scale)) % 2**32)
+    R = 0.5 * scale
+    checked = ties = 0
+    for _ in range(3000):
+        n = _f32(rng.normal(0, 0.4 * scale, size=(4, dim))).astype(np.float64)
+        w, k = WEIGHTS[wmode]
+        if w is None:
+            w = list(rng.uniform(0.3, 3.0, size=4))
+        if wmode != "std" and wmode != "unequal":
+            fixed = (0, 2) if wmode == "inf_lo" else (1, 3)
+            if np.linalg.norm(n[fixed[1]] - n[fixed[0]]) < R * 1.001:
+                continue
+        wref = [np.inf if kk == 2 else ww for ww, kk in zip(w, k)]
+        act, xr, gap = ref_coll(n, wref, R)
+        if not act:
+            continue
+        if gap < TOL:
+            ties += 1
+            continue
+        x = np.zeros(4 * dim, np.float32)
+        H.h_coll(dim, _f32(n.reshape(-1)).ctypes.data_as(_fp), _f32(w).ctypes.data_as(_fp),
+                 np.ascontiguousarray(k, np.int32).ctypes.data_as(_i32), R, x.ctypes.data_as(_fp))
+        assert _close(x.astype(np.float64), xr), (n, w, k, x, xr)
+        checked += 1
+        if checked >= 300:
+            break
+    assert checked >= 100 and ties <= 0.02 * checked
+
+
+@pytest.mark.parametrize("wmode", ["std", "inf0", "inf1", "unequal"])
+@pytest.mark.parametrize("scale", [1.0, 0.02])
+def test_capsule_matches_reference(H, wmode, scale):
+    rng = np.random.default_rng(hash((wmode, scale)) % 2**32)
+    checked = ties = 0
+    for _ in range(4000):
+        r = float(np.float32(rng.uniform(0.05, 0.3) * scale))
+        c = rng.uniform(-0.3, 0.3, 2) * scale
+        th = rng.uniform(0, np.pi)
+        L = rng.uniform(0, 0.8) * scale
+        h = 0.5 * L * np.array([np.cos(th), np.sin(th)])
+        a, b = _f32(c - h).astype(np.float64), _f32(c + h).astype(np.float64)
+        n = _f32(rng.normal(0, 0.4 * scale, 4)).astype(np.float64)
+        w0, w1 = (rng.uniform(0.3, 3.0, 2) if wmode == "unequal" else (1.0, 1.0))
+        k0 = 2 if wmode == "inf0" else 1
+        k1 = 2 if wmode == "inf1" else 1
+        if k0 == 2 and bf.point_seg(n[:2], a, b) < r * 1.001:
+            continue
+        if k1 == 2 and bf.point_seg(n[2:], a, b) < r * 1.001:
+            continue
+        act, xr, gap = ref_capsule(a, b, r, n[:2], n[2:], np.inf if k0 == 2 else w0, np.inf if k1 == 2 else w1)
+        if not act:
+            continue
+        if gap < TOL:
+            ties += 1
+            continue
+        x = np.zeros(4, np.float32)
+        H.h_capsule(_f32(np.concatenate([a, b])).ctypes.data_as(_fp), r, _f32(n).ctypes.data_as(_fp), float(w0),
+                    float(w1), k0, k1, x.ctypes.data_as(_fp))
+        assert _close(x.astype(np.float64), xr), (a, b, r, n, w0, w1, k0, k1, x, xr)
+        checked += 1
+        if checked >= 300:
+            break
+    assert checked >= 100 and ties <= 0.02 * checked
+
+
+def test_energy_matches_reference(H):
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        nl, nh = _f32(rng.normal(size=3)), _f32(rng.normal(size=3))
+        wl, wh, C = (float(np.float32(v)) for v in rng.uniform(0.05, 3, 3))
+        for kl, kh in [(1, 1), (2, 1), (1, 2), (2, 2)]:
+            xl, xh = np.zeros(3, np.float32), np.zeros(3, np.float32)
+            H.h_energy(nl.ctypes.data_as(_fp), nh.ctypes.data_as(_fp), 3, wl, wh, kl, kh, C, xl.ctypes.data_as(_fp),
+                       xh.ctypes.data_as(_fp))
+            rl, rh = O.prox_energy(nl, nh, np.inf if kl == 2 else wl, np.inf if kh == 2 else wh, C)
+            assert _close(xl, rl) and _close(xh, rh)
