@@ -151,6 +151,54 @@ void twa_destroy(twa_solver *s);
 /* Library version string. */
 const char *twa_version(void);
 
+/* ------------------------------------------------------------------------
+ * Batched instances.  Many independent problems of uneven p, eta and dim
+ * advance together in ONE persistent kernel launch (captured in a HIP
+ * graph): a workgroup owns a bin of whole instances and runs every
+ * iteration of each with workgroup barriers only.  Each instance evolves
+ * exactly as it would in its own solver (same arithmetic, bitwise).
+ * ------------------------------------------------------------------------ */
+typedef struct twa_batch twa_batch;
+
+/* One instance of a batch: the twa_create arguments (device pointers) and
+ * an optional initial z0 [p][eta+1][dim] (NULL = straight lines). */
+typedef struct {
+    int p, eta, dim, n_walls;
+    const float *radii, *x0, *xT, *walls, *C, *z0;
+    float rho0, alpha;
+} twa_instance;
+
+/* Create n >= 1 solvers (validation and errors as twa_create; the status of
+ * the first failing instance is returned) sharing one stream. */
+twa_status twa_batch_create(int n, const twa_instance *inst, unsigned flags, void *hip_stream,
+                            twa_batch **out);
+
+/* Launch shape of the persistent kernel: lanes per workgroup (256, 512 or
+ * 1024) and number of workgroups (bins; clamped to n).  Instances are
+ * packed onto bins longest-first.  Default: 256 lanes, one bin per instance. */
+twa_status twa_batch_config(twa_batch *b, int block, int groups);
+
+/* k >= 0 iterations of every instance (one launch). */
+twa_status twa_batch_iterate(twa_batch *b, int k);
+
+/* As twa_batch_iterate; *ms = device time of the launch (synchronises). */
+twa_status twa_batch_iterate_timed(twa_batch *b, int k, double *ms);
+
+/* Number of instances (host pointer). */
+twa_status twa_batch_size(const twa_batch *b, int *n);
+
+/* Instance i's solver, owned by the batch (for state get/set, stats...).
+ * Do not destroy it; do not give it a rho0 schedule. */
+twa_status twa_batch_solver(twa_batch *b, int i, twa_solver **s);
+
+/* twa_get_trajectories of instance i. */
+twa_status twa_batch_get_trajectories(twa_batch *b, int i, float *z_out);
+
+const char *twa_batch_last_error(const twa_batch *b);
+
+/* Frees every instance and the batch (synchronises).  NULL is a no-op. */
+void twa_batch_destroy(twa_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,7 +48,7 @@ constexpr unsigned kPrev = 0x80000000u; // factor was active last iteration: rec
 constexpr unsigned kIdx = 0x7fffffffu;
 
 struct Params {
-    int p, eta, W;
+    int p, eta, W, dim;
     long long Fc, Fw, Fe, Ff;
     long long nbc, nbw, nbe, nbf; // blocks per factor kind in k_stream
     // node records, time-major (s * p + i): x, y, z, <-rho code
@@ -64,6 +64,7 @@ struct Params {
     unsigned *bits_coll, *bits_wall;
     unsigned *qc, *qw;
     int *counters; // [0] qc length, [1] qw length, [2] active coll, [3] active wall
+    int *stats;    // last iteration: active coll, active wall, queued
     unsigned long long *acc; // [2 kinds][dim][N]  kind 0 = std, 1 = inf
     int *cnt;                // [2][N]
     long long N;
@@ -166,338 +167,319 @@ __device__ __forceinline__ void node_xyz(float4 r, float *z, int D) {
     if (D == 3) z[2] = r.z;
 }
 
-// ------------------------------------------------------------------ k_stream
+// ------------------------------------------------------------------ per-factor work
+// Collision factor f (valid lanes only do work): activity test; decides
+// whether the factor goes to the queue (written to *q, *val).
 template <int D, int MODE>
-__global__ __launch_bounds__(kBlock) void k_stream(Params P) {
-    long long b = blockIdx.x;
+__device__ __forceinline__ void coll_stream(const Params &P, long long f, bool valid, bool *q, unsigned *val) {
     const bool dense = P.dense != 0;
-    if (b < P.nbc) {
-        // ---------------- collision factors: activity only
-        long long f = b * kBlock + threadIdx.x;
-        bool valid = f < P.Fc;
-        bool push_prev = false, push_new = false;
-        int s = 0, i = 0, j = 1;
-        if (valid) {
-            decode_pair(f, P.p, s, i, j);
-            long long nd[4];
-            coll_nodes(P, s, i, j, nd);
-            float R = P.radii[i] + P.radii[j];
-            float n[4 * D];
-            bool check_cur = true;
-            float u[4 * D];
-            if (MODE == M_FIRST) {
-                load_u_coll<D>(P, f, u);
-            } else if (dense) {
-                load_u_coll<D>(P, f, u);
-                float zz[3];
-                for (int e = 0; e < 4; ++e) {
-                    node_xyz(P.zr_prev[nd[e]], zz, D);
-                    for (int c = 0; c < D; ++c) n[e * D + c] = zz[c] - u[e * D + c];
-                }
-                if (coll_active<D>(n, R)) {
-                    push_prev = true;
-                    check_cur = false;
-                } else {
-                    for (int q = 0; q < 4 * D; ++q) u[q] = 0.f;
-                    store_u_coll<D>(P, f, u);
-                }
-            } else {
-                unsigned w = P.bits_coll[f >> 5];
-                if ((w >> (f & 31)) & 1u) {
-                    push_prev = true;
-                    check_cur = false;
-                } else {
-                    for (int q = 0; q < 4 * D; ++q) u[q] = 0.f;
-                }
+    bool push_prev = false, push_new = false;
+    int s = 0, i = 0, j = 1;
+    if (valid) {
+        decode_pair(f, P.p, s, i, j);
+        long long nd[4];
+        coll_nodes(P, s, i, j, nd);
+        float R = P.radii[i] + P.radii[j];
+        float n[4 * D];
+        bool check_cur = true;
+        float u[4 * D];
+        if (MODE == M_FIRST) {
+            load_u_coll<D>(P, f, u);
+        } else if (dense) {
+            load_u_coll<D>(P, f, u);
+            float zz[3];
+            for (int e = 0; e < 4; ++e) {
+                node_xyz(P.zr_prev[nd[e]], zz, D);
+                for (int c = 0; c < D; ++c) n[e * D + c] = zz[c] - u[e * D + c];
             }
-            if (MODE == M_FINAL) {
+            if (coll_active<D>(n, R)) {
+                push_prev = true;
                 check_cur = false;
-                if (!dense && !push_prev) store_u_coll<D>(P, f, u); // zero
-            }
-            if (check_cur) {
-                float zz[3];
-                for (int e = 0; e < 4; ++e) {
-                    node_xyz(P.zr_cur[nd[e]], zz, D);
-                    for (int c = 0; c < D; ++c) n[e * D + c] = zz[c] - u[e * D + c];
-                }
-                push_new = coll_active<D>(n, R);
-                if (!push_new && P.dbg_x) {
-                    long long e0 = P.e_coll + 4 * f;
-                    for (int q = 0; q < 4 * D; ++q) P.dbg_x[e0 * D + q] = n[q];
-                    P.dbg_rho[P.f_coll + f] = W_ZERO;
-                }
-            }
-        }
-        if (MODE != M_FINAL && !dense) {
-            // bits of this iteration are set by k_queue; clear this wave's words
-            __syncthreads();
-            if (valid && (f & 31) == 0) P.bits_coll[f >> 5] = 0u;
-        }
-        push(P.qc, &P.counters[0], push_prev || push_new, (unsigned)f | (push_prev ? kPrev : 0u));
-    } else if (b < P.nbc + P.nbw) {
-        // ---------------- wall factors: activity only (planar)
-        long long f = (b - P.nbc) * kBlock + threadIdx.x;
-        bool valid = f < P.Fw;
-        bool push_prev = false, push_new = false;
-        if (valid) {
-            int w = (int)(f % P.W);
-            long long si = f / P.W;
-            int i = (int)(si % P.p), s = (int)(si / P.p);
-            long long na = (long long)s * P.p + i, nb = na + P.p;
-            float4 wl = P.walls[w];
-            f2 xa = mk(wl.x, wl.y), xb = mk(wl.z, wl.w);
-            float r = P.radii[i];
-            float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
-            bool check_cur = true;
-            if (MODE == M_FIRST) {
-                u = P.u_wall[f];
-            } else if (dense) {
-                u = P.u_wall[f];
-                float4 za = P.zr_prev[na], zb = P.zr_prev[nb];
-                f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
-                if (segseg_sq(n0, n1, xa, xb) < r * r) {
-                    push_prev = true;
-                    check_cur = false;
-                } else {
-                    u = make_float4(0.f, 0.f, 0.f, 0.f);
-                    P.u_wall[f] = u;
-                }
             } else {
-                unsigned wd = P.bits_wall[f >> 5];
-                if ((wd >> (f & 31)) & 1u) {
-                    push_prev = true;
-                    check_cur = false;
-                }
+                for (int q = 0; q < 4 * D; ++q) u[q] = 0.f;
+                store_u_coll<D>(P, f, u);
             }
-            if (MODE == M_FINAL) {
+        } else {
+            unsigned w = P.bits_coll[f >> 5];
+            if ((w >> (f & 31)) & 1u) {
+                push_prev = true;
                 check_cur = false;
-                if (!dense && !push_prev) P.u_wall[f] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-            if (check_cur) {
-                float4 za = P.zr_cur[na], zb = P.zr_cur[nb];
-                f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
-                push_new = segseg_sq(n0, n1, xa, xb) < r * r;
-                if (!push_new && P.dbg_x) {
-                    long long e0 = P.e_wall + 2 * f;
-                    P.dbg_x[e0 * 2 + 0] = n0.x, P.dbg_x[e0 * 2 + 1] = n0.y;
-                    P.dbg_x[e0 * 2 + 2] = n1.x, P.dbg_x[e0 * 2 + 3] = n1.y;
-                    P.dbg_rho[P.f_wall + f] = W_ZERO;
-                }
-            }
-        }
-        if (MODE != M_FINAL && !dense) {
-            __syncthreads();
-            if (valid && (f & 31) == 0) P.bits_wall[f >> 5] = 0u;
-        }
-        push(P.qw, &P.counters[1], push_prev || push_new, (unsigned)f | (push_prev ? kPrev : 0u));
-    } else if (b < P.nbc + P.nbw + P.nbe) {
-        // ---------------- energy factors: always weight rho0
-        long long f = (b - P.nbc - P.nbw) * kBlock + threadIdx.x;
-        if (f >= P.Fe) return;
-        int i = (int)(f / P.eta), s = (int)(f % P.eta);
-        long long na = (long long)s * P.p + i, nb = na + P.p;
-        float C = P.C[f];
-        float *up = P.u_energy + f * 2 * D;
-        float u[6];
-        for (int q = 0; q < 2 * D; ++q) u[q] = up[q];
-        float4 ca = P.zr_cur[na], cb = P.zr_cur[nb];
-        float zc[6];
-        node_xyz(ca, zc, D);
-        node_xyz(cb, zc + D, D);
-        int ka = wcode(ca), kb = wcode(cb);
-        if (MODE != M_FIRST) {
-            // recompute x^k from (z^{k-1}, u^{k-1}), then u^k
-            float4 pa = P.zr_prev[na], pb = P.zr_prev[nb];
-            float zp[6];
-            node_xyz(pa, zp, D);
-            node_xyz(pb, zp + D, D);
-            int pka = wcode(pa), pkb = wcode(pb);
-            float xk[6];
-            for (int c = 0; c < D; ++c)
-                energy_prox(zp[c] - u[c], zp[D + c] - u[D + c], wval(pka, P.rho_prev), wval(pkb, P.rho_prev), pka,
-                            pkb, C, xk[c], xk[D + c]);
-            for (int c = 0; c < D; ++c) {
-                u[c] = (ka == W_STD) ? u[c] + P.step_prev * (xk[c] - zc[c]) : 0.f;
-                u[D + c] = (kb == W_STD) ? u[D + c] + P.step_prev * (xk[D + c] - zc[D + c]) : 0.f;
-            }
-            for (int q = 0; q < 2 * D; ++q) up[q] = u[q];
-            if (MODE == M_FINAL) return;
-        }
-        float x[6], m[6];
-        for (int c = 0; c < D; ++c)
-            energy_prox(zc[c] - u[c], zc[D + c] - u[D + c], wval(ka, P.rho), wval(kb, P.rho), ka, kb, C, x[c],
-                        x[D + c]);
-        for (int q = 0; q < 2 * D; ++q) m[q] = x[q] + u[q];
-        contribute(P, na, 0, m, D);
-        contribute(P, nb, 0, m + D, D);
-        if (P.dbg_x) {
-            long long e0 = P.e_energy + 2 * f;
-            for (int q = 0; q < 2 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
-            P.dbg_rho[P.f_energy + f] = W_STD;
-        }
-    } else {
-        // ---------------- fixed start/goal factors: x = const, weight infinity
-        long long f = (b - P.nbc - P.nbw - P.nbe) * kBlock + threadIdx.x;
-        if (f >= P.Ff) return;
-        int i = (int)(f >> 1);
-        int s = (f & 1) ? P.eta : 0;
-        long long nd = (long long)s * P.p + i;
-        float *up = P.u_fixed + f * D;
-        float u[3];
-        for (int c = 0; c < D; ++c) u[c] = up[c];
-        if (MODE != M_FIRST) {
-            // ->rho^{k-1} = infinity, so u^k = 0
-            for (int c = 0; c < D; ++c) u[c] = 0.f, up[c] = 0.f;
-            if (MODE == M_FINAL) return;
-        }
-        float4 xf = P.xfix[f];
-        float x[3] = {xf.x, xf.y, xf.z}, m[3];
-        for (int c = 0; c < D; ++c) m[c] = x[c] + u[c];
-        contribute(P, nd, 1, m, D);
-        if (P.dbg_x) {
-            for (int c = 0; c < D; ++c) P.dbg_x[f * D + c] = x[c];
-            P.dbg_rho[f] = W_INF;
-        }
-    }
-}
-
-// ------------------------------------------------------------------ k_queue
-template <int D, int MODE>
-__global__ __launch_bounds__(kBlock) void k_queue(Params P) {
-    const int nqc = P.counters[0], nqw = P.counters[1];
-    const long long total = (long long)nqc + nqw;
-    const bool dense = P.dense != 0;
-    for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < total; t += (long long)gridDim.x * kBlock) {
-        if (t < nqc) {
-            unsigned e = P.qc[t];
-            long long f = e & kIdx;
-            bool prev = (e & kPrev) != 0;
-            int s, i, j;
-            decode_pair(f, P.p, s, i, j);
-            long long nd[4];
-            coll_nodes(P, s, i, j, nd);
-            float R = P.radii[i] + P.radii[j];
-            float u[4 * D], zc[4 * D], n[4 * D], x[4 * D], w[4];
-            int k[4];
-            float4 rc[4];
-            for (int q = 0; q < 4; ++q) {
-                rc[q] = P.zr_cur[nd[q]];
-                node_xyz(rc[q], zc + q * D, D);
-                k[q] = wcode(rc[q]);
-            }
-            if (prev) {
-                load_u_coll<D>(P, f, u);
-                float wp[4];
-                int kp[4];
-                for (int q = 0; q < 4; ++q) {
-                    float4 rp = P.zr_prev[nd[q]];
-                    float zp[3];
-                    node_xyz(rp, zp, D);
-                    kp[q] = wcode(rp);
-                    wp[q] = wval(kp[q], P.rho_prev);
-                    for (int c = 0; c < D; ++c) n[q * D + c] = zp[c] - u[q * D + c];
-                }
-                coll_prox<D>(n, wp, kp, R, x); // x^k; its weight was rho0 on all four edges
-                for (int q = 0; q < 4; ++q)
-                    for (int c = 0; c < D; ++c)
-                        u[q * D + c] =
-                            (k[q] == W_STD) ? u[q * D + c] + P.step_prev * (x[q * D + c] - zc[q * D + c]) : 0.f;
-                if (MODE == M_FINAL) {
-                    store_u_coll<D>(P, f, u);
-                    continue;
-                }
-            } else if (MODE == M_FIRST) {
-                load_u_coll<D>(P, f, u);
             } else {
                 for (int q = 0; q < 4 * D; ++q) u[q] = 0.f;
             }
-            for (int q = 0; q < 4 * D; ++q) n[q] = zc[q] - u[q];
-            bool act = coll_active<D>(n, R);
-            if (act) {
-                for (int q = 0; q < 4; ++q) w[q] = wval(k[q], P.rho);
-                coll_prox<D>(n, w, k, R, x);
-                float m[3];
-                for (int q = 0; q < 4; ++q) {
-                    for (int c = 0; c < D; ++c) m[c] = x[q * D + c] + u[q * D + c];
-                    contribute(P, nd[q], 0, m, D);
-                }
-                atomicOr(&P.bits_coll[f >> 5], 1u << (f & 31));
-                atomicAdd(&P.counters[2], 1);
-            } else {
-                for (int q = 0; q < 4 * D; ++q) x[q] = n[q];
+        }
+        if (MODE == M_FINAL) {
+            check_cur = false;
+            if (!dense && !push_prev) store_u_coll<D>(P, f, u); // zero
+        }
+        if (check_cur) {
+            float zz[3];
+            for (int e = 0; e < 4; ++e) {
+                node_xyz(P.zr_cur[nd[e]], zz, D);
+                for (int c = 0; c < D; ++c) n[e * D + c] = zz[c] - u[e * D + c];
             }
-            if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) store_u_coll<D>(P, f, u);
-            if (P.dbg_x) {
+            push_new = coll_active<D>(n, R);
+            if (!push_new && P.dbg_x) {
                 long long e0 = P.e_coll + 4 * f;
-                for (int q = 0; q < 4 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
-                P.dbg_rho[P.f_coll + f] = act ? W_STD : W_ZERO;
-            }
-        } else {
-            unsigned e = P.qw[t - nqc];
-            long long f = e & kIdx;
-            bool prev = (e & kPrev) != 0;
-            int wi = (int)(f % P.W);
-            long long si = f / P.W;
-            int i = (int)(si % P.p), s = (int)(si / P.p);
-            long long na = (long long)s * P.p + i, nb = na + P.p;
-            float4 wl = P.walls[wi];
-            Capsule Cw{mk(wl.x, wl.y), mk(wl.z, wl.w), P.radii[i]};
-            float4 ca = P.zr_cur[na], cb = P.zr_cur[nb];
-            int ka = wcode(ca), kb = wcode(cb);
-            float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (prev) {
-                u = P.u_wall[f];
-                float4 pa = P.zr_prev[na], pb = P.zr_prev[nb];
-                int pka = wcode(pa), pkb = wcode(pb);
-                f2 x0, x1;
-                capsule_prox(Cw, mk(pa.x - u.x, pa.y - u.y), mk(pb.x - u.z, pb.y - u.w), wval(pka, P.rho_prev),
-                             wval(pkb, P.rho_prev), pka, pkb, x0, x1);
-                u.x = (ka == W_STD) ? u.x + P.step_prev * (x0.x - ca.x) : 0.f;
-                u.y = (ka == W_STD) ? u.y + P.step_prev * (x0.y - ca.y) : 0.f;
-                u.z = (kb == W_STD) ? u.z + P.step_prev * (x1.x - cb.x) : 0.f;
-                u.w = (kb == W_STD) ? u.w + P.step_prev * (x1.y - cb.y) : 0.f;
-                if (MODE == M_FINAL) {
-                    P.u_wall[f] = u;
-                    continue;
-                }
-            } else if (MODE == M_FIRST) {
-                u = P.u_wall[f];
-            }
-            f2 n0 = mk(ca.x - u.x, ca.y - u.y), n1 = mk(cb.x - u.z, cb.y - u.w);
-            bool act = segseg_sq(n0, n1, Cw.a, Cw.b) < Cw.r * Cw.r;
-            f2 x0 = n0, x1 = n1;
-            if (act) {
-                capsule_prox(Cw, n0, n1, wval(ka, P.rho), wval(kb, P.rho), ka, kb, x0, x1);
-                float m0[2] = {x0.x + u.x, x0.y + u.y}, m1[2] = {x1.x + u.z, x1.y + u.w};
-                contribute(P, na, 0, m0, 2);
-                contribute(P, nb, 0, m1, 2);
-                atomicOr(&P.bits_wall[f >> 5], 1u << (f & 31));
-                atomicAdd(&P.counters[3], 1);
-            }
-            if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) P.u_wall[f] = u;
-            if (P.dbg_x) {
-                long long e0 = P.e_wall + 2 * f;
-                P.dbg_x[e0 * 2 + 0] = x0.x, P.dbg_x[e0 * 2 + 1] = x0.y;
-                P.dbg_x[e0 * 2 + 2] = x1.x, P.dbg_x[e0 * 2 + 3] = x1.y;
-                P.dbg_rho[P.f_wall + f] = act ? W_STD : W_ZERO;
+                for (int q = 0; q < 4 * D; ++q) P.dbg_x[e0 * D + q] = n[q];
+                P.dbg_rho[P.f_coll + f] = W_ZERO;
             }
         }
     }
+    *q = push_prev || push_new;
+    *val = (unsigned)f | (push_prev ? kPrev : 0u);
 }
 
-// ------------------------------------------------------------------ k_nodes
-// z^{k+1} and <-rho^{k+1} per node; shift the node records; clear the sums.
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_nodes(Params P, int *stats_out) {
-    long long nd = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (nd == 0) {
-        // counters of this iteration -> stats, then reset for the next one
-        stats_out[0] = P.counters[2];
-        stats_out[1] = P.counters[3];
-        stats_out[2] = P.counters[0] + P.counters[1];
-        P.counters[0] = P.counters[1] = P.counters[2] = P.counters[3] = 0;
+// Wall factor f: activity test (segment distance) and queue decision.
+template <int MODE>
+__device__ __forceinline__ void wall_stream(const Params &P, long long f, bool valid, bool *q, unsigned *val) {
+    const bool dense = P.dense != 0;
+    bool push_prev = false, push_new = false;
+    if (valid) {
+        int w = (int)(f % P.W);
+        long long si = f / P.W;
+        int i = (int)(si % P.p), s = (int)(si / P.p);
+        long long na = (long long)s * P.p + i, nb = na + P.p;
+        float4 wl = P.walls[w];
+        f2 xa = mk(wl.x, wl.y), xb = mk(wl.z, wl.w);
+        float r = P.radii[i];
+        float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+        bool check_cur = true;
+        if (MODE == M_FIRST) {
+            u = P.u_wall[f];
+        } else if (dense) {
+            u = P.u_wall[f];
+            float4 za = P.zr_prev[na], zb = P.zr_prev[nb];
+            f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
+            if (segseg_sq(n0, n1, xa, xb) < r * r) {
+                push_prev = true;
+                check_cur = false;
+            } else {
+                u = make_float4(0.f, 0.f, 0.f, 0.f);
+                P.u_wall[f] = u;
+            }
+        } else {
+            unsigned wd = P.bits_wall[f >> 5];
+            if ((wd >> (f & 31)) & 1u) {
+                push_prev = true;
+                check_cur = false;
+            }
+        }
+        if (MODE == M_FINAL) {
+            check_cur = false;
+            if (!dense && !push_prev) P.u_wall[f] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        if (check_cur) {
+            float4 za = P.zr_cur[na], zb = P.zr_cur[nb];
+            f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
+            push_new = segseg_sq(n0, n1, xa, xb) < r * r;
+            if (!push_new && P.dbg_x) {
+                long long e0 = P.e_wall + 2 * f;
+                P.dbg_x[e0 * 2 + 0] = n0.x, P.dbg_x[e0 * 2 + 1] = n0.y;
+                P.dbg_x[e0 * 2 + 2] = n1.x, P.dbg_x[e0 * 2 + 3] = n1.y;
+                P.dbg_rho[P.f_wall + f] = W_ZERO;
+            }
+        }
     }
-    if (nd >= P.N) return;
+    *q = push_prev || push_new;
+    *val = (unsigned)f | (push_prev ? kPrev : 0u);
+}
+
+// Energy factor f: always weight rho0; finished here.
+template <int D, int MODE>
+__device__ __forceinline__ void energy_stream(const Params &P, long long f) {
+    int i = (int)(f / P.eta), s = (int)(f % P.eta);
+    long long na = (long long)s * P.p + i, nb = na + P.p;
+    float C = P.C[f];
+    float *up = P.u_energy + f * 2 * D;
+    float u[6];
+    for (int q = 0; q < 2 * D; ++q) u[q] = up[q];
+    float4 ca = P.zr_cur[na], cb = P.zr_cur[nb];
+    float zc[6];
+    node_xyz(ca, zc, D);
+    node_xyz(cb, zc + D, D);
+    int ka = wcode(ca), kb = wcode(cb);
+    if (MODE != M_FIRST) {
+        // recompute x^k from (z^{k-1}, u^{k-1}), then u^k
+        float4 pa = P.zr_prev[na], pb = P.zr_prev[nb];
+        float zp[6];
+        node_xyz(pa, zp, D);
+        node_xyz(pb, zp + D, D);
+        int pka = wcode(pa), pkb = wcode(pb);
+        float xk[6];
+        for (int c = 0; c < D; ++c)
+            energy_prox(zp[c] - u[c], zp[D + c] - u[D + c], wval(pka, P.rho_prev), wval(pkb, P.rho_prev), pka,
+                        pkb, C, xk[c], xk[D + c]);
+        for (int c = 0; c < D; ++c) {
+            u[c] = (ka == W_STD) ? u[c] + P.step_prev * (xk[c] - zc[c]) : 0.f;
+            u[D + c] = (kb == W_STD) ? u[D + c] + P.step_prev * (xk[D + c] - zc[D + c]) : 0.f;
+        }
+        for (int q = 0; q < 2 * D; ++q) up[q] = u[q];
+        if (MODE == M_FINAL) return;
+    }
+    float x[6], m[6];
+    for (int c = 0; c < D; ++c)
+        energy_prox(zc[c] - u[c], zc[D + c] - u[D + c], wval(ka, P.rho), wval(kb, P.rho), ka, kb, C, x[c],
+                    x[D + c]);
+    for (int q = 0; q < 2 * D; ++q) m[q] = x[q] + u[q];
+    contribute(P, na, 0, m, D);
+    contribute(P, nb, 0, m + D, D);
+    if (P.dbg_x) {
+        long long e0 = P.e_energy + 2 * f;
+        for (int q = 0; q < 2 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
+        P.dbg_rho[P.f_energy + f] = W_STD;
+    }
+}
+
+// Fixed start/goal factor f: x = const, weight infinity.
+template <int D, int MODE>
+__device__ __forceinline__ void fixed_stream(const Params &P, long long f) {
+    int i = (int)(f >> 1);
+    int s = (f & 1) ? P.eta : 0;
+    long long nd = (long long)s * P.p + i;
+    float *up = P.u_fixed + f * D;
+    float u[3];
+    for (int c = 0; c < D; ++c) u[c] = up[c];
+    if (MODE != M_FIRST) {
+        // ->rho^{k-1} = infinity, so u^k = 0
+        for (int c = 0; c < D; ++c) u[c] = 0.f, up[c] = 0.f;
+        if (MODE == M_FINAL) return;
+    }
+    float4 xf = P.xfix[f];
+    float x[3] = {xf.x, xf.y, xf.z}, m[3];
+    for (int c = 0; c < D; ++c) m[c] = x[c] + u[c];
+    contribute(P, nd, 1, m, D);
+    if (P.dbg_x) {
+        for (int c = 0; c < D; ++c) P.dbg_x[f * D + c] = x[c];
+        P.dbg_rho[f] = W_INF;
+    }
+}
+
+// Queued collision factor (entry e): deferred u update, full minimiser,
+// consensus contributions.
+template <int D, int MODE>
+__device__ __forceinline__ void coll_queue(const Params &P, unsigned e) {
+    const bool dense = P.dense != 0;
+    long long f = e & kIdx;
+    bool prev = (e & kPrev) != 0;
+    int s, i, j;
+    decode_pair(f, P.p, s, i, j);
+    long long nd[4];
+    coll_nodes(P, s, i, j, nd);
+    float R = P.radii[i] + P.radii[j];
+    float u[4 * D], zc[4 * D], n[4 * D], x[4 * D], w[4];
+    int k[4];
+    float4 rc[4];
+    for (int q = 0; q < 4; ++q) {
+        rc[q] = P.zr_cur[nd[q]];
+        node_xyz(rc[q], zc + q * D, D);
+        k[q] = wcode(rc[q]);
+    }
+    if (prev) {
+        load_u_coll<D>(P, f, u);
+        float wp[4];
+        int kp[4];
+        for (int q = 0; q < 4; ++q) {
+            float4 rp = P.zr_prev[nd[q]];
+            float zp[3];
+            node_xyz(rp, zp, D);
+            kp[q] = wcode(rp);
+            wp[q] = wval(kp[q], P.rho_prev);
+            for (int c = 0; c < D; ++c) n[q * D + c] = zp[c] - u[q * D + c];
+        }
+        coll_prox<D>(n, wp, kp, R, x); // x^k; its weight was rho0 on all four edges
+        for (int q = 0; q < 4; ++q)
+            for (int c = 0; c < D; ++c)
+                u[q * D + c] =
+                    (k[q] == W_STD) ? u[q * D + c] + P.step_prev * (x[q * D + c] - zc[q * D + c]) : 0.f;
+        if (MODE == M_FINAL) {
+            store_u_coll<D>(P, f, u);
+            return;
+        }
+    } else if (MODE == M_FIRST) {
+        load_u_coll<D>(P, f, u);
+    } else {
+        for (int q = 0; q < 4 * D; ++q) u[q] = 0.f;
+    }
+    for (int q = 0; q < 4 * D; ++q) n[q] = zc[q] - u[q];
+    bool act = coll_active<D>(n, R);
+    if (act) {
+        for (int q = 0; q < 4; ++q) w[q] = wval(k[q], P.rho);
+        coll_prox<D>(n, w, k, R, x);
+        float m[3];
+        for (int q = 0; q < 4; ++q) {
+            for (int c = 0; c < D; ++c) m[c] = x[q * D + c] + u[q * D + c];
+            contribute(P, nd[q], 0, m, D);
+        }
+        atomicOr(&P.bits_coll[f >> 5], 1u << (f & 31));
+        atomicAdd(&P.counters[2], 1);
+    } else {
+        for (int q = 0; q < 4 * D; ++q) x[q] = n[q];
+    }
+    if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) store_u_coll<D>(P, f, u);
+    if (P.dbg_x) {
+        long long e0 = P.e_coll + 4 * f;
+        for (int q = 0; q < 4 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
+        P.dbg_rho[P.f_coll + f] = act ? W_STD : W_ZERO;
+    }
+}
+
+// Queued wall factor (entry e).
+template <int MODE>
+__device__ __forceinline__ void wall_queue(const Params &P, unsigned e) {
+    const bool dense = P.dense != 0;
+    long long f = e & kIdx;
+    bool prev = (e & kPrev) != 0;
+    int wi = (int)(f % P.W);
+    long long si = f / P.W;
+    int i = (int)(si % P.p), s = (int)(si / P.p);
+    long long na = (long long)s * P.p + i, nb = na + P.p;
+    float4 wl = P.walls[wi];
+    Capsule Cw{mk(wl.x, wl.y), mk(wl.z, wl.w), P.radii[i]};
+    float4 ca = P.zr_cur[na], cb = P.zr_cur[nb];
+    int ka = wcode(ca), kb = wcode(cb);
+    float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (prev) {
+        u = P.u_wall[f];
+        float4 pa = P.zr_prev[na], pb = P.zr_prev[nb];
+        int pka = wcode(pa), pkb = wcode(pb);
+        f2 x0, x1;
+        capsule_prox(Cw, mk(pa.x - u.x, pa.y - u.y), mk(pb.x - u.z, pb.y - u.w), wval(pka, P.rho_prev),
+                     wval(pkb, P.rho_prev), pka, pkb, x0, x1);
+        u.x = (ka == W_STD) ? u.x + P.step_prev * (x0.x - ca.x) : 0.f;
+        u.y = (ka == W_STD) ? u.y + P.step_prev * (x0.y - ca.y) : 0.f;
+        u.z = (kb == W_STD) ? u.z + P.step_prev * (x1.x - cb.x) : 0.f;
+        u.w = (kb == W_STD) ? u.w + P.step_prev * (x1.y - cb.y) : 0.f;
+        if (MODE == M_FINAL) {
+            P.u_wall[f] = u;
+            return;
+        }
+    } else if (MODE == M_FIRST) {
+        u = P.u_wall[f];
+    }
+    f2 n0 = mk(ca.x - u.x, ca.y - u.y), n1 = mk(cb.x - u.z, cb.y - u.w);
+    bool act = segseg_sq(n0, n1, Cw.a, Cw.b) < Cw.r * Cw.r;
+    f2 x0 = n0, x1 = n1;
+    if (act) {
+        capsule_prox(Cw, n0, n1, wval(ka, P.rho), wval(kb, P.rho), ka, kb, x0, x1);
+        float m0[2] = {x0.x + u.x, x0.y + u.y}, m1[2] = {x1.x + u.z, x1.y + u.w};
+        contribute(P, na, 0, m0, 2);
+        contribute(P, nb, 0, m1, 2);
+        atomicOr(&P.bits_wall[f >> 5], 1u << (f & 31));
+        atomicAdd(&P.counters[3], 1);
+    }
+    if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) P.u_wall[f] = u;
+    if (P.dbg_x) {
+        long long e0 = P.e_wall + 2 * f;
+        P.dbg_x[e0 * 2 + 0] = x0.x, P.dbg_x[e0 * 2 + 1] = x0.y;
+        P.dbg_x[e0 * 2 + 2] = x1.x, P.dbg_x[e0 * 2 + 3] = x1.y;
+        P.dbg_rho[P.f_wall + f] = act ? W_STD : W_ZERO;
+    }
+}
+
+// Node nd: z and <-rho of the next iteration, shift records, clear sums.
+template <int D>
+__device__ __forceinline__ void node_update(const Params &P, long long nd) {
     int ci = P.cnt[P.N + nd], cs = P.cnt[nd];
     float4 cur = P.zr_cur[nd];
     float4 nw = cur;
@@ -523,6 +505,132 @@ __global__ __launch_bounds__(kBlock) void k_nodes(Params P, int *stats_out) {
     for (int kind = 0; kind < 2; ++kind) {
         for (int c = 0; c < D; ++c) P.acc[((long long)kind * D + c) * P.N + nd] = 0ull;
         P.cnt[(long long)kind * P.N + nd] = 0;
+    }
+}
+
+// ------------------------------------------------------------------ plain kernels
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stream(Params P) {
+    long long b = blockIdx.x;
+    const bool clear_bits = MODE != M_FINAL && P.dense == 0;
+    if (b < P.nbc) {
+        long long f = b * kBlock + threadIdx.x;
+        bool valid = f < P.Fc, q;
+        unsigned val;
+        coll_stream<D, MODE>(P, f, valid, &q, &val);
+        if (clear_bits) {
+            // this iteration's bits are set by k_queue; clear this wave's words
+            __syncthreads();
+            if (valid && (f & 31) == 0) P.bits_coll[f >> 5] = 0u;
+        }
+        push(P.qc, &P.counters[0], q, val);
+    } else if (b < P.nbc + P.nbw) {
+        long long f = (b - P.nbc) * kBlock + threadIdx.x;
+        bool valid = f < P.Fw, q;
+        unsigned val;
+        wall_stream<MODE>(P, f, valid, &q, &val);
+        if (clear_bits) {
+            __syncthreads();
+            if (valid && (f & 31) == 0) P.bits_wall[f >> 5] = 0u;
+        }
+        push(P.qw, &P.counters[1], q, val);
+    } else if (b < P.nbc + P.nbw + P.nbe) {
+        long long f = (b - P.nbc - P.nbw) * kBlock + threadIdx.x;
+        if (f < P.Fe) energy_stream<D, MODE>(P, f);
+    } else {
+        long long f = (b - P.nbc - P.nbw - P.nbe) * kBlock + threadIdx.x;
+        if (f < P.Ff) fixed_stream<D, MODE>(P, f);
+    }
+}
+
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_queue(Params P) {
+    const int nqc = P.counters[0], nqw = P.counters[1];
+    const long long total = (long long)nqc + nqw;
+    for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < total; t += (long long)gridDim.x * kBlock) {
+        if (t < nqc) coll_queue<D, MODE>(P, P.qc[t]);
+        else wall_queue<MODE>(P, P.qw[t - nqc]);
+    }
+}
+
+__device__ __forceinline__ void close_counters(const Params &P) {
+    // counters of this iteration -> stats, then reset for the next one
+    P.stats[0] = P.counters[2];
+    P.stats[1] = P.counters[3];
+    P.stats[2] = P.counters[0] + P.counters[1];
+    P.counters[0] = P.counters[1] = P.counters[2] = P.counters[3] = 0;
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_nodes(Params P) {
+    long long nd = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (nd == 0) close_counters(P);
+    if (nd < P.N) node_update<D>(P, nd);
+}
+
+// ------------------------------------------------------------------ batched persistent kernel
+// One workgroup owns a bin of whole instances and runs all K iterations of
+// each of them; the three phases of an iteration are separated by
+// workgroup barriers only (instances are independent), so no workgroup
+// ever waits for another.  The per-factor work is the plain solver's, so a
+// batched instance evolves bitwise as it would on its own.
+template <int D, int MODE, int BLOCK>
+__device__ __forceinline__ void batch_instance(const Params &P) {
+    const bool clear_bits = P.dense == 0;
+    for (long long base = 0; base < P.Fc; base += BLOCK) {
+        long long f = base + threadIdx.x;
+        bool valid = f < P.Fc, q;
+        unsigned val;
+        coll_stream<D, MODE>(P, f, valid, &q, &val);
+        if (clear_bits) {
+            __syncthreads();
+            if (valid && (f & 31) == 0) P.bits_coll[f >> 5] = 0u;
+        }
+        push(P.qc, &P.counters[0], q, val);
+    }
+    for (long long base = 0; base < P.Fw; base += BLOCK) {
+        long long f = base + threadIdx.x;
+        bool valid = f < P.Fw, q;
+        unsigned val;
+        wall_stream<MODE>(P, f, valid, &q, &val);
+        if (clear_bits) {
+            __syncthreads();
+            if (valid && (f & 31) == 0) P.bits_wall[f >> 5] = 0u;
+        }
+        push(P.qw, &P.counters[1], q, val);
+    }
+    for (long long f = threadIdx.x; f < P.Fe; f += BLOCK) energy_stream<D, MODE>(P, f);
+    for (long long f = threadIdx.x; f < P.Ff; f += BLOCK) fixed_stream<D, MODE>(P, f);
+    __syncthreads();
+    const int nqc = __atomic_load_n(&P.counters[0], __ATOMIC_RELAXED);
+    const int nqw = __atomic_load_n(&P.counters[1], __ATOMIC_RELAXED);
+    for (int t = threadIdx.x; t < nqc + nqw; t += BLOCK) {
+        if (t < nqc) coll_queue<D, MODE>(P, P.qc[t]);
+        else wall_queue<MODE>(P, P.qw[t - nqc]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) close_counters(P);
+    for (long long nd = threadIdx.x; nd < P.N; nd += BLOCK) node_update<D>(P, nd);
+    __syncthreads();
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_batch(const Params *insts, const int *bin_start, const int *bin_items,
+                                                  int K, int first) {
+    const int g = blockIdx.x;
+    const int q0 = bin_start[g], q1 = bin_start[g + 1];
+    for (int it = 0; it < K; ++it) {
+        const bool fst = first && it == 0;
+        for (int q = q0; q < q1; ++q) {
+            const Params &P = insts[bin_items[q]];
+            if (P.dim == 2) {
+                if (fst) batch_instance<2, M_FIRST, BLOCK>(P);
+                else batch_instance<2, M_FUSED, BLOCK>(P);
+            } else {
+                if (fst) batch_instance<3, M_FIRST, BLOCK>(P);
+                else batch_instance<3, M_FUSED, BLOCK>(P);
+            }
+        }
     }
 }
 
@@ -728,7 +836,7 @@ twa_status launch_iteration(twa_solver *s, int mode) {
         return TWA_OK;
     }
     unsigned nb = (unsigned)((P.N + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_nodes<D>), dim3(nb), dim3(kBlock), 0, s->stream, P, s->stats_dev);
+    hipLaunchKernelGGL((k_nodes<D>), dim3(nb), dim3(kBlock), 0, s->stream, P);
     mark(s, 3);
     HIP_TRY(s, hipGetLastError());
     return TWA_OK;
@@ -893,7 +1001,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     }
     // --- device buffers
     Params &P = s->P;
-    P.p = p, P.eta = eta, P.W = n_walls;
+    P.p = p, P.eta = eta, P.W = n_walls, P.dim = dim;
     P.Fc = Fc, P.Fw = Fw, P.Fe = Fe, P.Ff = Ff;
     P.N = (long long)p * (eta + 1);
     P.nbc = (Fc + kBlock - 1) / kBlock;
@@ -931,6 +1039,9 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         dev_alloc(s, &s->stats_dev, 4) || dev_alloc(s, &s->bad_dev, 1))
         return bail(TWA_E_NOMEM);
     P.radii = radii_d, P.C = C_d, P.walls = walls_d, P.xfix = xfix_d;
+    P.stats = s->stats_dev;
+    P.rho = P.rho_prev = rho0;
+    P.step = P.step_prev = alpha / rho0;
     // constants
     std::vector<float4> hwall(std::max(1, n_walls)), hfix(Ff);
     for (int w = 0; w < n_walls; ++w) hwall[w] = make_float4(hw[w * 4 + 0], hw[w * 4 + 1], hw[w * 4 + 2], hw[w * 4 + 3]);
@@ -1130,6 +1241,250 @@ twa_status twa_check_finite(twa_solver *s) {
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     if (bad) return fail(s, TWA_E_NUMERIC, "non-finite value in z or u");
     return TWA_OK;
+}
+
+
+// ============================================================================
+// batched instances: one persistent launch over many solvers
+// ============================================================================
+
+} // extern "C"
+
+struct twa_batch {
+    std::vector<twa_solver *> solvers;
+    hipStream_t stream = nullptr;
+    Params *insts_dev = nullptr;
+    int *bin_start_dev = nullptr, *bin_items_dev = nullptr;
+    int block = 256, groups = 0;
+    std::string err;
+    twa_status latched = TWA_OK;
+    hipGraphExec_t gexec = nullptr;
+    int g_k = -1, g_first = -1;
+};
+
+namespace {
+
+twa_status bfail(twa_batch *b, twa_status st, const std::string &msg) {
+    if (b) {
+        b->err = msg;
+        if (st == TWA_E_DEVICE) b->latched = TWA_E_DEVICE;
+    }
+    return st;
+}
+
+#define BHIP_TRY(b, call)                                                                                      \
+    do {                                                                                                       \
+        hipError_t e_ = (call);                                                                                \
+        if (e_ != hipSuccess) return bfail((b), TWA_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// cost of one iteration of a solver inside one workgroup of `block` lanes
+double batch_cost(const twa_solver *s, int block) {
+    const Params &P = s->P;
+    auto ch = [block](long long n) { return (double)((n + block - 1) / block); };
+    return ch(P.Fc) + ch(P.Fw) + ch(P.Fe) + ch(P.Ff) + ch(P.N) + 4.0;
+}
+
+void drop_graph(twa_batch *b) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->g_k = b->g_first = -1;
+}
+
+twa_status batch_bins(twa_batch *b) {
+    int n = (int)b->solvers.size();
+    int G = std::max(1, std::min(b->groups > 0 ? b->groups : n, n));
+    // longest processing time first onto the least-loaded bin
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::vector<double> cost(n);
+    for (int i = 0; i < n; ++i) cost[i] = batch_cost(b->solvers[i], b->block);
+    std::sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    std::vector<double> load(G, 0.0);
+    std::vector<std::vector<int>> bins(G);
+    for (int i : order) {
+        int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        bins[g].push_back(i);
+        load[g] += cost[i];
+    }
+    std::vector<int> start(G + 1, 0), items;
+    for (int g = 0; g < G; ++g) {
+        start[g + 1] = start[g] + (int)bins[g].size();
+        for (int i : bins[g]) items.push_back(i);
+    }
+    BHIP_TRY(b, hipMemcpyAsync(b->bin_start_dev, start.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice, b->stream));
+    BHIP_TRY(b, hipMemcpyAsync(b->bin_items_dev, items.data(), sizeof(int) * n, hipMemcpyHostToDevice, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    b->groups = G;
+    drop_graph(b);
+    return TWA_OK;
+}
+
+void launch_batch(twa_batch *b, int k, int first) {
+    dim3 grid(b->groups);
+    if (b->block == 1024)
+        hipLaunchKernelGGL(k_batch<1024>, grid, dim3(1024), 0, b->stream, (const Params *)b->insts_dev,
+                           (const int *)b->bin_start_dev, (const int *)b->bin_items_dev, k, first);
+    else if (b->block == 512)
+        hipLaunchKernelGGL(k_batch<512>, grid, dim3(512), 0, b->stream, (const Params *)b->insts_dev,
+                           (const int *)b->bin_start_dev, (const int *)b->bin_items_dev, k, first);
+    else
+        hipLaunchKernelGGL(k_batch<256>, grid, dim3(256), 0, b->stream, (const Params *)b->insts_dev,
+                           (const int *)b->bin_start_dev, (const int *)b->bin_items_dev, k, first);
+}
+
+} // namespace
+
+extern "C" {
+
+const char *twa_batch_last_error(const twa_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+void twa_batch_destroy(twa_batch *b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    for (twa_solver *s : b->solvers) twa_destroy(s);
+    if (b->insts_dev) (void)hipFree(b->insts_dev);
+    if (b->bin_start_dev) (void)hipFree(b->bin_start_dev);
+    if (b->bin_items_dev) (void)hipFree(b->bin_items_dev);
+    delete b;
+}
+
+twa_status twa_batch_create(int n, const twa_instance *inst, unsigned flags, void *hip_stream, twa_batch **out) {
+    if (!out || n < 1 || !inst) return TWA_E_INVALID;
+    *out = nullptr;
+    twa_batch *b = new (std::nothrow) twa_batch();
+    if (!b) return TWA_E_NOMEM;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    for (int i = 0; i < n; ++i) {
+        const twa_instance &I = inst[i];
+        twa_solver *s = nullptr;
+        twa_status st = twa_create(I.p, I.eta, I.dim, I.radii, I.x0, I.xT, I.n_walls, I.walls, I.C, I.rho0, I.alpha,
+                                   flags, hip_stream, &s);
+        if (st == TWA_OK && I.z0) {
+            st = twa_set_init(s, I.z0);
+            if (st != TWA_OK) twa_destroy(s);
+        }
+        if (st != TWA_OK) {
+            twa_batch_destroy(b);
+            return st;
+        }
+        b->solvers.push_back(s);
+    }
+    hipError_t e = hipMalloc(&b->insts_dev, sizeof(Params) * n);
+    if (e == hipSuccess) e = hipMalloc(&b->bin_start_dev, sizeof(int) * (n + 1));
+    if (e == hipSuccess) e = hipMalloc(&b->bin_items_dev, sizeof(int) * n);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        twa_batch_destroy(b);
+        return TWA_E_NOMEM;
+    }
+    std::vector<Params> h(n);
+    for (int i = 0; i < n; ++i) {
+        h[i] = b->solvers[i]->P;
+        h[i].dbg_x = nullptr;
+        h[i].dbg_rho = nullptr;
+    }
+    if (hipMemcpyAsync(b->insts_dev, h.data(), sizeof(Params) * n, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        batch_bins(b) != TWA_OK) {
+        twa_batch_destroy(b);
+        return TWA_E_DEVICE;
+    }
+    *out = b;
+    return TWA_OK;
+}
+
+twa_status twa_batch_config(twa_batch *b, int block, int groups) {
+    if (!b) return TWA_E_INVALID;
+    if (b->latched != TWA_OK) return b->latched;
+    if (block != 256 && block != 512 && block != 1024) return bfail(b, TWA_E_INVALID, "block must be 256, 512 or 1024");
+    if (groups < 1) return bfail(b, TWA_E_INVALID, "groups must be >= 1");
+    b->block = block;
+    b->groups = groups;
+    return batch_bins(b);
+}
+
+twa_status twa_batch_iterate(twa_batch *b, int k) {
+    if (!b) return TWA_E_INVALID;
+    if (b->latched != TWA_OK) return b->latched;
+    if (k < 0) return bfail(b, TWA_E_INVALID, "k must be >= 0");
+    if (k == 0) return TWA_OK;
+    bool any_pending = false, all_pending = true;
+    for (twa_solver *s : b->solvers) {
+        if (s->latched != TWA_OK) return bfail(b, s->latched, "an instance has a latched device error");
+        if (s->n_warm > 0 && s->iter < s->n_warm) return bfail(b, TWA_E_STATE, "batched instances take no rho0 schedule");
+        any_pending |= s->pending;
+        all_pending &= s->pending;
+    }
+    if (any_pending && !all_pending)
+        for (twa_solver *s : b->solvers)
+            if (finalize(s) != TWA_OK) return bfail(b, TWA_E_DEVICE, "finalize: " + s->err);
+    int first = all_pending ? 0 : 1;
+    if (!b->gexec || b->g_k != k || b->g_first != first) {
+        drop_graph(b);
+        hipGraph_t g = nullptr;
+        bool captured = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (captured) {
+            launch_batch(b, k, first);
+            captured = hipStreamEndCapture(b->stream, &g) == hipSuccess && g != nullptr;
+            if (captured) captured = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+        }
+        (void)hipGetLastError();
+        if (captured) {
+            b->g_k = k;
+            b->g_first = first;
+        } else {
+            b->gexec = nullptr;
+        }
+    }
+    if (b->gexec) {
+        BHIP_TRY(b, hipGraphLaunch(b->gexec, b->stream));
+    } else {
+        launch_batch(b, k, first);
+        BHIP_TRY(b, hipGetLastError());
+    }
+    for (twa_solver *s : b->solvers) {
+        s->pending = true;
+        s->iter += k;
+    }
+    return TWA_OK;
+}
+
+twa_status twa_batch_iterate_timed(twa_batch *b, int k, double *ms) {
+    if (!b || !ms) return TWA_E_INVALID;
+    hipEvent_t e0, e1;
+    BHIP_TRY(b, hipEventCreate(&e0));
+    BHIP_TRY(b, hipEventCreate(&e1));
+    (void)hipEventRecord(e0, b->stream);
+    twa_status st = twa_batch_iterate(b, k);
+    (void)hipEventRecord(e1, b->stream);
+    hipError_t e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t;
+    if (st != TWA_OK) return st;
+    if (e != hipSuccess) return bfail(b, TWA_E_DEVICE, std::string("batch timing: ") + hipGetErrorString(e));
+    return TWA_OK;
+}
+
+twa_status twa_batch_size(const twa_batch *b, int *n) {
+    if (!b || !n) return TWA_E_INVALID;
+    *n = (int)b->solvers.size();
+    return TWA_OK;
+}
+
+twa_status twa_batch_solver(twa_batch *b, int i, twa_solver **s) {
+    if (!b || !s || i < 0 || i >= (int)b->solvers.size()) return TWA_E_INVALID;
+    *s = b->solvers[i];
+    return TWA_OK;
+}
+
+twa_status twa_batch_get_trajectories(twa_batch *b, int i, float *z_out) {
+    if (!b || i < 0 || i >= (int)b->solvers.size()) return TWA_E_INVALID;
+    return twa_get_trajectories(b->solvers[i], z_out);
 }
 
 } // extern "C"

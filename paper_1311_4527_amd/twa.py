@@ -79,6 +79,24 @@ def load_library():
     lib.twa_destroy.argtypes = [_vp]
     lib.twa_version.restype = ct.c_char_p
     lib.twa_version.argtypes = []
+    lib.twa_batch_create.restype = ct.c_int
+    lib.twa_batch_create.argtypes = [ct.c_int, ct.c_void_p, ct.c_uint, _vp, ct.POINTER(_vp)]
+    lib.twa_batch_config.restype = ct.c_int
+    lib.twa_batch_config.argtypes = [_vp, ct.c_int, ct.c_int]
+    lib.twa_batch_iterate.restype = ct.c_int
+    lib.twa_batch_iterate.argtypes = [_vp, ct.c_int]
+    lib.twa_batch_iterate_timed.restype = ct.c_int
+    lib.twa_batch_iterate_timed.argtypes = [_vp, ct.c_int, ct.POINTER(ct.c_double)]
+    lib.twa_batch_size.restype = ct.c_int
+    lib.twa_batch_size.argtypes = [_vp, ct.POINTER(ct.c_int)]
+    lib.twa_batch_solver.restype = ct.c_int
+    lib.twa_batch_solver.argtypes = [_vp, ct.c_int, ct.POINTER(_vp)]
+    lib.twa_batch_get_trajectories.restype = ct.c_int
+    lib.twa_batch_get_trajectories.argtypes = [_vp, ct.c_int, _vp]
+    lib.twa_batch_last_error.restype = ct.c_char_p
+    lib.twa_batch_last_error.argtypes = [_vp]
+    lib.twa_batch_destroy.restype = None
+    lib.twa_batch_destroy.argtypes = [_vp]
     _lib = lib
     return lib
 
@@ -214,6 +232,104 @@ class Solver:
         self.stream.synchronize()
         self._keep_dbg = None
         return x, r
+
+
+class _Instance(ct.Structure):
+    _fields_ = [("p", ct.c_int), ("eta", ct.c_int), ("dim", ct.c_int), ("n_walls", ct.c_int),
+                ("radii", _vp), ("x0", _vp), ("xT", _vp), ("walls", _vp), ("C", _vp), ("z0", _vp),
+                ("rho0", ct.c_float), ("alpha", ct.c_float)]
+
+
+class _Borrowed(Solver):
+    """A solver owned by a batch (never destroyed from Python)."""
+
+    def __init__(self, h, inst, stream, device):
+        self.h = h
+        self.p, self.eta, self.dim = inst.p, inst.eta, inst.dim
+        self.device = device
+        self.stream = stream
+        self.n_walls = inst.n_walls
+        nf, ne = ct.c_longlong(), ct.c_longlong()
+        load_library().twa_sizes(self.h, ct.byref(nf), ct.byref(ne))
+        self.n_factors, self.n_edges = nf.value, ne.value
+
+    def close(self):
+        self.h = None
+
+
+class Batch:
+    """Many independent instances advanced by one persistent launch
+    (twa_batch_create ... twa_batch_destroy)."""
+
+    def __init__(self, instances, flags=0, stream: Optional[torch.cuda.Stream] = None, device="cuda"):
+        lib = load_library()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.instances = list(instances)
+        self._keep = []
+        arr = (_Instance * len(self.instances))()
+        for k, inst in enumerate(self.instances):
+            t = dict(radii=_dev(inst.radii, device=device), x0=_dev(inst.x0, device=device),
+                     xT=_dev(inst.xT, device=device), C=_dev(inst.C, device=device),
+                     z0=_dev(inst.z0, device=device),
+                     walls=_dev(inst.walls, device=device) if inst.n_walls else None)
+            self._keep.append(t)
+            arr[k] = _Instance(inst.p, inst.eta, inst.dim, inst.n_walls, _ptr(t["radii"]), _ptr(t["x0"]),
+                               _ptr(t["xT"]), _ptr(t["walls"]), _ptr(t["C"]), _ptr(t["z0"]),
+                               float(inst.rho0), float(inst.alpha))
+        h = ct.c_void_p()
+        st = lib.twa_batch_create(len(self.instances), ct.cast(arr, ct.c_void_p), int(flags),
+                                  ct.c_void_p(self.stream.cuda_stream), ct.byref(h))
+        if st != TWA_OK:
+            raise TWAError(st, "twa_batch_create failed")
+        self.h = h
+        self.stream.synchronize()
+
+    def _check(self, st):
+        if st != TWA_OK:
+            msg = load_library().twa_batch_last_error(self.h)
+            raise TWAError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().twa_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.instances)
+
+    def twa_batch_config(self, block: int, groups: int):
+        self._check(load_library().twa_batch_config(self.h, int(block), int(groups)))
+
+    def twa_batch_iterate(self, k: int):
+        self._check(load_library().twa_batch_iterate(self.h, int(k)))
+
+    def twa_batch_iterate_timed(self, k: int) -> float:
+        ms = ct.c_double()
+        self._check(load_library().twa_batch_iterate_timed(self.h, int(k), ct.byref(ms)))
+        return ms.value
+
+    def twa_batch_size(self) -> int:
+        n = ct.c_int()
+        self._check(load_library().twa_batch_size(self.h, ct.byref(n)))
+        return n.value
+
+    def twa_batch_get_trajectories(self, i: int) -> torch.Tensor:
+        inst = self.instances[i]
+        out = torch.empty((inst.p, inst.eta + 1, inst.dim), dtype=torch.float32, device=self.device)
+        self._check(load_library().twa_batch_get_trajectories(self.h, int(i), _ptr(out)))
+        return out
+
+    def twa_batch_solver(self, i: int) -> Solver:
+        h = ct.c_void_p()
+        self._check(load_library().twa_batch_solver(self.h, int(i), ct.byref(h)))
+        return _Borrowed(h, self.instances[i], self.stream, self.device)
 
 
 def twa_version() -> str:
