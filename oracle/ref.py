@@ -63,6 +63,10 @@ def _load():
     lib.tor_iterate.argtypes = [ct.c_void_p, ct.c_long]
     lib.tor_get_margins.restype = None
     lib.tor_get_margins.argtypes = [ct.c_void_p, _dp, _dp]
+    lib.tor_tape.restype = ct.c_long
+    lib.tor_tape.argtypes = [ct.c_void_p, ct.c_long]
+    lib.tor_backward.restype = None
+    lib.tor_backward.argtypes = [ct.c_void_p, _dp, _dp, _dp, _dp, _dp]
     lib.tor_objective.restype = ct.c_double
     lib.tor_objective.argtypes = [ct.c_void_p]
     lib.tor_min_clearance.restype = ct.c_double
@@ -215,6 +219,24 @@ class Planner:
 
     def iterate(self, k: int):
         _load().tor_iterate(self.h, int(k))
+
+    def tape(self, k: int):
+        """Run k iterations keeping every state for :meth:`backward`."""
+        got = _load().tor_tape(self.h, int(k))
+        if got != k:
+            raise MemoryError("tape allocation failed")
+
+    def backward(self, dz):
+        """Gradient of L(z^K) after :meth:`tape`, given dL/dz^K [p][eta+1][dim]:
+        returns (dx0 [p][dim], dxT [p][dim], dr [p], dz0 [p][eta+1][dim], interior only)."""
+        dz = np.ascontiguousarray(dz, dtype=np.float64).reshape(self.N, self.dim)
+        dx0 = np.zeros((self.p, self.dim))
+        dxT = np.zeros((self.p, self.dim))
+        dr = np.zeros(self.p)
+        dz0 = np.zeros((self.N, self.dim))
+        _load().tor_backward(self.h, dz.ctypes.data_as(_dp), dx0.ctypes.data_as(_dp), dxT.ctypes.data_as(_dp),
+                             dr.ctypes.data_as(_dp), dz0.ctypes.data_as(_dp))
+        return dx0, dxT, dr, dz0.reshape(self.p, self.eta + 1, self.dim)
 
     @property
     def iteration(self) -> int:

@@ -777,6 +777,13 @@ typedef struct {
     double *z, *u, *x, *n, *m; /* z: [N][dim]; others [E][dim] */
     unsigned char *rout;  /* ->rho per edge */
     unsigned char *rin;   /* <-rho per edge */
+    /* reverse-mode tape: every iteration's state (small instances only) */
+    int taping;
+    long tape_len, tape_cap;
+    double *tape_z, *tape_u;          /* [t][N*dim], [t][E*dim] state before iteration t */
+    unsigned char *tape_rin, *tape_rout; /* [t][E] <-rho used by iteration t, ->rho it produced */
+    unsigned char *tape_rin_next;     /* [E] <-rho after the last taped iteration */
+    double tape_rho[4096];            /* rho0 of each taped iteration (schedule) */
     double *act_margin;   /* |closest approach - R| / R of the last activity test, per factor */
     double *tie_margin;   /* relative energy gap to the runner-up candidate, per factor */
 } tor_t;
@@ -887,6 +894,7 @@ void tor_destroy(void *h) {
     free(T->enode), free(T->adj_off), free(T->adj);
     free(T->z), free(T->u), free(T->x), free(T->n), free(T->m), free(T->rout), free(T->rin);
     free(T->act_margin), free(T->tie_margin);
+    free(T->tape_z), free(T->tape_u), free(T->tape_rin), free(T->tape_rout), free(T->tape_rin_next);
     free(T);
 }
 
@@ -990,6 +998,13 @@ static void one_iteration(tor_t *T) {
     int dim = T->dim;
     double rho = (T->iter < T->n_warm) ? T->rho0_init : T->rho0;
     long E = T->E, N = T->N, F = T->F;
+    if (T->taping && T->tape_len < T->tape_cap) {
+        long t = T->tape_len;
+        memcpy(T->tape_z + t * N * dim, T->z, sizeof(double) * N * dim);
+        memcpy(T->tape_u + t * E * dim, T->u, sizeof(double) * E * dim);
+        memcpy(T->tape_rin + t * E, T->rin, E);
+        T->tape_rho[t] = rho;
+    }
     /* 1. n = z - u */
 #pragma omp parallel for schedule(static)
     for (long e = 0; e < E; e++)
@@ -1039,6 +1054,11 @@ static void one_iteration(tor_t *T) {
             for (int k = 0; k < dim; k++) T->u[e * dim + k] = 0;
         }
     }
+    if (T->taping && T->tape_len < T->tape_cap) {
+        memcpy(T->tape_rout + T->tape_len * E, T->rout, E);
+        memcpy(T->tape_rin_next, T->rin, E);
+        T->tape_len++;
+    }
     T->iter++;
 }
 
@@ -1086,4 +1106,196 @@ double tor_min_clearance(int p, int eta, int dim, const double *radii, const dou
         }
     }
     return best;
+}
+
+/* ======================================================================== */
+/* Reverse mode of K unrolled iterations (test reference of the adjoint)     */
+/* ======================================================================== */
+/*
+ * tor_tape(h, K) runs K iterations from the current state and keeps every
+ * iteration's state.  tor_backward(h, dz, ...) then returns the gradient of
+ * L(z^K) given dL/dz^K, with respect to the start and goal positions, the
+ * radii and the initial break-points, holding every discrete decision of
+ * the forward run fixed (weights, minimiser configuration).
+ *
+ * The reverse sweep follows App. B backwards, per iteration:
+ *   step 7  u' = u + s (x - z') on edges whose ->rho and new <-rho are rho0,
+ *           else 0   (s = alpha/rho0)
+ *   step 5  z' = weighted mean of m over the edges that carried weight
+ *   step 4  m = x + u
+ *   step 2  x = g(n): each minimiser's local Jacobian (with respect to its
+ *           n-messages and its radius) by FP64 central differences; the
+ *           energy minimiser is linear in n; a fixed factor's x is the
+ *           start or goal itself
+ *   step 1  n = z - u
+ */
+static void coll_eval(tor_t *T, long f, const double *nin, double R, const double *w, double *xout) {
+    int dim = T->dim;
+    tor_prox_coll(nin, nin + dim, nin + 2 * dim, nin + 3 * dim, w[0], w[1], w[2], w[3], R, dim, xout, xout + dim,
+                  xout + 2 * dim, xout + 3 * dim, NULL, NULL);
+    (void)f;
+}
+
+static void wall_eval(tor_t *T, long f, const double *nin, double r, const double *w, double *xout) {
+    const double *wa = T->walls + T->fw[f] * 4, *wb = wa + 2;
+    tor_prox_capsule(wa, wb, r, nin, nin + 2, w[0], w[1], xout, xout + 2, NULL, NULL);
+}
+
+long tor_tape(void *h, long K) {
+    tor_t *T = (tor_t *)h;
+    long N = T->N, E = T->E;
+    int dim = T->dim;
+    if (K > 4096) K = 4096;
+    free(T->tape_z), free(T->tape_u), free(T->tape_rin), free(T->tape_rout), free(T->tape_rin_next);
+    T->tape_z = (double *)malloc(sizeof(double) * (K + 1) * N * dim);
+    T->tape_u = (double *)malloc(sizeof(double) * (K + 1) * E * dim);
+    T->tape_rin = (unsigned char *)malloc((size_t)(K + 1) * E);
+    T->tape_rout = (unsigned char *)malloc((size_t)(K + 1) * E);
+    T->tape_rin_next = (unsigned char *)malloc((size_t)E);
+    if (!T->tape_z || !T->tape_u || !T->tape_rin || !T->tape_rout || !T->tape_rin_next) return -1;
+    T->tape_len = 0;
+    T->tape_cap = K;
+    T->taping = 1;
+    tor_iterate(h, K);
+    T->taping = 0;
+    return T->tape_len;
+}
+
+/* dz [N][dim] = dL/dz^K (node order i*(eta+1)+s).  Outputs (accumulated,
+ * caller zeroes them): dx0, dxT [p][dim], dr [p], dz0 [N][dim]. */
+void tor_backward(void *h, const double *dz, double *dx0, double *dxT, double *dr, double *dz0) {
+    tor_t *T = (tor_t *)h;
+    long N = T->N, E = T->E, F = T->F;
+    int dim = T->dim;
+    double *zb = (double *)calloc(N * dim, sizeof(double));   /* adjoint of z^{k+1} */
+    double *ub = (double *)calloc(E * dim, sizeof(double));   /* adjoint of u^{k+1} */
+    double *xb = (double *)calloc(E * dim, sizeof(double));
+    double *ubn = (double *)calloc(E * dim, sizeof(double));
+    double *zbn = (double *)calloc(N * dim, sizeof(double));
+    double *zhat = (double *)calloc(N * dim, sizeof(double));
+    double *n = (double *)calloc(E * dim, sizeof(double));
+    memcpy(zb, dz, sizeof(double) * N * dim);
+    for (long t = T->tape_len - 1; t >= 0; t--) {
+        const double *z = T->tape_z + t * N * dim, *u = T->tape_u + t * E * dim;
+        const unsigned char *rin = T->tape_rin + t * E, *rout = T->tape_rout + t * E;
+        const unsigned char *rin1 = (t + 1 < T->tape_len) ? T->tape_rin + (t + 1) * E : T->tape_rin_next;
+        double rho = T->tape_rho[t], s = T->alpha / rho;
+        for (long e = 0; e < E; e++)
+            for (int k = 0; k < dim; k++) n[e * dim + k] = z[T->enode[e] * dim + k] - u[e * dim + k];
+        /* step 7 */
+        memcpy(zhat, zb, sizeof(double) * N * dim);
+        for (long e = 0; e < E; e++) {
+            int a = rout[e] == TOR_STD && rin1[e] == TOR_STD;
+            for (int k = 0; k < dim; k++) {
+                double g = a ? ub[e * dim + k] : 0.0;
+                xb[e * dim + k] = s * g;
+                ubn[e * dim + k] = g;
+                zhat[T->enode[e] * dim + k] -= s * g;
+            }
+        }
+        /* step 5 and 4 */
+        for (long j = 0; j < N; j++) {
+            long a0 = T->adj_off[j], a1 = T->adj_off[j + 1];
+            int ninf = 0, nstd = 0;
+            for (long q = a0; q < a1; q++) {
+                unsigned char w = rout[T->adj[q]];
+                ninf += (w == TOR_INF);
+                nstd += (w == TOR_STD);
+            }
+            double wsum = 0;
+            for (long q = a0; q < a1; q++) {
+                unsigned char w = rout[T->adj[q]];
+                wsum += ninf ? (w == TOR_INF) : (nstd ? (w == TOR_STD) * rho : 1.0);
+            }
+            for (long q = a0; q < a1; q++) {
+                long e = T->adj[q];
+                unsigned char w = rout[e];
+                double wv = ninf ? (w == TOR_INF) : (nstd ? (w == TOR_STD) * rho : 1.0);
+                if (wv == 0) continue;
+                for (int k = 0; k < dim; k++) {
+                    double mb = zhat[j * dim + k] * wv / wsum;
+                    xb[e * dim + k] += mb;
+                    ubn[e * dim + k] += mb;
+                }
+            }
+        }
+        /* step 2 and 1 */
+        memset(zbn, 0, sizeof(double) * N * dim);
+        for (long f = 0; f < F; f++) {
+            long e0 = T->fe0[f], ne = T->fe0[f + 1] - e0;
+            int tp = T->ftype[f];
+            double nb[12];
+            for (int q = 0; q < ne * dim; q++) nb[q] = 0;
+            if (tp == TOR_F_FIXED) {
+                double *dst = (T->fs[f] == 0) ? dx0 : dxT;
+                for (int k = 0; k < dim; k++) dst[T->fa[f] * dim + k] += xb[e0 * dim + k];
+            } else if (tp == TOR_F_ENERGY) {
+                double C = T->C[T->fa[f] * T->eta + T->fs[f]];
+                double wl = weight_value(T, rin[e0], rho), wh = weight_value(T, rin[e0 + 1], rho);
+                int both0 = rin[e0] == TOR_ZERO && rin[e0 + 1] == TOR_ZERO;
+                /* the minimiser is linear in n: its Jacobian from unit inputs */
+                for (int c = 0; c < 2; c++) {
+                    double a[3] = {0, 0, 0}, b[3] = {0, 0, 0}, xl[3], xh[3];
+                    if (c == 0) a[0] = 1; else b[0] = 1;
+                    tor_prox_energy(a, b, both0 ? 0.0 : wl, both0 ? 0.0 : wh, C, 1, xl, xh);
+                    for (int k = 0; k < dim; k++)
+                        nb[c * dim + k] = xl[0] * xb[e0 * dim + k] + xh[0] * xb[(e0 + 1) * dim + k];
+                }
+            } else {
+                int act = rout[e0] == TOR_STD;
+                if (!act) {
+                    for (int q = 0; q < ne * dim; q++) nb[q] = xb[e0 * dim + q];
+                } else {
+                    int nin = (int)(ne * dim);
+                    double w[4], R;
+                    for (int q = 0; q < ne; q++) w[q] = weight_value(T, rin[e0 + q], rho);
+                    if (tp == TOR_F_COLL) R = T->radii[T->fa[f]] + T->radii[T->fb[f]];
+                    else R = T->radii[T->fa[f]];
+                    double base[12], xp[12], xm[12];
+                    for (int q = 0; q < nin; q++) base[q] = n[e0 * dim + q];
+                    double sc = 1e-6;
+                    for (int q = 0; q <= nin; q++) {
+                        double in_p[12], in_m[12], Rp = R, Rm = R;
+                        memcpy(in_p, base, sizeof(double) * nin);
+                        memcpy(in_m, base, sizeof(double) * nin);
+                        if (q < nin) in_p[q] += sc, in_m[q] -= sc;
+                        else Rp += sc, Rm -= sc;
+                        if (tp == TOR_F_COLL) {
+                            coll_eval(T, f, in_p, Rp, w, xp);
+                            coll_eval(T, f, in_m, Rm, w, xm);
+                        } else {
+                            wall_eval(T, f, in_p, Rp, w, xp);
+                            wall_eval(T, f, in_m, Rm, w, xm);
+                        }
+                        double g = 0;
+                        for (int o = 0; o < nin; o++) g += (xp[o] - xm[o]) / (2 * sc) * xb[e0 * dim + o];
+                        if (q < nin) nb[q] = g;
+                        else if (tp == TOR_F_COLL) dr[T->fa[f]] += g, dr[T->fb[f]] += g;
+                        else dr[T->fa[f]] += g;
+                    }
+                }
+            }
+            for (long q = 0; q < ne; q++) {
+                long e = e0 + q;
+                for (int k = 0; k < dim; k++) {
+                    zbn[T->enode[e] * dim + k] += nb[q * dim + k];
+                    ubn[e * dim + k] -= nb[q * dim + k];
+                }
+            }
+        }
+        memcpy(zb, zbn, sizeof(double) * N * dim);
+        memcpy(ub, ubn, sizeof(double) * E * dim);
+    }
+    /* z^0: its end points are x(0) and x(T) */
+    for (int i = 0; i < T->p; i++)
+        for (int k = 0; k < dim; k++) {
+            dx0[i * dim + k] += zb[node_id(T, i, 0) * dim + k];
+            dxT[i * dim + k] += zb[node_id(T, i, T->eta) * dim + k];
+        }
+    for (long j = 0; j < N; j++) {
+        int sj = (int)(j % (T->eta + 1));
+        if (sj == 0 || sj == T->eta) continue;
+        for (int k = 0; k < dim; k++) dz0[j * dim + k] += zb[j * dim + k];
+    }
+    free(zb), free(ub), free(xb), free(ubn), free(zbn), free(zhat), free(n);
 }
