@@ -240,6 +240,14 @@ TWA_HD Eig2 piece_quadratic(f2 m0, f2 m1, float w0, float w1, float r) {
     return eig2(a, c, e, b);
 }
 
+// Which candidate a minimiser chose (for its derivative).
+enum : int { CH_NONE = 0, CH_T = 1, CH_R0 = 2, CH_R1 = 3, CH_TAN = 4, CH_RADF = 5, CH_FLAT = 6 };
+struct Choice {
+    int kind; // CH_*
+    f2 u;     // unit normal of the separating line
+    f2 c;     // centre of the arc the configuration rests on (disk: origin)
+};
+
 // ---------------------------------------------------------------------------
 // Disk (collision) minimiser on the difference variables (App. C, I):
 // min (w0/2)|v0 - m0|^2 + (w1/2)|v1 - m1|^2  s.t.  dist(0, [v0, v1]) >= R.
@@ -264,9 +272,14 @@ TWA_HD int tangent_normals(f2 q, f2 c, float r, f2 *out) {
     return 2;
 }
 
-TWA_HD void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R, f2 &v0,
-                                          f2 &v1) {
+TWA_HD void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R, f2 &v0, f2 &v1,
+                      Choice *ch = nullptr) {
     bool i0 = k0 == W_INF, i1 = k1 == W_INF;
+    if (ch) {
+        ch->kind = CH_NONE;
+        ch->u = mk(1.f, 0.f);
+        ch->c = mk(0.f, 0.f);
+    }
     if (i0 && i1) {
         v0 = m0;
         v1 = m1;
@@ -275,19 +288,26 @@ TWA_HD void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R,
     if (i0 || i1) {
         f2 q = i0 ? m0 : m1, m = i0 ? m1 : m0;
         f2 cand[3];
+        int kind[3];
         int nc = tangent_normals(q, mk(0.f, 0.f), R, cand);
+        kind[0] = kind[1] = CH_TAN;
         float mm = dot(m, m);
         if (mm > 0.f) {
             f2 u = scl(m, inv_sqrt(mm));
-            if (dot(q, u) >= R) cand[nc++] = u;
+            if (dot(q, u) >= R) {
+                kind[nc] = CH_RADF;
+                cand[nc++] = u;
+            }
         }
         f2 best = mk(1.f, 0.f);
+        int bk = CH_NONE;
         float bg = INFINITY;
         for (int k = 0; k < nc; ++k) {
             float g = pos(R - dot(m, cand[k]));
             if (g < bg) {
                 bg = g;
                 best = cand[k];
+                bk = kind[k];
             }
         }
         f2 vm = (bg < INFINITY) ? add(m, scl(best, bg)) : m;
@@ -298,27 +318,44 @@ TWA_HD void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R,
             v1 = m1;
             v0 = vm;
         }
+        if (ch) {
+            ch->kind = bk;
+            ch->u = best;
+        }
         return;
     }
     Eig2 g = piece_quadratic(m0, m1, w0, w1, R);
     f2 cand[4];
+    int kind[4] = {CH_T, CH_T, CH_T, CH_T};
     f2 alt;
     int nc = trs_global(g, cand, &alt);
     if (nc == 2) cand[1] = alt;
     float q0 = dot(m0, m0), q1 = dot(m1, m1);
-    if (q0 > 0.f && q0 < R * R) cand[nc++] = scl(m0, inv_sqrt(q0));
-    if (q1 > 0.f && q1 < R * R) cand[nc++] = scl(m1, inv_sqrt(q1));
+    if (q0 > 0.f && q0 < R * R) {
+        kind[nc] = CH_R0;
+        cand[nc++] = scl(m0, inv_sqrt(q0));
+    }
+    if (q1 > 0.f && q1 < R * R) {
+        kind[nc] = CH_R1;
+        cand[nc++] = scl(m1, inv_sqrt(q1));
+    }
     f2 best = cand[0];
+    int bk = kind[0];
     float bF = disk_F(cand[0], m0, m1, w0, w1, R);
     for (int k = 1; k < nc; ++k) {
         float Fk = disk_F(cand[k], m0, m1, w0, w1, R);
         if (Fk < bF) {
             bF = Fk;
             best = cand[k];
+            bk = kind[k];
         }
     }
     v0 = add(m0, scl(best, pos(R - dot(m0, best))));
     v1 = add(m1, scl(best, pos(R - dot(m1, best))));
+    if (ch) {
+        ch->kind = bk;
+        ch->u = best;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -342,9 +379,14 @@ TWA_HD f2 closest_on_seg(f2 q, f2 a, f2 b) {
     return add(a, scl(d, t));
 }
 
-TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int k0, int k1, f2 &x0,
-                                          f2 &x1) {
+TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int k0, int k1, f2 &x0, f2 &x1,
+                         Choice *ch = nullptr) {
     bool i0 = k0 == W_INF, i1 = k1 == W_INF;
+    if (ch) {
+        ch->kind = CH_NONE;
+        ch->u = mk(1.f, 0.f);
+        ch->c = C.a;
+    }
     if (i0 && i1) {
         x0 = n0;
         x1 = n1;
@@ -355,22 +397,39 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
     bool seg = L2 > 0.f;
     f2 sw = seg ? scl(perp(d), inv_sqrt(L2)) : mk(0.f, 1.f);
     f2 cand[16];
+    int kind[16];
+    unsigned char ctr[16]; // 0: centre a, 1: centre b
     int nc = 0;
     if (i0 || i1) {
         // one end certain: the other moves along normals u visible from it
         f2 q = i0 ? n0 : n1, m = i0 ? n1 : n0;
-        nc += tangent_normals(q, C.a, C.r, cand + nc);
-        if (seg) nc += tangent_normals(q, C.b, C.r, cand + nc);
+        int na = tangent_normals(q, C.a, C.r, cand + nc);
+        for (int k = 0; k < na; ++k) kind[nc + k] = CH_TAN, ctr[nc + k] = 0;
+        nc += na;
+        if (seg) {
+            int nb = tangent_normals(q, C.b, C.r, cand + nc);
+            for (int k = 0; k < nb; ++k) kind[nc + k] = CH_TAN, ctr[nc + k] = 1;
+            nc += nb;
+        }
         f2 t0 = sub(m, C.a);
-        if (dot(t0, t0) > 0.f) cand[nc++] = scl(t0, inv_sqrt(dot(t0, t0)));
+        if (dot(t0, t0) > 0.f) {
+            kind[nc] = CH_RADF, ctr[nc] = 0;
+            cand[nc++] = scl(t0, inv_sqrt(dot(t0, t0)));
+        }
         if (seg) {
             f2 t1 = sub(m, C.b);
-            if (dot(t1, t1) > 0.f) cand[nc++] = scl(t1, inv_sqrt(dot(t1, t1)));
+            if (dot(t1, t1) > 0.f) {
+                kind[nc] = CH_RADF, ctr[nc] = 1;
+                cand[nc++] = scl(t1, inv_sqrt(dot(t1, t1)));
+            }
+            kind[nc] = CH_FLAT, ctr[nc] = 0;
             cand[nc++] = sw;
+            kind[nc] = CH_FLAT, ctr[nc] = 0;
             cand[nc++] = scl(sw, -1.f);
         }
         float tol = 1e-5f * (fabsf(q.x) + fabsf(q.y) + C.r);
         f2 best = mk(1.f, 0.f);
+        int bi = -1;
         float bg = INFINITY;
         for (int k = 0; k < nc; ++k) {
             float h = cap_h(C, cand[k]);
@@ -379,6 +438,7 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
             if (g < bg) {
                 bg = g;
                 best = cand[k];
+                bi = k;
             }
         }
         f2 xm = (bg < INFINITY) ? add(m, scl(best, bg)) : m;
@@ -389,6 +449,11 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
             x1 = n1;
             x0 = xm;
         }
+        if (ch && bi >= 0) {
+            ch->kind = kind[bi];
+            ch->u = best;
+            ch->c = ctr[bi] ? C.b : C.a;
+        }
         return;
     }
     // (a) stationary points of each smooth piece
@@ -396,36 +461,163 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
         f2 c = pc ? C.b : C.a;
         Eig2 g = piece_quadratic(sub(n0, c), sub(n1, c), w0, w1, C.r);
         f2 alt;
+        int k0n = nc;
         int k = trs_global(g, cand + nc, &alt);
         nc += 1;
         if (k == 2) cand[nc++] = alt;
         nc += trs_middle(g, cand + nc);
+        for (int q = k0n; q < nc; ++q) kind[q] = CH_T, ctr[q] = (unsigned char)pc;
     }
     // (c) kinks: slab against a flat side
     if (seg) {
+        kind[nc] = CH_FLAT, ctr[nc] = 0;
         cand[nc++] = sw;
+        kind[nc] = CH_FLAT, ctr[nc] = 0;
         cand[nc++] = scl(sw, -1.f);
     }
     // (b) nearest boundary point of one end
     for (int e = 0; e < 2; ++e) {
         f2 n = e ? n1 : n0;
+        float tpar = seg ? fminf(fmaxf(dot(sub(n, C.a), d) / L2, 0.f), 1.f) : 0.f;
         f2 c = closest_on_seg(n, C.a, C.b);
         f2 t = sub(n, c);
         float tt = dot(t, t);
-        if (tt > 0.f && tt < C.r * C.r) cand[nc++] = scl(t, inv_sqrt(tt));
+        if (tt > 0.f && tt < C.r * C.r) {
+            kind[nc] = (tpar > 0.f && tpar < 1.f) ? CH_FLAT : (e ? CH_R1 : CH_R0);
+            ctr[nc] = (seg && tpar >= 1.f) ? 1 : 0;
+            cand[nc++] = scl(t, inv_sqrt(tt));
+        }
     }
     f2 best = cand[0];
+    int bi = 0;
     float bF = cap_F(C, cand[0], n0, n1, w0, w1);
     for (int k = 1; k < nc; ++k) {
         float Fk = cap_F(C, cand[k], n0, n1, w0, w1);
         if (Fk < bF) {
             bF = Fk;
             best = cand[k];
+            bi = k;
         }
     }
     float h = cap_h(C, best);
     x0 = add(n0, scl(best, pos(h - dot(n0, best))));
     x1 = add(n1, scl(best, pos(h - dot(n1, best))));
+    if (ch) {
+        ch->kind = kind[bi];
+        ch->u = best;
+        ch->c = ctr[bi] ? C.b : C.a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Derivatives (vector-Jacobian products) of the minimisers, holding the
+// chosen candidate fixed.  The tangent family's optimal direction theta*
+// depends on the inputs through E_theta(theta*, m, R) = 0 (implicit function
+// theorem: dtheta = -E_theta,q dq / E_theta,theta).
+// ---------------------------------------------------------------------------
+
+// v_k = m_k + g_k u, g_k = max(0, R - <m_k, u>), around the origin.
+// Given vb_k = dL/dv_k returns mb_k = dL/dm_k (added) and dL/dR (added).
+TWA_HD void disk_vjp(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R, const Choice &ch, f2 vb0, f2 vb1,
+                     f2 &mb0, f2 &mb1, float &Rb) {
+    f2 u = ch.u, up = perp(u);
+    bool i0 = k0 == W_INF, i1 = k1 == W_INF;
+    if (ch.kind == CH_NONE) {
+        mb0 = add(mb0, vb0);
+        mb1 = add(mb1, vb1);
+        return;
+    }
+    if (ch.kind == CH_TAN || ch.kind == CH_RADF) {
+        // one certain end q stays; the free end m moves
+        f2 q = i0 ? m0 : m1, m = i0 ? m1 : m0;
+        f2 vq = i0 ? vb0 : vb1, vm = i0 ? vb1 : vb0;
+        f2 qb = vq, mb;
+        float g = R - dot(m, u);
+        float a = g > 0.f ? 1.f : 0.f;
+        if (ch.kind == CH_TAN) {
+            // u on a tangent through q: <q, u(theta)> = R
+            f2 du_b = scl(sub(scl(vm, g), scl(m, dot(u, vm))), a);
+            float thb = dot(up, du_b);
+            float qu = dot(q, up);
+            float inv = fabsf(qu) > 1e-30f ? 1.f / qu : 0.f;
+            mb = sub(vm, scl(u, a * dot(u, vm)));
+            Rb += a * dot(u, vm) + thb * inv;
+            qb = sub(qb, scl(u, thb * inv));
+        } else {
+            float L = sqrtf(dot(m, m));
+            if (a > 0.f && L > 0.f) {
+                // v = R m/|m|
+                mb = scl(sub(vm, scl(u, dot(u, vm))), R / L);
+                Rb += dot(u, vm);
+            } else {
+                mb = vm;
+            }
+        }
+        if (i0) {
+            mb0 = add(mb0, qb);
+            mb1 = add(mb1, mb);
+        } else {
+            mb1 = add(mb1, qb);
+            mb0 = add(mb0, mb);
+        }
+        return;
+    }
+    float g0 = R - dot(m0, u), g1 = R - dot(m1, u);
+    float a0 = g0 > 0.f ? 1.f : 0.f, a1 = g1 > 0.f ? 1.f : 0.f;
+    if (ch.kind == CH_T) {
+        f2 r0 = sub(vb0, scl(u, a0 * dot(u, vb0)));
+        f2 r1 = sub(vb1, scl(u, a1 * dot(u, vb1)));
+        Rb += a0 * dot(u, vb0) + a1 * dot(u, vb1);
+        float p0 = dot(m0, up), p1 = dot(m1, up);
+        float thb = a0 * dot(sub(scl(up, g0), scl(u, p0)), vb0) + a1 * dot(sub(scl(up, g1), scl(u, p1)), vb1);
+        float Ett = w0 * a0 * (p0 * p0 + g0 * dot(m0, u)) + w1 * a1 * (p1 * p1 + g1 * dot(m1, u));
+        float c = fabsf(Ett) > 1e-30f ? -thb / Ett : 0.f;
+        // dE_theta/dm_k = w_k a_k (<m_k,up> u - g_k up);  dE_theta/dR = -sum w_k a_k <m_k,up>
+        r0 = add(r0, scl(sub(scl(u, p0), scl(up, g0)), c * w0 * a0));
+        r1 = add(r1, scl(sub(scl(u, p1), scl(up, g1)), c * w1 * a1));
+        Rb += c * (-(w0 * a0 * p0 + w1 * a1 * p1));
+        mb0 = add(mb0, r0);
+        mb1 = add(mb1, r1);
+        return;
+    }
+    // radial: u = m_e/|m_e| for end e, the other end pushed along u if needed
+    bool e1 = ch.kind == CH_R1;
+    f2 me = e1 ? m1 : m0, mo = e1 ? m0 : m1;
+    f2 ve = e1 ? vb1 : vb0, vo = e1 ? vb0 : vb1;
+    float go = e1 ? g0 : g1, ao = e1 ? a0 : a1;
+    float L = sqrtf(dot(me, me));
+    f2 ub = add(scl(ve, R), scl(sub(scl(vo, go), scl(mo, dot(u, vo))), ao));
+    Rb += dot(u, ve) + ao * dot(u, vo);
+    f2 mbo = sub(vo, scl(u, ao * dot(u, vo)));
+    f2 mbe = L > 0.f ? scl(sub(ub, scl(u, dot(u, ub))), 1.f / L) : mk(0.f, 0.f);
+    if (e1) {
+        mb1 = add(mb1, mbe);
+        mb0 = add(mb0, mbo);
+    } else {
+        mb0 = add(mb0, mbe);
+        mb1 = add(mb1, mbo);
+    }
+}
+
+// x_k = n_k + g_k u around the capsule: arc kinds reduce to the disk at the
+// chosen centre; a flat side keeps u fixed.
+TWA_HD void capsule_vjp(const Capsule C, f2 n0, f2 n1, float w0, float w1, int k0, int k1, const Choice &ch, f2 xb0,
+                        f2 xb1, f2 &nb0, f2 &nb1, float &rb) {
+    if (ch.kind == CH_FLAT) {
+        f2 u = ch.u;
+        float h = cap_h(C, u);
+        for (int e = 0; e < 2; ++e) {
+            f2 n = e ? n1 : n0, xb = e ? xb1 : xb0;
+            bool fixed = (e ? k1 : k0) == W_INF;
+            float a = (!fixed && h - dot(n, u) > 0.f) ? 1.f : 0.f;
+            f2 r = sub(xb, scl(u, a * dot(u, xb)));
+            rb += a * dot(u, xb);
+            if (e) nb1 = add(nb1, r);
+            else nb0 = add(nb0, r);
+        }
+        return;
+    }
+    disk_vjp(sub(n0, ch.c), sub(n1, ch.c), w0, w1, k0, k1, C.r, ch, xb0, xb1, nb0, nb1, rb);
 }
 
 // ---------------------------------------------------------------------------
@@ -471,7 +663,7 @@ TWA_HD void pair_rebuild(float r, float rp, int k, int kp, float n, float np, fl
 // Full collision minimiser (App. C): n, weights -> x.  D == 3 solves in the
 // plane spanned by the two difference vectors (the optimum lies there).
 template <int D>
-TWA_HD void coll_prox(const float *n, const float *w, const int *k, float R, float *x) {
+TWA_HD void coll_prox(const float *n, const float *w, const int *k, float R, float *x, Choice *ch = nullptr) {
     float om_l, om_h;
     int ko_l, ko_h;
     pair_weight(w[0], w[2], k[0], k[2], om_l, ko_l);
@@ -481,7 +673,7 @@ TWA_HD void coll_prox(const float *n, const float *w, const int *k, float R, flo
         f2 ml = mk(n[4] - n[0], n[5] - n[1]);
         f2 mh = mk(n[6] - n[2], n[7] - n[3]);
         f2 a, b;
-        disk_prox(ml, mh, om_l, om_h, ko_l, ko_h, R, a, b);
+        disk_prox(ml, mh, om_l, om_h, ko_l, ko_h, R, a, b, ch);
         vl[0] = a.x, vl[1] = a.y, vh[0] = b.x, vh[1] = b.y;
     } else {
         float ml[3] = {n[6] - n[0], n[7] - n[1], n[8] - n[2]};
@@ -519,6 +711,72 @@ TWA_HD void coll_prox(const float *n, const float *w, const int *k, float R, flo
     for (int c = 0; c < D; ++c) {
         pair_rebuild(w[0], w[2], k[0], k[2], n[c], n[2 * D + c], vl[c], x[c], x[2 * D + c]);
         pair_rebuild(w[1], w[3], k[1], k[3], n[D + c], n[3 * D + c], vh[c], x[D + c], x[3 * D + c]);
+    }
+}
+
+
+// VJP of pair_rebuild for one coordinate: x = a n + b np - b v, xp = x + v.
+TWA_HD void pair_rebuild_vjp(float r, float rp, int k, int kp, float xb, float xpb, float &nb, float &npb, float &vb) {
+    if (k == W_INF && kp == W_INF) {
+        nb += xb;
+        npb += xpb;
+        vb = 0.f;
+    } else if (k == W_INF) {
+        nb += xb + xpb;
+        vb = xpb;
+    } else if (kp == W_INF) {
+        npb += xb + xpb;
+        vb = -xb;
+    } else {
+        float a = r / (r + rp), b = rp / (r + rp);
+        nb += a * (xb + xpb);
+        npb += b * (xb + xpb);
+        vb = -b * xb + (1.f - b) * xpb;
+    }
+}
+
+// VJP of the planar collision minimiser: xb [8] -> nb [8] (added), Rb (added).
+TWA_HD void coll_vjp2(const float *n, const float *w, const int *k, float R, const float *xb, float *nb, float &Rb) {
+    float x[8];
+    Choice ch;
+    coll_prox<2>(n, w, k, R, x, &ch);
+    float om_l, om_h;
+    int ko_l, ko_h;
+    pair_weight(w[0], w[2], k[0], k[2], om_l, ko_l);
+    pair_weight(w[1], w[3], k[1], k[3], om_h, ko_h);
+    float vl[2], vh[2];
+    for (int c = 0; c < 2; ++c) {
+        pair_rebuild_vjp(w[0], w[2], k[0], k[2], xb[c], xb[4 + c], nb[c], nb[4 + c], vl[c]);
+        pair_rebuild_vjp(w[1], w[3], k[1], k[3], xb[2 + c], xb[6 + c], nb[2 + c], nb[6 + c], vh[c]);
+    }
+    f2 ml = mk(n[4] - n[0], n[5] - n[1]);
+    f2 mh = mk(n[6] - n[2], n[7] - n[3]);
+    f2 mbl = mk(0.f, 0.f), mbh = mk(0.f, 0.f);
+    disk_vjp(ml, mh, om_l, om_h, ko_l, ko_h, R, ch, mk(vl[0], vl[1]), mk(vh[0], vh[1]), mbl, mbh, Rb);
+    nb[4] += mbl.x, nb[5] += mbl.y, nb[0] -= mbl.x, nb[1] -= mbl.y;
+    nb[6] += mbh.x, nb[7] += mbh.y, nb[2] -= mbh.x, nb[3] -= mbh.y;
+}
+
+// VJP of the energy minimiser (linear in n) for one coordinate.
+TWA_HD void energy_vjp(float wl, float wh, int kl, int kh, float C, float xlb, float xhb, float &nlb, float &nhb) {
+    if (C <= 0.f || (kl == W_INF && kh == W_INF)) {
+        nlb += xlb;
+        nhb += xhb;
+    } else if (kl == W_INF) {
+        float a = 2.f * C / (2.f * C + wh), b = wh / (2.f * C + wh);
+        nlb += xlb + a * xhb;
+        nhb += b * xhb;
+    } else if (kh == W_INF) {
+        float a = 2.f * C / (2.f * C + wl), b = wl / (2.f * C + wl);
+        nhb += xhb + a * xlb;
+        nlb += b * xlb;
+    } else if (kl == W_ZERO && kh == W_ZERO) {
+        nlb += 0.5f * (xlb + xhb);
+        nhb += 0.5f * (xlb + xhb);
+    } else {
+        float den = 2.f * C * (wl + wh) + wl * wh;
+        nlb += (wl * (wh + 2.f * C) * xlb + 2.f * C * wl * xhb) / den;
+        nhb += (2.f * C * wh * xlb + wh * (wl + 2.f * C) * xhb) / den;
     }
 }
 

@@ -166,3 +166,128 @@ def test_energy_matches_reference(H):
                        xh.ctypes.data_as(_fp))
             rl, rh = O.prox_energy(nl, nh, np.inf if kl == 2 else wl, np.inf if kh == 2 else wh, C)
             assert _close(xl, rl) and _close(xh, rh)
+
+
+# ------------------------------------------------------------------ derivatives
+
+def _fd_vjp(fn, x, xb, h):
+    """sum_o xb_o d fn_o / d x_q by FP64 central differences, for each q."""
+    out = np.zeros(len(x))
+    for q in range(len(x)):
+        a, b = x.copy(), x.copy()
+        a[q] += h
+        b[q] -= h
+        out[q] = np.dot((fn(a) - fn(b)) / (2 * h), xb)
+    return out
+
+
+def _vjp_close(g, want, tol=2e-4):
+    return np.linalg.norm(g - want) <= tol * max(np.linalg.norm(want), 1e-3)
+
+
+@pytest.mark.parametrize("wmode", list(WEIGHTS))
+@pytest.mark.parametrize("scale", [1.0, 0.01])
+def test_coll_vjp_matches_reference_differences(H, wmode, scale):
+    H.h_coll_vjp.argtypes = [_fp, _fp, _i32, ct.c_float, _fp, _fp, _fp]
+    rng = np.random.default_rng(hash(("vjp", wmode, scale)) % 2**32)
+    R = 0.5 * scale
+    checked = 0
+    for _ in range(4000):
+        n = _f32(rng.normal(0, 0.4 * scale, size=(4, 2))).astype(np.float64)
+        w, k = WEIGHTS[wmode]
+        if w is None:
+            w = list(rng.uniform(0.3, 3.0, size=4))
+        if wmode in ("inf_lo", "inf_hi"):
+            fixed = (0, 2) if wmode == "inf_lo" else (1, 3)
+            if np.linalg.norm(n[fixed[1]] - n[fixed[0]]) < R * 1.01:
+                continue
+        wref = [np.inf if kk == 2 else ww for ww, kk in zip(w, k)]
+        act, xr, gap = ref_coll(n, wref, R)
+        if not act or gap < 1e-3:
+            continue
+        xb = rng.normal(size=8)
+        vec = np.concatenate([n.reshape(-1), [R]])
+
+        def fn(v):
+            return ref_coll(v[:8].reshape(4, 2), wref, v[8])[1]
+        fd1 = _fd_vjp(fn, vec, xb, 1e-6 * scale)
+        fd2 = _fd_vjp(fn, vec, xb, 3e-7 * scale)
+        if np.linalg.norm(fd1 - fd2) > 1e-5 * max(np.linalg.norm(fd1), 1.0):
+            continue  # a branch switch within the step
+        nb = np.zeros(8, np.float32)
+        Rb = np.zeros(1, np.float32)
+        H.h_coll_vjp(_f32(n.reshape(-1)).ctypes.data_as(_fp), _f32(w).ctypes.data_as(_fp),
+                     np.ascontiguousarray(k, np.int32).ctypes.data_as(_i32), R, _f32(xb).ctypes.data_as(_fp),
+                     nb.ctypes.data_as(_fp), Rb.ctypes.data_as(_fp))
+        got = np.concatenate([nb, Rb]).astype(np.float64)
+        assert _vjp_close(got, fd1), (n, w, k, got, fd1)
+        checked += 1
+        if checked >= 150:
+            break
+    assert checked >= 60
+
+
+@pytest.mark.parametrize("wmode", ["std", "inf0", "inf1", "unequal"])
+def test_capsule_vjp_matches_reference_differences(H, wmode):
+    H.h_capsule_vjp.argtypes = [_fp, ct.c_float, _fp, ct.c_float, ct.c_float, ct.c_int, ct.c_int, _fp, _fp, _fp]
+    rng = np.random.default_rng(hash(("cvjp", wmode)) % 2**32)
+    checked = 0
+    for _ in range(6000):
+        r = float(np.float32(rng.uniform(0.05, 0.3)))
+        c = rng.uniform(-0.3, 0.3, 2)
+        th = rng.uniform(0, np.pi)
+        L = rng.uniform(0, 0.8)
+        hh = 0.5 * L * np.array([np.cos(th), np.sin(th)])
+        a, b = _f32(c - hh).astype(np.float64), _f32(c + hh).astype(np.float64)
+        n = _f32(rng.normal(0, 0.4, 4)).astype(np.float64)
+        w0, w1 = (rng.uniform(0.3, 3.0, 2) if wmode == "unequal" else (1.0, 1.0))
+        k0 = 2 if wmode == "inf0" else 1
+        k1 = 2 if wmode == "inf1" else 1
+        if k0 == 2 and bf.point_seg(n[:2], a, b) < r * 1.01:
+            continue
+        if k1 == 2 and bf.point_seg(n[2:], a, b) < r * 1.01:
+            continue
+        W0, W1 = (np.inf if k0 == 2 else w0), (np.inf if k1 == 2 else w1)
+        act, xr, gap = ref_capsule(a, b, r, n[:2], n[2:], W0, W1)
+        if not act or gap < 1e-3:
+            continue
+        xb = rng.normal(size=4)
+        vec = np.concatenate([n, [r]])
+
+        def fn(v):
+            return ref_capsule(a, b, v[4], v[:2], v[2:4], W0, W1)[1]
+        fd1 = _fd_vjp(fn, vec, xb, 1e-6)
+        fd2 = _fd_vjp(fn, vec, xb, 3e-7)
+        if np.linalg.norm(fd1 - fd2) > 1e-5 * max(np.linalg.norm(fd1), 1.0):
+            continue
+        nb = np.zeros(4, np.float32)
+        rb = np.zeros(1, np.float32)
+        H.h_capsule_vjp(_f32(np.concatenate([a, b])).ctypes.data_as(_fp), r, _f32(n).ctypes.data_as(_fp),
+                        float(w0), float(w1), k0, k1, _f32(xb).ctypes.data_as(_fp), nb.ctypes.data_as(_fp),
+                        rb.ctypes.data_as(_fp))
+        got = np.concatenate([nb, rb]).astype(np.float64)
+        assert _vjp_close(got, fd1), (a, b, r, n, w0, w1, k0, k1, got, fd1)
+        checked += 1
+        if checked >= 150:
+            break
+    assert checked >= 60
+
+
+def test_energy_vjp_matches_reference_differences(H):
+    H.h_energy_vjp.argtypes = [ct.c_float, ct.c_float, ct.c_int, ct.c_int, ct.c_float, ct.c_float, ct.c_float, _fp,
+                               _fp]
+    rng = np.random.default_rng(17)
+    for _ in range(100):
+        wl, wh, C = (float(np.float32(v)) for v in rng.uniform(0.05, 3, 3))
+        xlb, xhb = rng.normal(size=2)
+        for kl, kh in [(1, 1), (2, 1), (1, 2)]:
+            Wl, Wh = (np.inf if kl == 2 else wl), (np.inf if kh == 2 else wh)
+
+            def fn(v):
+                a, b = O.prox_energy([v[0]], [v[1]], Wl, Wh, C)
+                return np.array([a[0], b[0]])
+            fd = _fd_vjp(fn, np.array([0.3, -0.2]), np.array([xlb, xhb]), 1e-6)
+            a = np.zeros(1, np.float32)
+            b = np.zeros(1, np.float32)
+            H.h_energy_vjp(wl, wh, kl, kh, C, xlb, xhb, a.ctypes.data_as(_fp), b.ctypes.data_as(_fp))
+            assert np.allclose([a[0], b[0]], fd, rtol=1e-5, atol=1e-6)
