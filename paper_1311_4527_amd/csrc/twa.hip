@@ -67,6 +67,7 @@ struct Params {
     int *stats;    // last iteration: active coll, active wall, queued
     unsigned long long *acc; // [2 kinds][dim][N]  kind 0 = std, 1 = inf
     int *cnt;                // [2][N]
+    float4 *inf_val;         // [N] m of a node's certain edge, kept exact when it is the only one
     long long N;
     double scale;
     float scalef;
@@ -349,6 +350,7 @@ __device__ __forceinline__ void fixed_stream(const Params &P, long long f) {
     float x[3] = {xf.x, xf.y, xf.z}, m[3];
     for (int c = 0; c < D; ++c) m[c] = x[c] + u[c];
     contribute(P, nd, 1, m, D);
+    P.inf_val[nd] = make_float4(m[0], m[1], D == 3 ? m[2] : 0.f, 0.f);
     if (P.dbg_x) {
         for (int c = 0; c < D; ++c) P.dbg_x[f * D + c] = x[c];
         P.dbg_rho[f] = W_INF;
@@ -483,7 +485,14 @@ __device__ __forceinline__ void node_update(const Params &P, long long nd) {
     int ci = P.cnt[P.N + nd], cs = P.cnt[nd];
     float4 cur = P.zr_cur[nd];
     float4 nw = cur;
-    if (ci > 0 || cs > 0) {
+    if (ci == 1) {
+        // a single certain edge (the fixed start or goal): z is its m exactly
+        float4 v = P.inf_val[nd];
+        nw.x = v.x;
+        nw.y = v.y;
+        if (D == 3) nw.z = v.z;
+        nw.w = (float)W_INF;
+    } else if (ci > 0 || cs > 0) {
         int kind = ci > 0 ? 1 : 0;
         double den = (double)(ci > 0 ? ci : cs) * P.scale;
         float z[3];
@@ -1036,6 +1045,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         dev_alloc(s, &P.qc, (size_t)std::max<long long>(1, Fc)) ||
         dev_alloc(s, &P.qw, (size_t)std::max<long long>(1, Fw)) || dev_alloc(s, &P.counters, 8) ||
         dev_alloc(s, &P.acc, (size_t)2 * dim * P.N) || dev_alloc(s, &P.cnt, (size_t)2 * P.N) ||
+        dev_alloc(s, &P.inf_val, (size_t)P.N) ||
         dev_alloc(s, &s->stats_dev, 4) || dev_alloc(s, &s->bad_dev, 1))
         return bail(TWA_E_NOMEM);
     P.radii = radii_d, P.C = C_d, P.walls = walls_d, P.xfix = xfix_d;
