@@ -101,8 +101,8 @@ def cpu_baseline(inst, budget_s=12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--workload", default="box1024")
     ap.add_argument("--variant", choices=["dense", "skip"], default="dense")
     ap.add_argument("--also", action="store_true", help="also time the other variant")

@@ -287,28 +287,24 @@ TWA_HD void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R,
     }
     if (i0 || i1) {
         f2 q = i0 ? m0 : m1, m = i0 ? m1 : m0;
-        f2 cand[3];
-        int kind[3];
-        int nc = tangent_normals(q, mk(0.f, 0.f), R, cand);
-        kind[0] = kind[1] = CH_TAN;
-        float mm = dot(m, m);
-        if (mm > 0.f) {
-            f2 u = scl(m, inv_sqrt(mm));
-            if (dot(q, u) >= R) {
-                kind[nc] = CH_RADF;
-                cand[nc++] = u;
-            }
-        }
         f2 best = mk(1.f, 0.f);
         int bk = CH_NONE;
         float bg = INFINITY;
-        for (int k = 0; k < nc; ++k) {
-            float g = pos(R - dot(m, cand[k]));
+        auto consider = [&](f2 u, int kind) {
+            float g = pos(R - dot(m, u));
             if (g < bg) {
                 bg = g;
-                best = cand[k];
-                bk = kind[k];
+                best = u;
+                bk = kind;
             }
+        };
+        f2 tn[2];
+        int nt = tangent_normals(q, mk(0.f, 0.f), R, tn);
+        for (int k = 0; k < nt; ++k) consider(tn[k], CH_TAN);
+        float mm = dot(m, m);
+        if (mm > 0.f) {
+            f2 u = scl(m, inv_sqrt(mm));
+            if (dot(q, u) >= R) consider(u, CH_RADF);
         }
         f2 vm = (bg < INFINITY) ? add(m, scl(best, bg)) : m;
         if (i0) {
@@ -325,31 +321,24 @@ TWA_HD void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R,
         return;
     }
     Eig2 g = piece_quadratic(m0, m1, w0, w1, R);
-    f2 cand[4];
-    int kind[4] = {CH_T, CH_T, CH_T, CH_T};
-    f2 alt;
-    int nc = trs_global(g, cand, &alt);
-    if (nc == 2) cand[1] = alt;
-    float q0 = dot(m0, m0), q1 = dot(m1, m1);
-    if (q0 > 0.f && q0 < R * R) {
-        kind[nc] = CH_R0;
-        cand[nc++] = scl(m0, inv_sqrt(q0));
-    }
-    if (q1 > 0.f && q1 < R * R) {
-        kind[nc] = CH_R1;
-        cand[nc++] = scl(m1, inv_sqrt(q1));
-    }
-    f2 best = cand[0];
-    int bk = kind[0];
-    float bF = disk_F(cand[0], m0, m1, w0, w1, R);
-    for (int k = 1; k < nc; ++k) {
-        float Fk = disk_F(cand[k], m0, m1, w0, w1, R);
-        if (Fk < bF) {
+    f2 best = mk(1.f, 0.f);
+    int bk = CH_NONE;
+    float bF = INFINITY;
+    auto consider = [&](f2 u, int kind) {
+        float Fk = disk_F(u, m0, m1, w0, w1, R);
+        if (Fk < bF || bk == CH_NONE) {
             bF = Fk;
-            best = cand[k];
-            bk = kind[k];
+            best = u;
+            bk = kind;
         }
-    }
+    };
+    f2 t0, alt;
+    int nt = trs_global(g, &t0, &alt);
+    consider(t0, CH_T);
+    if (nt == 2) consider(alt, CH_T);
+    float q0 = dot(m0, m0), q1 = dot(m1, m1);
+    if (q0 > 0.f && q0 < R * R) consider(scl(m0, inv_sqrt(q0)), CH_R0);
+    if (q1 > 0.f && q1 < R * R) consider(scl(m1, inv_sqrt(q1)), CH_R1);
     v0 = add(m0, scl(best, pos(R - dot(m0, best))));
     v1 = add(m1, scl(best, pos(R - dot(m1, best))));
     if (ch) {
@@ -396,50 +385,38 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
     float L2 = dot(d, d);
     bool seg = L2 > 0.f;
     f2 sw = seg ? scl(perp(d), inv_sqrt(L2)) : mk(0.f, 1.f);
-    f2 cand[16];
-    int kind[16];
-    unsigned char ctr[16]; // 0: centre a, 1: centre b
-    int nc = 0;
     if (i0 || i1) {
         // one end certain: the other moves along normals u visible from it
         f2 q = i0 ? n0 : n1, m = i0 ? n1 : n0;
-        int na = tangent_normals(q, C.a, C.r, cand + nc);
-        for (int k = 0; k < na; ++k) kind[nc + k] = CH_TAN, ctr[nc + k] = 0;
-        nc += na;
-        if (seg) {
-            int nb = tangent_normals(q, C.b, C.r, cand + nc);
-            for (int k = 0; k < nb; ++k) kind[nc + k] = CH_TAN, ctr[nc + k] = 1;
-            nc += nb;
-        }
-        f2 t0 = sub(m, C.a);
-        if (dot(t0, t0) > 0.f) {
-            kind[nc] = CH_RADF, ctr[nc] = 0;
-            cand[nc++] = scl(t0, inv_sqrt(dot(t0, t0)));
-        }
-        if (seg) {
-            f2 t1 = sub(m, C.b);
-            if (dot(t1, t1) > 0.f) {
-                kind[nc] = CH_RADF, ctr[nc] = 1;
-                cand[nc++] = scl(t1, inv_sqrt(dot(t1, t1)));
-            }
-            kind[nc] = CH_FLAT, ctr[nc] = 0;
-            cand[nc++] = sw;
-            kind[nc] = CH_FLAT, ctr[nc] = 0;
-            cand[nc++] = scl(sw, -1.f);
-        }
         float tol = 1e-5f * (fabsf(q.x) + fabsf(q.y) + C.r);
         f2 best = mk(1.f, 0.f);
-        int bi = -1;
+        int bk = CH_NONE, bc = 0;
         float bg = INFINITY;
-        for (int k = 0; k < nc; ++k) {
-            float h = cap_h(C, cand[k]);
-            if (dot(q, cand[k]) < h - tol) continue; // not visible from the certain end
-            float g = pos(h - dot(m, cand[k]));
+        auto consider = [&](f2 u, int kind, int ctr) {
+            float h = cap_h(C, u);
+            if (dot(q, u) < h - tol) return; // not visible from the certain end
+            float g = pos(h - dot(m, u));
             if (g < bg) {
                 bg = g;
-                best = cand[k];
-                bi = k;
+                best = u;
+                bk = kind;
+                bc = ctr;
             }
+        };
+        f2 tn[2];
+        int nt = tangent_normals(q, C.a, C.r, tn);
+        for (int k = 0; k < nt; ++k) consider(tn[k], CH_TAN, 0);
+        if (seg) {
+            nt = tangent_normals(q, C.b, C.r, tn);
+            for (int k = 0; k < nt; ++k) consider(tn[k], CH_TAN, 1);
+        }
+        f2 t0 = sub(m, C.a);
+        if (dot(t0, t0) > 0.f) consider(scl(t0, inv_sqrt(dot(t0, t0))), CH_RADF, 0);
+        if (seg) {
+            f2 t1 = sub(m, C.b);
+            if (dot(t1, t1) > 0.f) consider(scl(t1, inv_sqrt(dot(t1, t1))), CH_RADF, 1);
+            consider(sw, CH_FLAT, 0);
+            consider(scl(sw, -1.f), CH_FLAT, 0);
         }
         f2 xm = (bg < INFINITY) ? add(m, scl(best, bg)) : m;
         if (i0) {
@@ -449,31 +426,46 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
             x1 = n1;
             x0 = xm;
         }
-        if (ch && bi >= 0) {
-            ch->kind = kind[bi];
+        if (ch && bk != CH_NONE) {
+            ch->kind = bk;
             ch->u = best;
-            ch->c = ctr[bi] ? C.b : C.a;
+            ch->c = bc ? C.b : C.a;
         }
         return;
     }
+    f2 best = mk(1.f, 0.f);
+    int bk = CH_NONE, bc = 0;
+    float bF = INFINITY;
+    auto consider = [&](f2 u, int kind, int ctr) {
+        float Fk = cap_F(C, u, n0, n1, w0, w1);
+        if (Fk < bF || bk == CH_NONE) {
+            bF = Fk;
+            best = u;
+            bk = kind;
+            bc = ctr;
+        }
+    };
     // (a) stationary points of each smooth piece
     for (int pc = 0; pc < (seg ? 2 : 1); ++pc) {
         f2 c = pc ? C.b : C.a;
         Eig2 g = piece_quadratic(sub(n0, c), sub(n1, c), w0, w1, C.r);
-        f2 alt;
-        int k0n = nc;
-        int k = trs_global(g, cand + nc, &alt);
-        nc += 1;
-        if (k == 2) cand[nc++] = alt;
-        nc += trs_middle(g, cand + nc);
-        for (int q = k0n; q < nc; ++q) kind[q] = CH_T, ctr[q] = (unsigned char)pc;
+        f2 t0, alt, mid[2];
+        int k = trs_global(g, &t0, &alt);
+        consider(t0, CH_T, pc);
+        if (k == 2) consider(alt, CH_T, pc);
+        // the piece's other local minimum can only matter when its global
+        // one lies on the half-circle where the other end cap is the support
+        float side = dot(d, t0);
+        bool valid = !seg || (pc ? side >= 0.f : side <= 0.f);
+        if (!valid) {
+            int nm = trs_middle(g, mid);
+            for (int q = 0; q < nm; ++q) consider(mid[q], CH_T, pc);
+        }
     }
     // (c) kinks: slab against a flat side
     if (seg) {
-        kind[nc] = CH_FLAT, ctr[nc] = 0;
-        cand[nc++] = sw;
-        kind[nc] = CH_FLAT, ctr[nc] = 0;
-        cand[nc++] = scl(sw, -1.f);
+        consider(sw, CH_FLAT, 0);
+        consider(scl(sw, -1.f), CH_FLAT, 0);
     }
     // (b) nearest boundary point of one end
     for (int e = 0; e < 2; ++e) {
@@ -482,30 +474,17 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
         f2 c = closest_on_seg(n, C.a, C.b);
         f2 t = sub(n, c);
         float tt = dot(t, t);
-        if (tt > 0.f && tt < C.r * C.r) {
-            kind[nc] = (tpar > 0.f && tpar < 1.f) ? CH_FLAT : (e ? CH_R1 : CH_R0);
-            ctr[nc] = (seg && tpar >= 1.f) ? 1 : 0;
-            cand[nc++] = scl(t, inv_sqrt(tt));
-        }
-    }
-    f2 best = cand[0];
-    int bi = 0;
-    float bF = cap_F(C, cand[0], n0, n1, w0, w1);
-    for (int k = 1; k < nc; ++k) {
-        float Fk = cap_F(C, cand[k], n0, n1, w0, w1);
-        if (Fk < bF) {
-            bF = Fk;
-            best = cand[k];
-            bi = k;
-        }
+        if (tt > 0.f && tt < C.r * C.r)
+            consider(scl(t, inv_sqrt(tt)), (tpar > 0.f && tpar < 1.f) ? CH_FLAT : (e ? CH_R1 : CH_R0),
+                     (seg && tpar >= 1.f) ? 1 : 0);
     }
     float h = cap_h(C, best);
     x0 = add(n0, scl(best, pos(h - dot(n0, best))));
     x1 = add(n1, scl(best, pos(h - dot(n1, best))));
     if (ch) {
-        ch->kind = kind[bi];
+        ch->kind = bk;
         ch->u = best;
-        ch->c = ctr[bi] ? C.b : C.a;
+        ch->c = bc ? C.b : C.a;
     }
 }
 

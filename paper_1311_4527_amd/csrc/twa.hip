@@ -68,6 +68,10 @@ struct Params {
     unsigned long long *acc; // [2 kinds][dim][N]  kind 0 = std, 1 = inf
     int *cnt;                // [2][N]
     float4 *inf_val;         // [N] m of a node's certain edge, kept exact when it is the only one
+    float4 *x_coll;          // [dim planes][Fc] x of factors active in the last iteration
+    float4 *x_wall;          // [Fw]
+    const unsigned long long *wbase_coll; // per 64 factors: (s, i, j) of the first, packed 16|24|24 bits
+    const unsigned long long *wbase_wall; // per 64 factors: (s, i, w) of the first
     long long N;
     double scale;
     float scalef;
@@ -113,20 +117,33 @@ __device__ __forceinline__ void contribute(const Params &P, long long node, int 
     atomicAdd(&P.cnt[(long long)kind * P.N + node], 1);
 }
 
-// (s, i, j) of collision factor f: s-major, then i < j row-major
-__device__ __forceinline__ void decode_pair(long long f, int p, int &s, int &i, int &j) {
-    long long P2 = (long long)p * (p - 1) / 2;
-    s = (int)(f / P2);
-    long long t = f - (long long)s * P2;
-    // rows i hold p-1-i pairs; first pair of row i is at T(i) = i(2p-i-1)/2
-    double B = 2.0 * p - 1.0;
-    int r = (int)((B - sqrt(B * B - 8.0 * (double)t)) * 0.5);
-    if (r < 0) r = 0;
-    if (r > p - 2) r = p - 2;
-    while (r > 0 && (long long)r * (2LL * p - r - 1) / 2 > t) --r;
-    while (r < p - 2 && (long long)(r + 1) * (2LL * p - r - 2) / 2 <= t) ++r;
-    i = r;
-    j = (int)(t - (long long)r * (2LL * p - r - 1) / 2) + r + 1;
+// (s, i, j) of factor f0 + k given (s, i, j) of f0: walk along the rows of
+// the upper triangle (row i holds p-1-i pairs); 32-bit adds only.
+__device__ __forceinline__ void advance_pair(int p, int k, int &s, int &i, int &j) {
+    int c = j - i - 1 + k;
+    int L = p - 1 - i;
+    while (c >= L) {
+        c -= L;
+        if (++i >= p - 1) {
+            i = 0;
+            ++s;
+        }
+        L = p - 1 - i;
+    }
+    j = i + 1 + c;
+}
+
+// (s, i, w) of wall factor f0 + k given (s, i, w) of f0
+__device__ __forceinline__ void advance_wall(int p, int W, int k, int &s, int &i, int &w) {
+    int c = w + k;
+    while (c >= W) {
+        c -= W;
+        if (++i >= p) {
+            i = 0;
+            ++s;
+        }
+    }
+    w = c;
 }
 
 template <int D>
@@ -139,6 +156,23 @@ __device__ __forceinline__ void load_u_coll(const Params &P, long long f, float 
         float4 c = P.u_coll[2 * P.Fc + f];
         u[8] = c.x, u[9] = c.y, u[10] = c.z, u[11] = c.w;
     }
+}
+template <int D>
+__device__ __forceinline__ void load_x_coll(const Params &P, long long f, float *x) {
+    float4 a = P.x_coll[f];
+    float4 b = P.x_coll[P.Fc + f];
+    x[0] = a.x, x[1] = a.y, x[2] = a.z, x[3] = a.w;
+    x[4] = b.x, x[5] = b.y, x[6] = b.z, x[7] = b.w;
+    if constexpr (D == 3) {
+        float4 c = P.x_coll[2 * P.Fc + f];
+        x[8] = c.x, x[9] = c.y, x[10] = c.z, x[11] = c.w;
+    }
+}
+template <int D>
+__device__ __forceinline__ void store_x_coll(const Params &P, long long f, const float *x) {
+    P.x_coll[f] = make_float4(x[0], x[1], x[2], x[3]);
+    P.x_coll[P.Fc + f] = make_float4(x[4], x[5], x[6], x[7]);
+    if constexpr (D == 3) P.x_coll[2 * P.Fc + f] = make_float4(x[8], x[9], x[10], x[11]);
 }
 template <int D>
 __device__ __forceinline__ void store_u_coll(const Params &P, long long f, const float *u) {
@@ -175,9 +209,12 @@ template <int D, int MODE>
 __device__ __forceinline__ void coll_stream(const Params &P, long long f, bool valid, bool *q, unsigned *val) {
     const bool dense = P.dense != 0;
     bool push_prev = false, push_new = false;
-    int s = 0, i = 0, j = 1;
+    // (s, i, j) of the wavefront's first factor from a table, then walk per lane
+    int fw = __builtin_amdgcn_readfirstlane((int)f);
+    unsigned long long pk = P.wbase_coll[fw >> 6];
+    int s = (int)(pk >> 48), i = (int)((pk >> 24) & 0xffffffull), j = (int)(pk & 0xffffffull);
     if (valid) {
-        decode_pair(f, P.p, s, i, j);
+        advance_pair(P.p, (int)(f - fw), s, i, j);
         long long nd[4];
         coll_nodes(P, s, i, j, nd);
         float R = P.radii[i] + P.radii[j];
@@ -236,10 +273,11 @@ template <int MODE>
 __device__ __forceinline__ void wall_stream(const Params &P, long long f, bool valid, bool *q, unsigned *val) {
     const bool dense = P.dense != 0;
     bool push_prev = false, push_new = false;
+    int fw = __builtin_amdgcn_readfirstlane((int)f);
+    unsigned long long pk = P.wbase_wall[fw >> 6];
+    int s = (int)(pk >> 48), i = (int)((pk >> 24) & 0xffffffull), w = (int)(pk & 0xffffffull);
     if (valid) {
-        int w = (int)(f % P.W);
-        long long si = f / P.W;
-        int i = (int)(si % P.p), s = (int)(si / P.p);
+        advance_wall(P.p, P.W, (int)(f - fw), s, i, w);
         long long na = (long long)s * P.p + i, nb = na + P.p;
         float4 wl = P.walls[w];
         f2 xa = mk(wl.x, wl.y), xb = mk(wl.z, wl.w);
@@ -364,8 +402,9 @@ __device__ __forceinline__ void coll_queue(const Params &P, unsigned e) {
     const bool dense = P.dense != 0;
     long long f = e & kIdx;
     bool prev = (e & kPrev) != 0;
-    int s, i, j;
-    decode_pair(f, P.p, s, i, j);
+    unsigned long long pk = P.wbase_coll[f >> 6];
+    int s = (int)(pk >> 48), i = (int)((pk >> 24) & 0xffffffull), j = (int)(pk & 0xffffffull);
+    advance_pair(P.p, (int)(f & 63), s, i, j);
     long long nd[4];
     coll_nodes(P, s, i, j, nd);
     float R = P.radii[i] + P.radii[j];
@@ -378,18 +417,9 @@ __device__ __forceinline__ void coll_queue(const Params &P, unsigned e) {
         k[q] = wcode(rc[q]);
     }
     if (prev) {
+        // x^k was stored when the factor was active last iteration
         load_u_coll<D>(P, f, u);
-        float wp[4];
-        int kp[4];
-        for (int q = 0; q < 4; ++q) {
-            float4 rp = P.zr_prev[nd[q]];
-            float zp[3];
-            node_xyz(rp, zp, D);
-            kp[q] = wcode(rp);
-            wp[q] = wval(kp[q], P.rho_prev);
-            for (int c = 0; c < D; ++c) n[q * D + c] = zp[c] - u[q * D + c];
-        }
-        coll_prox<D>(n, wp, kp, R, x); // x^k; its weight was rho0 on all four edges
+        load_x_coll<D>(P, f, x);
         for (int q = 0; q < 4; ++q)
             for (int c = 0; c < D; ++c)
                 u[q * D + c] =
@@ -413,6 +443,7 @@ __device__ __forceinline__ void coll_queue(const Params &P, unsigned e) {
             for (int c = 0; c < D; ++c) m[c] = x[q * D + c] + u[q * D + c];
             contribute(P, nd[q], 0, m, D);
         }
+        store_x_coll<D>(P, f, x);
         atomicOr(&P.bits_coll[f >> 5], 1u << (f & 31));
         atomicAdd(&P.counters[2], 1);
     } else {
@@ -432,9 +463,9 @@ __device__ __forceinline__ void wall_queue(const Params &P, unsigned e) {
     const bool dense = P.dense != 0;
     long long f = e & kIdx;
     bool prev = (e & kPrev) != 0;
-    int wi = (int)(f % P.W);
-    long long si = f / P.W;
-    int i = (int)(si % P.p), s = (int)(si / P.p);
+    unsigned long long pk = P.wbase_wall[f >> 6];
+    int s = (int)(pk >> 48), i = (int)((pk >> 24) & 0xffffffull), wi = (int)(pk & 0xffffffull);
+    advance_wall(P.p, P.W, (int)(f & 63), s, i, wi);
     long long na = (long long)s * P.p + i, nb = na + P.p;
     float4 wl = P.walls[wi];
     Capsule Cw{mk(wl.x, wl.y), mk(wl.z, wl.w), P.radii[i]};
@@ -442,12 +473,10 @@ __device__ __forceinline__ void wall_queue(const Params &P, unsigned e) {
     int ka = wcode(ca), kb = wcode(cb);
     float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
     if (prev) {
+        // x^k was stored when the factor was active last iteration
         u = P.u_wall[f];
-        float4 pa = P.zr_prev[na], pb = P.zr_prev[nb];
-        int pka = wcode(pa), pkb = wcode(pb);
-        f2 x0, x1;
-        capsule_prox(Cw, mk(pa.x - u.x, pa.y - u.y), mk(pb.x - u.z, pb.y - u.w), wval(pka, P.rho_prev),
-                     wval(pkb, P.rho_prev), pka, pkb, x0, x1);
+        float4 xs = P.x_wall[f];
+        f2 x0 = mk(xs.x, xs.y), x1 = mk(xs.z, xs.w);
         u.x = (ka == W_STD) ? u.x + P.step_prev * (x0.x - ca.x) : 0.f;
         u.y = (ka == W_STD) ? u.y + P.step_prev * (x0.y - ca.y) : 0.f;
         u.z = (kb == W_STD) ? u.z + P.step_prev * (x1.x - cb.x) : 0.f;
@@ -464,6 +493,7 @@ __device__ __forceinline__ void wall_queue(const Params &P, unsigned e) {
     f2 x0 = n0, x1 = n1;
     if (act) {
         capsule_prox(Cw, n0, n1, wval(ka, P.rho), wval(kb, P.rho), ka, kb, x0, x1);
+        P.x_wall[f] = make_float4(x0.x, x0.y, x1.x, x1.y);
         float m0[2] = {x0.x + u.x, x0.y + u.y}, m1[2] = {x1.x + u.z, x1.y + u.w};
         contribute(P, na, 0, m0, 2);
         contribute(P, nb, 0, m1, 2);
@@ -752,20 +782,31 @@ struct twa_solver {
     unsigned char *dbg_rho = nullptr;
     long long nblocks_stream = 0;
     int nblocks_queue = 0;
-    // event timing (twa_iterate_timed)
+    // event timing (twa_iterate_timed): 1 = a new event per mark, 2 = the
+    // preallocated events of the graph being captured
     std::vector<hipEvent_t> events;
     int timing = 0;
+    // HIP graphs of kGraphIters fused iterations (plain, and with events)
+    hipGraphExec_t graph = nullptr, graph_timed = nullptr;
+    std::vector<hipEvent_t> gevents;
+    size_t gev_next = 0;
+    bool graph_failed = false;
 };
 
 namespace {
 
+constexpr int kGraphIters = 32;
+
 void mark(twa_solver *s, int slot) {
-    if (!s->timing) return;
-    hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
-    (void)hipEventRecord(e, s->stream);
-    s->events.push_back(e);
     (void)slot;
+    if (s->timing == 1) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        (void)hipEventRecord(e, s->stream);
+        s->events.push_back(e);
+    } else if (s->timing == 2 && s->gev_next < s->gevents.size()) {
+        (void)hipEventRecord(s->gevents[s->gev_next++], s->stream);
+    }
 }
 
 twa_status fail(twa_solver *s, twa_status st, const std::string &msg) {
@@ -866,6 +907,84 @@ twa_status run_iteration(twa_solver *s, int mode, float rho, float rho_prev) {
 
 float rho_at(const twa_solver *s, long long k) { return k < s->n_warm ? s->rho0_init : s->rho0; }
 
+// Capture kGraphIters fused iterations at the steady rho0 into a graph
+// (timed: with an event before and after every launch).  Returns false if
+// the stream cannot be captured (e.g. the legacy default stream).
+bool capture_graph(twa_solver *s, bool timed) {
+    hipGraphExec_t *slot = timed ? &s->graph_timed : &s->graph;
+    if (*slot) return true;
+    if (s->graph_failed) return false;
+    if (timed && s->gevents.empty()) {
+        s->gevents.resize((size_t)kGraphIters * 4);
+        for (auto &e : s->gevents)
+            if (hipEventCreate(&e) != hipSuccess) {
+                s->graph_failed = true;
+                return false;
+            }
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        s->graph_failed = true;
+        return false;
+    }
+    s->timing = timed ? 2 : 0;
+    s->gev_next = 0;
+    bool ok = true;
+    for (int it = 0; it < kGraphIters && ok; ++it) ok = run_iteration(s, M_FUSED, s->rho0, s->rho0) == TWA_OK;
+    s->timing = 0;
+    ok = (hipStreamEndCapture(s->stream, &g) == hipSuccess) && ok && g != nullptr;
+    if (ok) ok = hipGraphInstantiate(slot, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+        (void)hipGetLastError();
+        *slot = nullptr;
+        s->graph_failed = true;
+        s->err.clear();
+        s->latched = TWA_OK;
+    }
+    return ok;
+}
+
+// Run k iterations; graph replays where possible.  acc (timed) collects the
+// device milliseconds of the three kernels.
+twa_status iterate_impl(twa_solver *s, int k, double *acc) {
+    while (k > 0) {
+        bool steady = s->pending && s->iter - 1 >= s->n_warm && !s->dbg_x;
+        if (steady && k >= kGraphIters && capture_graph(s, acc != nullptr)) {
+            if (acc) {
+                HIP_TRY(s, hipGraphLaunch(s->graph_timed, s->stream));
+                HIP_TRY(s, hipStreamSynchronize(s->stream));
+                for (int it = 0; it < kGraphIters; ++it)
+                    for (int kk = 0; kk < 3; ++kk) {
+                        float ms = 0.f;
+                        if (hipEventElapsedTime(&ms, s->gevents[4 * it + kk], s->gevents[4 * it + kk + 1]) ==
+                            hipSuccess)
+                            acc[kk] += ms;
+                    }
+            } else {
+                HIP_TRY(s, hipGraphLaunch(s->graph, s->stream));
+            }
+            s->iter += kGraphIters;
+            k -= kGraphIters;
+            continue;
+        }
+        float rho = rho_at(s, s->iter);
+        if (acc) s->timing = 1;
+        twa_status st;
+        if (!s->pending) st = run_iteration(s, M_FIRST, rho, rho);
+        else st = run_iteration(s, M_FUSED, rho, rho_at(s, s->iter - 1));
+        s->timing = 0;
+        if (st != TWA_OK) return st;
+        s->pending = true;
+        s->iter++;
+        k--;
+        s->dbg_x = nullptr;
+        s->dbg_rho = nullptr;
+    }
+    return TWA_OK;
+}
+
 // pending -> canonical: materialise u^k
 twa_status finalize(twa_solver *s) {
     if (!s->pending) return TWA_OK;
@@ -908,6 +1027,9 @@ const char *twa_last_error(const twa_solver *s) { return s ? s->err.c_str() : "n
 void twa_destroy(twa_solver *s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    if (s->graph_timed) (void)hipGraphExecDestroy(s->graph_timed);
+    for (hipEvent_t e : s->gevents) (void)hipEventDestroy(e);
     for (void *p : s->allocs) (void)hipFree(p);
     delete s;
 }
@@ -948,7 +1070,8 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     }
     long long P2 = (long long)p * (p - 1) / 2;
     long long Fc = (long long)eta * P2, Fw = (long long)eta * p * n_walls, Fe = (long long)eta * p, Ff = 2LL * p;
-    if (Fc >= (long long)kIdx || Fw >= (long long)kIdx) {
+    if (Fc >= (long long)kIdx || Fw >= (long long)kIdx || p >= (1 << 24) || eta >= (1 << 16) ||
+        n_walls >= (1 << 24)) {
         fail(s, TWA_E_INVALID, "too many factors for one solver");
         return bail(TWA_E_INVALID);
     }
@@ -1035,6 +1158,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     P.scalef = (float)P.scale;
     float *radii_d, *C_d;
     float4 *walls_d, *xfix_d;
+    unsigned long long *wbc_d, *wbw_d;
     if (dev_alloc(s, &P.zr_prev, P.N) || dev_alloc(s, &P.zr_cur, P.N) || dev_alloc(s, &radii_d, p) ||
         dev_alloc(s, &walls_d, std::max(1, n_walls)) || dev_alloc(s, &C_d, (size_t)p * eta) ||
         dev_alloc(s, &xfix_d, Ff) || dev_alloc(s, &P.u_coll, (size_t)std::max<long long>(1, dim * Fc)) ||
@@ -1046,9 +1170,31 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         dev_alloc(s, &P.qw, (size_t)std::max<long long>(1, Fw)) || dev_alloc(s, &P.counters, 8) ||
         dev_alloc(s, &P.acc, (size_t)2 * dim * P.N) || dev_alloc(s, &P.cnt, (size_t)2 * P.N) ||
         dev_alloc(s, &P.inf_val, (size_t)P.N) ||
+        dev_alloc(s, &P.x_coll, (size_t)std::max<long long>(1, dim * Fc)) ||
+        dev_alloc(s, &P.x_wall, (size_t)std::max<long long>(1, Fw)) ||
+        dev_alloc(s, &wbc_d, (size_t)std::max<long long>(1, (Fc + 63) / 64)) ||
+        dev_alloc(s, &wbw_d, (size_t)std::max<long long>(1, (Fw + 63) / 64)) ||
         dev_alloc(s, &s->stats_dev, 4) || dev_alloc(s, &s->bad_dev, 1))
         return bail(TWA_E_NOMEM);
     P.radii = radii_d, P.C = C_d, P.walls = walls_d, P.xfix = xfix_d;
+    P.wbase_coll = wbc_d, P.wbase_wall = wbw_d;
+    // (s, i, j) / (s, i, w) of the first factor of every 64, in canonical order
+    std::vector<unsigned long long> hwbc((size_t)std::max<long long>(1, (Fc + 63) / 64)),
+        hwbw((size_t)std::max<long long>(1, (Fw + 63) / 64));
+    {
+        long long f = 0;
+        for (int s2 = 0; s2 < eta && Fc > 0; ++s2)
+            for (int i = 0; i < p; ++i)
+                for (int j = i + 1; j < p; ++j, ++f)
+                    if ((f & 63) == 0)
+                        hwbc[f >> 6] = ((unsigned long long)s2 << 48) | ((unsigned long long)i << 24) | (unsigned long long)j;
+        f = 0;
+        for (int s2 = 0; s2 < eta && Fw > 0; ++s2)
+            for (int i = 0; i < p; ++i)
+                for (int w = 0; w < n_walls; ++w, ++f)
+                    if ((f & 63) == 0)
+                        hwbw[f >> 6] = ((unsigned long long)s2 << 48) | ((unsigned long long)i << 24) | (unsigned long long)w;
+    }
     P.stats = s->stats_dev;
     P.rho = P.rho_prev = rho0;
     P.step = P.step_prev = alpha / rho0;
@@ -1078,6 +1224,12 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         e = hipMemcpyAsync(C_d, hC.data(), sizeof(float) * hC.size(), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(xfix_d, hfix.data(), sizeof(float4) * Ff, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(wbc_d, hwbc.data(), sizeof(unsigned long long) * hwbc.size(), hipMemcpyHostToDevice,
+                           s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(wbw_d, hwbw.data(), sizeof(unsigned long long) * hwbw.size(), hipMemcpyHostToDevice,
+                           s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(P.zr_cur, hz.data(), sizeof(float4) * P.N, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
@@ -1122,31 +1274,18 @@ twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm) {
 twa_status twa_iterate(twa_solver *s, int k) {
     TRY(check_alive(s));
     if (k < 0) return fail(s, TWA_E_INVALID, "k must be >= 0");
-    for (int it = 0; it < k; ++it) {
-        float rho = rho_at(s, s->iter);
-        if (!s->pending) {
-            TRY(run_iteration(s, M_FIRST, rho, rho));
-        } else {
-            TRY(run_iteration(s, M_FUSED, rho, rho_at(s, s->iter - 1)));
-        }
-        s->pending = true;
-        s->iter++;
-        s->dbg_x = nullptr;
-        s->dbg_rho = nullptr;
-    }
-    return TWA_OK;
+    return iterate_impl(s, k, nullptr);
 }
 
 twa_status twa_iterate_timed(twa_solver *s, int k, double *kernel_ms) {
     TRY(check_alive(s));
     if (!kernel_ms) return fail(s, TWA_E_INVALID, "null kernel_ms");
+    if (k < 0) return fail(s, TWA_E_INVALID, "k must be >= 0");
     s->events.clear();
-    s->timing = 1;
-    twa_status st = twa_iterate(s, k);
-    s->timing = 0;
     double acc[3] = {0, 0, 0};
+    twa_status st = iterate_impl(s, k, acc);
     hipError_t e = hipStreamSynchronize(s->stream);
-    // four marks per iteration: before stream, before queue, before nodes, after nodes
+    // eager iterations: four marks each (before stream, queue, nodes; after nodes)
     for (size_t q = 0; q + 3 < s->events.size() && e == hipSuccess; q += 4) {
         for (int kk = 0; kk < 3; ++kk) {
             float ms = 0.f;
