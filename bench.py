@@ -3,9 +3,12 @@ steps 1-7) on the p=1024, eta=16, 32-wall random-box workload (8.4 M
 collision factors), FP32 on one MI355X.
 
 A step is one full iteration over every factor of the graph.  Prints one
-JSON line: whole-job factor-updates/s (all factors, active or not), the
-roofline of the dominant kernel from HIP events on the solver's stream, and
-the FP64 reference timed on this host's cores on a bounded sample.
+JSON line: whole-job factor-updates/s (all factors, active or not) of the
+plain dense-state iteration, the roofline of its dominant kernel from HIP
+events on the solver's stream, the activity-bit variant, the batched
+launch of 256 ragged instances against the same instances solved one after
+another, the adjoint of 500 unrolled iterations against the forward run,
+and the FP64 reference timed on this host's cores on a bounded sample.
 """
 import argparse
 import json
@@ -20,6 +23,34 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 FP32_VALU_TFLOPS = 157.3   # MI355X FP32 vector peak
 KERNELS = ("k_stream", "k_queue", "k_nodes")
+
+# HBM bytes per launch of the factor-stream kernel on the 1024-agent box,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE (median KiB per dispatch) scaled
+# by the same counters over a 512 MiB device copy (read x2.000, write
+# x1.000).  Valid only for the kernel sources they were taken on.
+MEASURED_TRAFFIC = {
+    "dense": dict(fetch_kib=140098.3, write_kib=271295.3, sources="b0a9b1ea05fb76a3"),
+    "skip": dict(fetch_kib=5847.1, write_kib=2301.5, sources="b0a9b1ea05fb76a3"),
+}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+KERNEL_SOURCES = ("paper_1311_4527_amd/csrc/twa.hip", "paper_1311_4527_amd/csrc/prox.h",
+                  "paper_1311_4527_amd/csrc/solver.h")
+
+
+def kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(variant):
+    m = MEASURED_TRAFFIC[variant]
+    if m["sources"] != kernel_sources_digest():
+        return None
+    return (m["fetch_kib"] * FETCH_SCALE + m["write_kib"] * WRITE_SCALE) * 1024.0
 
 
 def workload(name):
@@ -76,6 +107,116 @@ def run_gpu(inst, dense, steps, warmup):
     return dict(seconds=t1 - t0, kernel_ms=kms, stats=stats, objective=J)
 
 
+def roofline(inst, variant, avg_ms):
+    """Roofline object of the dominant kernel (avg_ms: per-launch device ms of
+    the three kernels)."""
+    dom = max(range(3), key=lambda k: avg_ms[k])
+    dense = variant == "dense"
+    if dom == 0 and dense:
+        A = algorithmic_bytes(inst, True) / (avg_ms[0] * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=A, peak=HBM_PEAK_GBS, unit="GB/s", frac=A / HBM_PEAK_GBS,
+                    traffic=measured_traffic("dense"))
+    elif dom == 0:
+        A = activity_flops(inst) / (avg_ms[0] * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=A, peak=FP32_VALU_TFLOPS, unit="TFLOP/s", frac=A / FP32_VALU_TFLOPS,
+                    traffic=measured_traffic("skip"))
+    else:
+        roof = dict(bound="alu", achieved=None, peak=FP32_VALU_TFLOPS, unit="TFLOP/s", frac=None, traffic=None)
+    roof["kernel"] = KERNELS[dom]
+    roof["avg_us"] = {KERNELS[k]: avg_ms[k] * 1e3 for k in range(3)}
+    roof["algorithmic_bytes_per_launch"] = algorithmic_bytes(inst, dense)
+    return roof
+
+
+def objective(inst, z):
+    import numpy as np
+    z = np.asarray(z, dtype=np.float64)
+    return float(np.sum(inst.C * np.sum(np.diff(z, axis=1) ** 2, axis=2)))
+
+
+def run_batched(K, warmup):
+    """256 ragged instances (p ~ U{4..128}, eta in {4, 8, 16}, swaps and
+    boxes, 2-D and 3-D) in one persistent launch, against the same instances
+    solved one after another with the plain solver for the same iterations."""
+    import numpy as np
+    import torch
+    from paper_1311_4527_amd import autotune, instances as I
+    from paper_1311_4527_amd.twa import Batch, Solver
+    insts = I.conf_batch()
+    F = sum(i.counts()["factors"] for i in insts)
+    tuner = Batch(insts)
+    log = []
+    block, groups = autotune.tune(tuner, iters=20, use_cache=False, log=log)
+    tuner.close()
+    B = Batch(insts)
+    B.twa_batch_config(block, groups)
+    B.twa_batch_iterate(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev_ms = B.twa_batch_iterate_timed(K)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    zb = [B.twa_batch_get_trajectories(i).cpu().numpy() for i in range(len(insts))]
+    B.close()
+    t_plain = 0.0
+    worst = 0.0
+    for i, inst in enumerate(insts):
+        S = Solver.from_instance(inst)
+        S.twa_iterate(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.twa_iterate(K)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        zp = S.twa_get_trajectories().cpu().numpy()
+        S.close()
+        Jb, Jp = objective(inst, zb[i]), objective(inst, zp)
+        worst = max(worst, abs(Jb - Jp) / max(Jp, 1e-30))
+    return dict(instances=len(insts), factors=F, iterations=K, warmup=warmup,
+                value=F * K / t_batch, unit="factor-updates/s", seconds=t_batch, device_ms=dev_ms,
+                plain_sequential=dict(value=F * K / t_plain, seconds=t_plain),
+                speedup=t_plain / t_batch, max_rel_objective_diff=worst,
+                autotune=dict(block=block, groups=groups, candidates=log))
+
+
+def run_adjoint(K=500):
+    """Forward K iterations alone, then forward with the start remembered plus
+    the adjoint (sqrt(K) checkpoints) on the p=256, eta=8 swap."""
+    import numpy as np
+    import torch
+    from paper_1311_4527_amd import instances as I
+    from paper_1311_4527_amd.twa import Solver, TWA_F_TAPE
+    inst = I.conf_adjoint(7)
+    S = Solver.from_instance(inst)
+    S.twa_iterate(K)                     # warm (graphs, clocks)
+    S.twa_set_init(inst.z0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.twa_iterate(K)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    S.close()
+    T = Solver.from_instance(inst, flags=TWA_F_TAPE)
+    v = torch.from_numpy(np.random.default_rng(0).normal(size=inst.z0.shape).astype(np.float32)).cuda()
+    T.twa_iterate(K)
+    T.twa_backward(v)                    # warm
+    T.twa_set_init(inst.z0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T.twa_iterate(K)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dx0, dxT, dr, _ = T.twa_backward(v)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ok = bool(torch.isfinite(dx0).all() and torch.isfinite(dr).all())
+    T.close()
+    c = inst.counts()
+    return dict(workload=f"{inst.name}: p={inst.p}, eta={inst.eta}, {c['edges']} edges", K=K,
+                checkpoint_every=int(np.ceil(np.sqrt(K))), forward_s=t_fwd, forward_taped_s=t1 - t0,
+                backward_s=t2 - t1, backward_over_forward=(t2 - t1) / t_fwd, finite=ok)
+
+
 def cpu_baseline(inst, budget_s=12.0):
     """The FP64 reference, untouched, on this host's cores: one untimed
     iteration, then iterations until about budget_s seconds have passed."""
@@ -105,7 +246,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--workload", default="box1024")
     ap.add_argument("--variant", choices=["dense", "skip"], default="dense")
-    ap.add_argument("--also", action="store_true", help="also time the other variant")
+    ap.add_argument("--only", action="store_true", help="time the chosen variant only (for profiling)")
+    ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (for hardware-counter scaling)")
@@ -128,42 +270,34 @@ def main():
     torch.cuda.set_device(0)
     inst = workload(args.workload)
     c = inst.counts()
-    dense = args.variant == "dense"
-    r = run_gpu(inst, dense, args.steps, args.warmup)
     F = c["factors"]
-    value = F * args.steps / r["seconds"]
-    ms = r["kernel_ms"]
-    avg = [m / args.steps for m in ms]
-    dom = max(range(3), key=lambda k: avg[k])
-    if dom == 0 and dense:
-        A = algorithmic_bytes(inst, True) / (avg[0] * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=A, peak=HBM_PEAK_GBS, unit="GB/s", frac=A / HBM_PEAK_GBS, traffic=None)
-    elif dom == 0:
-        A = activity_flops(inst) / (avg[0] * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=A, peak=FP32_VALU_TFLOPS, unit="TFLOP/s", frac=A / FP32_VALU_TFLOPS,
-                    traffic=None)
-    else:
-        roof = dict(bound="alu", achieved=None, peak=FP32_VALU_TFLOPS, unit="TFLOP/s", frac=None, traffic=None)
-    roof["kernel"] = KERNELS[dom]
-    roof["avg_us"] = {KERNELS[k]: avg[k] * 1e3 for k in range(3)}
-    roof["algorithmic_bytes_per_launch"] = algorithmic_bytes(inst, dense)
+    r = run_gpu(inst, args.variant == "dense", args.steps, args.warmup)
+    avg = [m / args.steps for m in r["kernel_ms"]]
     out = dict(metric="TWA factor-prox updates/s (all factors, one full iteration = one step)",
-               value=value, unit="factor-updates/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-               ms_per_step=1e3 * r["seconds"] / args.steps, higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype="f32", data="synthetic",
+               value=F * args.steps / r["seconds"], unit="factor-updates/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=1e3 * r["seconds"] / args.steps, higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload=f"{inst.name}: random box p={inst.p}, eta={inst.eta}, {inst.n_walls} walls, "
-                                    f"r=0.005, FP32 ({c['coll']} collision + {c['wall']} wall + {c['energy']} "
-                                    f"energy + {c['fixed']} fixed factors, {c['edges']} edges)",
+                                    f"r={float(inst.radii[0])}, FP32 ({c['coll']} collision + {c['wall']} wall + "
+                                    f"{c['energy']} energy + {c['fixed']} fixed factors, {c['edges']} edges)",
                            variant=args.variant, iterations_per_s=args.steps / r["seconds"]),
-               roofline=roof,
+               roofline=roofline(inst, args.variant, avg),
                active=r["stats"], objective=r["objective"])
-    if args.also:
-        r2 = run_gpu(inst, not dense, args.steps, args.warmup)
-        out["other_variant"] = dict(variant="skip" if dense else "dense",
-                                    value=F * args.steps / r2["seconds"],
-                                    ms_per_step=1e3 * r2["seconds"] / args.steps,
-                                    avg_us={KERNELS[k]: r2["kernel_ms"][k] / args.steps * 1e3 for k in range(3)},
-                                    objective=r2["objective"])
+    print(f"# main {args.variant}: {out['value']:.4g} factor-updates/s", file=sys.stderr, flush=True)
+    if not args.only:
+        other = "skip" if args.variant == "dense" else "dense"
+        r2 = run_gpu(inst, other == "dense", args.steps, args.warmup)
+        avg2 = [m / args.steps for m in r2["kernel_ms"]]
+        out["variants"] = {other: dict(value=F * args.steps / r2["seconds"],
+                                       ms_per_step=1e3 * r2["seconds"] / args.steps,
+                                       roofline=roofline(inst, other, avg2), objective=r2["objective"])}
+        print(f"# variant {other}: {out['variants'][other]['value']:.4g}", file=sys.stderr, flush=True)
+        out["batched"] = run_batched(args.batch_steps, 50)
+        print(f"# batched: {out['batched']['value']:.4g} (x{out['batched']['speedup']:.1f} vs sequential)",
+              file=sys.stderr, flush=True)
+        out["adjoint"] = run_adjoint(500)
+        print(f"# adjoint: backward/forward {out['adjoint']['backward_over_forward']:.2f}", file=sys.stderr,
+              flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(out), flush=True)

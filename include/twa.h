@@ -63,7 +63,11 @@ enum {
      * of App. B step 7.  Without it an edge whose factor sent weight 0 keeps
      * no u (it is zero by the update rule), and a bit per factor records
      * which factors carry one.  Results are identical. */
-    TWA_F_DENSE = 1u << 0
+    TWA_F_DENSE = 1u << 0,
+    /* Make twa_backward available: the solver remembers the state each run
+     * starts from (at create, twa_set_init and twa_set_state).  No cost per
+     * iteration. */
+    TWA_F_TAPE = 1u << 1
 };
 
 typedef struct {
@@ -141,6 +145,33 @@ twa_status twa_sizes(const twa_solver *s, long long *n_factors, long long *n_edg
 
 /* Scan z and u for NaN/Inf (synchronises): TWA_E_NUMERIC if any. */
 twa_status twa_check_finite(twa_solver *s);
+
+/*
+ * Reverse-mode gradient of a loss L(z^K) of the trajectories after the run
+ * (not a step of the paper: the derivative of its unrolled iterations).
+ * Needs TWA_F_TAPE at create.  The run is every iteration since the last
+ * twa_create / twa_set_init / twa_set_state, K = their number.  Each of the
+ * K iterations of App. B is differentiated with its discrete decisions held
+ * at the forward run's (the 0 / rho0 / infinity weights, and which candidate
+ * configuration each collision and wall minimiser took); the minimisers'
+ * derivatives come from their optimality conditions (App. C, D, E, I).
+ *   dL_dz  [p][eta+1][dim]  dL/dz^K (read).
+ *   dL_dx0 [p][dim]         dL/dx(0) (written): through the fixed start
+ *                           factors and break-point 0 of the initial state.
+ *   dL_dxT [p][dim]         dL/dx(T) (written), likewise.
+ *   dL_dr  [p]              dL/dr_i (written), through the active collision
+ *                           and wall minimisers.
+ *   dL_dz0 [p][eta+1][dim]  dL/dz^0 at the interior break-points (written;
+ *                           0 at s = 0 and s = eta), or NULL.
+ * All device arrays, caller-owned.  The initial u is held constant.
+ * Checkpoints every ceil(sqrt(K)) iterations and recomputes one segment at
+ * a time: about 2 sqrt(K) copies of (z, u, <-rho), allocated for the call
+ * and freed before it returns (TWA_E_NOMEM if they do not fit).  The solver's
+ * forward state is the same afterwards.  dim == 2 only (TWA_E_INVALID
+ * otherwise); TWA_E_STATE without TWA_F_TAPE.  Synchronises the stream.
+ */
+twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT, float *dL_dr,
+                        float *dL_dz0);
 
 /* Text of the last error on this solver ("" if none). */
 const char *twa_last_error(const twa_solver *s);

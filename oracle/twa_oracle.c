@@ -1124,9 +1124,12 @@ double tor_min_clearance(int p, int eta, int dim, const double *radii, const dou
  *   step 5  z' = weighted mean of m over the edges that carried weight
  *   step 4  m = x + u
  *   step 2  x = g(n): each minimiser's local Jacobian (with respect to its
- *           n-messages and its radius) by FP64 central differences; the
- *           energy minimiser is linear in n; a fixed factor's x is the
- *           start or goal itself
+ *           n-messages and its radius) by FP64 central differences with a
+ *           step of 1e-9, small enough to stay inside the smooth piece the
+ *           input lies on (the minimisers are piecewise smooth: a segment
+ *           end that is pushed or just clear of the separating line, the
+ *           candidate that wins); the energy minimiser is linear in n; a
+ *           fixed factor's x is the start or goal itself
  *   step 1  n = z - u
  */
 static void coll_eval(tor_t *T, long f, const double *nin, double R, const double *w, double *xout) {
@@ -1253,7 +1256,7 @@ void tor_backward(void *h, const double *dz, double *dx0, double *dxT, double *d
                     else R = T->radii[T->fa[f]];
                     double base[12], xp[12], xm[12];
                     for (int q = 0; q < nin; q++) base[q] = n[e0 * dim + q];
-                    double sc = 1e-6;
+                    double sc = 1e-9; /* inside one smooth piece of the minimiser */
                     for (int q = 0; q <= nin; q++) {
                         double in_p[12], in_m[12], Rp = R, Rm = R;
                         memcpy(in_p, base, sizeof(double) * nin);

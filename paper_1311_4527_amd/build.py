@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", "twa.hip")]
+SRC = [os.path.join(HERE, "csrc", "twa.hip"), os.path.join(HERE, "csrc", "adjoint.hip")]
 LIB = os.path.join(HERE, "libtwa.so")
 ARCH = os.environ.get("TWA_OFFLOAD_ARCH", "gfx950")
 

@@ -336,9 +336,18 @@ TWA_HD void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R,
     int nt = trs_global(g, &t0, &alt);
     consider(t0, CH_T);
     if (nt == 2) consider(alt, CH_T);
+    // one end pushed straight out while the other is clear: the stationary
+    // point of the one-sided piece (with both ends pushed the tangent
+    // family above already holds the minimum)
     float q0 = dot(m0, m0), q1 = dot(m1, m1);
-    if (q0 > 0.f && q0 < R * R) consider(scl(m0, inv_sqrt(q0)), CH_R0);
-    if (q1 > 0.f && q1 < R * R) consider(scl(m1, inv_sqrt(q1)), CH_R1);
+    if (q0 > 0.f && q0 < R * R) {
+        f2 u = scl(m0, inv_sqrt(q0));
+        if (dot(m1, u) >= R) consider(u, CH_R0);
+    }
+    if (q1 > 0.f && q1 < R * R) {
+        f2 u = scl(m1, inv_sqrt(q1));
+        if (dot(m0, u) >= R) consider(u, CH_R1);
+    }
     v0 = add(m0, scl(best, pos(R - dot(m0, best))));
     v1 = add(m1, scl(best, pos(R - dot(m1, best))));
     if (ch) {
@@ -467,16 +476,18 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
         consider(sw, CH_FLAT, 0);
         consider(scl(sw, -1.f), CH_FLAT, 0);
     }
-    // (b) nearest boundary point of one end
+    // (b) nearest boundary point of one end while the other end is clear
     for (int e = 0; e < 2; ++e) {
-        f2 n = e ? n1 : n0;
+        f2 n = e ? n1 : n0, other = e ? n0 : n1;
         float tpar = seg ? fminf(fmaxf(dot(sub(n, C.a), d) / L2, 0.f), 1.f) : 0.f;
         f2 c = closest_on_seg(n, C.a, C.b);
         f2 t = sub(n, c);
         float tt = dot(t, t);
-        if (tt > 0.f && tt < C.r * C.r)
-            consider(scl(t, inv_sqrt(tt)), (tpar > 0.f && tpar < 1.f) ? CH_FLAT : (e ? CH_R1 : CH_R0),
-                     (seg && tpar >= 1.f) ? 1 : 0);
+        if (tt > 0.f && tt < C.r * C.r) {
+            f2 u = scl(t, inv_sqrt(tt));
+            if (dot(other, u) >= cap_h(C, u))
+                consider(u, (tpar > 0.f && tpar < 1.f) ? CH_FLAT : (e ? CH_R1 : CH_R0), (seg && tpar >= 1.f) ? 1 : 0);
+        }
     }
     float h = cap_h(C, best);
     x0 = add(n0, scl(best, pos(h - dot(n0, best))));

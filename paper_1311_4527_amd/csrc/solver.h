@@ -1,0 +1,123 @@
+// solver.h -- state of one planner instance shared by the translation
+// units of libtwa.so (forward iteration in twa.hip, adjoint in adjoint.hip).
+// Internal: not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/twa.h"
+#include "prox.h"
+
+namespace twa_rt {
+
+// a zero weight enters the minimisers as a small equal value (App. C-E)
+constexpr float kZeroWeight = 1e-9f;
+
+// weight value of a <-rho code under standard weight rho (infinity is
+// carried by the code; its value slot is unused)
+__host__ __device__ __forceinline__ float wval(int code, float rho) {
+    return code == twa::W_STD ? rho : (code == twa::W_ZERO ? kZeroWeight * rho : 0.f);
+}
+
+struct Params {
+    int p, eta, W, dim;
+    long long Fc, Fw, Fe, Ff;
+    long long nbc, nbw, nbe, nbf; // blocks per factor kind in k_stream
+    // node records, time-major (s * p + i): x, y, z, <-rho code
+    float4 *zr_prev, *zr_cur;
+    const float *radii;  // [p]
+    const float4 *walls; // [W] (xL.x, xL.y, xR.x, xR.y)
+    const float *C;      // [p][eta]
+    const float4 *xfix;  // [2p] start(i), goal(i)
+    float4 *u_coll;      // [dim planes][Fc]
+    float4 *u_wall;      // [Fw]
+    float *u_energy;     // [Fe][2*dim]
+    float *u_fixed;      // [2p][dim]
+    unsigned *bits_coll, *bits_wall;
+    unsigned *qc, *qw;
+    int *counters; // [0] qc length, [1] qw length, [2] active coll, [3] active wall
+    int *stats;    // last iteration: active coll, active wall, queued
+    unsigned long long *acc; // [2 kinds][dim][N]  kind 0 = std, 1 = inf
+    int *cnt;                // [2][N]
+    float4 *inf_val;         // [N] m of a node's certain edge, kept exact when it is the only one
+    float4 *x_coll;          // [dim planes][Fc] x of factors active in the last iteration
+    float4 *x_wall;          // [Fw]
+    const unsigned long long *wbase_coll; // per 64 factors: (s, i, j) of the first, packed 16|24|24 bits
+    const unsigned long long *wbase_wall; // per 64 factors: (s, i, w) of the first
+    long long N;
+    double scale;
+    float scalef;
+    float rho, step;      // this iteration: weight value of rho0, alpha/rho0
+    float rho_prev, step_prev;
+    int dense;
+    // debug capture of this iteration
+    float *dbg_x;
+    unsigned char *dbg_rho;
+    long long e_energy, e_coll, e_wall; // canonical edge offsets
+    long long f_energy, f_coll, f_wall; // canonical factor offsets
+};
+
+} // namespace twa_rt
+
+struct twa_solver {
+    int p = 0, eta = 0, dim = 0, W = 0;
+    float rho0 = 1.f, alpha = 1.f, rho0_init = 1.f;
+    int n_warm = 0;
+    unsigned flags = 0;
+    long long iter = 0;
+    bool pending = false;
+    hipStream_t stream = nullptr;
+    twa_rt::Params P{};
+    int *stats_dev = nullptr;
+    int *bad_dev = nullptr;
+    std::vector<void *> allocs;
+    std::string err;
+    twa_status latched = TWA_OK;
+    float *dbg_x = nullptr;
+    unsigned char *dbg_rho = nullptr;
+    long long nblocks_stream = 0;
+    int nblocks_queue = 0;
+    // event timing (twa_iterate_timed): 1 = a new event per mark, 2 = the
+    // preallocated events of the graph being captured
+    std::vector<hipEvent_t> events;
+    int timing = 0;
+    // HIP graphs of kGraphIters fused iterations (plain, and with events)
+    hipGraphExec_t graph = nullptr, graph_timed = nullptr;
+    std::vector<hipEvent_t> gevents;
+    size_t gev_next = 0;
+    bool graph_failed = false;
+    // TWA_F_TAPE: the state the differentiated run starts from (canonical
+    // layouts), saved by create / set_init / set_state
+    float *origin_z = nullptr, *origin_u = nullptr;
+    unsigned char *origin_l = nullptr;
+    long long origin_iter = 0;
+};
+
+namespace twa_rt {
+
+// record an error on the solver (device errors latch) and return st
+twa_status fail(twa_solver *s, twa_status st, const std::string &msg);
+// TWA_E_INVALID for NULL, the latched error if any, else TWA_OK
+twa_status check_alive(twa_solver *s);
+// weight value rho0 of iteration k under the warm-up schedule
+float rho_at(const twa_solver *s, long long k);
+// replace the state (canonical device arrays) without touching the start
+// of the differentiated run
+twa_status import_state(twa_solver *s, const float *z, const float *u, const unsigned char *lrho, long long iter);
+
+} // namespace twa_rt
+
+#define HIP_TRY(s, call)                                                                                       \
+    do {                                                                                                       \
+        hipError_t e_ = (call);                                                                                \
+        if (e_ != hipSuccess)                                                                                  \
+            return twa_rt::fail((s), TWA_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+#define TRY(x)                                                                                                 \
+    do {                                                                                                       \
+        twa_status st_ = (x);                                                                                  \
+        if (st_ != TWA_OK) return st_;                                                                         \
+    } while (0)

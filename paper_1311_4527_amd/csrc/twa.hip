@@ -31,15 +31,16 @@
 
 #include "../../include/twa.h"
 #include "prox.h"
+#include "solver.h"
 
 using namespace twa;
+using twa_rt::Params;
 
 #define TWA_VERSION "twa-mi355x 0.1"
 
 namespace {
 
 constexpr int kBlock = 256;
-constexpr float kZeroWeight = 1e-9f; // a zero weight is replaced by a small equal value (App. C-E)
 
 enum Mode : int { M_FIRST = 0, M_FUSED = 1, M_FINAL = 2 };
 
@@ -47,47 +48,9 @@ enum Mode : int { M_FIRST = 0, M_FUSED = 1, M_FINAL = 2 };
 constexpr unsigned kPrev = 0x80000000u; // factor was active last iteration: recompute and update u
 constexpr unsigned kIdx = 0x7fffffffu;
 
-struct Params {
-    int p, eta, W, dim;
-    long long Fc, Fw, Fe, Ff;
-    long long nbc, nbw, nbe, nbf; // blocks per factor kind in k_stream
-    // node records, time-major (s * p + i): x, y, z, <-rho code
-    float4 *zr_prev, *zr_cur;
-    const float *radii;  // [p]
-    const float4 *walls; // [W] (xL.x, xL.y, xR.x, xR.y)
-    const float *C;      // [p][eta]
-    const float4 *xfix;  // [2p] start(i), goal(i)
-    float4 *u_coll;      // [dim planes][Fc]
-    float4 *u_wall;      // [Fw]
-    float *u_energy;     // [Fe][2*dim]
-    float *u_fixed;      // [2p][dim]
-    unsigned *bits_coll, *bits_wall;
-    unsigned *qc, *qw;
-    int *counters; // [0] qc length, [1] qw length, [2] active coll, [3] active wall
-    int *stats;    // last iteration: active coll, active wall, queued
-    unsigned long long *acc; // [2 kinds][dim][N]  kind 0 = std, 1 = inf
-    int *cnt;                // [2][N]
-    float4 *inf_val;         // [N] m of a node's certain edge, kept exact when it is the only one
-    float4 *x_coll;          // [dim planes][Fc] x of factors active in the last iteration
-    float4 *x_wall;          // [Fw]
-    const unsigned long long *wbase_coll; // per 64 factors: (s, i, j) of the first, packed 16|24|24 bits
-    const unsigned long long *wbase_wall; // per 64 factors: (s, i, w) of the first
-    long long N;
-    double scale;
-    float scalef;
-    float rho, step;      // this iteration: weight value of rho0, alpha/rho0
-    float rho_prev, step_prev;
-    int dense;
-    // debug capture of this iteration
-    float *dbg_x;
-    unsigned char *dbg_rho;
-    long long e_energy, e_coll, e_wall; // canonical edge offsets
-    long long f_energy, f_coll, f_wall; // canonical factor offsets
-};
 
-__device__ __forceinline__ float wval(int code, float rho) {
-    return code == W_STD ? rho : (code == W_ZERO ? kZeroWeight * rho : 0.f);
-}
+
+using twa_rt::wval;
 
 __device__ __forceinline__ int wcode(float4 r) { return (int)r.w; }
 
@@ -764,34 +727,29 @@ __global__ void k_finite(const float4 *zr, long long N, const float *u, long lon
 // host runtime
 // ============================================================================
 
-struct twa_solver {
-    int p = 0, eta = 0, dim = 0, W = 0;
-    float rho0 = 1.f, alpha = 1.f, rho0_init = 1.f;
-    int n_warm = 0;
-    unsigned flags = 0;
-    long long iter = 0;
-    bool pending = false;
-    hipStream_t stream = nullptr;
-    Params P{};
-    int *stats_dev = nullptr;
-    int *bad_dev = nullptr;
-    std::vector<void *> allocs;
-    std::string err;
-    twa_status latched = TWA_OK;
-    float *dbg_x = nullptr;
-    unsigned char *dbg_rho = nullptr;
-    long long nblocks_stream = 0;
-    int nblocks_queue = 0;
-    // event timing (twa_iterate_timed): 1 = a new event per mark, 2 = the
-    // preallocated events of the graph being captured
-    std::vector<hipEvent_t> events;
-    int timing = 0;
-    // HIP graphs of kGraphIters fused iterations (plain, and with events)
-    hipGraphExec_t graph = nullptr, graph_timed = nullptr;
-    std::vector<hipEvent_t> gevents;
-    size_t gev_next = 0;
-    bool graph_failed = false;
-};
+namespace twa_rt {
+
+twa_status fail(twa_solver *s, twa_status st, const std::string &msg) {
+    if (s) {
+        s->err = msg;
+        if (st == TWA_E_DEVICE) s->latched = TWA_E_DEVICE;
+    }
+    return st;
+}
+
+twa_status check_alive(twa_solver *s) {
+    if (!s) return TWA_E_INVALID;
+    if (s->latched != TWA_OK) return s->latched;
+    return TWA_OK;
+}
+
+float rho_at(const twa_solver *s, long long k) { return k < s->n_warm ? s->rho0_init : s->rho0; }
+
+} // namespace twa_rt
+
+using twa_rt::check_alive;
+using twa_rt::fail;
+using twa_rt::rho_at;
 
 namespace {
 
@@ -809,20 +767,6 @@ void mark(twa_solver *s, int slot) {
     }
 }
 
-twa_status fail(twa_solver *s, twa_status st, const std::string &msg) {
-    if (s) {
-        s->err = msg;
-        if (st == TWA_E_DEVICE) s->latched = TWA_E_DEVICE;
-    }
-    return st;
-}
-
-#define HIP_TRY(s, call)                                                                                       \
-    do {                                                                                                       \
-        hipError_t e_ = (call);                                                                                \
-        if (e_ != hipSuccess)                                                                                  \
-            return fail((s), TWA_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));                 \
-    } while (0)
 
 template <class T>
 twa_status dev_alloc(twa_solver *s, T **ptr, size_t count) {
@@ -847,17 +791,6 @@ twa_status to_host(twa_solver *s, std::vector<T> &dst, const T *src, size_t coun
     return TWA_OK;
 }
 
-#define TRY(x)                                                                                                 \
-    do {                                                                                                       \
-        twa_status st_ = (x);                                                                                  \
-        if (st_ != TWA_OK) return st_;                                                                         \
-    } while (0)
-
-twa_status check_alive(twa_solver *s) {
-    if (!s) return TWA_E_INVALID;
-    if (s->latched != TWA_OK) return s->latched;
-    return TWA_OK;
-}
 
 void mark(twa_solver *s, int slot);
 
@@ -905,7 +838,6 @@ twa_status run_iteration(twa_solver *s, int mode, float rho, float rho_prev) {
     return st;
 }
 
-float rho_at(const twa_solver *s, long long k) { return k < s->n_warm ? s->rho0_init : s->rho0; }
 
 // Capture kGraphIters fused iterations at the steady rho0 into a graph
 // (timed: with an event before and after every launch).  Returns false if
@@ -1010,6 +942,25 @@ twa_status reset_state_buffers(twa_solver *s) {
     return TWA_OK;
 }
 
+// canonical z, u, <-rho of a state without a pending u update
+__global__ void k_z_export(const float4 *zr, float *z, unsigned char *lrho, int p, int eta, int D);
+__global__ void k_u_convert(Params P, float *u, int D, int dir);
+
+// TWA_F_TAPE: remember the current (settled) state as the start of the
+// differentiated run
+twa_status save_origin(twa_solver *s) {
+    if (!(s->flags & TWA_F_TAPE)) return TWA_OK;
+    unsigned nb = (unsigned)((s->P.N + 255) / 256);
+    hipLaunchKernelGGL(k_z_export, dim3(nb), dim3(256), 0, s->stream, (const float4 *)s->P.zr_cur, s->origin_z,
+                       s->origin_l, s->p, s->eta, s->dim);
+    long long E = s->P.e_wall + 2 * s->P.Fw;
+    hipLaunchKernelGGL(k_u_convert, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s->stream, s->P, s->origin_u,
+                       s->dim, 1);
+    HIP_TRY(s, hipGetLastError());
+    s->origin_iter = s->iter;
+    return TWA_OK;
+}
+
 bool finite_all(const std::vector<float> &v) {
     for (float x : v)
         if (!std::isfinite(x)) return false;
@@ -1017,6 +968,27 @@ bool finite_all(const std::vector<float> &v) {
 }
 
 } // namespace
+
+namespace twa_rt {
+
+twa_status import_state(twa_solver *s, const float *z, const float *u, const unsigned char *lrho, long long iter) {
+    TRY(check_alive(s));
+    if (!z || !u || !lrho) return fail(s, TWA_E_INVALID, "null state array");
+    if (iter < 0) return fail(s, TWA_E_INVALID, "iter must be >= 0");
+    TRY(reset_state_buffers(s));
+    unsigned nb = (unsigned)((s->P.N + 255) / 256);
+    hipLaunchKernelGGL(k_z_import, dim3(nb), dim3(256), 0, s->stream, s->P.zr_cur, z, s->p, s->eta, s->dim, lrho, 1);
+    long long E = s->P.e_wall + 2 * s->P.Fw;
+    hipLaunchKernelGGL(k_u_convert, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s->stream, s->P,
+                       const_cast<float *>(u), s->dim, 0);
+    HIP_TRY(s, hipGetLastError());
+    HIP_TRY(s, hipMemcpyAsync(s->P.zr_prev, s->P.zr_cur, sizeof(float4) * s->P.N, hipMemcpyDeviceToDevice, s->stream));
+    s->iter = iter;
+    s->pending = false;
+    return TWA_OK;
+}
+
+} // namespace twa_rt
 
 extern "C" {
 
@@ -1064,7 +1036,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         fail(s, TWA_E_INVALID, "rho0 and alpha must be finite and > 0");
         return bail(TWA_E_INVALID);
     }
-    if (flags & ~(unsigned)(TWA_F_DENSE)) {
+    if (flags & ~(unsigned)(TWA_F_DENSE | TWA_F_TAPE)) {
         fail(s, TWA_E_INVALID, "unsupported flag");
         return bail(TWA_E_INVALID);
     }
@@ -1176,6 +1148,10 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         dev_alloc(s, &wbw_d, (size_t)std::max<long long>(1, (Fw + 63) / 64)) ||
         dev_alloc(s, &s->stats_dev, 4) || dev_alloc(s, &s->bad_dev, 1))
         return bail(TWA_E_NOMEM);
+    if ((flags & TWA_F_TAPE) &&
+        (dev_alloc(s, &s->origin_z, (size_t)P.N * dim) ||
+         dev_alloc(s, &s->origin_u, (size_t)(P.e_wall + 2 * Fw) * dim) || dev_alloc(s, &s->origin_l, (size_t)P.N)))
+        return bail(TWA_E_NOMEM);
     P.radii = radii_d, P.C = C_d, P.walls = walls_d, P.xfix = xfix_d;
     P.wbase_coll = wbc_d, P.wbase_wall = wbw_d;
     // (s, i, j) / (s, i, w) of the first factor of every 64, in canonical order
@@ -1240,6 +1216,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         return bail(TWA_E_DEVICE);
     }
     if (reset_state_buffers(s) != TWA_OK) return bail(TWA_E_DEVICE);
+    if (save_origin(s) != TWA_OK) return bail(TWA_E_DEVICE);
     if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(TWA_E_DEVICE);
     *out = s;
     return TWA_OK;
@@ -1260,7 +1237,7 @@ twa_status twa_set_init(twa_solver *s, const float *z) {
     HIP_TRY(s, hipMemcpyAsync(s->P.zr_prev, s->P.zr_cur, sizeof(float4) * N, hipMemcpyDeviceToDevice, s->stream));
     TRY(reset_state_buffers(s));
     s->iter = 0;
-    return TWA_OK;
+    return save_origin(s);
 }
 
 twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm) {
@@ -1336,20 +1313,8 @@ twa_status twa_get_state(twa_solver *s, float *z, float *u, unsigned char *lrho,
 }
 
 twa_status twa_set_state(twa_solver *s, const float *z, const float *u, const unsigned char *lrho, long long iter) {
-    TRY(check_alive(s));
-    if (!z || !u || !lrho) return fail(s, TWA_E_INVALID, "null state array");
-    if (iter < 0) return fail(s, TWA_E_INVALID, "iter must be >= 0");
-    TRY(reset_state_buffers(s));
-    unsigned nb = (unsigned)((s->P.N + 255) / 256);
-    hipLaunchKernelGGL(k_z_import, dim3(nb), dim3(256), 0, s->stream, s->P.zr_cur, z, s->p, s->eta, s->dim, lrho, 1);
-    long long E = s->P.e_wall + 2 * s->P.Fw;
-    hipLaunchKernelGGL(k_u_convert, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s->stream, s->P,
-                       const_cast<float *>(u), s->dim, 0);
-    HIP_TRY(s, hipGetLastError());
-    HIP_TRY(s, hipMemcpyAsync(s->P.zr_prev, s->P.zr_cur, sizeof(float4) * s->P.N, hipMemcpyDeviceToDevice, s->stream));
-    s->iter = iter;
-    s->pending = false;
-    return TWA_OK;
+    TRY(twa_rt::import_state(s, z, u, lrho, iter));
+    return save_origin(s);
 }
 
 twa_status twa_get_stats(twa_solver *s, twa_stats *out) {

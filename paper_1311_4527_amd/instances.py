@@ -85,6 +85,17 @@ def circle_swap(p: int, r: float, eta: int, *, dim: int = 2, radius: float = 1.0
     xT = -x0.copy()
     if goal_sigma > 0:
         xT[:, :2] += rng.normal(0.0, goal_sigma, size=(p, 2))
+        # goals must stay pairwise >= 2r apart: redraw the perturbation of
+        # the later agent of every overlapping pair until none is left
+        for _ in range(10000):
+            d2 = np.sum((xT[:, None, :] - xT[None, :, :]) ** 2, axis=2)
+            np.fill_diagonal(d2, np.inf)
+            bad = np.unique(np.nonzero(np.triu(d2 < (2.0 * r) ** 2))[1])
+            if bad.size == 0:
+                break
+            xT[bad, :2] = -x0[bad, :2] + rng.normal(0.0, goal_sigma, size=(bad.size, 2))
+        else:
+            raise RuntimeError("goal perturbation did not separate the goals")
     z0 = _line_init(x0, xT, eta, rng, sigma)
     return Instance(p=p, eta=eta, dim=dim, radii=np.full(p, float(r)), x0=x0, xT=xT,
                     walls=np.zeros((0, 2, dim)), C=np.full((p, eta), float(C)), z0=z0,

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libtwa.so")
 TWA_OK, TWA_E_INVALID, TWA_E_INFEASIBLE, TWA_E_NOMEM, TWA_E_DEVICE, TWA_E_NUMERIC, TWA_E_STATE = range(7)
 TWA_W_ZERO, TWA_W_STD, TWA_W_INF = 0, 1, 2
 TWA_F_DENSE = 1
+TWA_F_TAPE = 2
 _STATUS = {0: "TWA_OK", 1: "TWA_E_INVALID", 2: "TWA_E_INFEASIBLE", 3: "TWA_E_NOMEM", 4: "TWA_E_DEVICE",
            5: "TWA_E_NUMERIC", 6: "TWA_E_STATE"}
 
@@ -73,6 +74,8 @@ def load_library():
     lib.twa_sizes.argtypes = [_vp, ct.POINTER(ct.c_longlong), ct.POINTER(ct.c_longlong)]
     lib.twa_check_finite.restype = ct.c_int
     lib.twa_check_finite.argtypes = [_vp]
+    lib.twa_backward.restype = ct.c_int
+    lib.twa_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     lib.twa_last_error.restype = ct.c_char_p
     lib.twa_last_error.argtypes = [_vp]
     lib.twa_destroy.restype = None
@@ -221,6 +224,18 @@ class Solver:
 
     def twa_check_finite(self):
         self._check(load_library().twa_check_finite(self.h))
+
+    def twa_backward(self, dL_dz, want_dz0: bool = True):
+        """Gradient of L(z^K) for the run since the last create / set_init /
+        set_state (solver created with TWA_F_TAPE): returns (dL/dx0 [p][dim],
+        dL/dxT [p][dim], dL/dr [p], dL/dz0 [p][eta+1][dim] or None)."""
+        dz = _dev(dL_dz, device=self.device).reshape(self.p, self.eta + 1, self.dim)
+        dx0 = torch.empty((self.p, self.dim), dtype=torch.float32, device=self.device)
+        dxT = torch.empty_like(dx0)
+        dr = torch.empty((self.p,), dtype=torch.float32, device=self.device)
+        dz0 = torch.empty_like(dz) if want_dz0 else None
+        self._check(load_library().twa_backward(self.h, _ptr(dz), _ptr(dx0), _ptr(dxT), _ptr(dr), _ptr(dz0)))
+        return dx0, dxT, dr, dz0
 
     # -- convenience
     def step_debug(self):

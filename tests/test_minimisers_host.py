@@ -291,3 +291,47 @@ def test_energy_vjp_matches_reference_differences(H):
             b = np.zeros(1, np.float32)
             H.h_energy_vjp(wl, wh, kl, kh, C, xlb, xhb, a.ctypes.data_as(_fp), b.ctypes.data_as(_fp))
             assert np.allclose([a[0], b[0]], fd, rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("ratio", [0.5, 0.9, -0.4])
+def test_coll_vjp_parallel_differences(H, ratio):
+    """Both relative positions on one line through the origin and inside the
+    disk (agents heading straight at each other, the straight-line start of a
+    circle swap): the minimiser is the tangent-family stationary point, whose
+    derivative the VJP must give (a radial push of one end alone would be a
+    tie in value but not in derivative)."""
+    H.h_coll_vjp.argtypes = [_fp, _fp, _i32, ct.c_float, _fp, _fp, _fp]
+    rng = np.random.default_rng(int(1000 * (ratio + 1)))
+    R = 0.6
+    checked = 0
+    for _ in range(200):
+        d = rng.normal(size=2)
+        d /= np.linalg.norm(d)
+        a = rng.uniform(0.05, 0.5)
+        base = rng.normal(0, 0.3, size=(2, 2))
+        m0, m1 = a * d, ratio * a * d + rng.normal(0, 1e-4, size=2)
+        n = np.array([base[0], base[1], base[0] + m0, base[1] + m1])
+        n = _f32(n).astype(np.float64)
+        act, xr, gap = ref_coll(n, [1.0] * 4, R)
+        if not act or gap < 1e-3:
+            continue
+        xb = rng.normal(size=8)
+        vec = np.concatenate([n.reshape(-1), [R]])
+
+        def fn(v):
+            return ref_coll(v[:8].reshape(4, 2), [1.0] * 4, v[8])[1]
+        fd1 = _fd_vjp(fn, vec, xb, 1e-9)
+        fd2 = _fd_vjp(fn, vec, xb, 1e-8)
+        if np.linalg.norm(fd1 - fd2) > 1e-4 * max(np.linalg.norm(fd1), 1.0):
+            continue
+        nb = np.zeros(8, np.float32)
+        Rb = np.zeros(1, np.float32)
+        H.h_coll_vjp(_f32(n.reshape(-1)).ctypes.data_as(_fp), _f32([1.0] * 4).ctypes.data_as(_fp),
+                     np.ones(4, np.int32).ctypes.data_as(_i32), R, _f32(xb).ctypes.data_as(_fp),
+                     nb.ctypes.data_as(_fp), Rb.ctypes.data_as(_fp))
+        got = np.concatenate([nb, Rb]).astype(np.float64)
+        assert _vjp_close(got, fd1), (n, got, fd1)
+        checked += 1
+        if checked >= 40:
+            break
+    assert checked >= 20
