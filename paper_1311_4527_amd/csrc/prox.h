@@ -198,37 +198,47 @@ TWA_HD int trs_global(const Eig2 &g, f2 *out, f2 *alt) {
     return 1;
 }
 
+// Root in (0, xm] of  bn^2/x^2 + bf^2/(gap - x)^2 = 1, where the left side
+// is convex in x with its minimum (< 1) at xm: Newton's method from x = |bn|
+// (where the left side is > 1) increases monotonically onto the root.
+TWA_HD float secular_side(float bn, float bf, float gap, float xm) {
+    float x = fabsf(bn);
+    for (int it = 0; it < 32; ++it) {
+        float y = gap - x;
+        float r1 = bn / x, r2 = bf / y;
+        float f = r1 * r1 + r2 * r2 - 1.f;
+        float fp = 2.f * (r2 * r2 / y - r1 * r1 / x);
+        float xn = x - f / fp;
+        if (!(xn > x)) break; // converged: rounding turns the step back
+        x = fminf(xn, xm);
+    }
+    return x;
+}
+
 // The two stationary points between the eigenvalues (a local minimum and a
 // local maximum), when they exist.  Returns how many were written.
+// With t = lambda - q1 they are the roots in (0, gap) of
+//     b1^2/t^2 + b2^2/(gap - t)^2 = 1,
+// whose left side is convex with its minimum at tm (closed form): when that
+// minimum is below 1 there is one root on each side of tm.  Each side is
+// solved in the distance from its own end (t, and gap - t), which keeps
+// full precision when the root lies close to that end.
 TWA_HD int trs_middle(const Eig2 &g, f2 *out) {
     float b1 = g.b1, b2 = g.b2, gap = g.gap;
     if (!(gap > 0.f) || b1 == 0.f || b2 == 0.f) return 0;
     float c1 = cbrtf(b1 * b1), c2 = cbrtf(b2 * b2);
-    float tm = gap * c1 / (c1 + c2); // t = lambda - q1 in (0, gap)
+    float tm = gap * c1 / (c1 + c2);
     float y1 = b1 / tm, y2 = b2 / (gap - tm);
     if (y1 * y1 + y2 * y2 >= 1.f) return 0;
-    int n = 0;
-    for (int side = 0; side < 2; ++side) {
-        float lo = side ? tm : 0.f, hi = side ? gap : tm;
-        for (int it = 0; it < 40; ++it) {
-            float mid = 0.5f * (lo + hi);
-            float a1 = b1 / mid, a2 = b2 / (gap - mid);
-            bool above = a1 * a1 + a2 * a2 > 1.f; // f > 0
-            // f decreases on (0, tm) and increases on (tm, gap)
-            if (side == 0) {
-                if (above) lo = mid;
-                else hi = mid;
-            } else {
-                if (above) hi = mid;
-                else lo = mid;
-            }
-        }
-        float t = 0.5f * (lo + hi);
-        float z1 = -b1 / t, z2 = b2 / (gap - t); // (q1 - lambda) = -t, (q2 - lambda) = gap - t
-        float inv = inv_sqrt(z1 * z1 + z2 * z2);
-        out[n++] = add(scl(g.v1, z1 * inv), scl(g.v2, z2 * inv));
+    float t = secular_side(b1, b2, gap, tm);
+    float sr = secular_side(b2, b1, gap, gap - tm);
+    // (q1 - lambda) = -t, (q2 - lambda) = gap - t
+    float z[2][2] = {{-b1 / t, b2 / (gap - t)}, {-b1 / (gap - sr), b2 / sr}};
+    for (int k = 0; k < 2; ++k) {
+        float inv = inv_sqrt(z[k][0] * z[k][0] + z[k][1] * z[k][1]);
+        out[k] = add(scl(g.v1, z[k][0] * inv), scl(g.v2, z[k][1] * inv));
     }
-    return n;
+    return 2;
 }
 
 // Q and b of E_c(u) = sum_k (w_k/2)(r - <m_k, u>)^2 up to a constant
@@ -307,13 +317,8 @@ TWA_HD void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R,
             if (dot(q, u) >= R) consider(u, CH_RADF);
         }
         f2 vm = (bg < INFINITY) ? add(m, scl(best, bg)) : m;
-        if (i0) {
-            v0 = m0;
-            v1 = vm;
-        } else {
-            v1 = m1;
-            v0 = vm;
-        }
+        v0 = i0 ? m0 : vm;
+        v1 = i0 ? vm : m1;
         if (ch) {
             ch->kind = bk;
             ch->u = best;
@@ -428,13 +433,8 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
             consider(scl(sw, -1.f), CH_FLAT, 0);
         }
         f2 xm = (bg < INFINITY) ? add(m, scl(best, bg)) : m;
-        if (i0) {
-            x0 = n0;
-            x1 = xm;
-        } else {
-            x1 = n1;
-            x0 = xm;
-        }
+        x0 = i0 ? n0 : xm;
+        x1 = i0 ? xm : n1;
         if (ch && bk != CH_NONE) {
             ch->kind = bk;
             ch->u = best;

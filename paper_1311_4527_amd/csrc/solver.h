@@ -25,6 +25,7 @@ struct Params {
     int p, eta, W, dim;
     long long Fc, Fw, Fe, Ff;
     long long nbc, nbw, nbe, nbf; // blocks per factor kind in k_stream
+    int cpw;                      // collision chunks of 64 per wave in k_stream
     // node records, time-major (s * p + i): x, y, z, <-rho code
     float4 *zr_prev, *zr_cur;
     const float *radii;  // [p]

@@ -361,7 +361,7 @@ __device__ __forceinline__ void fixed_stream(const Params &P, long long f) {
 // Queued collision factor (entry e): deferred u update, full minimiser,
 // consensus contributions.
 template <int D, int MODE>
-__device__ __forceinline__ void coll_queue(const Params &P, unsigned e) {
+__device__ __forceinline__ bool coll_queue(const Params &P, unsigned e) {
     const bool dense = P.dense != 0;
     long long f = e & kIdx;
     bool prev = (e & kPrev) != 0;
@@ -389,7 +389,7 @@ __device__ __forceinline__ void coll_queue(const Params &P, unsigned e) {
                     (k[q] == W_STD) ? u[q * D + c] + P.step_prev * (x[q * D + c] - zc[q * D + c]) : 0.f;
         if (MODE == M_FINAL) {
             store_u_coll<D>(P, f, u);
-            return;
+            return false;
         }
     } else if (MODE == M_FIRST) {
         load_u_coll<D>(P, f, u);
@@ -408,7 +408,6 @@ __device__ __forceinline__ void coll_queue(const Params &P, unsigned e) {
         }
         store_x_coll<D>(P, f, x);
         atomicOr(&P.bits_coll[f >> 5], 1u << (f & 31));
-        atomicAdd(&P.counters[2], 1);
     } else {
         for (int q = 0; q < 4 * D; ++q) x[q] = n[q];
     }
@@ -418,11 +417,12 @@ __device__ __forceinline__ void coll_queue(const Params &P, unsigned e) {
         for (int q = 0; q < 4 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
         P.dbg_rho[P.f_coll + f] = act ? W_STD : W_ZERO;
     }
+    return act;
 }
 
 // Queued wall factor (entry e).
 template <int MODE>
-__device__ __forceinline__ void wall_queue(const Params &P, unsigned e) {
+__device__ __forceinline__ bool wall_queue(const Params &P, unsigned e) {
     const bool dense = P.dense != 0;
     long long f = e & kIdx;
     bool prev = (e & kPrev) != 0;
@@ -446,7 +446,7 @@ __device__ __forceinline__ void wall_queue(const Params &P, unsigned e) {
         u.w = (kb == W_STD) ? u.w + P.step_prev * (x1.y - cb.y) : 0.f;
         if (MODE == M_FINAL) {
             P.u_wall[f] = u;
-            return;
+            return false;
         }
     } else if (MODE == M_FIRST) {
         u = P.u_wall[f];
@@ -461,7 +461,6 @@ __device__ __forceinline__ void wall_queue(const Params &P, unsigned e) {
         contribute(P, na, 0, m0, 2);
         contribute(P, nb, 0, m1, 2);
         atomicOr(&P.bits_wall[f >> 5], 1u << (f & 31));
-        atomicAdd(&P.counters[3], 1);
     }
     if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) P.u_wall[f] = u;
     if (P.dbg_x) {
@@ -470,6 +469,7 @@ __device__ __forceinline__ void wall_queue(const Params &P, unsigned e) {
         P.dbg_x[e0 * 2 + 2] = x1.x, P.dbg_x[e0 * 2 + 3] = x1.y;
         P.dbg_rho[P.f_wall + f] = act ? W_STD : W_ZERO;
     }
+    return act;
 }
 
 // Node nd: z and <-rho of the next iteration, shift records, clear sums.
@@ -516,16 +516,25 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
     long long b = blockIdx.x;
     const bool clear_bits = MODE != M_FINAL && P.dense == 0;
     if (b < P.nbc) {
-        long long f = b * kBlock + threadIdx.x;
-        bool valid = f < P.Fc, q;
-        unsigned val;
-        coll_stream<D, MODE>(P, f, valid, &q, &val);
-        if (clear_bits) {
-            // this iteration's bits are set by k_queue; clear this wave's words
-            __syncthreads();
-            if (valid && (f & 31) == 0) P.bits_coll[f >> 5] = 0u;
+        // each wave walks cpw consecutive chunks of 64 collision factors
+        const int lane = threadIdx.x & 63;
+        const long long wave = b * (kBlock / 64) + (threadIdx.x >> 6);
+        const long long nch = (P.Fc + 63) / 64;
+        for (int k = 0; k < P.cpw; ++k) {
+            const long long c = wave * P.cpw + k;
+            if (c >= nch) break;
+            long long f = c * 64 + lane;
+            bool valid = f < P.Fc, q;
+            unsigned val;
+            coll_stream<D, MODE>(P, f, valid, &q, &val);
+            if (clear_bits) {
+                // this iteration's bits are set by k_queue; the two words of
+                // this chunk were read by this wave only
+                __builtin_amdgcn_wave_barrier();
+                if (valid && (f & 31) == 0) P.bits_coll[f >> 5] = 0u;
+            }
+            push(P.qc, &P.counters[0], q, val);
         }
-        push(P.qc, &P.counters[0], q, val);
     } else if (b < P.nbc + P.nbw) {
         long long f = (b - P.nbc) * kBlock + threadIdx.x;
         bool valid = f < P.Fw, q;
@@ -545,14 +554,25 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
     }
 }
 
+// Queue entry t of a wave-uniform loop: collision entries first, wall
+// entries from the next multiple of 64 (a wave never mixes the two
+// minimisers, whose run times differ several-fold).
+template <int D, int MODE>
+__device__ __forceinline__ void queue_entry(const Params &P, long long t, int nqc, long long wall0, long long total) {
+    bool ac = false, aw = false;
+    if (t < nqc) ac = coll_queue<D, MODE>(P, P.qc[t]);
+    else if (t >= wall0 && t < total) aw = wall_queue<MODE>(P, P.qw[t - wall0]);
+    count_wave(&P.counters[2], ac);
+    count_wave(&P.counters[3], aw);
+}
+
 template <int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_queue(Params P) {
     const int nqc = P.counters[0], nqw = P.counters[1];
-    const long long total = (long long)nqc + nqw;
-    for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < total; t += (long long)gridDim.x * kBlock) {
-        if (t < nqc) coll_queue<D, MODE>(P, P.qc[t]);
-        else wall_queue<MODE>(P, P.qw[t - nqc]);
-    }
+    const long long wall0 = ((long long)nqc + 63) & ~63LL, total = wall0 + nqw;
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long t0 = (long long)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < total; t0 += stride)
+        queue_entry<D, MODE>(P, t0 + (threadIdx.x & 63), nqc, wall0, total);
 }
 
 __device__ __forceinline__ void close_counters(const Params &P) {
@@ -606,10 +626,9 @@ __device__ __forceinline__ void batch_instance(const Params &P) {
     __syncthreads();
     const int nqc = __atomic_load_n(&P.counters[0], __ATOMIC_RELAXED);
     const int nqw = __atomic_load_n(&P.counters[1], __ATOMIC_RELAXED);
-    for (int t = threadIdx.x; t < nqc + nqw; t += BLOCK) {
-        if (t < nqc) coll_queue<D, MODE>(P, P.qc[t]);
-        else wall_queue<MODE>(P, P.qw[t - nqc]);
-    }
+    const long long wall0 = ((long long)nqc + 63) & ~63LL, total = wall0 + nqw;
+    for (long long t0 = threadIdx.x & ~63; t0 < total; t0 += BLOCK)
+        queue_entry<D, MODE>(P, t0 + (threadIdx.x & 63), nqc, wall0, total);
     __syncthreads();
     if (threadIdx.x == 0) close_counters(P);
     for (long long nd = threadIdx.x; nd < P.N; nd += BLOCK) node_update<D>(P, nd);
@@ -1108,7 +1127,11 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     P.p = p, P.eta = eta, P.W = n_walls, P.dim = dim;
     P.Fc = Fc, P.Fw = Fw, P.Fe = Fe, P.Ff = Ff;
     P.N = (long long)p * (eta + 1);
-    P.nbc = (Fc + kBlock - 1) / kBlock;
+    // collision chunks (64 factors) per wave in k_stream: with activity bits
+    // the per-chunk work is short, and walking several amortises the wave
+    // launch; the dense form is bound by its u stream and keeps one
+    P.cpw = (flags & TWA_F_DENSE) ? 1 : 4;
+    P.nbc = ((Fc + 63) / 64 + (kBlock / 64) * P.cpw - 1) / ((kBlock / 64) * P.cpw);
     P.nbw = (Fw + kBlock - 1) / kBlock;
     P.nbe = (Fe + kBlock - 1) / kBlock;
     P.nbf = (Ff + kBlock - 1) / kBlock;
