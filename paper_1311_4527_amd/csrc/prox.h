@@ -59,6 +59,18 @@ TWA_HD float cpa_sq(f3 d0, f3 d1) {
     return dot3(v, v);
 }
 
+// Whether (1-a) d0 + a d1 comes closer to the origin than sqrt(R2) for some
+// a in [0, 1], without a division: the closest point is an end unless the
+// projection of the origin falls inside, and then its squared distance is
+// |d0 x e|^2 / |e|^2 with e = d1 - d0.
+TWA_HD bool cpa_below(f3 d0, f3 d1, float R2) {
+    f3 e = sub3(d1, d0);
+    if (dot3(d0, e) >= 0.f) return dot3(d0, d0) < R2;
+    if (dot3(d1, e) <= 0.f) return dot3(d1, d1) < R2;
+    f3 c{d0.y * e.z - d0.z * e.y, d0.z * e.x - d0.x * e.z, d0.x * e.y - d0.y * e.x};
+    return dot3(c, c) < R2 * dot3(e, e);
+}
+
 TWA_HD float point_seg_sq(f2 q, f2 a, f2 b) {
     f2 d = sub(b, a);
     float L2 = dot(d, d);

@@ -25,7 +25,7 @@ struct Params {
     int p, eta, W, dim;
     long long Fc, Fw, Fe, Ff;
     long long nbc, nbw, nbe, nbf; // blocks per factor kind in k_stream
-    int cpw;                      // collision chunks of 64 per wave in k_stream
+    int cpw;                      // break-point intervals per wave in k_stream
     // node records, time-major (s * p + i): x, y, z, <-rho code
     float4 *zr_prev, *zr_cur;
     const float *radii;  // [p]
@@ -36,7 +36,11 @@ struct Params {
     float4 *u_wall;      // [Fw]
     float *u_energy;     // [Fe][2*dim]
     float *u_fixed;      // [2p][dim]
-    unsigned *bits_coll, *bits_wall;
+    unsigned long long *bits_coll;      // [nch] activity of each collision chunk's pairs
+    unsigned *bits_wall;                // [Fw / 32] activity of wall factors
+    const unsigned long long *chunk_coll; // [cps] (i, j0) of each chunk of an interval, packed 24|24 bits
+    const int *rowchunk;                // [p] first chunk of row i within a break-point interval
+    long long nch, cps, P2;             // chunks, chunks per interval, pairs p(p-1)/2
     unsigned *qc, *qw;
     int *counters; // [0] qc length, [1] qw length, [2] active coll, [3] active wall
     int *stats;    // last iteration: active coll, active wall, queued

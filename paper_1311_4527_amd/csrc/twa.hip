@@ -157,7 +157,7 @@ __device__ __forceinline__ bool coll_active(const float *n, float R) {
     // n: 4 edges x D; relative positions agent j - agent i at s and s+1
     f3 d0{n[2 * D + 0] - n[0], n[2 * D + 1] - n[1], D == 3 ? n[2 * D + 2] - n[2] : 0.f};
     f3 d1{n[3 * D + 0] - n[D + 0], n[3 * D + 1] - n[D + 1], D == 3 ? n[3 * D + 2] - n[D + 2] : 0.f};
-    return cpa_sq(d0, d1) < R * R;
+    return cpa_below(d0, d1, R * R);
 }
 
 __device__ __forceinline__ void node_xyz(float4 r, float *z, int D) {
@@ -166,69 +166,168 @@ __device__ __forceinline__ void node_xyz(float4 r, float *z, int D) {
 }
 
 // ------------------------------------------------------------------ per-factor work
-// Collision factor f (valid lanes only do work): activity test; decides
-// whether the factor goes to the queue (written to *q, *val).
-template <int D, int MODE>
-__device__ __forceinline__ void coll_stream(const Params &P, long long f, bool valid, bool *q, unsigned *val) {
-    const bool dense = P.dense != 0;
+// Node record read through the scalar cache: for an address that is the
+// same for the whole wave (agent i of a collision column).  Only for arrays
+// the running kernel does not write.
+__device__ __forceinline__ float4 load_uniform(const float4 *p, long long idx) {
+    const __attribute__((address_space(4))) float *q = (const __attribute__((address_space(4))) float *)p + 4 * idx;
+    return make_float4(q[0], q[1], q[2], q[3]);
+}
+__device__ __forceinline__ float load_uniform(const float *p, long long idx) {
+    return ((const __attribute__((address_space(4))) float *)p)[idx];
+}
+
+// Collision factor f given its four node records ((i,s), (i,s+1), (j,s),
+// (j,s+1): current, and the previous iteration's for the dense form) and
+// its u as loaded: activity test on n = z - u and the queue decision.
+// word: the chunk's activity bits.
+template <int D, int MODE, bool DENSE>
+__device__ __forceinline__ bool coll_factor(const Params &P, long long f, float R, const float4 *rc, const float4 *rp,
+                                            float *u, unsigned long long word, int lane, unsigned *val) {
+    constexpr bool dense = DENSE;
     bool push_prev = false, push_new = false;
-    // (s, i, j) of the wavefront's first factor from a table, then walk per lane
-    int fw = __builtin_amdgcn_readfirstlane((int)f);
-    unsigned long long pk = P.wbase_coll[fw >> 6];
+    float n[4 * D];
+    bool check_cur = true;
+    if (MODE == M_FIRST) {
+        // u as loaded
+    } else if (dense) {
+        float zz[3];
+        for (int e = 0; e < 4; ++e) {
+            node_xyz(rp[e], zz, D);
+            for (int k = 0; k < D; ++k) n[e * D + k] = zz[k] - u[e * D + k];
+        }
+        if (coll_active<D>(n, R)) {
+            push_prev = true;
+            check_cur = false;
+        } else {
+            for (int k = 0; k < 4 * D; ++k) u[k] = 0.f;
+            store_u_coll<D>(P, f, u);
+        }
+    } else {
+        if ((word >> lane) & 1ull) {
+            push_prev = true;
+            check_cur = false;
+        } else {
+            for (int k = 0; k < 4 * D; ++k) u[k] = 0.f;
+        }
+    }
+    if (MODE == M_FINAL) {
+        check_cur = false;
+        if (!dense && !push_prev) store_u_coll<D>(P, f, u); // zero
+    }
+    if (check_cur) {
+        float zz[3];
+        for (int e = 0; e < 4; ++e) {
+            node_xyz(rc[e], zz, D);
+            for (int k = 0; k < D; ++k) n[e * D + k] = zz[k] - u[e * D + k];
+        }
+        push_new = coll_active<D>(n, R);
+        if (!push_new && P.dbg_x) {
+            long long e0 = P.e_coll + 4 * f;
+            for (int k = 0; k < 4 * D; ++k) P.dbg_x[e0 * D + k] = n[k];
+            P.dbg_rho[P.f_coll + f] = W_ZERO;
+        }
+    }
+    *val = (unsigned)f | (push_prev ? kPrev : 0u);
+    return push_prev || push_new;
+}
+
+// Collision column col: the pairs (i, j0 + lane) of one chunk of row i of
+// the pair triangle (rows are cut into chunks of 64, so i is the same for
+// the whole wave), over the break-point intervals s0 <= s < s1 <= s0 + CPW.
+// Every load of the column (node records of break-points s0..s1, agent i's
+// through the scalar cache; the chunks' activity words; u where it is read)
+// is issued before any factor is evaluated.  Each chunk's activity word is
+// cleared after it was read (k_queue sets it again for the factors active
+// in this iteration).
+template <int D, int MODE, int CPW, bool DENSE>
+__device__ __forceinline__ void coll_column(const Params &P, int col, int s0, int s1, int lane, bool clear_bits) {
+    constexpr bool need_prev = DENSE && MODE != M_FIRST;
+    constexpr bool need_u = DENSE || MODE == M_FIRST;
+    constexpr bool need_word = !DENSE && MODE != M_FIRST;
+    const int cu = __builtin_amdgcn_readfirstlane(col);
+    const unsigned long long pk = P.chunk_coll[cu];
+    const int i = (int)(pk >> 24), j0 = (int)(pk & 0xffffffull);
+    const int p = P.p;
+    const int j = j0 + lane;
+    const bool valid = j < p;
+    const int jj = valid ? j : j0; // in-bounds address for idle lanes
+    const float R = load_uniform(P.radii, i) + P.radii[jj];
+    // canonical index of (s, i, j) is s p(p-1)/2 + fr (all factor indices
+    // fit in 31 bits): row i of the triangle holds the pairs (i, j > i)
+    const unsigned fr = (unsigned)((long long)i * (2 * p - i - 1) / 2 + (j - i - 1));
+    const unsigned P2 = (unsigned)P.P2;
+    const float4 *ci = P.zr_cur + (long long)s0 * p + i, *cj = P.zr_cur + (long long)s0 * p + jj;
+    const float4 *pi_ = P.zr_prev + (long long)s0 * p + i, *pj_ = P.zr_prev + (long long)s0 * p + jj;
+    float4 ri[CPW + 1], rj[CPW + 1], pi[CPW + 1], pj[CPW + 1];
+    unsigned long long word[CPW];
+    float u[CPW][4 * D];
+#pragma unroll
+    for (int k = 0; k <= CPW; ++k) {
+        if (s0 + k <= s1) {
+            ri[k] = load_uniform(ci, k * p);
+            rj[k] = cj[k * p];
+            if (need_prev) {
+                pi[k] = load_uniform(pi_, k * p);
+                pj[k] = pj_[k * p];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+        word[k] = 0ull;
+        for (int q = 0; q < 4 * D; ++q) u[k][q] = 0.f;
+        if (s0 + k < s1) {
+            if (need_word) word[k] = P.bits_coll[(s0 + k) * (int)P.cps + cu];
+            if (need_u && valid) load_u_coll<D>(P, (s0 + k) * P2 + fr, u[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+        if (s0 + k < s1) {
+            const float4 rc[4] = {ri[k], ri[k + 1], rj[k], rj[k + 1]};
+            const float4 rp[4] = {pi[k], pi[k + 1], pj[k], pj[k + 1]};
+            bool q = false;
+            unsigned val = 0u;
+            if (valid) q = coll_factor<D, MODE, DENSE>(P, (s0 + k) * P2 + fr, R, rc, rp, u[k], word[k], lane, &val);
+            if (clear_bits && lane == 0) P.bits_coll[(s0 + k) * (int)P.cps + cu] = 0ull;
+            push(P.qc, &P.counters[0], q, val);
+        }
+    }
+}
+
+// Collision factor f of a flat walk over the canonical order (64
+// consecutive factors per wave, rows mixed): the batched kernel's form for
+// small instances, whose rows are shorter than a wave.  Reads the factor's
+// activity bit from its row chunk's word without clearing it (the words are
+// cleared in a separate pass once every factor has read its bit).
+template <int D, int MODE>
+__device__ __forceinline__ void coll_flat(const Params &P, long long f, bool valid) {
+    const bool dense = P.dense != 0;
+    const int fw = __builtin_amdgcn_readfirstlane((int)f);
+    const unsigned long long pk = P.wbase_coll[fw >> 6];
     int s = (int)(pk >> 48), i = (int)((pk >> 24) & 0xffffffull), j = (int)(pk & 0xffffffull);
+    bool q = false;
+    unsigned val = 0u;
     if (valid) {
         advance_pair(P.p, (int)(f - fw), s, i, j);
         long long nd[4];
         coll_nodes(P, s, i, j, nd);
-        float R = P.radii[i] + P.radii[j];
-        float n[4 * D];
-        bool check_cur = true;
+        const float4 rc[4] = {P.zr_cur[nd[0]], P.zr_cur[nd[1]], P.zr_cur[nd[2]], P.zr_cur[nd[3]]};
+        float4 rp[4] = {rc[0], rc[1], rc[2], rc[3]};
         float u[4 * D];
-        if (MODE == M_FIRST) {
-            load_u_coll<D>(P, f, u);
-        } else if (dense) {
-            load_u_coll<D>(P, f, u);
-            float zz[3];
-            for (int e = 0; e < 4; ++e) {
-                node_xyz(P.zr_prev[nd[e]], zz, D);
-                for (int c = 0; c < D; ++c) n[e * D + c] = zz[c] - u[e * D + c];
-            }
-            if (coll_active<D>(n, R)) {
-                push_prev = true;
-                check_cur = false;
-            } else {
-                for (int q = 0; q < 4 * D; ++q) u[q] = 0.f;
-                store_u_coll<D>(P, f, u);
-            }
-        } else {
-            unsigned w = P.bits_coll[f >> 5];
-            if ((w >> (f & 31)) & 1u) {
-                push_prev = true;
-                check_cur = false;
-            } else {
-                for (int q = 0; q < 4 * D; ++q) u[q] = 0.f;
-            }
-        }
-        if (MODE == M_FINAL) {
-            check_cur = false;
-            if (!dense && !push_prev) store_u_coll<D>(P, f, u); // zero
-        }
-        if (check_cur) {
-            float zz[3];
-            for (int e = 0; e < 4; ++e) {
-                node_xyz(P.zr_cur[nd[e]], zz, D);
-                for (int c = 0; c < D; ++c) n[e * D + c] = zz[c] - u[e * D + c];
-            }
-            push_new = coll_active<D>(n, R);
-            if (!push_new && P.dbg_x) {
-                long long e0 = P.e_coll + 4 * f;
-                for (int q = 0; q < 4 * D; ++q) P.dbg_x[e0 * D + q] = n[q];
-                P.dbg_rho[P.f_coll + f] = W_ZERO;
-            }
-        }
+        for (int k = 0; k < 4 * D; ++k) u[k] = 0.f;
+        if (dense || MODE == M_FIRST) load_u_coll<D>(P, f, u);
+        if (dense && MODE != M_FIRST)
+            for (int e = 0; e < 4; ++e) rp[e] = P.zr_prev[nd[e]];
+        const int r = j - i - 1;
+        unsigned long long word = 0ull;
+        if (!dense && MODE != M_FIRST) word = P.bits_coll[(long long)s * P.cps + P.rowchunk[i] + (r >> 6)] >> (r & 63);
+        const float R = P.radii[i] + P.radii[j];
+        if (dense) q = coll_factor<D, MODE, true>(P, f, R, rc, rp, u, word, 0, &val);
+        else q = coll_factor<D, MODE, false>(P, f, R, rc, rp, u, word, 0, &val);
     }
-    *q = push_prev || push_new;
-    *val = (unsigned)f | (push_prev ? kPrev : 0u);
+    push(P.qc, &P.counters[0], q, val);
 }
 
 // Wall factor f: activity test (segment distance) and queue decision.
@@ -290,7 +389,7 @@ __device__ __forceinline__ void wall_stream(const Params &P, long long f, bool v
 // Energy factor f: always weight rho0; finished here.
 template <int D, int MODE>
 __device__ __forceinline__ void energy_stream(const Params &P, long long f) {
-    int i = (int)(f / P.eta), s = (int)(f % P.eta);
+    int i = (int)f / P.eta, s = (int)f - i * P.eta;
     long long na = (long long)s * P.p + i, nb = na + P.p;
     float C = P.C[f];
     float *up = P.u_energy + f * 2 * D;
@@ -407,7 +506,8 @@ __device__ __forceinline__ bool coll_queue(const Params &P, unsigned e) {
             contribute(P, nd[q], 0, m, D);
         }
         store_x_coll<D>(P, f, x);
-        atomicOr(&P.bits_coll[f >> 5], 1u << (f & 31));
+        const int r = j - i - 1;
+        atomicOr(&P.bits_coll[(long long)s * P.cps + P.rowchunk[i] + (r >> 6)], 1ull << (r & 63));
     } else {
         for (int q = 0; q < 4 * D; ++q) x[q] = n[q];
     }
@@ -511,30 +611,20 @@ __device__ __forceinline__ void node_update(const Params &P, long long nd) {
 }
 
 // ------------------------------------------------------------------ plain kernels
-template <int D, int MODE>
+// DENSE: the literal dense form (u of every edge read and written); it
+// walks two break-point intervals per wave, the activity-bit form four.
+template <int D, int MODE, bool DENSE>
 __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
+    constexpr int CPW = DENSE ? 2 : 4;
     long long b = blockIdx.x;
     const bool clear_bits = MODE != M_FINAL && P.dense == 0;
     if (b < P.nbc) {
-        // each wave walks cpw consecutive chunks of 64 collision factors
-        const int lane = threadIdx.x & 63;
-        const long long wave = b * (kBlock / 64) + (threadIdx.x >> 6);
-        const long long nch = (P.Fc + 63) / 64;
-        for (int k = 0; k < P.cpw; ++k) {
-            const long long c = wave * P.cpw + k;
-            if (c >= nch) break;
-            long long f = c * 64 + lane;
-            bool valid = f < P.Fc, q;
-            unsigned val;
-            coll_stream<D, MODE>(P, f, valid, &q, &val);
-            if (clear_bits) {
-                // this iteration's bits are set by k_queue; the two words of
-                // this chunk were read by this wave only
-                __builtin_amdgcn_wave_barrier();
-                if (valid && (f & 31) == 0) P.bits_coll[f >> 5] = 0u;
-            }
-            push(P.qc, &P.counters[0], q, val);
-        }
+        // wave -> (column, block of CPW break-point intervals); consecutive
+        // waves take consecutive columns of the same intervals
+        const unsigned wave = (unsigned)b * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const unsigned cps = (unsigned)P.cps;
+        const int col = (int)(wave % cps), s0 = (int)(wave / cps) * CPW;
+        if (s0 < P.eta) coll_column<D, MODE, CPW, DENSE>(P, col, s0, min(s0 + CPW, P.eta), threadIdx.x & 63, clear_bits);
     } else if (b < P.nbc + P.nbw) {
         long long f = (b - P.nbc) * kBlock + threadIdx.x;
         bool valid = f < P.Fw, q;
@@ -566,13 +656,15 @@ __device__ __forceinline__ void queue_entry(const Params &P, long long t, int nq
     count_wave(&P.counters[3], aw);
 }
 
+// One wave per workgroup: the few busy waves land on different compute
+// units instead of sharing one unit's scalar pipeline and caches.
 template <int D, int MODE>
-__global__ __launch_bounds__(kBlock) void k_queue(Params P) {
+__global__ __launch_bounds__(64) void k_queue(Params P) {
     const int nqc = P.counters[0], nqw = P.counters[1];
     const long long wall0 = ((long long)nqc + 63) & ~63LL, total = wall0 + nqw;
-    const long long stride = (long long)gridDim.x * kBlock;
-    for (long long t0 = (long long)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < total; t0 += stride)
-        queue_entry<D, MODE>(P, t0 + (threadIdx.x & 63), nqc, wall0, total);
+    const long long stride = (long long)gridDim.x * 64;
+    for (long long t0 = (long long)blockIdx.x * 64; t0 < total; t0 += stride)
+        queue_entry<D, MODE>(P, t0 + threadIdx.x, nqc, wall0, total);
 }
 
 __device__ __forceinline__ void close_counters(const Params &P) {
@@ -600,15 +692,13 @@ template <int D, int MODE, int BLOCK>
 __device__ __forceinline__ void batch_instance(const Params &P) {
     const bool clear_bits = P.dense == 0;
     for (long long base = 0; base < P.Fc; base += BLOCK) {
-        long long f = base + threadIdx.x;
-        bool valid = f < P.Fc, q;
-        unsigned val;
-        coll_stream<D, MODE>(P, f, valid, &q, &val);
-        if (clear_bits) {
-            __syncthreads();
-            if (valid && (f & 31) == 0) P.bits_coll[f >> 5] = 0u;
-        }
-        push(P.qc, &P.counters[0], q, val);
+        const long long f = base + threadIdx.x;
+        coll_flat<D, MODE>(P, f, f < P.Fc);
+    }
+    if (clear_bits) {
+        // every factor has read its activity bit: clear the words for k_queue
+        __syncthreads();
+        for (long long w = threadIdx.x; w < P.nch; w += BLOCK) P.bits_coll[w] = 0ull;
     }
     for (long long base = 0; base < P.Fw; base += BLOCK) {
         long long f = base + threadIdx.x;
@@ -820,19 +910,22 @@ twa_status launch_iteration(twa_solver *s, int mode) {
     int gq = s->nblocks_queue;
     if (mode == M_FIRST) {
         mark(s, 0);
-        hipLaunchKernelGGL((k_stream<D, M_FIRST>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
+        if (P.dense) hipLaunchKernelGGL((k_stream<D, M_FIRST, true>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
+        else hipLaunchKernelGGL((k_stream<D, M_FIRST, false>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
         mark(s, 1);
-        hipLaunchKernelGGL((k_queue<D, M_FIRST>), dim3(gq), dim3(kBlock), 0, s->stream, P);
+        hipLaunchKernelGGL((k_queue<D, M_FIRST>), dim3(gq), dim3(64), 0, s->stream, P);
         mark(s, 2);
     } else if (mode == M_FUSED) {
         mark(s, 0);
-        hipLaunchKernelGGL((k_stream<D, M_FUSED>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
+        if (P.dense) hipLaunchKernelGGL((k_stream<D, M_FUSED, true>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
+        else hipLaunchKernelGGL((k_stream<D, M_FUSED, false>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
         mark(s, 1);
-        hipLaunchKernelGGL((k_queue<D, M_FUSED>), dim3(gq), dim3(kBlock), 0, s->stream, P);
+        hipLaunchKernelGGL((k_queue<D, M_FUSED>), dim3(gq), dim3(64), 0, s->stream, P);
         mark(s, 2);
     } else {
-        hipLaunchKernelGGL((k_stream<D, M_FINAL>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
-        hipLaunchKernelGGL((k_queue<D, M_FINAL>), dim3(gq), dim3(kBlock), 0, s->stream, P);
+        if (P.dense) hipLaunchKernelGGL((k_stream<D, M_FINAL, true>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
+        else hipLaunchKernelGGL((k_stream<D, M_FINAL, false>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
+        hipLaunchKernelGGL((k_queue<D, M_FINAL>), dim3(gq), dim3(64), 0, s->stream, P);
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s->stream, P.counters);
         HIP_TRY(s, hipGetLastError());
         return TWA_OK;
@@ -951,7 +1044,7 @@ twa_status reset_state_buffers(twa_solver *s) {
     HIP_TRY(s, hipMemsetAsync(P.u_wall, 0, sizeof(float4) * std::max<long long>(1, P.Fw), s->stream));
     HIP_TRY(s, hipMemsetAsync(P.u_energy, 0, sizeof(float) * std::max<long long>(1, P.Fe * 2 * D), s->stream));
     HIP_TRY(s, hipMemsetAsync(P.u_fixed, 0, sizeof(float) * std::max<long long>(1, P.Ff * D), s->stream));
-    HIP_TRY(s, hipMemsetAsync(P.bits_coll, 0, sizeof(unsigned) * std::max<long long>(1, (P.Fc + 31) / 32), s->stream));
+    HIP_TRY(s, hipMemsetAsync(P.bits_coll, 0, sizeof(unsigned long long) * std::max<long long>(1, P.nch), s->stream));
     HIP_TRY(s, hipMemsetAsync(P.bits_wall, 0, sizeof(unsigned) * std::max<long long>(1, (P.Fw + 31) / 32), s->stream));
     HIP_TRY(s, hipMemsetAsync(P.acc, 0, sizeof(unsigned long long) * 2 * D * P.N, s->stream));
     HIP_TRY(s, hipMemsetAsync(P.cnt, 0, sizeof(int) * 2 * P.N, s->stream));
@@ -1127,16 +1220,32 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     P.p = p, P.eta = eta, P.W = n_walls, P.dim = dim;
     P.Fc = Fc, P.Fw = Fw, P.Fe = Fe, P.Ff = Ff;
     P.N = (long long)p * (eta + 1);
-    // collision chunks (64 factors) per wave in k_stream: with activity bits
-    // the per-chunk work is short, and walking several amortises the wave
-    // launch; the dense form is bound by its u stream and keeps one
-    P.cpw = (flags & TWA_F_DENSE) ? 1 : 4;
-    P.nbc = ((Fc + 63) / 64 + (kBlock / 64) * P.cpw - 1) / ((kBlock / 64) * P.cpw);
+    // break-point intervals per wave in k_stream (see k_stream)
+    P.cpw = (flags & TWA_F_DENSE) ? 2 : 4;
+    // rows of the pair triangle cut into chunks of 64: chunk (s, i, j0)
+    std::vector<int> hrowchunk((size_t)p, 0);
+    for (int i = 0; i + 1 < p; ++i) hrowchunk[i + 1] = hrowchunk[i] + (p - 1 - i + 63) / 64;
+    P.cps = p > 1 ? hrowchunk[p - 1] : 0;
+    P.nch = (long long)eta * P.cps;
+    P.P2 = P2;
+    if (P.nch >= (1LL << 31)) {
+        fail(s, TWA_E_INVALID, "too many factors for one solver");
+        return bail(TWA_E_INVALID);
+    }
+    // (i, j0) of each chunk of a break-point interval (the same for every s)
+    std::vector<unsigned long long> hchunk((size_t)std::max<long long>(1, P.cps));
+    {
+        long long c = 0;
+        for (int i = 0; i + 1 < p; ++i)
+            for (int j0 = i + 1; j0 < p; j0 += 64, ++c)
+                hchunk[c] = ((unsigned long long)i << 24) | (unsigned long long)j0;
+    }
+    P.nbc = (P.cps * ((eta + P.cpw - 1) / P.cpw) + kBlock / 64 - 1) / (kBlock / 64);
     P.nbw = (Fw + kBlock - 1) / kBlock;
     P.nbe = (Fe + kBlock - 1) / kBlock;
     P.nbf = (Ff + kBlock - 1) / kBlock;
     s->nblocks_stream = P.nbc + P.nbw + P.nbe + P.nbf;
-    s->nblocks_queue = 1024;
+    s->nblocks_queue = 4096;
     P.e_energy = Ff;
     P.e_coll = Ff + 2 * Fe;
     P.e_wall = P.e_coll + 4 * Fc;
@@ -1159,7 +1268,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         dev_alloc(s, &xfix_d, Ff) || dev_alloc(s, &P.u_coll, (size_t)std::max<long long>(1, dim * Fc)) ||
         dev_alloc(s, &P.u_wall, (size_t)std::max<long long>(1, Fw)) ||
         dev_alloc(s, &P.u_energy, (size_t)Fe * 2 * dim) || dev_alloc(s, &P.u_fixed, (size_t)Ff * dim) ||
-        dev_alloc(s, &P.bits_coll, (size_t)std::max<long long>(1, (Fc + 31) / 32)) ||
+        dev_alloc(s, &P.bits_coll, (size_t)std::max<long long>(1, P.nch)) ||
         dev_alloc(s, &P.bits_wall, (size_t)std::max<long long>(1, (Fw + 31) / 32)) ||
         dev_alloc(s, &P.qc, (size_t)std::max<long long>(1, Fc)) ||
         dev_alloc(s, &P.qw, (size_t)std::max<long long>(1, Fw)) || dev_alloc(s, &P.counters, 8) ||
@@ -1171,6 +1280,11 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         dev_alloc(s, &wbw_d, (size_t)std::max<long long>(1, (Fw + 63) / 64)) ||
         dev_alloc(s, &s->stats_dev, 4) || dev_alloc(s, &s->bad_dev, 1))
         return bail(TWA_E_NOMEM);
+    unsigned long long *chunk_d;
+    int *rowchunk_d;
+    if (dev_alloc(s, &chunk_d, hchunk.size()) || dev_alloc(s, &rowchunk_d, hrowchunk.size()))
+        return bail(TWA_E_NOMEM);
+    P.chunk_coll = chunk_d, P.rowchunk = rowchunk_d;
     if ((flags & TWA_F_TAPE) &&
         (dev_alloc(s, &s->origin_z, (size_t)P.N * dim) ||
          dev_alloc(s, &s->origin_u, (size_t)(P.e_wall + 2 * Fw) * dim) || dev_alloc(s, &s->origin_l, (size_t)P.N)))
@@ -1225,6 +1339,12 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         e = hipMemcpyAsync(xfix_d, hfix.data(), sizeof(float4) * Ff, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(wbc_d, hwbc.data(), sizeof(unsigned long long) * hwbc.size(), hipMemcpyHostToDevice,
+                           s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(chunk_d, hchunk.data(), sizeof(unsigned long long) * hchunk.size(), hipMemcpyHostToDevice,
+                           s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(rowchunk_d, hrowchunk.data(), sizeof(int) * hrowchunk.size(), hipMemcpyHostToDevice,
                            s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(wbw_d, hwbw.data(), sizeof(unsigned long long) * hwbw.size(), hipMemcpyHostToDevice,
