@@ -179,6 +179,52 @@ def run_batched(K, warmup):
                 autotune=dict(block=block, groups=groups, candidates=log))
 
 
+def min_clearance_pairs(radii, z):
+    """Smallest closest-approach distance minus r_i + r_j over every pair and
+    segment of trajectories z [p][eta+1][dim] (constant velocity per segment)."""
+    import numpy as np
+    z = np.asarray(z, dtype=np.float64)
+    p = z.shape[0]
+    iu, ju = np.triu_indices(p, 1)
+    d0 = z[ju, :-1] - z[iu, :-1]
+    d1 = z[ju, 1:] - z[iu, 1:]
+    e = d1 - d0
+    ee = np.sum(e * e, axis=-1)
+    a = np.clip(-np.sum(d0 * e, axis=-1) / np.where(ee > 0, ee, 1.0), 0.0, 1.0)
+    v = d0 + a[..., None] * e
+    dist = np.sqrt(np.sum(v * v, axis=-1))
+    return float(np.min(dist - (radii[iu] + radii[ju])[:, None]))
+
+
+def run_admm_vs_twa(max_iters=20000, every=50):
+    """Iterations until the trajectories are collision-free (clearance
+    >= -1e-6, checked every 50 iterations) for the three-weight algorithm and
+    for standard ADMM (all weights rho0) on antipodal circle swaps."""
+    import torch
+    from paper_1311_4527_amd import instances as I
+    from paper_1311_4527_amd.twa import Solver, TWA_F_ADMM
+    out = []
+    for p, r, eta in ((8, 0.05, 4), (16, 0.05, 6), (32, 0.03, 6)):
+        inst = I.circle_swap(p, r, eta, sigma=1e-3, seed=0, alpha=0.1, C=1.0 / (p * 4), name=f"swap{p}")
+        row = dict(p=p, eta=eta, r=r)
+        for flags, name in ((0, "twa"), (TWA_F_ADMM, "admm")):
+            S = Solver.from_instance(inst, flags=flags)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            done, free_at = 0, None
+            while done < max_iters:
+                S.twa_iterate(every)
+                done += every
+                if min_clearance_pairs(inst.radii, S.twa_get_trajectories().cpu().numpy()) >= -1e-6:
+                    free_at = done
+                    break
+            torch.cuda.synchronize()
+            row[name] = dict(iterations_to_collision_free=free_at, seconds=time.perf_counter() - t0)
+            S.close()
+        out.append(row)
+    return out
+
+
 def run_adjoint(K=500):
     """Forward K iterations alone, then forward with the start remembered plus
     the adjoint (sqrt(K) checkpoints) on the p=256, eta=8 swap."""
@@ -294,6 +340,9 @@ def main():
         print(f"# variant {other}: {out['variants'][other]['value']:.4g}", file=sys.stderr, flush=True)
         out["batched"] = run_batched(args.batch_steps, 50)
         print(f"# batched: {out['batched']['value']:.4g} (x{out['batched']['speedup']:.1f} vs sequential)",
+              file=sys.stderr, flush=True)
+        out["admm_vs_twa"] = run_admm_vs_twa()
+        print(f"# admm vs twa: {[(r['p'], r['twa']['iterations_to_collision_free'], r['admm']['iterations_to_collision_free']) for r in out['admm_vs_twa']]}",
               file=sys.stderr, flush=True)
         out["adjoint"] = run_adjoint(500)
         print(f"# adjoint: backward/forward {out['adjoint']['backward_over_forward']:.2f}", file=sys.stderr,

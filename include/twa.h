@@ -67,7 +67,14 @@ enum {
     /* Make twa_backward available: the solver remembers the state each run
      * starts from (at create, twa_set_init and twa_set_state).  No cost per
      * iteration. */
-    TWA_F_TAPE = 1u << 1
+    TWA_F_TAPE = 1u << 1,
+    /* Standard ADMM instead of the three-weight algorithm: every factor sends
+     * weight rho0 on every edge (no zero or infinite weights), so <-rho is
+     * rho0 everywhere and the start/goal factors take part in the consensus
+     * like any other (Sec. 2, App. B: the three-weight algorithm reduces to
+     * ADMM when every weight is rho0).  Implies TWA_F_DENSE.  For comparing
+     * the two methods; twa_backward is not available in this mode. */
+    TWA_F_ADMM = 1u << 2
 };
 
 typedef struct {

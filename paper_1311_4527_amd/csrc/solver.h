@@ -57,6 +57,7 @@ struct Params {
     float rho, step;      // this iteration: weight value of rho0, alpha/rho0
     float rho_prev, step_prev;
     int dense;
+    int admm; // standard ADMM: every factor sends weight rho0 (TWA_F_ADMM)
     // debug capture of this iteration
     float *dbg_x;
     unsigned char *dbg_rho;

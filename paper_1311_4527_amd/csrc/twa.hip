@@ -190,6 +190,10 @@ __device__ __forceinline__ bool coll_factor(const Params &P, long long f, float 
     bool check_cur = true;
     if (MODE == M_FIRST) {
         // u as loaded
+    } else if (dense && P.admm) {
+        // standard ADMM: every factor sent weight rho0 last iteration
+        push_prev = true;
+        check_cur = false;
     } else if (dense) {
         float zz[3];
         for (int e = 0; e < 4; ++e) {
@@ -221,7 +225,7 @@ __device__ __forceinline__ bool coll_factor(const Params &P, long long f, float 
             node_xyz(rc[e], zz, D);
             for (int k = 0; k < D; ++k) n[e * D + k] = zz[k] - u[e * D + k];
         }
-        push_new = coll_active<D>(n, R);
+        push_new = P.admm || coll_active<D>(n, R);
         if (!push_new && P.dbg_x) {
             long long e0 = P.e_coll + 4 * f;
             for (int k = 0; k < 4 * D; ++k) P.dbg_x[e0 * D + k] = n[k];
@@ -348,6 +352,9 @@ __device__ __forceinline__ void wall_stream(const Params &P, long long f, bool v
         bool check_cur = true;
         if (MODE == M_FIRST) {
             u = P.u_wall[f];
+        } else if (dense && P.admm) {
+            push_prev = true;
+            check_cur = false;
         } else if (dense) {
             u = P.u_wall[f];
             float4 za = P.zr_prev[na], zb = P.zr_prev[nb];
@@ -373,7 +380,7 @@ __device__ __forceinline__ void wall_stream(const Params &P, long long f, bool v
         if (check_cur) {
             float4 za = P.zr_cur[na], zb = P.zr_cur[nb];
             f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
-            push_new = segseg_sq(n0, n1, xa, xb) < r * r;
+            push_new = P.admm || segseg_sq(n0, n1, xa, xb) < r * r;
             if (!push_new && P.dbg_x) {
                 long long e0 = P.e_wall + 2 * f;
                 P.dbg_x[e0 * 2 + 0] = n0.x, P.dbg_x[e0 * 2 + 1] = n0.y;
@@ -441,19 +448,26 @@ __device__ __forceinline__ void fixed_stream(const Params &P, long long f) {
     float *up = P.u_fixed + f * D;
     float u[3];
     for (int c = 0; c < D; ++c) u[c] = up[c];
-    if (MODE != M_FIRST) {
-        // ->rho^{k-1} = infinity, so u^k = 0
-        for (int c = 0; c < D; ++c) u[c] = 0.f, up[c] = 0.f;
-        if (MODE == M_FINAL) return;
-    }
     float4 xf = P.xfix[f];
     float x[3] = {xf.x, xf.y, xf.z}, m[3];
+    if (MODE != M_FIRST) {
+        if (P.admm) {
+            // weight rho0 both ways: the ordinary update with z^k
+            float zc[3];
+            node_xyz(P.zr_cur[nd], zc, D);
+            for (int c = 0; c < D; ++c) u[c] = u[c] + P.step_prev * (x[c] - zc[c]), up[c] = u[c];
+        } else {
+            // ->rho^{k-1} = infinity, so u^k = 0
+            for (int c = 0; c < D; ++c) u[c] = 0.f, up[c] = 0.f;
+        }
+        if (MODE == M_FINAL) return;
+    }
     for (int c = 0; c < D; ++c) m[c] = x[c] + u[c];
-    contribute(P, nd, 1, m, D);
-    P.inf_val[nd] = make_float4(m[0], m[1], D == 3 ? m[2] : 0.f, 0.f);
+    contribute(P, nd, P.admm ? 0 : 1, m, D);
+    if (!P.admm) P.inf_val[nd] = make_float4(m[0], m[1], D == 3 ? m[2] : 0.f, 0.f);
     if (P.dbg_x) {
         for (int c = 0; c < D; ++c) P.dbg_x[f * D + c] = x[c];
-        P.dbg_rho[f] = W_INF;
+        P.dbg_rho[f] = P.admm ? W_STD : W_INF;
     }
 }
 
@@ -510,12 +524,21 @@ __device__ __forceinline__ bool coll_queue(const Params &P, unsigned e) {
         atomicOr(&P.bits_coll[(long long)s * P.cps + P.rowchunk[i] + (r >> 6)], 1ull << (r & 63));
     } else {
         for (int q = 0; q < 4 * D; ++q) x[q] = n[q];
+        if (P.admm) {
+            // standard ADMM: x = n still carries weight rho0
+            float m[3];
+            for (int q = 0; q < 4; ++q) {
+                for (int c = 0; c < D; ++c) m[c] = x[q * D + c] + u[q * D + c];
+                contribute(P, nd[q], 0, m, D);
+            }
+            store_x_coll<D>(P, f, x);
+        }
     }
     if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) store_u_coll<D>(P, f, u);
     if (P.dbg_x) {
         long long e0 = P.e_coll + 4 * f;
         for (int q = 0; q < 4 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
-        P.dbg_rho[P.f_coll + f] = act ? W_STD : W_ZERO;
+        P.dbg_rho[P.f_coll + f] = (act || P.admm) ? W_STD : W_ZERO;
     }
     return act;
 }
@@ -561,13 +584,19 @@ __device__ __forceinline__ bool wall_queue(const Params &P, unsigned e) {
         contribute(P, na, 0, m0, 2);
         contribute(P, nb, 0, m1, 2);
         atomicOr(&P.bits_wall[f >> 5], 1u << (f & 31));
+    } else if (P.admm) {
+        // standard ADMM: x = n still carries weight rho0
+        P.x_wall[f] = make_float4(x0.x, x0.y, x1.x, x1.y);
+        float m0[2] = {x0.x + u.x, x0.y + u.y}, m1[2] = {x1.x + u.z, x1.y + u.w};
+        contribute(P, na, 0, m0, 2);
+        contribute(P, nb, 0, m1, 2);
     }
     if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) P.u_wall[f] = u;
     if (P.dbg_x) {
         long long e0 = P.e_wall + 2 * f;
         P.dbg_x[e0 * 2 + 0] = x0.x, P.dbg_x[e0 * 2 + 1] = x0.y;
         P.dbg_x[e0 * 2 + 2] = x1.x, P.dbg_x[e0 * 2 + 3] = x1.y;
-        P.dbg_rho[P.f_wall + f] = act ? W_STD : W_ZERO;
+        P.dbg_rho[P.f_wall + f] = (act || P.admm) ? W_STD : W_ZERO;
     }
     return act;
 }
@@ -751,7 +780,8 @@ __global__ void k_reset_counters(int *counters) {
 
 // ------------------------------------------------------------------ layout conversion
 // canonical [p][eta+1][dim] <-> time-major node records
-__global__ void k_z_import(float4 *zr, const float *z, int p, int eta, int D, const unsigned char *lrho, int keep_w) {
+__global__ void k_z_import(float4 *zr, const float *z, int p, int eta, int D, const unsigned char *lrho, int keep_w,
+                           int endcode) {
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long N = (long long)p * (eta + 1);
     if (t >= N) return;
@@ -762,7 +792,7 @@ __global__ void k_z_import(float4 *zr, const float *z, int p, int eta, int D, co
     r.y = z[t * D + 1];
     r.z = D == 3 ? z[t * D + 2] : 0.f;
     if (lrho) r.w = (float)lrho[t];
-    else if (!keep_w) r.w = (float)((s == 0 || s == eta) ? W_INF : W_STD);
+    else if (!keep_w) r.w = (float)((s == 0 || s == eta) ? endcode : W_STD);
     zr[nd] = r;
 }
 __global__ void k_z_export(const float4 *zr, float *z, unsigned char *lrho, int p, int eta, int D) {
@@ -807,12 +837,12 @@ __global__ void k_u_convert(Params P, float *u, int D, int dir) {
         else *src = *dst;
     }
 }
-__global__ void k_fix_ends(float4 *zr, const float4 *xfix, int p, int eta) {
+__global__ void k_fix_ends(float4 *zr, const float4 *xfix, int p, int eta, int endcode) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p) return;
     float4 a = xfix[2 * i], b = xfix[2 * i + 1];
-    a.w = (float)W_INF;
-    b.w = (float)W_INF;
+    a.w = (float)endcode;
+    b.w = (float)endcode;
     zr[i] = a;
     zr[(long long)eta * p + i] = b;
 }
@@ -1089,7 +1119,8 @@ twa_status import_state(twa_solver *s, const float *z, const float *u, const uns
     if (iter < 0) return fail(s, TWA_E_INVALID, "iter must be >= 0");
     TRY(reset_state_buffers(s));
     unsigned nb = (unsigned)((s->P.N + 255) / 256);
-    hipLaunchKernelGGL(k_z_import, dim3(nb), dim3(256), 0, s->stream, s->P.zr_cur, z, s->p, s->eta, s->dim, lrho, 1);
+    hipLaunchKernelGGL(k_z_import, dim3(nb), dim3(256), 0, s->stream, s->P.zr_cur, z, s->p, s->eta, s->dim, lrho, 1,
+                       (int)W_INF);
     long long E = s->P.e_wall + 2 * s->P.Fw;
     hipLaunchKernelGGL(k_u_convert, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s->stream, s->P,
                        const_cast<float *>(u), s->dim, 0);
@@ -1148,7 +1179,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         fail(s, TWA_E_INVALID, "rho0 and alpha must be finite and > 0");
         return bail(TWA_E_INVALID);
     }
-    if (flags & ~(unsigned)(TWA_F_DENSE | TWA_F_TAPE)) {
+    if (flags & ~(unsigned)(TWA_F_DENSE | TWA_F_TAPE | TWA_F_ADMM)) {
         fail(s, TWA_E_INVALID, "unsupported flag");
         return bail(TWA_E_INVALID);
     }
@@ -1221,7 +1252,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     P.Fc = Fc, P.Fw = Fw, P.Fe = Fe, P.Ff = Ff;
     P.N = (long long)p * (eta + 1);
     // break-point intervals per wave in k_stream (see k_stream)
-    P.cpw = (flags & TWA_F_DENSE) ? 2 : 4;
+    P.cpw = (flags & (TWA_F_DENSE | TWA_F_ADMM)) ? 2 : 4; // as k_stream<..., DENSE> (ADMM runs dense)
     // rows of the pair triangle cut into chunks of 64: chunk (s, i, j0)
     std::vector<int> hrowchunk((size_t)p, 0);
     for (int i = 0; i + 1 < p; ++i) hrowchunk[i + 1] = hrowchunk[i] + (p - 1 - i + 63) / 64;
@@ -1252,7 +1283,9 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     P.f_energy = Ff;
     P.f_coll = Ff + Fe;
     P.f_wall = Ff + Fe + Fc;
-    P.dense = (flags & TWA_F_DENSE) ? 1 : 0;
+    // standard ADMM keeps u on every edge: it runs in the dense form
+    P.admm = (flags & TWA_F_ADMM) ? 1 : 0;
+    P.dense = ((flags & TWA_F_DENSE) || P.admm) ? 1 : 0;
     // fixed-point scale: |m| * scale * (degree + 1) stays below 2^62
     long long deg = 2LL * (p - 1) + 2 + 2LL * n_walls + 1;
     double lim = std::ldexp(1.0, 62) / (8.0 * Lmax * (double)deg);
@@ -1327,7 +1360,8 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
                 double a = h0[i * dim + c], b = hT[i * dim + c];
                 v[c] = (s2 == 0) ? (float)a : (s2 == eta) ? (float)b : (float)(a + (double)s2 / eta * (b - a));
             }
-            hz[(size_t)s2 * p + i] = make_float4(v[0], v[1], v[2], (float)((s2 == 0 || s2 == eta) ? W_INF : W_STD));
+            hz[(size_t)s2 * p + i] =
+                make_float4(v[0], v[1], v[2], (float)((s2 == 0 || s2 == eta) && !P.admm ? W_INF : W_STD));
         }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpyAsync(radii_d, hr.data(), sizeof(float) * p, hipMemcpyHostToDevice, s->stream);
@@ -1370,12 +1404,13 @@ twa_status twa_set_init(twa_solver *s, const float *z) {
     if (!z) return fail(s, TWA_E_INVALID, "null z");
     long long N = s->P.N;
     unsigned nb = (unsigned)((N + 255) / 256);
+    const int endcode = s->P.admm ? (int)W_STD : (int)W_INF;
     hipLaunchKernelGGL(k_z_import, dim3(nb), dim3(256), 0, s->stream, s->P.zr_cur, z, s->p, s->eta, s->dim,
-                       (const unsigned char *)nullptr, 0);
+                       (const unsigned char *)nullptr, 0, endcode);
     HIP_TRY(s, hipGetLastError());
     // the end points are the constants x(0), x(T)
     hipLaunchKernelGGL(k_fix_ends, dim3((unsigned)((s->p + 255) / 256)), dim3(256), 0, s->stream, s->P.zr_cur,
-                       (const float4 *)s->P.xfix, s->p, s->eta);
+                       (const float4 *)s->P.xfix, s->p, s->eta, endcode);
     HIP_TRY(s, hipGetLastError());
     HIP_TRY(s, hipMemcpyAsync(s->P.zr_prev, s->P.zr_cur, sizeof(float4) * N, hipMemcpyDeviceToDevice, s->stream));
     TRY(reset_state_buffers(s));

@@ -22,6 +22,7 @@ TWA_OK, TWA_E_INVALID, TWA_E_INFEASIBLE, TWA_E_NOMEM, TWA_E_DEVICE, TWA_E_NUMERI
 TWA_W_ZERO, TWA_W_STD, TWA_W_INF = 0, 1, 2
 TWA_F_DENSE = 1
 TWA_F_TAPE = 2
+TWA_F_ADMM = 4
 _STATUS = {0: "TWA_OK", 1: "TWA_E_INVALID", 2: "TWA_E_INFEASIBLE", 3: "TWA_E_NOMEM", 4: "TWA_E_DEVICE",
            5: "TWA_E_NUMERIC", 6: "TWA_E_STATE"}
 
