@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libtwa_oracle.so")
 
 ZERO, STD, INF = 0, 1, 2
 MODE_TWA, MODE_ADMM = 0, 1
+COST_ENERGY, COST_NONE, COST_MAXVEL, COST_MINVEL = 0, 1, 2, 3
 
 _lib = None
 _dp = ct.POINTER(ct.c_double)
@@ -37,6 +38,8 @@ def _load():
     lib.tor_segseg.argtypes = [_dp, _dp, _dp, _dp]
     lib.tor_prox_energy.restype = None
     lib.tor_prox_energy.argtypes = [_dp, _dp, ct.c_double, ct.c_double, ct.c_double, ct.c_int, _dp, _dp]
+    lib.tor_prox_vel.restype = ct.c_int
+    lib.tor_prox_vel.argtypes = [_dp, _dp, ct.c_double, ct.c_double, ct.c_double, ct.c_int, ct.c_int, _dp, _dp]
     lib.tor_prox_capsule.restype = ct.c_int
     lib.tor_prox_capsule.argtypes = [_dp, _dp, ct.c_double, _dp, _dp, ct.c_double, ct.c_double, _dp, _dp,
                                      _ip, _dp]
@@ -45,7 +48,7 @@ def _load():
                                   ct.c_double, ct.c_int, _dp, _dp, _dp, _dp, _ip, _dp]
     lib.tor_create.restype = ct.c_void_p
     lib.tor_create.argtypes = [ct.c_int, ct.c_int, ct.c_int, _dp, _dp, _dp, ct.c_int, _dp, _dp,
-                               ct.c_double, ct.c_double, ct.c_int]
+                               ct.c_double, ct.c_double, ct.c_int, ct.c_int]
     lib.tor_destroy.restype = None
     lib.tor_destroy.argtypes = [ct.c_void_p]
     for nm in ("tor_num_factors", "tor_num_edges", "tor_iteration"):
@@ -113,6 +116,18 @@ def prox_energy(nl, nh, wl, wh, C):
     return xl, xh
 
 
+def prox_vel(nl, nh, wl, wh, C, minimum: bool):
+    """Maximum (minimum) velocity minimiser, App. F (App. G): returns
+    (binding, x_lo, x_hi)."""
+    a, pa = _d(nl)
+    b, pb = _d(nh)
+    xl = np.zeros_like(a)
+    xh = np.zeros_like(a)
+    act = _load().tor_prox_vel(pa, pb, _w(wl), _w(wh), float(C), a.shape[0], int(bool(minimum)),
+                               xl.ctypes.data_as(_dp), xh.ctypes.data_as(_dp))
+    return bool(act), xl, xh
+
+
 def prox_capsule(xL, xR, r, n0, n1, w0, w1):
     """Agent-wall minimiser, App. D/I.  Returns (active, x0, x1, kind, theta).
 
@@ -160,7 +175,7 @@ def min_clearance(radii, z, walls=None) -> float:
 class Planner:
     """The full planner (App. B) on one instance, in FP64."""
 
-    def __init__(self, inst, mode: int = MODE_TWA):
+    def __init__(self, inst, mode: int = MODE_TWA, cost: int = COST_ENERGY):
         lib = _load()
         self.inst = inst
         self.p, self.eta, self.dim = inst.p, inst.eta, inst.dim
@@ -168,7 +183,7 @@ class Planner:
                       if inst.n_walls else np.zeros(4)), _d(inst.C)]
         self.h = lib.tor_create(inst.p, inst.eta, inst.dim, self._keep[0][1], self._keep[1][1],
                                 self._keep[2][1], inst.n_walls, self._keep[3][1], self._keep[4][1],
-                                float(inst.rho0), float(inst.alpha), int(mode))
+                                float(inst.rho0), float(inst.alpha), int(mode), int(cost))
         if not self.h:
             raise ValueError("invalid instance for the reference planner")
         self.F = lib.tor_num_factors(self.h)
@@ -223,6 +238,8 @@ class Planner:
     def tape(self, k: int):
         """Run k iterations keeping every state for :meth:`backward`."""
         got = _load().tor_tape(self.h, int(k))
+        if got == -2:
+            raise ValueError("the reference adjoint covers the energy cost only")
         if got != k:
             raise MemoryError("tape allocation failed")
 

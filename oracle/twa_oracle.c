@@ -58,6 +58,8 @@
 enum { TOR_ZERO = 0, TOR_STD = 1, TOR_INF = 2 };
 enum { TOR_F_FIXED = 0, TOR_F_ENERGY = 1, TOR_F_COLL = 2, TOR_F_WALL = 3 };
 enum { TOR_MODE_TWA = 0, TOR_MODE_ADMM = 1 };
+/* the per-segment factor of each agent (eq. velo_cost_pair_wise, eq. max_vel_min) */
+enum { TOR_COST_ENERGY = 0, TOR_COST_NONE = 1, TOR_COST_MAXVEL = 2, TOR_COST_MINVEL = 3 };
 
 /* Relative size of the "small equal value" that replaces a zero weight. */
 #define TOR_ZERO_WEIGHT 1e-9
@@ -171,6 +173,72 @@ void tor_prox_energy(const double *nl, const double *nh, double wl, double wh, d
             xh[k] = (wl * wh * b + 2 * C * (wl * a + wh * b)) / den;
         }
     }
+}
+
+/*
+ * Maximum / minimum velocity minimiser (App. F and App. G): minimise
+ *   (wl/2)|xl - nl|^2 + (wh/2)|xh - nh|^2  subject to  |xl - xh| <= C
+ * (maximum) or |xl - xh| >= C (minimum).  Returns 1 when the constraint
+ * binds (the factor then sends weight rho0, Sec. 3.3.3), 0 when x = n (weight
+ * zero).  With the constraint active the KKT conditions give x as a function
+ * of the multiplier lambda (eq. sol_paramterized_max_vel), and lambda follows
+ * from |xl - xh| = C (eq. unique_lambda_val_max_vel, the same expression for
+ * both: positive for the maximum, negative for the minimum).  Infinite
+ * weights are taken as exact limits: the certain end stays, the other end
+ * moves to distance C of it.  Both weights zero: equal small weights (the
+ * result does not depend on their common value).  A minimum-velocity factor
+ * whose two ends coincide has no direction to push along: +e1 is used.
+ */
+int tor_prox_vel(const double *nl, const double *nh, double wl, double wh, double C, int dim, int minimum,
+                 double *xl, double *xh) {
+    double d[3] = {0, 0, 0}, dn = 0;
+    for (int k = 0; k < dim; k++) {
+        d[k] = nl[k] - nh[k];
+        dn += d[k] * d[k];
+    }
+    dn = sqrt(dn);
+    int bind = minimum ? (dn < C) : (dn > C);
+    if (!bind) {
+        for (int k = 0; k < dim; k++) xl[k] = nl[k], xh[k] = nh[k];
+        return 0;
+    }
+    int il = isinf(wl), ih = isinf(wh);
+    if (il && ih) {
+        for (int k = 0; k < dim; k++) xl[k] = nl[k], xh[k] = nh[k];
+        return 1;
+    }
+    if (wl == 0 && wh == 0) wl = wh = 1.0;
+    if (dn == 0) {
+        /* coinciding ends (minimum velocity only; lambda is then singular):
+         * the KKT conditions keep the weighted mean and put the ends C apart
+         * along the chosen direction +e1 */
+        double sl = il ? 0.0 : (ih ? 1.0 : wh / (wl + wh));
+        for (int k = 0; k < dim; k++) {
+            double e = (k == 0) ? C : 0.0;
+            xl[k] = nl[k] + sl * e;
+            xh[k] = nh[k] - (1.0 - sl) * e;
+        }
+        return 1;
+    }
+    double ratio = dn / C; /* |n_lo - n_hi| / C */
+    if (il || ih) {
+        /* lambda / w_free -> ratio - 1 as w_certain -> infinity */
+        const double *nf = il ? nl : nh, *nv = il ? nh : nl;
+        double *xf = il ? xl : xh, *xv = il ? xh : xl;
+        for (int k = 0; k < dim; k++) {
+            xf[k] = nf[k];
+            xv[k] = (nv[k] + (ratio - 1.0) * nf[k]) / ratio;
+        }
+        return 1;
+    }
+    double lambda = (ratio - 1.0) / (1.0 / wl + 1.0 / wh);
+    double den = wl * wh + lambda * (wl + wh);
+    for (int k = 0; k < dim; k++) {
+        double a = nl[k], b = nh[k];
+        xl[k] = (wl * (wh + lambda) * a + lambda * wh * b) / den;
+        xh[k] = (wh * (wl + lambda) * b + lambda * wl * a) / den;
+    }
+    return 1;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -786,15 +854,17 @@ typedef struct {
     double tape_rho[4096];            /* rho0 of each taped iteration (schedule) */
     double *act_margin;   /* |closest approach - R| / R of the last activity test, per factor */
     double *tie_margin;   /* relative energy gap to the runner-up candidate, per factor */
+    int cost;             /* TOR_COST_*: what the per-segment factors are */
 } tor_t;
 
 static long node_id(const tor_t *T, int i, int s) { return (long)i * (T->eta + 1) + s; }
 
 void *tor_create(int p, int eta, int dim, const double *radii, const double *x0, const double *xT, int W,
-                 const double *walls, const double *C, double rho0, double alpha, int mode) {
+                 const double *walls, const double *C, double rho0, double alpha, int mode, int cost) {
     if (p < 1 || eta < 1 || (dim != 2 && dim != 3) || W < 0 || (W > 0 && dim != 2)) return NULL;
+    if (cost < TOR_COST_ENERGY || cost > TOR_COST_MINVEL) return NULL;
     tor_t *T = (tor_t *)calloc(1, sizeof(tor_t));
-    T->p = p, T->eta = eta, T->dim = dim, T->W = W, T->mode = mode;
+    T->p = p, T->eta = eta, T->dim = dim, T->W = W, T->mode = mode, T->cost = cost;
     T->rho0 = rho0, T->alpha = alpha, T->rho0_init = rho0, T->n_warm = 0;
     T->radii = (double *)malloc(sizeof(double) * p);
     memcpy(T->radii, radii, sizeof(double) * p);
@@ -963,9 +1033,25 @@ static void run_factor(tor_t *T, long f, double rho) {
     } else if (t == TOR_F_ENERGY) {
         double wl = weight_value(T, T->rin[e], rho), wh = weight_value(T, T->rin[e + 1], rho);
         if (T->rin[e] == TOR_ZERO && T->rin[e + 1] == TOR_ZERO) wl = wh = 0; /* equal-weight limit */
-        tor_prox_energy(n + e * dim, n + (e + 1) * dim, wl, wh, T->C[T->fa[f] * T->eta + T->fs[f]], dim,
-                        x + e * dim, x + (e + 1) * dim);
-        out = TOR_STD;
+        double Cf = T->C[T->fa[f] * T->eta + T->fs[f]];
+        if (T->cost == TOR_COST_ENERGY) {
+            tor_prox_energy(n + e * dim, n + (e + 1) * dim, wl, wh, Cf, dim, x + e * dim, x + (e + 1) * dim);
+            out = TOR_STD;
+        } else if (T->cost == TOR_COST_NONE) {
+            /* no cost: the factor is absent (x = n, weight zero) */
+            for (int k = 0; k < 2 * dim; k++) x[e * dim + k] = n[e * dim + k];
+            out = TOR_ZERO;
+        } else {
+            double dd = 0;
+            for (int k = 0; k < dim; k++) {
+                double q = n[e * dim + k] - n[(e + 1) * dim + k];
+                dd += q * q;
+            }
+            T->act_margin[f] = fabs(sqrt(dd) - Cf) / Cf;
+            int b = tor_prox_vel(n + e * dim, n + (e + 1) * dim, wl, wh, Cf, dim, T->cost == TOR_COST_MINVEL,
+                                 x + e * dim, x + (e + 1) * dim);
+            out = b ? TOR_STD : TOR_ZERO;
+        }
     } else if (t == TOR_F_COLL) {
         double R = T->radii[T->fa[f]] + T->radii[T->fb[f]];
         double w[4];
@@ -1146,6 +1232,7 @@ static void wall_eval(tor_t *T, long f, const double *nin, double r, const doubl
 
 long tor_tape(void *h, long K) {
     tor_t *T = (tor_t *)h;
+    if (T->cost != TOR_COST_ENERGY) return -2; /* the reverse sweep covers the energy cost only */
     long N = T->N, E = T->E;
     int dim = T->dim;
     if (K > 4096) K = 4096;

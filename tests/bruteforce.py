@@ -169,3 +169,29 @@ def separating_scan(xL, xR, r, n, w, N=200000):
         else:
             a = c
     return float(min(F(0.5 * (a + b))[0], vals[k]))
+
+
+def brute_vel(nl, nh, wl, wh, C, minimum, starts=12, seed=0):
+    """min (wl/2)|xl-nl|^2 + (wh/2)|xh-nh|^2 s.t. |xl-xh| <= C (or >= C for
+    the minimum-velocity constraint), multi-start SLSQP."""
+    nl, nh = np.asarray(nl, float), np.asarray(nh, float)
+    dim = nl.shape[0]
+    rng = np.random.default_rng(seed)
+
+    def f(v):
+        return 0.5 * wl * np.sum((v[:dim] - nl) ** 2) + 0.5 * wh * np.sum((v[dim:] - nh) ** 2)
+
+    def g(v):
+        dd = np.sum((v[:dim] - v[dim:]) ** 2)
+        return (dd - C * C) if minimum else (C * C - dd)
+
+    best = None
+    for k in range(starts):
+        x0 = np.concatenate([nl, nh]) + rng.normal(0, 0.3 * (C + 1e-3), 2 * dim) * (k > 0)
+        r = minimize(f, x0, constraints=[dict(type="ineq", fun=g)], method="SLSQP",
+                     options=dict(ftol=1e-14, maxiter=500))
+        if g(r.x) < -1e-9:
+            continue
+        if best is None or r.fun < best.fun:
+            best = r
+    return best.x[:dim], best.x[dim:], best.fun

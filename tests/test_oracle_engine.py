@@ -166,3 +166,55 @@ def test_full_solve_small_swap_is_collision_free():
     assert O.min_clearance(inst.radii, z) > -1e-5
     # every agent still ends at its antipode
     assert np.array_equal(z[:, -1], inst.xT)
+
+
+# ------------------------------------------------------------------ other per-segment factors
+
+def test_no_cost_leaves_a_collision_free_start_alone():
+    """Without a cost term (feasibility only) every factor of a collision-free
+    start sends weight zero: each node keeps its z (App. B step 5 over all
+    edges, whose m all equal z) and u stays zero."""
+    inst = I.random_box(6, 0.01, 5, sigma=3e-2, seed=1, alpha=0.1, C=1.0)
+    P = O.Planner(inst, cost=O.COST_NONE)
+    assert P.min_clearance() > 0  # the noisy straight lines already avoid each other
+    z0 = P.trajectories().copy()
+    P.iterate(25)
+    z, u, lr = P.get_state()
+    assert np.allclose(z, z0, atol=1e-15)
+    assert np.all(u == 0)
+    assert np.all(lr[:, 1:-1] == O.ZERO) and np.all(lr[:, [0, -1]] == O.INF)
+
+
+def test_no_cost_finds_a_feasible_swap_quickly():
+    """Sec. 4: finding a feasible plan is much cheaper than minimising energy."""
+    inst = I.conf_small(0)
+    P = O.Planner(inst, cost=O.COST_NONE)
+    free_at = None
+    for k in range(1, 41):
+        P.iterate(25)
+        if P.min_clearance() >= -1e-9:
+            free_at = 25 * k
+            break
+    assert free_at is not None and free_at <= 1000
+    E = O.Planner(inst)
+    E.iterate(free_at)
+    assert E.min_clearance() < -1e-6  # the energy run is not there yet
+
+
+@pytest.mark.parametrize("minimum", [False, True])
+def test_velocity_limits_hold_at_convergence(minimum):
+    """eq. max_vel_min: with a feasible limit the converged plan keeps every
+    segment within (outside) the limit and is collision-free."""
+    inst = I.conf_small(1)
+    seg = np.linalg.norm(inst.xT - inst.x0, axis=1) / inst.eta  # straight-line step per segment
+    C = np.repeat((seg * (1.6 if not minimum else 0.7))[:, None], inst.eta, axis=1)
+    inst.C = C
+    P = O.Planner(inst, cost=O.COST_MINVEL if minimum else O.COST_MAXVEL)
+    P.iterate(3000)
+    z = P.trajectories()
+    steps = np.linalg.norm(np.diff(z, axis=1), axis=2)
+    if minimum:
+        assert np.all(steps >= C * (1 - 1e-3))
+    else:
+        assert np.all(steps <= C * (1 + 1e-3))
+    assert P.min_clearance() > -1e-4

@@ -311,3 +311,58 @@ def test_capsule_certain_end():
         best = bf.brute_capsule(xL, xR, r, n, [1e7, 1.0], rng, starts=30)
         assert E <= best[0] * (1 + 1e-5) + 1e-10
         checked += 1
+
+
+# ------------------------------------------------------------------ velocity limits (App. F, G)
+
+@pytest.mark.parametrize("minimum", [False, True])
+def test_velocity_minimiser_vs_bruteforce(minimum):
+    rng = np.random.default_rng(40 + minimum)
+    checked = 0
+    for _ in range(60):
+        dim = int(rng.choice([2, 3]))
+        nl, nh = rng.normal(0, 1, dim), rng.normal(0, 1, dim)
+        wl, wh = rng.uniform(0.2, 3.0, 2)
+        d = np.linalg.norm(nl - nh)
+        C = d * rng.uniform(1.2, 2.5) if minimum else d * rng.uniform(0.2, 0.8)
+        act, xl, xh = O.prox_vel(nl, nh, wl, wh, C, minimum)
+        assert act
+        bl, bh, bf_val = bf.brute_vel(nl, nh, wl, wh, C, minimum, seed=checked)
+        val = 0.5 * wl * np.sum((xl - nl) ** 2) + 0.5 * wh * np.sum((xh - nh) ** 2)
+        assert abs(np.linalg.norm(xl - xh) - C) < 1e-9 * max(C, 1)
+        assert val <= bf_val + 1e-8 * max(bf_val, 1e-8)
+        assert np.allclose(xl, bl, atol=1e-5) and np.allclose(xh, bh, atol=1e-5)
+        checked += 1
+    assert checked == 60
+
+
+@pytest.mark.parametrize("minimum", [False, True])
+def test_velocity_minimiser_inactive_keeps_n(minimum):
+    nl, nh = np.array([0.2, -0.1]), np.array([0.5, 0.3])  # distance 0.5
+    C = 0.3 if minimum else 0.7
+    act, xl, xh = O.prox_vel(nl, nh, 1.0, 2.0, C, minimum)
+    assert not act and np.array_equal(xl, nl) and np.array_equal(xh, nh)
+
+
+def test_velocity_minimiser_weighted_mean_and_certain_end():
+    nl, nh = np.array([0.0, 0.0]), np.array([3.0, 4.0])
+    # equal weights: the midpoint stays, the ends move symmetrically to distance C
+    act, xl, xh = O.prox_vel(nl, nh, 1.0, 1.0, 2.0, False)
+    assert np.allclose(0.5 * (xl + xh), [1.5, 2.0]) and np.allclose(xh - xl, [1.2, 1.6])
+    # unequal: the weighted mean stays
+    act, xl, xh = O.prox_vel(nl, nh, 1.0, 3.0, 2.0, False)
+    assert np.allclose((1.0 * xl + 3.0 * xh) / 4.0, (1.0 * nl + 3.0 * nh) / 4.0)
+    # a certain lower end: the upper end is projected onto the circle of radius C around it
+    act, xl, xh = O.prox_vel(nl, nh, np.inf, 1.0, 2.0, False)
+    assert np.array_equal(xl, nl) and np.allclose(xh, [1.2, 1.6])
+    act, xl, xh = O.prox_vel(nl, nh, 1.0, np.inf, 10.0, True)
+    assert np.array_equal(xh, nh) and np.allclose(xl, [-3.0, -4.0])
+    # large finite weight approaches the certain-end limit
+    act, xl2, xh2 = O.prox_vel(nl, nh, 1.0, 1e9, 10.0, True)
+    assert np.allclose(xl2, xl, atol=1e-6)
+
+
+def test_minimum_velocity_coinciding_ends():
+    p = np.array([0.4, -0.2])
+    act, xl, xh = O.prox_vel(p, p, 1.0, 3.0, 2.0, True)
+    assert act and np.allclose(xl - xh, [2.0, 0.0]) and np.allclose((xl + 3 * xh) / 4, p)
