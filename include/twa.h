@@ -74,7 +74,19 @@ enum {
      * like any other (Sec. 2, App. B: the three-weight algorithm reduces to
      * ADMM when every weight is rho0).  Implies TWA_F_DENSE.  For comparing
      * the two methods; twa_backward is not available in this mode. */
-    TWA_F_ADMM = 1u << 2
+    TWA_F_ADMM = 1u << 2,
+    /* What the factor between consecutive break-points of an agent is (at
+     * most one of these; default: the kinetic-energy cost of
+     * eq. velo_cost_pair_wise, C = energy coefficient):
+     *   COST_NONE    no cost, feasibility only (Sec. 4): the factor is absent
+     *                (weight zero), C unused;
+     *   COST_MAXVEL  |x_i(s+1) - x_i(s)| <= C_{i,s} (eq. max_vel_min, App. F),
+     *                weight rho0 while the limit binds, else zero;
+     *   COST_MINVEL  |x_i(s+1) - x_i(s)| >= C_{i,s} (App. G), likewise.
+     * Velocity limits must be > 0.  twa_backward needs the energy cost. */
+    TWA_F_COST_NONE = 1u << 3,
+    TWA_F_COST_MAXVEL = 1u << 4,
+    TWA_F_COST_MINVEL = 1u << 5
 };
 
 typedef struct {

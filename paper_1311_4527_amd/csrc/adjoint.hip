@@ -344,6 +344,7 @@ extern "C" twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_
     if (!(s->flags & TWA_F_TAPE)) return fail(s, TWA_E_STATE, "twa_backward needs TWA_F_TAPE at create");
     if (s->dim != 2) return fail(s, TWA_E_INVALID, "twa_backward supports dim == 2 only");
     if (s->P.admm) return fail(s, TWA_E_INVALID, "twa_backward supports the three-weight mode only");
+    if (s->P.cost != 0) return fail(s, TWA_E_INVALID, "twa_backward supports the energy cost only");
     if (!dL_dz || !dL_dx0 || !dL_dxT || !dL_dr) return fail(s, TWA_E_INVALID, "null array argument");
     const twa_rt::Params &P = s->P;
     const long long N = P.N, E = P.e_wall + 2 * P.Fw, F = P.Ff + P.Fe + P.Fc + P.Fw;

@@ -124,6 +124,45 @@ TWA_HD void energy_prox(float nl, float nh, float wl, float wh, int kl, int kh, 
 }
 
 // ---------------------------------------------------------------------------
+// Velocity-limit minimiser, App. F (maximum) and App. G (minimum): the
+// closest pair (xl, xh) to (nl, nh) in the weighted norm with |xl - xh| <= C
+// (>= C).  When the limit binds, the KKT conditions keep the weighted mean
+// (wl nl + wh nh)/(wl + wh) and put the ends at distance C along nl - nh; a
+// certain end stays and the other moves to distance C of it.  Returns whether
+// the limit binds (the factor then sends weight rho0).  Coinciding ends under
+// a minimum: direction +e1.
+// ---------------------------------------------------------------------------
+template <int D>
+TWA_HD bool vel_prox(const float *nl, const float *nh, float wl, float wh, int kl, int kh, float C, bool minimum,
+                     float *xl, float *xh) {
+    float d[3] = {0.f, 0.f, 0.f}, dd = 0.f;
+    for (int c = 0; c < D; ++c) {
+        d[c] = nl[c] - nh[c];
+        dd += d[c] * d[c];
+    }
+    const bool bind = minimum ? (dd < C * C) : (dd > C * C);
+    for (int c = 0; c < D; ++c) xl[c] = nl[c], xh[c] = nh[c];
+    if (!bind || (kl == W_INF && kh == W_INF)) return bind;
+    float e[3] = {1.f, 0.f, 0.f};
+    if (dd > 0.f) {
+        const float inv = 1.f / sqrtf(dd);
+        for (int c = 0; c < D; ++c) e[c] = d[c] * inv;
+    }
+    // share of the correction taken by the lower end
+    float sl;
+    if (kl == W_INF) sl = 0.f;
+    else if (kh == W_INF) sl = 1.f;
+    else if (kl == W_ZERO && kh == W_ZERO) sl = 0.5f;
+    else sl = wh / (wl + wh);
+    for (int c = 0; c < D; ++c) {
+        const float corr = C * e[c] - d[c]; // change of xl - xh
+        xl[c] = nl[c] + sl * corr;
+        xh[c] = nh[c] - (1.f - sl) * corr;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // Quadratic on the unit circle: E(u) = 1/2 u^T Q u - <b, u>,
 // Q = [[a, c], [c, e]] positive semi-definite.
 // ---------------------------------------------------------------------------

@@ -58,6 +58,7 @@ struct Params {
     float rho_prev, step_prev;
     int dense;
     int admm; // standard ADMM: every factor sends weight rho0 (TWA_F_ADMM)
+    int cost; // per-segment factors: energy, none, maximum or minimum velocity
     // debug capture of this iteration
     float *dbg_x;
     unsigned char *dbg_rho;

@@ -44,6 +44,9 @@ constexpr int kBlock = 256;
 
 enum Mode : int { M_FIRST = 0, M_FUSED = 1, M_FINAL = 2 };
 
+// what the per-segment factors are (twa_create flags)
+enum Cost : int { COST_ENERGY = 0, COST_NONE = 1, COST_MAXVEL = 2, COST_MINVEL = 3 };
+
 // queue entry flags
 constexpr unsigned kPrev = 0x80000000u; // factor was active last iteration: recompute and update u
 constexpr unsigned kIdx = 0x7fffffffu;
@@ -393,14 +396,35 @@ __device__ __forceinline__ void wall_stream(const Params &P, long long f, bool v
     *val = (unsigned)f | (push_prev ? kPrev : 0u);
 }
 
-// Energy factor f: always weight rho0; finished here.
+// Per-segment factor of agent i between break-points s and s+1: the energy
+// minimiser (App. E, always weight rho0), a velocity limit (App. F, G:
+// weight rho0 while the limit binds, else zero and x = n) or no cost at all
+// (feasibility only: weight zero).  Returns x in x[] and whether the factor
+// sends weight rho0.
+template <int D>
+__device__ __forceinline__ bool segment_prox(const Params &P, float C, const float *n, int ka, int kb, float rho,
+                                             float *x) {
+    if (P.cost == COST_ENERGY) {
+        for (int c = 0; c < D; ++c)
+            energy_prox(n[c], n[D + c], wval(ka, rho), wval(kb, rho), ka, kb, C, x[c], x[D + c]);
+        return true;
+    }
+    if (P.cost == COST_NONE) {
+        for (int q = 0; q < 2 * D; ++q) x[q] = n[q];
+        return P.admm != 0;
+    }
+    const bool bind = vel_prox<D>(n, n + D, wval(ka, rho), wval(kb, rho), ka, kb, C, P.cost == COST_MINVEL, x, x + D);
+    return bind || P.admm;
+}
+
+// Per-segment factor f: finished here.
 template <int D, int MODE>
 __device__ __forceinline__ void energy_stream(const Params &P, long long f) {
     int i = (int)f / P.eta, s = (int)f - i * P.eta;
     long long na = (long long)s * P.p + i, nb = na + P.p;
     float C = P.C[f];
     float *up = P.u_energy + f * 2 * D;
-    float u[6];
+    float u[6], n[6];
     for (int q = 0; q < 2 * D; ++q) u[q] = up[q];
     float4 ca = P.zr_cur[na], cb = P.zr_cur[nb];
     float zc[6];
@@ -408,34 +432,33 @@ __device__ __forceinline__ void energy_stream(const Params &P, long long f) {
     node_xyz(cb, zc + D, D);
     int ka = wcode(ca), kb = wcode(cb);
     if (MODE != M_FIRST) {
-        // recompute x^k from (z^{k-1}, u^{k-1}), then u^k
+        // recompute x^k and ->rho^k from (z^{k-1}, u^{k-1}), then u^k
         float4 pa = P.zr_prev[na], pb = P.zr_prev[nb];
         float zp[6];
         node_xyz(pa, zp, D);
         node_xyz(pb, zp + D, D);
-        int pka = wcode(pa), pkb = wcode(pb);
         float xk[6];
-        for (int c = 0; c < D; ++c)
-            energy_prox(zp[c] - u[c], zp[D + c] - u[D + c], wval(pka, P.rho_prev), wval(pkb, P.rho_prev), pka,
-                        pkb, C, xk[c], xk[D + c]);
+        for (int q = 0; q < 2 * D; ++q) n[q] = zp[q] - u[q];
+        const bool sent = segment_prox<D>(P, C, n, wcode(pa), wcode(pb), P.rho_prev, xk);
         for (int c = 0; c < D; ++c) {
-            u[c] = (ka == W_STD) ? u[c] + P.step_prev * (xk[c] - zc[c]) : 0.f;
-            u[D + c] = (kb == W_STD) ? u[D + c] + P.step_prev * (xk[D + c] - zc[D + c]) : 0.f;
+            u[c] = (sent && ka == W_STD) ? u[c] + P.step_prev * (xk[c] - zc[c]) : 0.f;
+            u[D + c] = (sent && kb == W_STD) ? u[D + c] + P.step_prev * (xk[D + c] - zc[D + c]) : 0.f;
         }
         for (int q = 0; q < 2 * D; ++q) up[q] = u[q];
         if (MODE == M_FINAL) return;
     }
     float x[6], m[6];
-    for (int c = 0; c < D; ++c)
-        energy_prox(zc[c] - u[c], zc[D + c] - u[D + c], wval(ka, P.rho), wval(kb, P.rho), ka, kb, C, x[c],
-                    x[D + c]);
-    for (int q = 0; q < 2 * D; ++q) m[q] = x[q] + u[q];
-    contribute(P, na, 0, m, D);
-    contribute(P, nb, 0, m + D, D);
+    for (int q = 0; q < 2 * D; ++q) n[q] = zc[q] - u[q];
+    const bool send = segment_prox<D>(P, C, n, ka, kb, P.rho, x);
+    if (send) {
+        for (int q = 0; q < 2 * D; ++q) m[q] = x[q] + u[q];
+        contribute(P, na, 0, m, D);
+        contribute(P, nb, 0, m + D, D);
+    }
     if (P.dbg_x) {
         long long e0 = P.e_energy + 2 * f;
         for (int q = 0; q < 2 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
-        P.dbg_rho[P.f_energy + f] = W_STD;
+        P.dbg_rho[P.f_energy + f] = send ? W_STD : W_ZERO;
     }
 }
 
@@ -1179,7 +1202,13 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         fail(s, TWA_E_INVALID, "rho0 and alpha must be finite and > 0");
         return bail(TWA_E_INVALID);
     }
-    if (flags & ~(unsigned)(TWA_F_DENSE | TWA_F_TAPE | TWA_F_ADMM)) {
+    const unsigned cost_flags = flags & (TWA_F_COST_NONE | TWA_F_COST_MAXVEL | TWA_F_COST_MINVEL);
+    if ((cost_flags & (cost_flags - 1)) != 0) {
+        fail(s, TWA_E_INVALID, "choose at most one TWA_F_COST_* flag");
+        return bail(TWA_E_INVALID);
+    }
+    if (flags & ~(unsigned)(TWA_F_DENSE | TWA_F_TAPE | TWA_F_ADMM | TWA_F_COST_NONE | TWA_F_COST_MAXVEL |
+                            TWA_F_COST_MINVEL)) {
         fail(s, TWA_E_INVALID, "unsupported flag");
         return bail(TWA_E_INVALID);
     }
@@ -1206,9 +1235,10 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
             fail(s, TWA_E_INVALID, "radii must be > 0");
             return bail(TWA_E_INVALID);
         }
+    const bool vel = (flags & (TWA_F_COST_MAXVEL | TWA_F_COST_MINVEL)) != 0;
     for (float c : hC)
-        if (c < 0.f) {
-            fail(s, TWA_E_INVALID, "energy coefficients must be >= 0");
+        if (vel ? !(c > 0.f) : c < 0.f) {
+            fail(s, TWA_E_INVALID, vel ? "velocity limits must be > 0" : "energy coefficients must be >= 0");
             return bail(TWA_E_INVALID);
         }
     double Lmax = 1.0;
@@ -1285,6 +1315,10 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     P.f_wall = Ff + Fe + Fc;
     // standard ADMM keeps u on every edge: it runs in the dense form
     P.admm = (flags & TWA_F_ADMM) ? 1 : 0;
+    P.cost = (flags & TWA_F_COST_NONE)     ? COST_NONE
+             : (flags & TWA_F_COST_MAXVEL) ? COST_MAXVEL
+             : (flags & TWA_F_COST_MINVEL) ? COST_MINVEL
+                                           : COST_ENERGY;
     P.dense = ((flags & TWA_F_DENSE) || P.admm) ? 1 : 0;
     // fixed-point scale: |m| * scale * (degree + 1) stays below 2^62
     long long deg = 2LL * (p - 1) + 2 + 2LL * n_walls + 1;

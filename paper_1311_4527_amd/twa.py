@@ -23,6 +23,9 @@ TWA_W_ZERO, TWA_W_STD, TWA_W_INF = 0, 1, 2
 TWA_F_DENSE = 1
 TWA_F_TAPE = 2
 TWA_F_ADMM = 4
+TWA_F_COST_NONE = 8
+TWA_F_COST_MAXVEL = 16
+TWA_F_COST_MINVEL = 32
 _STATUS = {0: "TWA_OK", 1: "TWA_E_INVALID", 2: "TWA_E_INFEASIBLE", 3: "TWA_E_NOMEM", 4: "TWA_E_DEVICE",
            5: "TWA_E_NUMERIC", 6: "TWA_E_STATE"}
 

@@ -44,3 +44,10 @@ void h_energy_vjp(float wl, float wh, int kl, int kh, float C, float xlb, float 
     *nlb = a, *nhb = b;
 }
 }
+extern "C" {
+int h_vel(int dim, const float *nl, const float *nh, float wl, float wh, int kl, int kh, float C, int minimum,
+          float *xl, float *xh) {
+    if (dim == 2) return vel_prox<2>(nl, nh, wl, wh, kl, kh, C, minimum != 0, xl, xh);
+    return vel_prox<3>(nl, nh, wl, wh, kl, kh, C, minimum != 0, xl, xh);
+}
+}

@@ -39,12 +39,13 @@ def _close(a, b):
     return np.abs(a - b) <= TOL * np.maximum(np.abs(b), 1.0)
 
 
-def one_iteration_parity(inst, z, u, lrho, k=0, flags=0, solver=None, report=None, mode=O.MODE_TWA):
+def one_iteration_parity(inst, z, u, lrho, k=0, flags=0, solver=None, report=None, mode=O.MODE_TWA,
+                         cost=O.COST_ENERGY):
     """Run one iteration from (z, u, lrho) on both sides and compare."""
     import torch
     z32 = np.asarray(z, np.float32)
     u32 = np.asarray(u, np.float32)
-    P = O.Planner(inst, mode=mode)
+    P = O.Planner(inst, mode=mode, cost=cost)
     P.set_state(z32.astype(np.float64), u32.astype(np.float64), lrho, k)
     P.iterate(1)
     zr, ur, lr = P.get_state()
@@ -78,8 +79,8 @@ def one_iteration_parity(inst, z, u, lrho, k=0, flags=0, solver=None, report=Non
     return info
 
 
-def _reference_states(inst, ks, mode=O.MODE_TWA):
-    P = O.Planner(inst, mode=mode)
+def _reference_states(inst, ks, mode=O.MODE_TWA, cost=O.COST_ENERGY):
+    P = O.Planner(inst, mode=mode, cost=cost)
     out = []
     done = 0
     for k in ks:

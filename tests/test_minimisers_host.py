@@ -335,3 +335,32 @@ def test_coll_vjp_parallel_differences(H, ratio):
         if checked >= 40:
             break
     assert checked >= 20
+
+
+@pytest.mark.parametrize("minimum", [False, True])
+@pytest.mark.parametrize("wmode", ["std", "inf_lo", "inf_hi", "unequal"])
+def test_velocity_minimiser_matches_reference(H, minimum, wmode):
+    H.h_vel.argtypes = [ct.c_int, _fp, _fp, ct.c_float, ct.c_float, ct.c_int, ct.c_int, ct.c_float, ct.c_int, _fp,
+                        _fp]
+    H.h_vel.restype = ct.c_int
+    rng = np.random.default_rng(hash(("vel", minimum, wmode)) % 2**32)
+    for _ in range(300):
+        dim = int(rng.choice([2, 3]))
+        nl = _f32(rng.normal(0, 1, dim)).astype(np.float64)
+        nh = _f32(rng.normal(0, 1, dim)).astype(np.float64)
+        C = float(np.float32(rng.uniform(0.2, 2.5)))
+        d = np.linalg.norm(nl - nh)
+        if abs(d - C) < 1e-4 * C:
+            continue  # the binding test itself is within rounding
+        wl, wh = (float(np.float32(v)) for v in rng.uniform(0.2, 3.0, 2))
+        if wmode == "std":
+            wl = wh = 1.0
+        kl = 2 if wmode == "inf_lo" else 1
+        kh = 2 if wmode == "inf_hi" else 1
+        act, xl, xh = O.prox_vel(nl, nh, np.inf if kl == 2 else wl, np.inf if kh == 2 else wh, C, minimum)
+        gl = np.zeros(dim, np.float32)
+        gh = np.zeros(dim, np.float32)
+        got = H.h_vel(dim, _f32(nl).ctypes.data_as(_fp), _f32(nh).ctypes.data_as(_fp), wl, wh, kl, kh, C,
+                      int(minimum), gl.ctypes.data_as(_fp), gh.ctypes.data_as(_fp))
+        assert bool(got) == act
+        assert _close(np.concatenate([gl, gh]).astype(np.float64), np.concatenate([xl, xh]))
