@@ -225,6 +225,65 @@ def run_admm_vs_twa(max_iters=20000, every=50):
     return out
 
 
+def run_feasible_vs_energy(max_iters=20000, every=25):
+    """Sec. 4 (CONF2): random starts and goals in the plane.  Iterations to a
+    collision-free plan with no cost term, against iterations until the
+    energy run is collision-free and its objective has settled (within 1e-3
+    of the value after max_iters), and the feasibility restart from the
+    energy run stopped at 10% of that."""
+    import numpy as np
+    import torch
+    from paper_1311_4527_amd import instances as I
+    from paper_1311_4527_amd.twa import Solver, TWA_F_COST_NONE
+    out = []
+    for p in (16, 32, 64):
+        inst = I.random_box(p, 0.02, 8, min_sep=0.05, sigma=1e-3, seed=100 + p, alpha=0.1, C=1.0 / (p * 8))
+        row = dict(p=p, eta=8, r=0.02)
+        # feasibility only
+        S = Solver.from_instance(inst, flags=TWA_F_COST_NONE)
+        free = None
+        for k in range(every, max_iters + 1, every):
+            S.twa_iterate(every)
+            if min_clearance_pairs(inst.radii, S.twa_get_trajectories().cpu().numpy()) >= -1e-6:
+                free = k
+                break
+        row["feasible_iterations"] = free
+        S.close()
+        # energy: objective trace
+        E = Solver.from_instance(inst)
+        trace = []
+        for k in range(every, max_iters + 1, every):
+            E.twa_iterate(every)
+            z = E.twa_get_trajectories().cpu().numpy()
+            trace.append((k, objective(inst, z), min_clearance_pairs(inst.radii, z)))
+        E.close()
+        Jf = trace[-1][1]
+        row["energy_iterations"] = next((k for k, J, c in trace if abs(J - Jf) <= 1e-3 * Jf and c >= -1e-6), None)
+        # stop the energy run early, then solve the feasibility problem from its state
+        stop = max(every, (row["energy_iterations"] or max_iters) // 10)
+        E = Solver.from_instance(inst)
+        E.twa_iterate(stop)
+        zz, uu, ll, _ = E.twa_get_state()
+        row["energy_stopped_at"] = stop
+        row["stopped_clearance"] = min_clearance_pairs(inst.radii, zz.cpu().numpy())
+        F = Solver.from_instance(inst, flags=TWA_F_COST_NONE)
+        F.twa_set_state(zz, uu, ll, 0)
+        restart = None
+        for k in range(every, max_iters + 1, every):
+            F.twa_iterate(every)
+            if min_clearance_pairs(inst.radii, F.twa_get_trajectories().cpu().numpy()) >= -1e-6:
+                restart = k
+                break
+        row["restart_iterations"] = restart
+        row["restart_objective"] = objective(inst, F.twa_get_trajectories().cpu().numpy())
+        row["converged_objective"] = Jf
+        E.close()
+        F.close()
+        out.append(row)
+    torch.cuda.synchronize()
+    return out
+
+
 def run_adjoint(K=500):
     """Forward K iterations alone, then forward with the start remembered plus
     the adjoint (sqrt(K) checkpoints) on the p=256, eta=8 swap."""
@@ -343,6 +402,9 @@ def main():
               file=sys.stderr, flush=True)
         out["admm_vs_twa"] = run_admm_vs_twa()
         print(f"# admm vs twa: {[(r['p'], r['twa']['iterations_to_collision_free'], r['admm']['iterations_to_collision_free']) for r in out['admm_vs_twa']]}",
+              file=sys.stderr, flush=True)
+        out["feasible_vs_energy"] = run_feasible_vs_energy()
+        print(f"# feasible vs energy: {[(r['p'], r['feasible_iterations'], r['energy_iterations'], r['restart_iterations']) for r in out['feasible_vs_energy']]}",
               file=sys.stderr, flush=True)
         out["adjoint"] = run_adjoint(500)
         print(f"# adjoint: backward/forward {out['adjoint']['backward_over_forward']:.2f}", file=sys.stderr,
