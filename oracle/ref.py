@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libtwa_oracle.so")
 
 ZERO, STD, INF = 0, 1, 2
 MODE_TWA, MODE_ADMM = 0, 1
-COST_ENERGY, COST_NONE, COST_MAXVEL, COST_MINVEL = 0, 1, 2, 3
+COST_ENERGY, COST_NONE, COST_MAXVEL, COST_MINVEL, COST_VO = 0, 1, 2, 3, 4
 
 _lib = None
 _dp = ct.POINTER(ct.c_double)
@@ -193,6 +193,8 @@ class Planner:
         lrho = np.full((self.p, self.eta + 1), INF if mode == MODE_TWA else STD, dtype=np.uint8)
         if self.eta > 1:
             lrho[:, 1:self.eta] = STD
+        if cost == COST_VO:
+            lrho[:, self.eta] = STD  # the reference end is soft
         self.set_state(inst.z0, np.zeros((self.E, self.dim)), lrho, 0)
 
     def __del__(self):

@@ -59,7 +59,14 @@ enum { TOR_ZERO = 0, TOR_STD = 1, TOR_INF = 2 };
 enum { TOR_F_FIXED = 0, TOR_F_ENERGY = 1, TOR_F_COLL = 2, TOR_F_WALL = 3 };
 enum { TOR_MODE_TWA = 0, TOR_MODE_ADMM = 1 };
 /* the per-segment factor of each agent (eq. velo_cost_pair_wise, eq. max_vel_min) */
-enum { TOR_COST_ENERGY = 0, TOR_COST_NONE = 1, TOR_COST_MAXVEL = 2, TOR_COST_MINVEL = 3 };
+enum { TOR_COST_ENERGY = 0, TOR_COST_NONE = 1, TOR_COST_MAXVEL = 2, TOR_COST_MINVEL = 3, TOR_COST_VO = 4 };
+/* TOR_COST_VO: one planning epoch of the velocity-obstacle local planner
+ * (Sec. 5, App. H), eta = 1: x(0) are the current positions, xT the
+ * reference end positions x^ref, C[i] the cost c_i of deviating from them.
+ * The energy factors are absent and each goal factor becomes the VO cost
+ * minimiser g^cost(x^ref, n, inf, rho, c) (eq. minimizer_rvo_cost), weight
+ * rho0; the agent-agent and agent-wall factors with their start ends fixed
+ * are eq. minimizer_rvo_coll and eq. minimizer_rvo_wall as they stand. */
 
 /* Relative size of the "small equal value" that replaces a zero weight. */
 #define TOR_ZERO_WEIGHT 1e-9
@@ -862,7 +869,7 @@ static long node_id(const tor_t *T, int i, int s) { return (long)i * (T->eta + 1
 void *tor_create(int p, int eta, int dim, const double *radii, const double *x0, const double *xT, int W,
                  const double *walls, const double *C, double rho0, double alpha, int mode, int cost) {
     if (p < 1 || eta < 1 || (dim != 2 && dim != 3) || W < 0 || (W > 0 && dim != 2)) return NULL;
-    if (cost < TOR_COST_ENERGY || cost > TOR_COST_MINVEL) return NULL;
+    if (cost < TOR_COST_ENERGY || cost > TOR_COST_VO || (cost == TOR_COST_VO && eta != 1)) return NULL;
     tor_t *T = (tor_t *)calloc(1, sizeof(tor_t));
     T->p = p, T->eta = eta, T->dim = dim, T->W = W, T->mode = mode, T->cost = cost;
     T->rho0 = rho0, T->alpha = alpha, T->rho0_init = rho0, T->n_warm = 0;
@@ -951,7 +958,7 @@ void *tor_create(int p, int eta, int dim, const double *radii, const double *x0,
                     x0[i * dim + k] + ((double)s / eta) * (xT[i * dim + k] - x0[i * dim + k]);
     for (long k = 0; k < T->E; k++) {
         int s = (int)(T->enode[k] % (eta + 1));
-        T->rin[k] = (mode == TOR_MODE_TWA && (s == 0 || s == eta)) ? TOR_INF : TOR_STD;
+        T->rin[k] = (mode == TOR_MODE_TWA && (s == 0 || (s == eta && cost != TOR_COST_VO))) ? TOR_INF : TOR_STD;
     }
     return T;
 }
@@ -1025,7 +1032,14 @@ static void run_factor(tor_t *T, long f, double rho) {
     int t = T->ftype[f];
     double *n = T->n, *x = T->x;
     unsigned char out = TOR_STD;
-    if (t == TOR_F_FIXED) {
+    if (t == TOR_F_FIXED && T->cost == TOR_COST_VO && T->fs[f] != 0) {
+        /* VO cost: the energy minimiser with its first end certain at x^ref */
+        int i = T->fa[f];
+        double tmp[3];
+        tor_prox_energy(T->xT + i * dim, n + e * dim, INFINITY, weight_value(T, T->rin[e], rho), T->C[i], dim, tmp,
+                        x + e * dim);
+        out = TOR_STD;
+    } else if (t == TOR_F_FIXED) {
         int i = T->fa[f];
         const double *c = (T->fs[f] == 0) ? T->x0 + i * dim : T->xT + i * dim;
         for (int k = 0; k < dim; k++) x[e * dim + k] = c[k];
@@ -1037,7 +1051,7 @@ static void run_factor(tor_t *T, long f, double rho) {
         if (T->cost == TOR_COST_ENERGY) {
             tor_prox_energy(n + e * dim, n + (e + 1) * dim, wl, wh, Cf, dim, x + e * dim, x + (e + 1) * dim);
             out = TOR_STD;
-        } else if (T->cost == TOR_COST_NONE) {
+        } else if (T->cost == TOR_COST_NONE || T->cost == TOR_COST_VO) {
             /* no cost: the factor is absent (x = n, weight zero) */
             for (int k = 0; k < 2 * dim; k++) x[e * dim + k] = n[e * dim + k];
             out = TOR_ZERO;

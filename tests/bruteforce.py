@@ -195,3 +195,34 @@ def brute_vel(nl, nh, wl, wh, C, minimum, starts=12, seed=0):
         if best is None or r.fun < best.fun:
             best = r
     return best.x[:dim], best.x[dim:], best.fun
+
+
+def brute_vo_epoch(x0, xref, radii, c, starts=60, seed=0):
+    """Velocity-obstacle epoch (eq. rec_col_avoi_pos): min sum_i c_i |x_i - xref_i|^2
+    s.t. every pair moving at constant velocity from x0 to x stays >= r_i + r_j
+    apart, by multi-start SLSQP on the exact closest-approach constraint."""
+    x0, xref = np.asarray(x0, float), np.asarray(xref, float)
+    p, dim = x0.shape
+    rng = np.random.default_rng(seed)
+    iu, ju = np.triu_indices(p, 1)
+
+    def f(v):
+        return float(np.sum(c[:, None] * (v.reshape(p, dim) - xref) ** 2))
+
+    def g(v):
+        x = v.reshape(p, dim)
+        out = []
+        for i, j in zip(iu, ju):
+            out.append(cpa_np(x0[j] - x0[i], x[j] - x[i]) - (radii[i] + radii[j]))
+        return np.array(out)
+
+    best = None
+    for k in range(starts):
+        v0 = (xref + rng.normal(0, 0.3 * float(np.max(radii)) * (k > 0) * 4, xref.shape)).reshape(-1)
+        r = minimize(f, v0, constraints=[dict(type="ineq", fun=g)], method="SLSQP",
+                     options=dict(ftol=1e-13, maxiter=1000))
+        if np.min(g(r.x)) < -1e-8:
+            continue
+        if best is None or r.fun < best.fun:
+            best = r
+    return best.x.reshape(p, dim), best.fun

@@ -218,3 +218,68 @@ def test_velocity_limits_hold_at_convergence(minimum):
     else:
         assert np.all(steps <= C * (1 + 1e-3))
     assert P.min_clearance() > -1e-4
+
+
+# ------------------------------------------------------------------ velocity-obstacle epochs (Sec. 5, App. H)
+
+def _vo_epoch_instance(x0, xref, radii, c, walls=None):
+    p, dim = x0.shape
+    z0 = np.stack([x0, xref], axis=1)
+    return I.Instance(p=p, eta=1, dim=dim, radii=np.asarray(radii, float), x0=x0.copy(), xT=xref.copy(),
+                      walls=np.zeros((0, 2, dim)) if walls is None else walls, C=np.asarray(c, float)[:, None],
+                      z0=z0, rho0=1.0, alpha=0.1)
+
+
+def test_vo_epoch_with_free_references_returns_them():
+    x0 = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    xref = x0 + np.array([[0.1, 0.0], [0.0, 0.1], [-0.1, 0.0]])
+    P = O.Planner(_vo_epoch_instance(x0, xref, [0.05] * 3, [1.0, 1.0, 1.0]), cost=O.COST_VO)
+    P.iterate(2000)
+    assert np.allclose(P.trajectories()[:, 1], xref, atol=1e-9)
+
+
+def test_vo_epoch_head_on_matches_bruteforce():
+    """Two agents whose preferred motions cross: the converged epoch solution
+    is collision-free and as cheap as the best multi-start SLSQP solution."""
+    x0 = np.array([[-0.5, 0.0], [0.5, 0.01]])
+    xref = np.array([[0.5, 0.0], [-0.5, 0.0]])
+    radii = np.array([0.1, 0.1])
+    c = 0.1 * np.array([1.0, 1.001])  # deviation cost well below rho0 (see the design notes' readings)
+    inst = _vo_epoch_instance(x0, xref, radii, c)
+    P = O.Planner(inst, cost=O.COST_VO)
+    P.iterate(6000)
+    x = P.trajectories()[:, 1]
+    d = bf.cpa_np(x0[1] - x0[0], x[1] - x[0]) - radii.sum()
+    assert d > -1e-6
+    J = float(np.sum(c[:, None] * (x - xref) ** 2))
+    xb, Jb = bf.brute_vo_epoch(x0, xref, radii, c)
+    assert J <= Jb * (1 + 1e-3) + 1e-9, (J, Jb)
+
+
+def test_vo_local_planner_swaps_collision_free():
+    """Sec. 5: epochs of horizon tau, moving a fraction of the way each epoch;
+    CONF1 with p=6, every agent reaches its goal and the executed motion never
+    overlaps (C_i = 1 + 0.001 i breaks the symmetry)."""
+    p, r, tau, frac, vmax = 6, 0.1, 1.0, 0.5, 0.25
+    ang = 2 * np.pi * np.arange(p) / p
+    pos = np.stack([np.cos(ang), np.sin(ang)], 1)
+    goal = -pos
+    c = 0.1 * (1.0 + 0.001 * np.arange(p))
+    radii = np.full(p, r)
+    for epoch in range(200):
+        dvec = goal - pos
+        dist = np.linalg.norm(dvec, axis=1)
+        if np.all(dist < 1e-3):
+            break
+        v = dvec / np.maximum(dist, 1e-12)[:, None] * np.minimum(dist / tau, vmax)[:, None]
+        xref = pos + v * tau
+        P = O.Planner(_vo_epoch_instance(pos, xref, radii, c), cost=O.COST_VO)
+        P.iterate(1500)
+        x = P.trajectories()[:, 1]
+        new = pos + frac * (x - pos)
+        # the executed part of the epoch is collision-free
+        iu, ju = np.triu_indices(p, 1)
+        for i, j in zip(iu, ju):
+            assert bf.cpa_np(pos[j] - pos[i], new[j] - new[i]) >= 2 * r - 1e-6
+        pos = new
+    assert np.all(np.linalg.norm(goal - pos, axis=1) < 1e-2)
