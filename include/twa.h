@@ -86,7 +86,17 @@ enum {
      * Velocity limits must be > 0.  twa_backward needs the energy cost. */
     TWA_F_COST_NONE = 1u << 3,
     TWA_F_COST_MAXVEL = 1u << 4,
-    TWA_F_COST_MINVEL = 1u << 5
+    TWA_F_COST_MINVEL = 1u << 5,
+    /* One epoch of the velocity-obstacle local planner (Sec. 5, eq.
+     * rec_col_avoi_pos, App. H): eta must be 1; x0 are the current positions,
+     * xT the reference end positions x^ref = x0 + v^ref tau (preferences:
+     * they may overlap), C[i] > 0 the cost c_i of deviating from them.  The
+     * goal factors become the VO cost minimiser (energy minimiser with its
+     * reference end certain, weight rho0); the collision and wall factors
+     * keep their start ends fixed.  The solution's break-point 1 is each
+     * agent's collision-free end position for the epoch.  No TWA_F_COST_*
+     * flag with it. */
+    TWA_F_VO = 1u << 6
 };
 
 typedef struct {

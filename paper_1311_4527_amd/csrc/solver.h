@@ -59,6 +59,7 @@ struct Params {
     int dense;
     int admm; // standard ADMM: every factor sends weight rho0 (TWA_F_ADMM)
     int cost; // per-segment factors: energy, none, maximum or minimum velocity
+    int vo;   // one epoch of the velocity-obstacle planner (TWA_F_VO)
     // debug capture of this iteration
     float *dbg_x;
     unsigned char *dbg_rho;

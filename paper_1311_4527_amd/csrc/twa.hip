@@ -462,9 +462,57 @@ __device__ __forceinline__ void energy_stream(const Params &P, long long f) {
     }
 }
 
+// Goal factor of a velocity-obstacle epoch (Sec. 5, App. H): the VO cost
+// c |x - x^ref|^2 as the energy minimiser with its reference end certain
+// (eq. minimizer_rvo_cost), always weight rho0.
+template <int D>
+__device__ __forceinline__ void vo_cost_prox(const float4 &xref, float C, const float *n, int k, float rho, float *x) {
+    const float r[3] = {xref.x, xref.y, xref.z};
+    for (int c = 0; c < D; ++c) {
+        float lo;
+        energy_prox(r[c], n[c], 0.f, wval(k, rho), W_INF, k, C, lo, x[c]);
+    }
+}
+
+template <int D, int MODE>
+__device__ __forceinline__ void vo_goal_stream(const Params &P, long long f) {
+    const int i = (int)(f >> 1);
+    const long long nd = (long long)P.eta * P.p + i;
+    const float C = P.C[i];
+    const float4 xr = P.xfix[f];
+    float *up = P.u_fixed + f * D;
+    float u[3], n[3], x[3], m[3], zc[3];
+    for (int c = 0; c < D; ++c) u[c] = up[c];
+    const float4 rc = P.zr_cur[nd];
+    node_xyz(rc, zc, D);
+    const int k = wcode(rc);
+    if (MODE != M_FIRST) {
+        // recompute x^k from (z^{k-1}, u^{k-1}), then u^k (weight rho0 both ways)
+        const float4 rp = P.zr_prev[nd];
+        float zp[3], xk[3];
+        node_xyz(rp, zp, D);
+        for (int c = 0; c < D; ++c) n[c] = zp[c] - u[c];
+        vo_cost_prox<D>(xr, C, n, wcode(rp), P.rho_prev, xk);
+        for (int c = 0; c < D; ++c) u[c] = (k == W_STD) ? u[c] + P.step_prev * (xk[c] - zc[c]) : 0.f, up[c] = u[c];
+        if (MODE == M_FINAL) return;
+    }
+    for (int c = 0; c < D; ++c) n[c] = zc[c] - u[c];
+    vo_cost_prox<D>(xr, C, n, k, P.rho, x);
+    for (int c = 0; c < D; ++c) m[c] = x[c] + u[c];
+    contribute(P, nd, 0, m, D);
+    if (P.dbg_x) {
+        for (int c = 0; c < D; ++c) P.dbg_x[f * D + c] = x[c];
+        P.dbg_rho[f] = W_STD;
+    }
+}
+
 // Fixed start/goal factor f: x = const, weight infinity.
 template <int D, int MODE>
 __device__ __forceinline__ void fixed_stream(const Params &P, long long f) {
+    if (P.vo && (f & 1)) {
+        vo_goal_stream<D, MODE>(P, f);
+        return;
+    }
     int i = (int)(f >> 1);
     int s = (f & 1) ? P.eta : 0;
     long long nd = (long long)s * P.p + i;
@@ -804,7 +852,7 @@ __global__ void k_reset_counters(int *counters) {
 // ------------------------------------------------------------------ layout conversion
 // canonical [p][eta+1][dim] <-> time-major node records
 __global__ void k_z_import(float4 *zr, const float *z, int p, int eta, int D, const unsigned char *lrho, int keep_w,
-                           int endcode) {
+                           int startcode, int goalcode) {
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long N = (long long)p * (eta + 1);
     if (t >= N) return;
@@ -815,7 +863,7 @@ __global__ void k_z_import(float4 *zr, const float *z, int p, int eta, int D, co
     r.y = z[t * D + 1];
     r.z = D == 3 ? z[t * D + 2] : 0.f;
     if (lrho) r.w = (float)lrho[t];
-    else if (!keep_w) r.w = (float)((s == 0 || s == eta) ? endcode : W_STD);
+    else if (!keep_w) r.w = (float)(s == 0 ? startcode : (s == eta ? goalcode : W_STD));
     zr[nd] = r;
 }
 __global__ void k_z_export(const float4 *zr, float *z, unsigned char *lrho, int p, int eta, int D) {
@@ -860,12 +908,12 @@ __global__ void k_u_convert(Params P, float *u, int D, int dir) {
         else *src = *dst;
     }
 }
-__global__ void k_fix_ends(float4 *zr, const float4 *xfix, int p, int eta, int endcode) {
+__global__ void k_fix_ends(float4 *zr, const float4 *xfix, int p, int eta, int startcode, int goalcode) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p) return;
     float4 a = xfix[2 * i], b = xfix[2 * i + 1];
-    a.w = (float)endcode;
-    b.w = (float)endcode;
+    a.w = (float)startcode;
+    b.w = (float)goalcode;
     zr[i] = a;
     zr[(long long)eta * p + i] = b;
 }
@@ -1143,7 +1191,7 @@ twa_status import_state(twa_solver *s, const float *z, const float *u, const uns
     TRY(reset_state_buffers(s));
     unsigned nb = (unsigned)((s->P.N + 255) / 256);
     hipLaunchKernelGGL(k_z_import, dim3(nb), dim3(256), 0, s->stream, s->P.zr_cur, z, s->p, s->eta, s->dim, lrho, 1,
-                       (int)W_INF);
+                       (int)W_INF, (int)W_INF);
     long long E = s->P.e_wall + 2 * s->P.Fw;
     hipLaunchKernelGGL(k_u_convert, dim3((unsigned)((E + 255) / 256)), dim3(256), 0, s->stream, s->P,
                        const_cast<float *>(u), s->dim, 0);
@@ -1207,8 +1255,12 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         fail(s, TWA_E_INVALID, "choose at most one TWA_F_COST_* flag");
         return bail(TWA_E_INVALID);
     }
+    if ((flags & TWA_F_VO) && (cost_flags || eta != 1)) {
+        fail(s, TWA_E_INVALID, "TWA_F_VO needs eta == 1 and no TWA_F_COST_* flag");
+        return bail(TWA_E_INVALID);
+    }
     if (flags & ~(unsigned)(TWA_F_DENSE | TWA_F_TAPE | TWA_F_ADMM | TWA_F_COST_NONE | TWA_F_COST_MAXVEL |
-                            TWA_F_COST_MINVEL)) {
+                            TWA_F_COST_MINVEL | TWA_F_VO)) {
         fail(s, TWA_E_INVALID, "unsupported flag");
         return bail(TWA_E_INVALID);
     }
@@ -1235,18 +1287,20 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
             fail(s, TWA_E_INVALID, "radii must be > 0");
             return bail(TWA_E_INVALID);
         }
-    const bool vel = (flags & (TWA_F_COST_MAXVEL | TWA_F_COST_MINVEL)) != 0;
+    const bool vel = (flags & (TWA_F_COST_MAXVEL | TWA_F_COST_MINVEL | TWA_F_VO)) != 0;
     for (float c : hC)
         if (vel ? !(c > 0.f) : c < 0.f) {
-            fail(s, TWA_E_INVALID, vel ? "velocity limits must be > 0" : "energy coefficients must be >= 0");
+            fail(s, TWA_E_INVALID,
+                 vel ? "velocity limits and deviation costs must be > 0" : "energy coefficients must be >= 0");
             return bail(TWA_E_INVALID);
         }
     double Lmax = 1.0;
     for (float v : h0) Lmax = std::max(Lmax, (double)std::fabs(v));
     for (float v : hT) Lmax = std::max(Lmax, (double)std::fabs(v));
     for (float v : hw) Lmax = std::max(Lmax, (double)std::fabs(v));
-    // feasibility of the fixed end points (Sec. 1: non-strict separation)
-    for (int which = 0; which < 2; ++which) {
+    // feasibility of the fixed end points (Sec. 1: non-strict separation);
+    // a velocity-obstacle epoch's reference ends are preferences, not constraints
+    for (int which = 0; which < ((flags & TWA_F_VO) ? 1 : 2); ++which) {
         const std::vector<float> &X = which ? hT : h0;
         for (int i = 0; i < p; ++i)
             for (int j = i + 1; j < p; ++j) {
@@ -1315,7 +1369,8 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     P.f_wall = Ff + Fe + Fc;
     // standard ADMM keeps u on every edge: it runs in the dense form
     P.admm = (flags & TWA_F_ADMM) ? 1 : 0;
-    P.cost = (flags & TWA_F_COST_NONE)     ? COST_NONE
+    P.vo = (flags & TWA_F_VO) ? 1 : 0;
+    P.cost = (flags & (TWA_F_COST_NONE | TWA_F_VO)) ? COST_NONE
              : (flags & TWA_F_COST_MAXVEL) ? COST_MAXVEL
              : (flags & TWA_F_COST_MINVEL) ? COST_MINVEL
                                            : COST_ENERGY;
@@ -1395,7 +1450,8 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
                 v[c] = (s2 == 0) ? (float)a : (s2 == eta) ? (float)b : (float)(a + (double)s2 / eta * (b - a));
             }
             hz[(size_t)s2 * p + i] =
-                make_float4(v[0], v[1], v[2], (float)((s2 == 0 || s2 == eta) && !P.admm ? W_INF : W_STD));
+                make_float4(v[0], v[1], v[2],
+                            (float)(((s2 == 0 && !P.admm) || (s2 == eta && !P.admm && !P.vo)) ? W_INF : W_STD));
         }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpyAsync(radii_d, hr.data(), sizeof(float) * p, hipMemcpyHostToDevice, s->stream);
@@ -1438,13 +1494,14 @@ twa_status twa_set_init(twa_solver *s, const float *z) {
     if (!z) return fail(s, TWA_E_INVALID, "null z");
     long long N = s->P.N;
     unsigned nb = (unsigned)((N + 255) / 256);
-    const int endcode = s->P.admm ? (int)W_STD : (int)W_INF;
+    const int startcode = s->P.admm ? (int)W_STD : (int)W_INF;
+    const int goalcode = (s->P.admm || s->P.vo) ? (int)W_STD : (int)W_INF;
     hipLaunchKernelGGL(k_z_import, dim3(nb), dim3(256), 0, s->stream, s->P.zr_cur, z, s->p, s->eta, s->dim,
-                       (const unsigned char *)nullptr, 0, endcode);
+                       (const unsigned char *)nullptr, 0, startcode, goalcode);
     HIP_TRY(s, hipGetLastError());
     // the end points are the constants x(0), x(T)
     hipLaunchKernelGGL(k_fix_ends, dim3((unsigned)((s->p + 255) / 256)), dim3(256), 0, s->stream, s->P.zr_cur,
-                       (const float4 *)s->P.xfix, s->p, s->eta, endcode);
+                       (const float4 *)s->P.xfix, s->p, s->eta, startcode, goalcode);
     HIP_TRY(s, hipGetLastError());
     HIP_TRY(s, hipMemcpyAsync(s->P.zr_prev, s->P.zr_cur, sizeof(float4) * N, hipMemcpyDeviceToDevice, s->stream));
     TRY(reset_state_buffers(s));

@@ -26,6 +26,7 @@ TWA_F_ADMM = 4
 TWA_F_COST_NONE = 8
 TWA_F_COST_MAXVEL = 16
 TWA_F_COST_MINVEL = 32
+TWA_F_VO = 64
 _STATUS = {0: "TWA_OK", 1: "TWA_E_INVALID", 2: "TWA_E_INFEASIBLE", 3: "TWA_E_NOMEM", 4: "TWA_E_DEVICE",
            5: "TWA_E_NUMERIC", 6: "TWA_E_STATE"}
 

@@ -1,0 +1,73 @@
+"""Velocity-obstacle epochs on the GPU (TWA_F_VO) against the FP64 reference
+epoch, and the epoch loop of the local planner (Sec. 5)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import bruteforce as bf
+from tests.test_gpu_parity import _reference_states, one_iteration_parity
+from tests.test_oracle_engine import _vo_epoch_instance
+
+pytestmark = pytest.mark.gpu
+
+
+def _swap_epoch(p=6, r=0.1, step=0.25, seed=0):
+    """Agents on a circle heading inwards, perturbed so that no two
+    candidate configurations of a minimiser tie exactly."""
+    rng = np.random.default_rng(seed)
+    ang = 2 * np.pi * np.arange(p) / p + rng.normal(0, 0.02, p)
+    pos = np.stack([np.cos(ang), np.sin(ang)], 1) * 0.4
+    xref = pos - pos / np.linalg.norm(pos, axis=1)[:, None] * step * 2 + rng.normal(0, 0.01, (p, 2))
+    return _vo_epoch_instance(pos, xref, np.full(p, r), 0.1 * (1 + 0.001 * np.arange(p)))
+
+
+def _flags():
+    from paper_1311_4527_amd.twa import TWA_F_VO
+    return TWA_F_VO
+
+
+def test_vo_one_iteration_parity():
+    inst = _swap_epoch()
+    for k, z, u, lr in _reference_states(inst, [0, 1, 10, 100, 600], cost=O.COST_VO):
+        one_iteration_parity(inst, z, u, lr, k, flags=_flags(), cost=O.COST_VO)
+
+
+def test_vo_one_iteration_parity_walls():
+    x0 = np.array([[0.2, 0.2], [0.8, 0.2], [0.5, 0.8]])
+    xref = np.array([[0.8, 0.5], [0.2, 0.5], [0.5, 0.3]])
+    walls = np.array([[[0.45, 0.35], [0.55, 0.45]]])
+    inst = _vo_epoch_instance(x0, xref, [0.05, 0.05, 0.05], [0.1, 0.1001, 0.1002], walls=walls)
+    for k, z, u, lr in _reference_states(inst, [0, 2, 40, 300], cost=O.COST_VO):
+        one_iteration_parity(inst, z, u, lr, k, flags=_flags(), cost=O.COST_VO)
+
+
+def test_vo_epoch_matches_reference():
+    from paper_1311_4527_amd.twa import Solver
+    inst = _swap_epoch()
+    S = Solver.from_instance(inst, flags=_flags())
+    S.twa_iterate(3000)
+    xg = S.twa_get_trajectories().cpu().numpy().astype(np.float64)[:, 1]
+    P = O.Planner(inst, cost=O.COST_VO)
+    P.iterate(3000)
+    xr = P.trajectories()[:, 1]
+    c = inst.C[:, 0]
+    Jg = float(np.sum(c[:, None] * (xg - inst.xT) ** 2))
+    Jr = float(np.sum(c[:, None] * (xr - inst.xT) ** 2))
+    assert abs(Jg - Jr) <= 1e-3 * Jr, (Jg, Jr)
+    iu, ju = np.triu_indices(inst.p, 1)
+    for i, j in zip(iu, ju):
+        assert bf.cpa_np(inst.x0[j] - inst.x0[i], xg[j] - xg[i]) >= 2 * inst.radii[0] - 1e-5
+
+
+def test_vo_planner_swaps_collision_free():
+    from paper_1311_4527_amd.vo import VOPlanner
+    p, r = 6, 0.1
+    ang = 2 * np.pi * np.arange(p) / p
+    pos = np.stack([np.cos(ang), np.sin(ang)], 1)
+    V = VOPlanner(pos, -pos, np.full(p, r), tau=1.0, fraction=0.5, vmax=0.25)
+    path = V.run(200)
+    assert V.arrived()
+    iu, ju = np.triu_indices(p, 1)
+    for a, b in zip(path[:-1], path[1:]):
+        for i, j in zip(iu, ju):
+            assert bf.cpa_np(a[j] - a[i], b[j] - b[i]) >= 2 * r - 1e-5

@@ -83,3 +83,14 @@ def test_binding_exposes_the_abi_names():
         if n in internal:
             continue
         assert hasattr(twa.Solver, n) or hasattr(twa.Batch, n) or hasattr(twa, n), n
+
+
+def test_create_rejects_flag_combinations(lib):
+    lib.twa_create.restype = ct.c_int
+    out = ct.c_void_p()
+    dummy = ct.c_void_p(16)
+    vo, none, maxv = 1 << 6, 1 << 3, 1 << 4
+    for eta, flags in [(2, vo), (1, vo | none), (4, none | maxv)]:
+        st = lib.twa_create(4, eta, 2, dummy, dummy, dummy, 0, None, dummy, ct.c_float(1.0), ct.c_float(0.1), flags,
+                            None, ct.byref(out))
+        assert st == 1 and not out.value
