@@ -122,7 +122,8 @@ typedef struct {
  *   flags              TWA_F_* above.
  *   hip_stream         hipStream_t on which every call runs (NULL = default).
  * Starts must be pairwise >= r_i + r_j apart, and so must goals; no start or
- * goal may lie within r_i of a wall (TWA_E_INFEASIBLE otherwise).
+ * goal may lie within r_i of a wall (TWA_E_INFEASIBLE otherwise; overlaps up
+ * to 1e-5 relative, the rounding of positions left in contact, are accepted).
  * Initial state: straight lines from start to goal, u = 0, <-rho = infinity
  * at start and goal, rho0 elsewhere.  Synchronises the stream.
  * On success *out owns all device memory it allocated (twa_destroy frees it).

@@ -64,11 +64,12 @@ TWA_HD float cpa_sq(f3 d0, f3 d1) {
 // projection of the origin falls inside, and then its squared distance is
 // |d0 x e|^2 / |e|^2 with e = d1 - d0.
 TWA_HD bool cpa_below(f3 d0, f3 d1, float R2) {
+    // all three cases evaluated and selected (no divergent branches)
     f3 e = sub3(d1, d0);
-    if (dot3(d0, e) >= 0.f) return dot3(d0, d0) < R2;
-    if (dot3(d1, e) <= 0.f) return dot3(d1, d1) < R2;
     f3 c{d0.y * e.z - d0.z * e.y, d0.z * e.x - d0.x * e.z, d0.x * e.y - d0.y * e.x};
-    return dot3(c, c) < R2 * dot3(e, e);
+    const bool at0 = dot3(d0, e) >= 0.f, at1 = dot3(d1, e) <= 0.f;
+    const bool in0 = dot3(d0, d0) < R2, in1 = dot3(d1, d1) < R2, inm = dot3(c, c) < R2 * dot3(e, e);
+    return at0 ? in0 : (at1 ? in1 : inm);
 }
 
 TWA_HD float point_seg_sq(f2 q, f2 a, f2 b) {

@@ -179,6 +179,9 @@ __device__ __forceinline__ float4 load_uniform(const float4 *p, long long idx) {
 __device__ __forceinline__ float load_uniform(const float *p, long long idx) {
     return ((const __attribute__((address_space(4))) float *)p)[idx];
 }
+__device__ __forceinline__ unsigned long long load_uniform(const unsigned long long *p, long long idx) {
+    return ((const __attribute__((address_space(4))) unsigned long long *)p)[idx];
+}
 
 // Collision factor f given its four node records ((i,s), (i,s+1), (j,s),
 // (j,s+1): current, and the previous iteration's for the dense form) and
@@ -253,7 +256,7 @@ __device__ __forceinline__ void coll_column(const Params &P, int col, int s0, in
     constexpr bool need_u = DENSE || MODE == M_FIRST;
     constexpr bool need_word = !DENSE && MODE != M_FIRST;
     const int cu = __builtin_amdgcn_readfirstlane(col);
-    const unsigned long long pk = P.chunk_coll[cu];
+    const unsigned long long pk = load_uniform(P.chunk_coll, cu);
     const int i = (int)(pk >> 24), j0 = (int)(pk & 0xffffffull);
     const int p = P.p;
     const int j = j0 + lane;
@@ -289,18 +292,32 @@ __device__ __forceinline__ void coll_column(const Params &P, int col, int s0, in
             if (need_u && valid) load_u_coll<D>(P, (s0 + k) * P2 + fr, u[k]);
         }
     }
+    // every factor of the column first, then the stores: the activity words
+    // and the queue appends do not wait on each other's round trips
+    bool q[CPW];
+    unsigned val[CPW];
 #pragma unroll
     for (int k = 0; k < CPW; ++k) {
-        if (s0 + k < s1) {
+        q[k] = false;
+        val[k] = 0u;
+        if (s0 + k < s1 && valid) {
             const float4 rc[4] = {ri[k], ri[k + 1], rj[k], rj[k + 1]};
             const float4 rp[4] = {pi[k], pi[k + 1], pj[k], pj[k + 1]};
-            bool q = false;
-            unsigned val = 0u;
-            if (valid) q = coll_factor<D, MODE, DENSE>(P, (s0 + k) * P2 + fr, R, rc, rp, u[k], word[k], lane, &val);
-            if (clear_bits && lane == 0) P.bits_coll[(s0 + k) * (int)P.cps + cu] = 0ull;
-            push(P.qc, &P.counters[0], q, val);
+            q[k] = coll_factor<D, MODE, DENSE>(P, (s0 + k) * P2 + fr, R, rc, rp, u[k], word[k], lane, &val[k]);
         }
     }
+    if (clear_bits && lane == 0) {
+#pragma unroll
+        for (int k = 0; k < CPW; ++k)
+            if (s0 + k < s1) P.bits_coll[(s0 + k) * (int)P.cps + cu] = 0ull;
+    }
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) any = any || q[k];
+    if (__ballot(any) == 0ull) return; // nothing to queue: the common case
+#pragma unroll
+    for (int k = 0; k < CPW; ++k)
+        if (s0 + k < s1) push(P.qc, &P.counters[0], q[k], val[k]);
 }
 
 // Collision factor f of a flat walk over the canonical order (64
@@ -1309,7 +1326,8 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
                     double d = (double)X[i * dim + c] - X[j * dim + c];
                     d2 += d * d;
                 }
-                double R = (double)hr[i] + hr[j];
+                // FP32 positions in contact may overlap by rounding: 1e-5 relative slack
+                double R = ((double)hr[i] + hr[j]) * (1.0 - 1e-5);
                 if (d2 < R * R) {
                     fail(s, TWA_E_INFEASIBLE, std::string(which ? "goals " : "starts ") + std::to_string(i) + " and " +
                                                   std::to_string(j) + " overlap");
@@ -1323,7 +1341,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
                 double dx = bx - ax, dy = by - ay, L2 = dx * dx + dy * dy, t = 0;
                 if (L2 > 0) t = std::min(1.0, std::max(0.0, ((qx - ax) * dx + (qy - ay) * dy) / L2));
                 double ex = ax + t * dx - qx, ey = ay + t * dy - qy;
-                if (ex * ex + ey * ey < (double)hr[i] * hr[i]) {
+                if (ex * ex + ey * ey < (double)hr[i] * hr[i] * (1.0 - 2e-5)) {
                     fail(s, TWA_E_INFEASIBLE, std::string(which ? "goal " : "start ") + std::to_string(i) +
                                                   " touches wall " + std::to_string(w));
                     return bail(TWA_E_INFEASIBLE);
