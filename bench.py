@@ -284,6 +284,34 @@ def run_feasible_vs_energy(max_iters=20000, every=25):
     return out
 
 
+def run_vo(p=16, r=0.05):
+    """Sec. 5: the velocity-obstacle local planner on an antipodal swap of p
+    agents; wall time of every epoch's joint solve (eq. rec_col_avoi_pos) on
+    the GPU, iterated to a collision-free plan, as the paper times it."""
+    import numpy as np
+    import torch
+    from paper_1311_4527_amd.vo import VOPlanner
+    ang = 2 * np.pi * np.arange(p) / p
+    pos = np.stack([np.cos(ang), np.sin(ang)], 1)
+    V = VOPlanner(pos, -pos, np.full(p, r), tau=1.0, fraction=0.5, vmax=0.25)
+    V.solve_epoch()  # warm
+    times, its = [], []
+    for _ in range(200):
+        if V.arrived():
+            break
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        V.step()
+        times.append(time.perf_counter() - t0)
+        its.append(V.last_iterations)
+    t = np.array(times)
+    conv = [n for n in its if n > 0]
+    return dict(p=p, r=r, epochs=len(times), arrived=V.arrived(), epochs_at_cap=len(its) - len(conv),
+                iterations_median=float(np.median(conv)) if conv else None,
+                epoch_ms_median=float(np.median(t) * 1e3), epoch_ms_p90=float(np.percentile(t, 90) * 1e3),
+                epoch_ms_max=float(t.max() * 1e3))
+
+
 def run_adjoint(K=500):
     """Forward K iterations alone, then forward with the start remembered plus
     the adjoint (sqrt(K) checkpoints) on the p=256, eta=8 swap."""
@@ -406,6 +434,8 @@ def main():
         out["feasible_vs_energy"] = run_feasible_vs_energy()
         print(f"# feasible vs energy: {[(r['p'], r['feasible_iterations'], r['energy_iterations'], r['restart_iterations']) for r in out['feasible_vs_energy']]}",
               file=sys.stderr, flush=True)
+        out["vo_local_planner"] = run_vo()
+        print(f"# vo: {out['vo_local_planner']}", file=sys.stderr, flush=True)
         out["adjoint"] = run_adjoint(500)
         print(f"# adjoint: backward/forward {out['adjoint']['backward_over_forward']:.2f}", file=sys.stderr,
               flush=True)

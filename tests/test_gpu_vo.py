@@ -71,3 +71,18 @@ def test_vo_planner_swaps_collision_free():
     for a, b in zip(path[:-1], path[1:]):
         for i, j in zip(iu, ju):
             assert bf.cpa_np(a[j] - a[i], b[j] - b[i]) >= 2 * r - 1e-5
+
+
+def test_vo_planner_crowded_swap_collision_free():
+    """p=16 agents of radius 0.05 swapping across the unit circle: every epoch
+    is iterated to a collision-free plan (or its executed share shrunk), the
+    executed motion never overlaps and everyone arrives."""
+    from paper_1311_4527_amd.vo import VOPlanner
+    p, r = 16, 0.05
+    ang = 2 * np.pi * np.arange(p) / p
+    pos = np.stack([np.cos(ang), np.sin(ang)], 1)
+    V = VOPlanner(pos, -pos, np.full(p, r), tau=1.0, fraction=0.5, vmax=0.25)
+    path = V.run(200)
+    assert V.arrived()
+    for a, b in zip(path[:-1], path[1:]):
+        assert V.clearance(a, b) >= 0.0
