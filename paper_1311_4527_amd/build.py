@@ -11,7 +11,10 @@ ARCH = os.environ.get("TWA_OFFLOAD_ARCH", "gfx950")
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # -ffp-contract=on: a*b+c is fused only within one source expression, so
+    # every kernel that inlines a device function (plain, dense, batched)
+    # rounds it identically and their results stay bitwise equal.
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp"] + SRC
     if verbose:

@@ -42,7 +42,9 @@ struct Params {
     const int *rowchunk;                // [p] first chunk of row i within a break-point interval
     long long nch, cps, P2;             // chunks, chunks per interval, pairs p(p-1)/2
     unsigned *qc, *qw;
-    int *counters; // [0] qc length, [1] qw length, [2] active coll, [3] active wall
+    int *qcnt;        // collision queue shard lengths, shard q at [q * kQueueStride]
+    long long qcap;   // entries per collision queue shard
+    int *counters; // [1] qw length, [2] active coll, [3] active wall
     int *stats;    // last iteration: active coll, active wall, queued
     unsigned long long *acc; // [2 kinds][dim][N]  kind 0 = std, 1 = inf
     int *cnt;                // [2][N]

@@ -42,6 +42,13 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// The collision queue is cut into kShards shards with their lengths 256 B
+// apart: a wave of the factor stream appends to shard (wave mod kShards), so
+// the appends of the whole grid do not serialise on one address.  A shard
+// holds every factor its waves could append (no overflow is possible).
+constexpr int kShards = 32;
+constexpr int kQueueStride = 64;
+
 enum Mode : int { M_FIRST = 0, M_FUSED = 1, M_FINAL = 2 };
 
 // what the per-segment factors are (twa_create flags)
@@ -182,6 +189,9 @@ __device__ __forceinline__ float load_uniform(const float *p, long long idx) {
 __device__ __forceinline__ unsigned long long load_uniform(const unsigned long long *p, long long idx) {
     return ((const __attribute__((address_space(4))) unsigned long long *)p)[idx];
 }
+__device__ __forceinline__ int load_uniform(const int *p, long long idx) {
+    return ((const __attribute__((address_space(4))) int *)p)[idx];
+}
 
 // Collision factor f given its four node records ((i,s), (i,s+1), (j,s),
 // (j,s+1): current, and the previous iteration's for the dense form) and
@@ -249,9 +259,10 @@ __device__ __forceinline__ bool coll_factor(const Params &P, long long f, float 
 // through the scalar cache; the chunks' activity words; u where it is read)
 // is issued before any factor is evaluated.  Each chunk's activity word is
 // cleared after it was read (k_queue sets it again for the factors active
-// in this iteration).
+// in this iteration).  Queued factors go to collision queue shard `shard`.
 template <int D, int MODE, int CPW, bool DENSE>
-__device__ __forceinline__ void coll_column(const Params &P, int col, int s0, int s1, int lane, bool clear_bits) {
+__device__ __forceinline__ void coll_column(const Params &P, int col, int s0, int s1, int lane, bool clear_bits,
+                                            int shard) {
     constexpr bool need_prev = DENSE && MODE != M_FIRST;
     constexpr bool need_u = DENSE || MODE == M_FIRST;
     constexpr bool need_word = !DENSE && MODE != M_FIRST;
@@ -315,9 +326,10 @@ __device__ __forceinline__ void coll_column(const Params &P, int col, int s0, in
 #pragma unroll
     for (int k = 0; k < CPW; ++k) any = any || q[k];
     if (__ballot(any) == 0ull) return; // nothing to queue: the common case
+    unsigned *qs = P.qc + (long long)shard * P.qcap;
 #pragma unroll
     for (int k = 0; k < CPW; ++k)
-        if (s0 + k < s1) push(P.qc, &P.counters[0], q[k], val[k]);
+        if (s0 + k < s1) push(qs, &P.qcnt[shard * kQueueStride], q[k], val[k]);
 }
 
 // Collision factor f of a flat walk over the canonical order (64
@@ -351,7 +363,7 @@ __device__ __forceinline__ void coll_flat(const Params &P, long long f, bool val
         if (dense) q = coll_factor<D, MODE, true>(P, f, R, rc, rp, u, word, 0, &val);
         else q = coll_factor<D, MODE, false>(P, f, R, rc, rp, u, word, 0, &val);
     }
-    push(P.qc, &P.counters[0], q, val);
+    push(P.qc, &P.qcnt[0], q, val); // one shard spanning the whole queue
 }
 
 // Wall factor f: activity test (segment distance) and queue decision.
@@ -741,7 +753,9 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
         const unsigned wave = (unsigned)b * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const unsigned cps = (unsigned)P.cps;
         const int col = (int)(wave % cps), s0 = (int)(wave / cps) * CPW;
-        if (s0 < P.eta) coll_column<D, MODE, CPW, DENSE>(P, col, s0, min(s0 + CPW, P.eta), threadIdx.x & 63, clear_bits);
+        if (s0 < P.eta)
+            coll_column<D, MODE, CPW, DENSE>(P, col, s0, min(s0 + CPW, P.eta), threadIdx.x & 63, clear_bits,
+                                             (int)(wave % kShards));
     } else if (b < P.nbc + P.nbw) {
         long long f = (b - P.nbc) * kBlock + threadIdx.x;
         bool valid = f < P.Fw, q;
@@ -761,41 +775,70 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
     }
 }
 
-// Queue entry t of a wave-uniform loop: collision entries first, wall
-// entries from the next multiple of 64 (a wave never mixes the two
+// One queue entry per lane of a wave-uniform loop: collision entries first,
+// wall entries from the next multiple of 64 (a wave never mixes the two
 // minimisers, whose run times differ several-fold).
 template <int D, int MODE>
-__device__ __forceinline__ void queue_entry(const Params &P, long long t, int nqc, long long wall0, long long total) {
+__device__ __forceinline__ void queue_entry(const Params &P, bool is_coll, bool is_wall, unsigned e) {
     bool ac = false, aw = false;
-    if (t < nqc) ac = coll_queue<D, MODE>(P, P.qc[t]);
-    else if (t >= wall0 && t < total) aw = wall_queue<MODE>(P, P.qw[t - wall0]);
+    if (is_coll) ac = coll_queue<D, MODE>(P, e);
+    else if (is_wall) aw = wall_queue<MODE>(P, e);
     count_wave(&P.counters[2], ac);
     count_wave(&P.counters[3], aw);
 }
 
 // One wave per workgroup: the few busy waves land on different compute
-// units instead of sharing one unit's scalar pipeline and caches.
+// units instead of sharing one unit's scalar pipeline and caches.  Entry t
+// of the collision queue is entry t - (lengths of shards before it) of its
+// shard.
 template <int D, int MODE>
 __global__ __launch_bounds__(64) void k_queue(Params P) {
-    const int nqc = P.counters[0], nqw = P.counters[1];
+    int len[kShards];
+    int nqc = 0;
+#pragma unroll
+    for (int q = 0; q < kShards; ++q) {
+        len[q] = load_uniform(P.qcnt, q * kQueueStride);
+        nqc += len[q];
+    }
+    const int nqw = P.counters[1];
     const long long wall0 = ((long long)nqc + 63) & ~63LL, total = wall0 + nqw;
     const long long stride = (long long)gridDim.x * 64;
-    for (long long t0 = (long long)blockIdx.x * 64; t0 < total; t0 += stride)
-        queue_entry<D, MODE>(P, t0 + threadIdx.x, nqc, wall0, total);
+    for (long long t0 = (long long)blockIdx.x * 64; t0 < total; t0 += stride) {
+        const long long t = t0 + threadIdx.x;
+        const bool is_coll = t < nqc, is_wall = t >= wall0 && t < total;
+        unsigned e = 0u;
+        if (is_coll) {
+            long long off = t;
+            int sh = 0;
+#pragma unroll
+            for (int q = 0; q < kShards; ++q)
+                if (sh == q && off >= len[q]) off -= len[q], sh = q + 1;
+            e = P.qc[(long long)sh * P.qcap + off];
+        } else if (is_wall) {
+            e = P.qw[t - wall0];
+        }
+        queue_entry<D, MODE>(P, is_coll, is_wall, e);
+    }
 }
 
-__device__ __forceinline__ void close_counters(const Params &P) {
-    // counters of this iteration -> stats, then reset for the next one
+// counters of this iteration -> stats, then reset for the next one (the
+// first `shards` collision queue shards were in use)
+__device__ __forceinline__ void close_counters(const Params &P, int shards) {
+    int nq = P.counters[1];
+    for (int q = 0; q < shards; ++q) {
+        nq += P.qcnt[q * kQueueStride];
+        P.qcnt[q * kQueueStride] = 0;
+    }
     P.stats[0] = P.counters[2];
     P.stats[1] = P.counters[3];
-    P.stats[2] = P.counters[0] + P.counters[1];
-    P.counters[0] = P.counters[1] = P.counters[2] = P.counters[3] = 0;
+    P.stats[2] = nq;
+    P.counters[1] = P.counters[2] = P.counters[3] = 0;
 }
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_nodes(Params P) {
     long long nd = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (nd == 0) close_counters(P);
+    if (nd == 0) close_counters(P, kShards);
     if (nd < P.N) node_update<D>(P, nd);
 }
 
@@ -831,13 +874,16 @@ __device__ __forceinline__ void batch_instance(const Params &P) {
     for (long long f = threadIdx.x; f < P.Fe; f += BLOCK) energy_stream<D, MODE>(P, f);
     for (long long f = threadIdx.x; f < P.Ff; f += BLOCK) fixed_stream<D, MODE>(P, f);
     __syncthreads();
-    const int nqc = __atomic_load_n(&P.counters[0], __ATOMIC_RELAXED);
+    const int nqc = __atomic_load_n(&P.qcnt[0], __ATOMIC_RELAXED);
     const int nqw = __atomic_load_n(&P.counters[1], __ATOMIC_RELAXED);
     const long long wall0 = ((long long)nqc + 63) & ~63LL, total = wall0 + nqw;
-    for (long long t0 = threadIdx.x & ~63; t0 < total; t0 += BLOCK)
-        queue_entry<D, MODE>(P, t0 + (threadIdx.x & 63), nqc, wall0, total);
+    for (long long t0 = threadIdx.x & ~63; t0 < total; t0 += BLOCK) {
+        const long long t = t0 + (threadIdx.x & 63);
+        const bool is_coll = t < nqc, is_wall = t >= wall0 && t < total;
+        queue_entry<D, MODE>(P, is_coll, is_wall, is_coll ? P.qc[t] : is_wall ? P.qw[t - wall0] : 0u);
+    }
     __syncthreads();
-    if (threadIdx.x == 0) close_counters(P);
+    if (threadIdx.x == 0) close_counters(P, 1);
     for (long long nd = threadIdx.x; nd < P.N; nd += BLOCK) node_update<D>(P, nd);
     __syncthreads();
 }
@@ -862,8 +908,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const Params *insts, const int 
     }
 }
 
-__global__ void k_reset_counters(int *counters) {
-    if (threadIdx.x < 4) counters[threadIdx.x] = 0;
+__global__ void k_reset_counters(Params P) {
+    if (threadIdx.x < 4) P.counters[threadIdx.x] = 0;
+    if (threadIdx.x < kShards) P.qcnt[threadIdx.x * kQueueStride] = 0;
 }
 
 // ------------------------------------------------------------------ layout conversion
@@ -1044,7 +1091,7 @@ twa_status launch_iteration(twa_solver *s, int mode) {
         if (P.dense) hipLaunchKernelGGL((k_stream<D, M_FINAL, true>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
         else hipLaunchKernelGGL((k_stream<D, M_FINAL, false>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
         hipLaunchKernelGGL((k_queue<D, M_FINAL>), dim3(gq), dim3(64), 0, s->stream, P);
-        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s->stream, P.counters);
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s->stream, P);
         HIP_TRY(s, hipGetLastError());
         return TWA_OK;
     }
@@ -1167,6 +1214,7 @@ twa_status reset_state_buffers(twa_solver *s) {
     HIP_TRY(s, hipMemsetAsync(P.acc, 0, sizeof(unsigned long long) * 2 * D * P.N, s->stream));
     HIP_TRY(s, hipMemsetAsync(P.cnt, 0, sizeof(int) * 2 * P.N, s->stream));
     HIP_TRY(s, hipMemsetAsync(P.counters, 0, sizeof(int) * 8, s->stream));
+    HIP_TRY(s, hipMemsetAsync(P.qcnt, 0, sizeof(int) * kShards * kQueueStride, s->stream));
     HIP_TRY(s, hipMemsetAsync(s->stats_dev, 0, sizeof(int) * 4, s->stream));
     s->pending = false;
     return TWA_OK;
@@ -1379,6 +1427,11 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     P.nbf = (Ff + kBlock - 1) / kBlock;
     s->nblocks_stream = P.nbc + P.nbw + P.nbe + P.nbf;
     s->nblocks_queue = 4096;
+    {
+        // a shard takes the appends of every kShards-th wave of the column walk
+        long long waves = P.cps * ((eta + P.cpw - 1) / P.cpw);
+        P.qcap = (waves + kShards - 1) / kShards * 64 * P.cpw;
+    }
     P.e_energy = Ff;
     P.e_coll = Ff + 2 * Fe;
     P.e_wall = P.e_coll + 4 * Fc;
@@ -1410,8 +1463,9 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         dev_alloc(s, &P.u_energy, (size_t)Fe * 2 * dim) || dev_alloc(s, &P.u_fixed, (size_t)Ff * dim) ||
         dev_alloc(s, &P.bits_coll, (size_t)std::max<long long>(1, P.nch)) ||
         dev_alloc(s, &P.bits_wall, (size_t)std::max<long long>(1, (Fw + 31) / 32)) ||
-        dev_alloc(s, &P.qc, (size_t)std::max<long long>(1, Fc)) ||
+        dev_alloc(s, &P.qc, (size_t)std::max<long long>(1, std::max<long long>(Fc, kShards * P.qcap))) ||
         dev_alloc(s, &P.qw, (size_t)std::max<long long>(1, Fw)) || dev_alloc(s, &P.counters, 8) ||
+        dev_alloc(s, &P.qcnt, (size_t)kShards * kQueueStride) ||
         dev_alloc(s, &P.acc, (size_t)2 * dim * P.N) || dev_alloc(s, &P.cnt, (size_t)2 * P.N) ||
         dev_alloc(s, &P.inf_val, (size_t)P.N) ||
         dev_alloc(s, &P.x_coll, (size_t)std::max<long long>(1, dim * Fc)) ||
