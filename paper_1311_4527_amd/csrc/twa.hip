@@ -741,10 +741,10 @@ __device__ __forceinline__ void node_update(const Params &P, long long nd) {
 
 // ------------------------------------------------------------------ plain kernels
 // DENSE: the literal dense form (u of every edge read and written); it
-// walks two break-point intervals per wave, the activity-bit form four.
+// walks two break-point intervals per wave, the activity-bit form eight.
 template <int D, int MODE, bool DENSE>
 __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
-    constexpr int CPW = DENSE ? 2 : 4;
+    constexpr int CPW = DENSE ? 2 : 8;
     long long b = blockIdx.x;
     const bool clear_bits = MODE != M_FINAL && P.dense == 0;
     if (b < P.nbc) {
@@ -789,31 +789,36 @@ __device__ __forceinline__ void queue_entry(const Params &P, bool is_coll, bool 
 
 // One wave per workgroup: the few busy waves land on different compute
 // units instead of sharing one unit's scalar pipeline and caches.  Entry t
-// of the collision queue is entry t - (lengths of shards before it) of its
-// shard.
+// of the collision queue is entry t - pre[q] of shard q, where pre holds the
+// prefix sums of the shard lengths and pre[q] <= t < pre[q + 1].
 template <int D, int MODE>
 __global__ __launch_bounds__(64) void k_queue(Params P) {
-    int len[kShards];
-    int nqc = 0;
-#pragma unroll
-    for (int q = 0; q < kShards; ++q) {
-        len[q] = load_uniform(P.qcnt, q * kQueueStride);
-        nqc += len[q];
+    __shared__ int pre[kShards + 1];
+    const int lane = threadIdx.x;
+    int v = lane < kShards ? P.qcnt[lane * kQueueStride] : 0;
+    for (int d = 1; d < kShards; d <<= 1) {
+        const int o = __shfl_up(v, d);
+        if (lane >= d) v += o;
     }
+    if (lane < kShards) pre[lane + 1] = v;
+    if (lane == 0) pre[0] = 0;
+    const int nqc = __shfl(v, kShards - 1);
+    __syncthreads();
     const int nqw = P.counters[1];
     const long long wall0 = ((long long)nqc + 63) & ~63LL, total = wall0 + nqw;
     const long long stride = (long long)gridDim.x * 64;
     for (long long t0 = (long long)blockIdx.x * 64; t0 < total; t0 += stride) {
-        const long long t = t0 + threadIdx.x;
+        const long long t = t0 + lane;
         const bool is_coll = t < nqc, is_wall = t >= wall0 && t < total;
         unsigned e = 0u;
         if (is_coll) {
-            long long off = t;
-            int sh = 0;
-#pragma unroll
-            for (int q = 0; q < kShards; ++q)
-                if (sh == q && off >= len[q]) off -= len[q], sh = q + 1;
-            e = P.qc[(long long)sh * P.qcap + off];
+            int lo = 0, hi = kShards;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (pre[mid] <= t) lo = mid;
+                else hi = mid;
+            }
+            e = P.qc[(long long)lo * P.qcap + (t - pre[lo])];
         } else if (is_wall) {
             e = P.qw[t - wall0];
         }
@@ -1402,7 +1407,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     P.Fc = Fc, P.Fw = Fw, P.Fe = Fe, P.Ff = Ff;
     P.N = (long long)p * (eta + 1);
     // break-point intervals per wave in k_stream (see k_stream)
-    P.cpw = (flags & (TWA_F_DENSE | TWA_F_ADMM)) ? 2 : 4; // as k_stream<..., DENSE> (ADMM runs dense)
+    P.cpw = (flags & (TWA_F_DENSE | TWA_F_ADMM)) ? 2 : 8; // as k_stream<..., DENSE> (ADMM runs dense)
     // rows of the pair triangle cut into chunks of 64: chunk (s, i, j0)
     std::vector<int> hrowchunk((size_t)p, 0);
     for (int i = 0; i + 1 < p; ++i) hrowchunk[i + 1] = hrowchunk[i] + (p - 1 - i + 63) / 64;
