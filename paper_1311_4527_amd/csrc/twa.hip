@@ -58,6 +58,12 @@ enum Cost : int { COST_ENERGY = 0, COST_NONE = 1, COST_MAXVEL = 2, COST_MINVEL =
 constexpr unsigned kPrev = 0x80000000u; // factor was active last iteration: recompute and update u
 constexpr unsigned kIdx = 0x7fffffffu;
 
+// Where the per-factor code reads node records: this and last iteration's
+// (global memory, or a workgroup's copy in LDS in the batched kernel).
+struct Rec {
+    const float4 *cur, *prev;
+};
+
 
 
 using twa_rt::wval;
@@ -332,43 +338,70 @@ __device__ __forceinline__ void coll_column(const Params &P, int col, int s0, in
         if (s0 + k < s1) push(qs, &P.qcnt[shard * kQueueStride], q[k], val[k]);
 }
 
-// Collision factor f of a flat walk over the canonical order (64
-// consecutive factors per wave, rows mixed): the batched kernel's form for
-// small instances, whose rows are shorter than a wave.  Reads the factor's
+// Collision factors f0 + k step (k < U) of a flat walk over the canonical
+// order (64 consecutive factors per wave, rows mixed): the batched kernel's
+// form for small instances, whose rows are shorter than a wave.  Every load
+// of the U factors is issued before any is evaluated.  Reads each factor's
 // activity bit from its row chunk's word without clearing it (the words are
-// cleared in a separate pass once every factor has read its bit).
-template <int D, int MODE>
-__device__ __forceinline__ void coll_flat(const Params &P, long long f, bool valid) {
+// cleared in a separate pass once every factor has read its bit); queued
+// factors are appended to the one queue of length *qlen.
+template <int D, int MODE, int U>
+__device__ __forceinline__ void coll_flat(const Params &P, const Rec &Z, long long f0, long long step, int *qlen) {
     const bool dense = P.dense != 0;
-    const int fw = __builtin_amdgcn_readfirstlane((int)f);
-    const unsigned long long pk = P.wbase_coll[fw >> 6];
-    int s = (int)(pk >> 48), i = (int)((pk >> 24) & 0xffffffull), j = (int)(pk & 0xffffffull);
-    bool q = false;
-    unsigned val = 0u;
-    if (valid) {
-        advance_pair(P.p, (int)(f - fw), s, i, j);
-        long long nd[4];
-        coll_nodes(P, s, i, j, nd);
-        const float4 rc[4] = {P.zr_cur[nd[0]], P.zr_cur[nd[1]], P.zr_cur[nd[2]], P.zr_cur[nd[3]]};
-        float4 rp[4] = {rc[0], rc[1], rc[2], rc[3]};
-        float u[4 * D];
-        for (int k = 0; k < 4 * D; ++k) u[k] = 0.f;
-        if (dense || MODE == M_FIRST) load_u_coll<D>(P, f, u);
-        if (dense && MODE != M_FIRST)
-            for (int e = 0; e < 4; ++e) rp[e] = P.zr_prev[nd[e]];
-        const int r = j - i - 1;
-        unsigned long long word = 0ull;
-        if (!dense && MODE != M_FIRST) word = P.bits_coll[(long long)s * P.cps + P.rowchunk[i] + (r >> 6)] >> (r & 63);
-        const float R = P.radii[i] + P.radii[j];
-        if (dense) q = coll_factor<D, MODE, true>(P, f, R, rc, rp, u, word, 0, &val);
-        else q = coll_factor<D, MODE, false>(P, f, R, rc, rp, u, word, 0, &val);
+    long long f[U];
+    bool valid[U];
+    int s[U], i[U], j[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        f[k] = f0 + k * step;
+        valid[k] = f[k] < P.Fc;
+        const int fw = __builtin_amdgcn_readfirstlane((int)f[k]);
+        const unsigned long long pk = fw < P.Fc ? P.wbase_coll[fw >> 6] : 0ull;
+        s[k] = (int)(pk >> 48), i[k] = (int)((pk >> 24) & 0xffffffull), j[k] = (int)(pk & 0xffffffull);
+        if (valid[k]) advance_pair(P.p, (int)(f[k] - fw), s[k], i[k], j[k]);
     }
-    push(P.qc, &P.qcnt[0], q, val); // one shard spanning the whole queue
+    float4 rc[U][4], rp[U][4];
+    float u[U][4 * D];
+    unsigned long long word[U];
+    float R[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        word[k] = 0ull;
+        R[k] = 0.f;
+        for (int q = 0; q < 4 * D; ++q) u[k][q] = 0.f;
+        if (valid[k]) {
+            long long nd[4];
+            coll_nodes(P, s[k], i[k], j[k], nd);
+            for (int e = 0; e < 4; ++e) rc[k][e] = Z.cur[nd[e]];
+            for (int e = 0; e < 4; ++e) rp[k][e] = rc[k][e];
+            if (dense || MODE == M_FIRST) load_u_coll<D>(P, f[k], u[k]);
+            if (dense && MODE != M_FIRST)
+                for (int e = 0; e < 4; ++e) rp[k][e] = Z.prev[nd[e]];
+            const int r = j[k] - i[k] - 1;
+            if (!dense && MODE != M_FIRST)
+                word[k] = P.bits_coll[(long long)s[k] * P.cps + P.rowchunk[i[k]] + (r >> 6)] >> (r & 63);
+            R[k] = P.radii[i[k]] + P.radii[j[k]];
+        }
+    }
+    bool q[U];
+    unsigned val[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        q[k] = false;
+        val[k] = 0u;
+        if (valid[k]) {
+            if (dense) q[k] = coll_factor<D, MODE, true>(P, f[k], R[k], rc[k], rp[k], u[k], word[k], 0, &val[k]);
+            else q[k] = coll_factor<D, MODE, false>(P, f[k], R[k], rc[k], rp[k], u[k], word[k], 0, &val[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) push(P.qc, qlen, q[k], val[k]);
 }
 
 // Wall factor f: activity test (segment distance) and queue decision.
 template <int MODE>
-__device__ __forceinline__ void wall_stream(const Params &P, long long f, bool valid, bool *q, unsigned *val) {
+__device__ __forceinline__ void wall_stream(const Params &P, const Rec &Z, long long f, bool valid, bool *q,
+                                            unsigned *val) {
     const bool dense = P.dense != 0;
     bool push_prev = false, push_new = false;
     int fw = __builtin_amdgcn_readfirstlane((int)f);
@@ -389,7 +422,7 @@ __device__ __forceinline__ void wall_stream(const Params &P, long long f, bool v
             check_cur = false;
         } else if (dense) {
             u = P.u_wall[f];
-            float4 za = P.zr_prev[na], zb = P.zr_prev[nb];
+            float4 za = Z.prev[na], zb = Z.prev[nb];
             f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
             if (segseg_sq(n0, n1, xa, xb) < r * r) {
                 push_prev = true;
@@ -410,7 +443,7 @@ __device__ __forceinline__ void wall_stream(const Params &P, long long f, bool v
             if (!dense && !push_prev) P.u_wall[f] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         if (check_cur) {
-            float4 za = P.zr_cur[na], zb = P.zr_cur[nb];
+            float4 za = Z.cur[na], zb = Z.cur[nb];
             f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
             push_new = P.admm || segseg_sq(n0, n1, xa, xb) < r * r;
             if (!push_new && P.dbg_x) {
@@ -448,21 +481,21 @@ __device__ __forceinline__ bool segment_prox(const Params &P, float C, const flo
 
 // Per-segment factor f: finished here.
 template <int D, int MODE>
-__device__ __forceinline__ void energy_stream(const Params &P, long long f) {
+__device__ __forceinline__ void energy_stream(const Params &P, const Rec &Z, long long f) {
     int i = (int)f / P.eta, s = (int)f - i * P.eta;
     long long na = (long long)s * P.p + i, nb = na + P.p;
     float C = P.C[f];
     float *up = P.u_energy + f * 2 * D;
     float u[6], n[6];
     for (int q = 0; q < 2 * D; ++q) u[q] = up[q];
-    float4 ca = P.zr_cur[na], cb = P.zr_cur[nb];
+    float4 ca = Z.cur[na], cb = Z.cur[nb];
     float zc[6];
     node_xyz(ca, zc, D);
     node_xyz(cb, zc + D, D);
     int ka = wcode(ca), kb = wcode(cb);
     if (MODE != M_FIRST) {
         // recompute x^k and ->rho^k from (z^{k-1}, u^{k-1}), then u^k
-        float4 pa = P.zr_prev[na], pb = P.zr_prev[nb];
+        float4 pa = Z.prev[na], pb = Z.prev[nb];
         float zp[6];
         node_xyz(pa, zp, D);
         node_xyz(pb, zp + D, D);
@@ -504,7 +537,7 @@ __device__ __forceinline__ void vo_cost_prox(const float4 &xref, float C, const 
 }
 
 template <int D, int MODE>
-__device__ __forceinline__ void vo_goal_stream(const Params &P, long long f) {
+__device__ __forceinline__ void vo_goal_stream(const Params &P, const Rec &Z, long long f) {
     const int i = (int)(f >> 1);
     const long long nd = (long long)P.eta * P.p + i;
     const float C = P.C[i];
@@ -512,12 +545,12 @@ __device__ __forceinline__ void vo_goal_stream(const Params &P, long long f) {
     float *up = P.u_fixed + f * D;
     float u[3], n[3], x[3], m[3], zc[3];
     for (int c = 0; c < D; ++c) u[c] = up[c];
-    const float4 rc = P.zr_cur[nd];
+    const float4 rc = Z.cur[nd];
     node_xyz(rc, zc, D);
     const int k = wcode(rc);
     if (MODE != M_FIRST) {
         // recompute x^k from (z^{k-1}, u^{k-1}), then u^k (weight rho0 both ways)
-        const float4 rp = P.zr_prev[nd];
+        const float4 rp = Z.prev[nd];
         float zp[3], xk[3];
         node_xyz(rp, zp, D);
         for (int c = 0; c < D; ++c) n[c] = zp[c] - u[c];
@@ -537,9 +570,9 @@ __device__ __forceinline__ void vo_goal_stream(const Params &P, long long f) {
 
 // Fixed start/goal factor f: x = const, weight infinity.
 template <int D, int MODE>
-__device__ __forceinline__ void fixed_stream(const Params &P, long long f) {
+__device__ __forceinline__ void fixed_stream(const Params &P, const Rec &Z, long long f) {
     if (P.vo && (f & 1)) {
-        vo_goal_stream<D, MODE>(P, f);
+        vo_goal_stream<D, MODE>(P, Z, f);
         return;
     }
     int i = (int)(f >> 1);
@@ -554,7 +587,7 @@ __device__ __forceinline__ void fixed_stream(const Params &P, long long f) {
         if (P.admm) {
             // weight rho0 both ways: the ordinary update with z^k
             float zc[3];
-            node_xyz(P.zr_cur[nd], zc, D);
+            node_xyz(Z.cur[nd], zc, D);
             for (int c = 0; c < D; ++c) u[c] = u[c] + P.step_prev * (x[c] - zc[c]), up[c] = u[c];
         } else {
             // ->rho^{k-1} = infinity, so u^k = 0
@@ -574,7 +607,7 @@ __device__ __forceinline__ void fixed_stream(const Params &P, long long f) {
 // Queued collision factor (entry e): deferred u update, full minimiser,
 // consensus contributions.
 template <int D, int MODE>
-__device__ __forceinline__ bool coll_queue(const Params &P, unsigned e) {
+__device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsigned e) {
     const bool dense = P.dense != 0;
     long long f = e & kIdx;
     bool prev = (e & kPrev) != 0;
@@ -588,7 +621,7 @@ __device__ __forceinline__ bool coll_queue(const Params &P, unsigned e) {
     int k[4];
     float4 rc[4];
     for (int q = 0; q < 4; ++q) {
-        rc[q] = P.zr_cur[nd[q]];
+        rc[q] = Z.cur[nd[q]];
         node_xyz(rc[q], zc + q * D, D);
         k[q] = wcode(rc[q]);
     }
@@ -645,7 +678,7 @@ __device__ __forceinline__ bool coll_queue(const Params &P, unsigned e) {
 
 // Queued wall factor (entry e).
 template <int MODE>
-__device__ __forceinline__ bool wall_queue(const Params &P, unsigned e) {
+__device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsigned e) {
     const bool dense = P.dense != 0;
     long long f = e & kIdx;
     bool prev = (e & kPrev) != 0;
@@ -655,7 +688,7 @@ __device__ __forceinline__ bool wall_queue(const Params &P, unsigned e) {
     long long na = (long long)s * P.p + i, nb = na + P.p;
     float4 wl = P.walls[wi];
     Capsule Cw{mk(wl.x, wl.y), mk(wl.z, wl.w), P.radii[i]};
-    float4 ca = P.zr_cur[na], cb = P.zr_cur[nb];
+    float4 ca = Z.cur[na], cb = Z.cur[nb];
     int ka = wcode(ca), kb = wcode(cb);
     float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
     if (prev) {
@@ -747,6 +780,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
     constexpr int CPW = DENSE ? 2 : 8;
     long long b = blockIdx.x;
     const bool clear_bits = MODE != M_FINAL && P.dense == 0;
+    const Rec Z{P.zr_cur, P.zr_prev};
     if (b < P.nbc) {
         // wave -> (column, block of CPW break-point intervals); consecutive
         // waves take consecutive columns of the same intervals
@@ -760,7 +794,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
         long long f = (b - P.nbc) * kBlock + threadIdx.x;
         bool valid = f < P.Fw, q;
         unsigned val;
-        wall_stream<MODE>(P, f, valid, &q, &val);
+        wall_stream<MODE>(P, Z, f, valid, &q, &val);
         if (clear_bits) {
             __syncthreads();
             if (valid && (f & 31) == 0) P.bits_wall[f >> 5] = 0u;
@@ -768,10 +802,10 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
         push(P.qw, &P.counters[1], q, val);
     } else if (b < P.nbc + P.nbw + P.nbe) {
         long long f = (b - P.nbc - P.nbw) * kBlock + threadIdx.x;
-        if (f < P.Fe) energy_stream<D, MODE>(P, f);
+        if (f < P.Fe) energy_stream<D, MODE>(P, Z, f);
     } else {
         long long f = (b - P.nbc - P.nbw - P.nbe) * kBlock + threadIdx.x;
-        if (f < P.Ff) fixed_stream<D, MODE>(P, f);
+        if (f < P.Ff) fixed_stream<D, MODE>(P, Z, f);
     }
 }
 
@@ -779,10 +813,10 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
 // wall entries from the next multiple of 64 (a wave never mixes the two
 // minimisers, whose run times differ several-fold).
 template <int D, int MODE>
-__device__ __forceinline__ void queue_entry(const Params &P, bool is_coll, bool is_wall, unsigned e) {
+__device__ __forceinline__ void queue_entry(const Params &P, const Rec &Z, bool is_coll, bool is_wall, unsigned e) {
     bool ac = false, aw = false;
-    if (is_coll) ac = coll_queue<D, MODE>(P, e);
-    else if (is_wall) aw = wall_queue<MODE>(P, e);
+    if (is_coll) ac = coll_queue<D, MODE>(P, Z, e);
+    else if (is_wall) aw = wall_queue<MODE>(P, Z, e);
     count_wave(&P.counters[2], ac);
     count_wave(&P.counters[3], aw);
 }
@@ -807,6 +841,7 @@ __global__ __launch_bounds__(64) void k_queue(Params P) {
     const int nqw = P.counters[1];
     const long long wall0 = ((long long)nqc + 63) & ~63LL, total = wall0 + nqw;
     const long long stride = (long long)gridDim.x * 64;
+    const Rec Z{P.zr_cur, P.zr_prev};
     for (long long t0 = (long long)blockIdx.x * 64; t0 < total; t0 += stride) {
         const long long t = t0 + lane;
         const bool is_coll = t < nqc, is_wall = t >= wall0 && t < total;
@@ -822,7 +857,7 @@ __global__ __launch_bounds__(64) void k_queue(Params P) {
         } else if (is_wall) {
             e = P.qw[t - wall0];
         }
-        queue_entry<D, MODE>(P, is_coll, is_wall, e);
+        queue_entry<D, MODE>(P, Z, is_coll, is_wall, e);
     }
 }
 
@@ -852,43 +887,56 @@ __global__ __launch_bounds__(kBlock) void k_nodes(Params P) {
 // each of them; the three phases of an iteration are separated by
 // workgroup barriers only (instances are independent), so no workgroup
 // ever waits for another.  The per-factor work is the plain solver's, so a
-// batched instance evolves bitwise as it would on its own.
+// batched instance evolves bitwise as it would on its own.  The instance's
+// node records are copied into LDS at the start of each of its iterations
+// when they fit (this iteration's, and last iteration's too in the dense
+// form), so the walk and the minimisers read them from there; the queue
+// lengths are workgroup-local counters.
+constexpr int kBatchLdsNodes = 4000; // 62.5 KiB of node records per workgroup
+
 template <int D, int MODE, int BLOCK>
-__device__ __forceinline__ void batch_instance(const Params &P) {
+__device__ __forceinline__ void batch_instance(const Params &P, float4 *zs, int *len) {
     const bool clear_bits = P.dense == 0;
-    for (long long base = 0; base < P.Fc; base += BLOCK) {
-        const long long f = base + threadIdx.x;
-        coll_flat<D, MODE>(P, f, f < P.Fc);
-    }
-    if (clear_bits) {
-        // every factor has read its activity bit: clear the words for k_queue
-        __syncthreads();
-        for (long long w = threadIdx.x; w < P.nch; w += BLOCK) P.bits_coll[w] = 0ull;
-    }
+    const bool stage = P.N <= kBatchLdsNodes;
+    const bool stage_prev = P.dense && MODE != M_FIRST && 2 * P.N <= kBatchLdsNodes;
+    if (stage)
+        for (long long nd = threadIdx.x; nd < P.N; nd += BLOCK) zs[nd] = P.zr_cur[nd];
+    if (stage_prev)
+        for (long long nd = threadIdx.x; nd < P.N; nd += BLOCK) zs[P.N + nd] = P.zr_prev[nd];
+    if (threadIdx.x == 0) len[0] = len[1] = 0;
+    __syncthreads();
+    const Rec Z{stage ? zs : P.zr_cur, stage_prev ? zs + P.N : P.zr_prev};
+    for (long long base = 0; base < P.Fc; base += 2 * BLOCK)
+        coll_flat<D, MODE, 2>(P, Z, base + threadIdx.x, BLOCK, &len[0]);
     for (long long base = 0; base < P.Fw; base += BLOCK) {
         long long f = base + threadIdx.x;
         bool valid = f < P.Fw, q;
         unsigned val;
-        wall_stream<MODE>(P, f, valid, &q, &val);
-        if (clear_bits) {
-            __syncthreads();
-            if (valid && (f & 31) == 0) P.bits_wall[f >> 5] = 0u;
-        }
-        push(P.qw, &P.counters[1], q, val);
+        wall_stream<MODE>(P, Z, f, valid, &q, &val);
+        push(P.qw, &len[1], q, val);
     }
-    for (long long f = threadIdx.x; f < P.Fe; f += BLOCK) energy_stream<D, MODE>(P, f);
-    for (long long f = threadIdx.x; f < P.Ff; f += BLOCK) fixed_stream<D, MODE>(P, f);
+    for (long long f = threadIdx.x; f < P.Fe; f += BLOCK) energy_stream<D, MODE>(P, Z, f);
+    for (long long f = threadIdx.x; f < P.Ff; f += BLOCK) fixed_stream<D, MODE>(P, Z, f);
     __syncthreads();
-    const int nqc = __atomic_load_n(&P.qcnt[0], __ATOMIC_RELAXED);
-    const int nqw = __atomic_load_n(&P.counters[1], __ATOMIC_RELAXED);
+    if (clear_bits) {
+        // every factor has read its activity bit: clear the words for the queue
+        for (long long w = threadIdx.x; w < P.nch; w += BLOCK) P.bits_coll[w] = 0ull;
+        for (long long w = threadIdx.x; w < (P.Fw + 31) / 32; w += BLOCK) P.bits_wall[w] = 0u;
+        __syncthreads();
+    }
+    const int nqc = len[0], nqw = len[1];
     const long long wall0 = ((long long)nqc + 63) & ~63LL, total = wall0 + nqw;
     for (long long t0 = threadIdx.x & ~63; t0 < total; t0 += BLOCK) {
         const long long t = t0 + (threadIdx.x & 63);
         const bool is_coll = t < nqc, is_wall = t >= wall0 && t < total;
-        queue_entry<D, MODE>(P, is_coll, is_wall, is_coll ? P.qc[t] : is_wall ? P.qw[t - wall0] : 0u);
+        queue_entry<D, MODE>(P, Z, is_coll, is_wall, is_coll ? P.qc[t] : is_wall ? P.qw[t - wall0] : 0u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) close_counters(P, 1);
+    if (threadIdx.x == 0) {
+        P.qcnt[0] = nqc;
+        P.counters[1] = nqw;
+        close_counters(P, 1);
+    }
     for (long long nd = threadIdx.x; nd < P.N; nd += BLOCK) node_update<D>(P, nd);
     __syncthreads();
 }
@@ -896,6 +944,8 @@ __device__ __forceinline__ void batch_instance(const Params &P) {
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_batch(const Params *insts, const int *bin_start, const int *bin_items,
                                                   int K, int first) {
+    __shared__ float4 zs[kBatchLdsNodes];
+    __shared__ int len[2];
     const int g = blockIdx.x;
     const int q0 = bin_start[g], q1 = bin_start[g + 1];
     for (int it = 0; it < K; ++it) {
@@ -903,11 +953,11 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const Params *insts, const int 
         for (int q = q0; q < q1; ++q) {
             const Params &P = insts[bin_items[q]];
             if (P.dim == 2) {
-                if (fst) batch_instance<2, M_FIRST, BLOCK>(P);
-                else batch_instance<2, M_FUSED, BLOCK>(P);
+                if (fst) batch_instance<2, M_FIRST, BLOCK>(P, zs, len);
+                else batch_instance<2, M_FUSED, BLOCK>(P, zs, len);
             } else {
-                if (fst) batch_instance<3, M_FIRST, BLOCK>(P);
-                else batch_instance<3, M_FUSED, BLOCK>(P);
+                if (fst) batch_instance<3, M_FIRST, BLOCK>(P, zs, len);
+                else batch_instance<3, M_FUSED, BLOCK>(P, zs, len);
             }
         }
     }
