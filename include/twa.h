@@ -234,12 +234,18 @@ typedef struct {
 twa_status twa_batch_create(int n, const twa_instance *inst, unsigned flags, void *hip_stream,
                             twa_batch **out);
 
-/* Launch shape of the persistent kernel: lanes per workgroup (256, 512 or
- * 1024) and number of workgroups (bins; clamped to n).  Instances are
- * packed onto bins longest-first.  Default: 256 lanes, one bin per instance. */
+/* Launch shape.  block 256, 512 or 1024: the persistent kernel, with that
+ * many lanes per workgroup and `groups` workgroups (bins; clamped to n);
+ * instances are packed onto bins longest-first and each bin runs all k
+ * iterations of its instances in one launch.  block 0 (groups ignored):
+ * one launch per phase of an iteration (factor stream, minimisers,
+ * consensus) over the blocks of every instance, so a large instance spreads
+ * over many compute units.  Either way the evolution is bitwise that of the
+ * instances' own solvers.  Default: 256 lanes, one bin per instance. */
 twa_status twa_batch_config(twa_batch *b, int block, int groups);
 
-/* k >= 0 iterations of every instance (one launch). */
+/* k >= 0 iterations of every instance (one launch of the persistent kernel,
+ * or 3k launches in the phased form; captured in a HIP graph either way). */
 twa_status twa_batch_iterate(twa_batch *b, int k);
 
 /* As twa_batch_iterate; *ms = device time of the launch (synchronises). */

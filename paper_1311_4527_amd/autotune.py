@@ -1,9 +1,11 @@
-"""Launch-shape autotuner of the batched persistent kernel.
+"""Launch-shape autotuner of the batched solver.
 
-Candidates are (lanes per workgroup, number of workgroups).  Instances are
-packed onto workgroups longest-first by the library; this driver times a
-few iterations of each candidate on the actual batch (HIP events, through
-the C ABI) and keeps the fastest.  Results are cached in a JSON file keyed
+Candidates are (lanes per workgroup, number of workgroups) of the
+persistent kernel, where instances are packed onto workgroups
+longest-first by the library, and (0, 1): one launch per phase of an
+iteration over all instances.  This driver times a few iterations of each
+candidate on the actual batch (HIP events, through the C ABI) and keeps
+the fastest.  Results are cached in a JSON file keyed
 by device name and a shape signature of the batch, so a repeated batch
 shape skips the search.
 """
@@ -24,7 +26,7 @@ def shape_signature(instances) -> str:
 
 def candidates(n: int) -> List[Tuple[int, int]]:
     groups = sorted({max(1, n // 8), max(1, n // 4), max(1, n // 2), n})
-    return [(b, g) for b in (256, 512, 1024) for g in groups]
+    return [(b, g) for b in (256, 512, 1024) for g in groups] + [(0, 1)]
 
 
 def _load_cache() -> Dict:

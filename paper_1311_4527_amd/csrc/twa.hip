@@ -262,13 +262,15 @@ __device__ __forceinline__ bool coll_factor(const Params &P, long long f, float 
 // the pair triangle (rows are cut into chunks of 64, so i is the same for
 // the whole wave), over the break-point intervals s0 <= s < s1 <= s0 + CPW.
 // Every load of the column (node records of break-points s0..s1, agent i's
-// through the scalar cache; the chunks' activity words; u where it is read)
-// is issued before any factor is evaluated.  Each chunk's activity word is
-// cleared after it was read (k_queue sets it again for the factors active
-// in this iteration).  Queued factors go to collision queue shard `shard`.
-template <int D, int MODE, int CPW, bool DENSE>
-__device__ __forceinline__ void coll_column(const Params &P, int col, int s0, int s1, int lane, bool clear_bits,
-                                            int shard) {
+// through the scalar cache when SCALAR_I, i.e. when Z points to global
+// memory; the chunks' activity words; u where it is read) is issued before
+// any factor is evaluated.  With clear_bits each chunk's activity word is
+// cleared after it was read (the minimisers set it again for the factors
+// active in this iteration).  Queued factors are appended to qs (length
+// *qlen).
+template <int D, int MODE, int CPW, bool DENSE, bool SCALAR_I>
+__device__ __forceinline__ void coll_column(const Params &P, const Rec &Z, int col, int s0, int s1, int lane,
+                                            bool clear_bits, unsigned *qs, int *qlen) {
     constexpr bool need_prev = DENSE && MODE != M_FIRST;
     constexpr bool need_u = DENSE || MODE == M_FIRST;
     constexpr bool need_word = !DENSE && MODE != M_FIRST;
@@ -284,18 +286,18 @@ __device__ __forceinline__ void coll_column(const Params &P, int col, int s0, in
     // fit in 31 bits): row i of the triangle holds the pairs (i, j > i)
     const unsigned fr = (unsigned)((long long)i * (2 * p - i - 1) / 2 + (j - i - 1));
     const unsigned P2 = (unsigned)P.P2;
-    const float4 *ci = P.zr_cur + (long long)s0 * p + i, *cj = P.zr_cur + (long long)s0 * p + jj;
-    const float4 *pi_ = P.zr_prev + (long long)s0 * p + i, *pj_ = P.zr_prev + (long long)s0 * p + jj;
+    const float4 *ci = Z.cur + (long long)s0 * p + i, *cj = Z.cur + (long long)s0 * p + jj;
+    const float4 *pi_ = Z.prev + (long long)s0 * p + i, *pj_ = Z.prev + (long long)s0 * p + jj;
     float4 ri[CPW + 1], rj[CPW + 1], pi[CPW + 1], pj[CPW + 1];
     unsigned long long word[CPW];
     float u[CPW][4 * D];
 #pragma unroll
     for (int k = 0; k <= CPW; ++k) {
         if (s0 + k <= s1) {
-            ri[k] = load_uniform(ci, k * p);
+            ri[k] = SCALAR_I ? load_uniform(ci, k * p) : ci[k * p];
             rj[k] = cj[k * p];
             if (need_prev) {
-                pi[k] = load_uniform(pi_, k * p);
+                pi[k] = SCALAR_I ? load_uniform(pi_, k * p) : pi_[k * p];
                 pj[k] = pj_[k * p];
             }
         }
@@ -332,10 +334,9 @@ __device__ __forceinline__ void coll_column(const Params &P, int col, int s0, in
 #pragma unroll
     for (int k = 0; k < CPW; ++k) any = any || q[k];
     if (__ballot(any) == 0ull) return; // nothing to queue: the common case
-    unsigned *qs = P.qc + (long long)shard * P.qcap;
 #pragma unroll
     for (int k = 0; k < CPW; ++k)
-        if (s0 + k < s1) push(qs, &P.qcnt[shard * kQueueStride], q[k], val[k]);
+        if (s0 + k < s1) push(qs, qlen, q[k], val[k]);
 }
 
 // Collision factors f0 + k step (k < U) of a flat walk over the canonical
@@ -776,9 +777,8 @@ __device__ __forceinline__ void node_update(const Params &P, long long nd) {
 // DENSE: the literal dense form (u of every edge read and written); it
 // walks two break-point intervals per wave, the activity-bit form eight.
 template <int D, int MODE, bool DENSE>
-__global__ __launch_bounds__(kBlock) void k_stream(Params P) {
+__device__ __forceinline__ void stream_block(const Params &P, long long b) {
     constexpr int CPW = DENSE ? 2 : 8;
-    long long b = blockIdx.x;
     const bool clear_bits = MODE != M_FINAL && P.dense == 0;
     const Rec Z{P.zr_cur, P.zr_prev};
     if (b < P.nbc) {
@@ -787,9 +787,10 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
         const unsigned wave = (unsigned)b * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const unsigned cps = (unsigned)P.cps;
         const int col = (int)(wave % cps), s0 = (int)(wave / cps) * CPW;
+        const int shard = (int)(wave % kShards);
         if (s0 < P.eta)
-            coll_column<D, MODE, CPW, DENSE>(P, col, s0, min(s0 + CPW, P.eta), threadIdx.x & 63, clear_bits,
-                                             (int)(wave % kShards));
+            coll_column<D, MODE, CPW, DENSE, true>(P, Z, col, s0, min(s0 + CPW, P.eta), threadIdx.x & 63, clear_bits,
+                                                   P.qc + (long long)shard * P.qcap, &P.qcnt[shard * kQueueStride]);
     } else if (b < P.nbc + P.nbw) {
         long long f = (b - P.nbc) * kBlock + threadIdx.x;
         bool valid = f < P.Fw, q;
@@ -809,6 +810,11 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
     }
 }
 
+template <int D, int MODE, bool DENSE>
+__global__ __launch_bounds__(kBlock) void k_stream(Params P) {
+    stream_block<D, MODE, DENSE>(P, blockIdx.x);
+}
+
 // One queue entry per lane of a wave-uniform loop: collision entries first,
 // wall entries from the next multiple of 64 (a wave never mixes the two
 // minimisers, whose run times differ several-fold).
@@ -826,7 +832,7 @@ __device__ __forceinline__ void queue_entry(const Params &P, const Rec &Z, bool 
 // of the collision queue is entry t - pre[q] of shard q, where pre holds the
 // prefix sums of the shard lengths and pre[q] <= t < pre[q + 1].
 template <int D, int MODE>
-__global__ __launch_bounds__(64) void k_queue(Params P) {
+__device__ __forceinline__ void queue_block(const Params &P, long long qb, long long nqb) {
     __shared__ int pre[kShards + 1];
     const int lane = threadIdx.x;
     int v = lane < kShards ? P.qcnt[lane * kQueueStride] : 0;
@@ -840,9 +846,9 @@ __global__ __launch_bounds__(64) void k_queue(Params P) {
     __syncthreads();
     const int nqw = P.counters[1];
     const long long wall0 = ((long long)nqc + 63) & ~63LL, total = wall0 + nqw;
-    const long long stride = (long long)gridDim.x * 64;
+    const long long stride = nqb * 64;
     const Rec Z{P.zr_cur, P.zr_prev};
-    for (long long t0 = (long long)blockIdx.x * 64; t0 < total; t0 += stride) {
+    for (long long t0 = qb * 64; t0 < total; t0 += stride) {
         const long long t = t0 + lane;
         const bool is_coll = t < nqc, is_wall = t >= wall0 && t < total;
         unsigned e = 0u;
@@ -861,6 +867,11 @@ __global__ __launch_bounds__(64) void k_queue(Params P) {
     }
 }
 
+template <int D, int MODE>
+__global__ __launch_bounds__(64) void k_queue(Params P) {
+    queue_block<D, MODE>(P, blockIdx.x, gridDim.x);
+}
+
 // counters of this iteration -> stats, then reset for the next one (the
 // first `shards` collision queue shards were in use)
 __device__ __forceinline__ void close_counters(const Params &P, int shards) {
@@ -876,10 +887,15 @@ __device__ __forceinline__ void close_counters(const Params &P, int shards) {
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_nodes(Params P) {
-    long long nd = (long long)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void nodes_block(const Params &P, long long b) {
+    long long nd = b * kBlock + threadIdx.x;
     if (nd == 0) close_counters(P, kShards);
     if (nd < P.N) node_update<D>(P, nd);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_nodes(Params P) {
+    nodes_block<D>(P, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ batched persistent kernel
@@ -906,8 +922,30 @@ __device__ __forceinline__ void batch_instance(const Params &P, float4 *zs, int 
     if (threadIdx.x == 0) len[0] = len[1] = 0;
     __syncthreads();
     const Rec Z{stage ? zs : P.zr_cur, stage_prev ? zs + P.N : P.zr_prev};
-    for (long long base = 0; base < P.Fc; base += 2 * BLOCK)
-        coll_flat<D, MODE, 2>(P, Z, base + threadIdx.x, BLOCK, &len[0]);
+    if (P.p >= 64) {
+        // rows of at least 64 pairs for the most part: the column walk of
+        // the plain factor stream, wave by wave over (column, intervals)
+        const unsigned w0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const unsigned cps = (unsigned)P.cps;
+        if (P.dense) {
+            const unsigned nw = cps * (unsigned)((P.eta + 1) / 2);
+            for (unsigned w = w0; w < nw; w += BLOCK / 64) {
+                const int s0 = (int)(w / cps) * 2;
+                coll_column<D, MODE, 2, true, false>(P, Z, (int)(w % cps), s0, min(s0 + 2, P.eta), threadIdx.x & 63,
+                                                     false, P.qc, &len[0]);
+            }
+        } else {
+            const unsigned nw = cps * (unsigned)((P.eta + 3) / 4);
+            for (unsigned w = w0; w < nw; w += BLOCK / 64) {
+                const int s0 = (int)(w / cps) * 4;
+                coll_column<D, MODE, 4, false, false>(P, Z, (int)(w % cps), s0, min(s0 + 4, P.eta), threadIdx.x & 63,
+                                                      false, P.qc, &len[0]);
+            }
+        }
+    } else {
+        for (long long base = 0; base < P.Fc; base += 2 * BLOCK)
+            coll_flat<D, MODE, 2>(P, Z, base + threadIdx.x, BLOCK, &len[0]);
+    }
     for (long long base = 0; base < P.Fw; base += BLOCK) {
         long long f = base + threadIdx.x;
         bool valid = f < P.Fw, q;
@@ -966,6 +1004,36 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const Params *insts, const int 
 __global__ void k_reset_counters(Params P) {
     if (threadIdx.x < 4) P.counters[threadIdx.x] = 0;
     if (threadIdx.x < kShards) P.qcnt[threadIdx.x * kQueueStride] = 0;
+}
+
+// ------------------------------------------------------------------ phased batch
+// The other batched form: one launch per phase of an iteration over every
+// instance of the batch.  A host-built map sends each block to (instance,
+// block of that instance's own launch), so a large instance spreads over
+// many compute units; the per-block bodies are the plain kernels', hence
+// the same bitwise evolution.
+template <int MODE, bool DENSE>
+__global__ __launch_bounds__(kBlock) void kp_stream(const Params *insts, const int2 *map) {
+    const int2 m = map[blockIdx.x];
+    const Params &P = insts[m.x];
+    if (P.dim == 2) stream_block<2, MODE, DENSE>(P, m.y);
+    else stream_block<3, MODE, DENSE>(P, m.y);
+}
+
+// map: (instance, qb | nqb << 16), block qb of the nqb that share its queue
+template <int MODE>
+__global__ __launch_bounds__(64) void kp_queue(const Params *insts, const int2 *map) {
+    const int2 m = map[blockIdx.x];
+    const Params &P = insts[m.x];
+    if (P.dim == 2) queue_block<2, MODE>(P, m.y & 0xffff, m.y >> 16);
+    else queue_block<3, MODE>(P, m.y & 0xffff, m.y >> 16);
+}
+
+__global__ __launch_bounds__(kBlock) void kp_nodes(const Params *insts, const int2 *map) {
+    const int2 m = map[blockIdx.x];
+    const Params &P = insts[m.x];
+    if (P.dim == 2) nodes_block<2>(P, m.y);
+    else nodes_block<3>(P, m.y);
 }
 
 // ------------------------------------------------------------------ layout conversion
@@ -1765,7 +1833,10 @@ struct twa_batch {
     hipStream_t stream = nullptr;
     Params *insts_dev = nullptr;
     int *bin_start_dev = nullptr, *bin_items_dev = nullptr;
-    int block = 256, groups = 0;
+    int block = 256, groups = 0;       // block 0: the phased form
+    int2 *map_dev = nullptr;           // phased form: stream, queue, node block maps
+    int n_stream = 0, n_queue = 0, n_nodes = 0;
+    hipGraphExec_t pexec = nullptr;    // phased form: kPhasedChunk iterations
     std::string err;
     twa_status latched = TWA_OK;
     hipGraphExec_t gexec = nullptr;
@@ -1830,7 +1901,28 @@ twa_status batch_bins(twa_batch *b) {
     return TWA_OK;
 }
 
+constexpr int kPhasedChunk = 32;
+
 void launch_batch(twa_batch *b, int k, int first) {
+    if (b->block == 0) {
+        const bool dense = b->solvers[0]->P.dense != 0;
+        const Params *ins = (const Params *)b->insts_dev;
+        const int2 *ms = b->map_dev, *mq = ms + b->n_stream, *mn = mq + b->n_queue;
+        const dim3 gs(b->n_stream), gq(b->n_queue), gn(b->n_nodes);
+        for (int it = 0; it < k; ++it) {
+            if (first && it == 0) {
+                if (dense) hipLaunchKernelGGL((kp_stream<M_FIRST, true>), gs, dim3(kBlock), 0, b->stream, ins, ms);
+                else hipLaunchKernelGGL((kp_stream<M_FIRST, false>), gs, dim3(kBlock), 0, b->stream, ins, ms);
+                hipLaunchKernelGGL(kp_queue<M_FIRST>, gq, dim3(64), 0, b->stream, ins, mq);
+            } else {
+                if (dense) hipLaunchKernelGGL((kp_stream<M_FUSED, true>), gs, dim3(kBlock), 0, b->stream, ins, ms);
+                else hipLaunchKernelGGL((kp_stream<M_FUSED, false>), gs, dim3(kBlock), 0, b->stream, ins, ms);
+                hipLaunchKernelGGL(kp_queue<M_FUSED>, gq, dim3(64), 0, b->stream, ins, mq);
+            }
+            hipLaunchKernelGGL(kp_nodes, gn, dim3(kBlock), 0, b->stream, ins, mn);
+        }
+        return;
+    }
     dim3 grid(b->groups);
     if (b->block == 1024)
         hipLaunchKernelGGL(k_batch<1024>, grid, dim3(1024), 0, b->stream, (const Params *)b->insts_dev,
@@ -1857,6 +1949,8 @@ void twa_batch_destroy(twa_batch *b) {
     if (b->insts_dev) (void)hipFree(b->insts_dev);
     if (b->bin_start_dev) (void)hipFree(b->bin_start_dev);
     if (b->bin_items_dev) (void)hipFree(b->bin_items_dev);
+    if (b->map_dev) (void)hipFree(b->map_dev);
+    if (b->pexec) (void)hipGraphExecDestroy(b->pexec);
     delete b;
 }
 
@@ -1895,7 +1989,32 @@ twa_status twa_batch_create(int n, const twa_instance *inst, unsigned flags, voi
         h[i].dbg_x = nullptr;
         h[i].dbg_rho = nullptr;
     }
-    if (hipMemcpyAsync(b->insts_dev, h.data(), sizeof(Params) * n, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+    // block maps of the phased form: each instance's own stream and node
+    // blocks, and one queue block per 256 factors (1..64: crowded instances
+    // queue a good share of their factors, and a block's entries beyond the
+    // first 64 wait for a whole minimiser each)
+    std::vector<int2> ms, mq, mn;
+    for (int i = 0; i < n; ++i) {
+        const twa_solver *s = b->solvers[i];
+        for (long long lb = 0; lb < s->nblocks_stream; ++lb) ms.push_back(make_int2(i, (int)lb));
+        const int nqb = (int)std::min<long long>(64, std::max<long long>(1, (s->P.Fc + s->P.Fw + 255) / 256));
+        for (int qb = 0; qb < nqb; ++qb) mq.push_back(make_int2(i, qb | (nqb << 16)));
+        for (long long lb = 0; lb < (s->P.N + kBlock - 1) / kBlock; ++lb) mn.push_back(make_int2(i, (int)lb));
+    }
+    b->n_stream = (int)ms.size();
+    b->n_queue = (int)mq.size();
+    b->n_nodes = (int)mn.size();
+    ms.insert(ms.end(), mq.begin(), mq.end());
+    ms.insert(ms.end(), mn.begin(), mn.end());
+    if (hipMalloc(&b->map_dev, sizeof(int2) * ms.size()) != hipSuccess) {
+        (void)hipGetLastError();
+        b->map_dev = nullptr;
+        twa_batch_destroy(b);
+        return TWA_E_NOMEM;
+    }
+    if (hipMemcpyAsync(b->map_dev, ms.data(), sizeof(int2) * ms.size(), hipMemcpyHostToDevice, b->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(b->insts_dev, h.data(), sizeof(Params) * n, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         batch_bins(b) != TWA_OK) {
         twa_batch_destroy(b);
         return TWA_E_DEVICE;
@@ -1907,7 +2026,13 @@ twa_status twa_batch_create(int n, const twa_instance *inst, unsigned flags, voi
 twa_status twa_batch_config(twa_batch *b, int block, int groups) {
     if (!b) return TWA_E_INVALID;
     if (b->latched != TWA_OK) return b->latched;
-    if (block != 256 && block != 512 && block != 1024) return bfail(b, TWA_E_INVALID, "block must be 256, 512 or 1024");
+    if (block == 0) {
+        b->block = 0;
+        drop_graph(b);
+        return TWA_OK;
+    }
+    if (block != 256 && block != 512 && block != 1024)
+        return bfail(b, TWA_E_INVALID, "block must be 0, 256, 512 or 1024");
     if (groups < 1) return bfail(b, TWA_E_INVALID, "groups must be >= 1");
     b->block = block;
     b->groups = groups;
@@ -1930,6 +2055,35 @@ twa_status twa_batch_iterate(twa_batch *b, int k) {
         for (twa_solver *s : b->solvers)
             if (finalize(s) != TWA_OK) return bfail(b, TWA_E_DEVICE, "finalize: " + s->err);
     int first = all_pending ? 0 : 1;
+    if (b->block == 0) {
+        // phased form: a first iteration on its own, then a captured graph
+        // of kPhasedChunk iterations replayed, then the rest launched directly
+        int left = k;
+        if (first) {
+            launch_batch(b, 1, 1);
+            --left;
+        }
+        if (left >= kPhasedChunk && !b->pexec) {
+            hipGraph_t g = nullptr;
+            bool ok = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                launch_batch(b, kPhasedChunk, 0);
+                ok = hipStreamEndCapture(b->stream, &g) == hipSuccess && g != nullptr;
+                if (ok) ok = hipGraphInstantiate(&b->pexec, g, nullptr, nullptr, 0) == hipSuccess;
+                if (g) (void)hipGraphDestroy(g);
+            }
+            (void)hipGetLastError();
+            if (!ok) b->pexec = nullptr;
+        }
+        for (; left >= kPhasedChunk && b->pexec; left -= kPhasedChunk) BHIP_TRY(b, hipGraphLaunch(b->pexec, b->stream));
+        if (left > 0) launch_batch(b, left, 0);
+        BHIP_TRY(b, hipGetLastError());
+        for (twa_solver *s : b->solvers) {
+            s->pending = true;
+            s->iter += k;
+        }
+        return TWA_OK;
+    }
     if (!b->gexec || b->g_k != k || b->g_first != first) {
         drop_graph(b);
         hipGraph_t g = nullptr;

@@ -1,5 +1,6 @@
-"""Batched instances (one persistent launch) evolve bitwise as the same
-instances do in their own solvers; ragged p, eta, 2-D and 3-D, walls."""
+"""Batched instances (one persistent launch, or one launch per phase over
+all instances) evolve bitwise as the same instances do in their own
+solvers; ragged p, eta, 2-D and 3-D, walls."""
 import numpy as np
 import pytest
 
@@ -13,7 +14,7 @@ def _mixed(n=12, seed=5):
     return out
 
 
-@pytest.mark.parametrize("block,groups", [(256, 12), (512, 3), (1024, 1), (256, 5)])
+@pytest.mark.parametrize("block,groups", [(256, 12), (512, 3), (1024, 1), (256, 5), (0, 1)])
 def test_batch_equals_plain(block, groups):
     import torch
     from paper_1311_4527_amd.twa import Batch, Solver
@@ -31,6 +32,22 @@ def test_batch_equals_plain(block, groups):
         za, ua, la, ka = B.twa_batch_solver(i).twa_get_state()
         zb, ub, lb, kb = S.twa_get_state()
         assert ka == kb == 65 and torch.equal(ua, ub) and torch.equal(la, lb)
+
+
+@pytest.mark.parametrize("block,groups,flags", [(1024, 2, 0), (512, 5, 1), (0, 1, 0), (0, 1, 1)])
+def test_batch_equals_plain_long_rows(block, groups, flags):
+    """Instances with p >= 64 take the column walk in the persistent kernel."""
+    import torch
+    from paper_1311_4527_amd.twa import Batch, Solver
+    insts = I.conf_batch(6, base_seed=21, p_range=(60, 100))
+    B = Batch(insts, flags=flags)
+    B.twa_batch_config(block, groups)
+    B.twa_batch_iterate(30)
+    for i, inst in enumerate(insts):
+        S = Solver.from_instance(inst, flags=flags)
+        S.twa_iterate(30)
+        a, b = B.twa_batch_get_trajectories(i), S.twa_get_trajectories()
+        assert torch.equal(a, b), (i, inst.name, (a - b).abs().max().item())
 
 
 def test_batch_dense_equals_skip():
