@@ -898,6 +898,19 @@ __global__ __launch_bounds__(kBlock) void k_nodes(Params P) {
     nodes_block<D>(P, blockIdx.x);
 }
 
+// A batched kernel's instance parameters, copied into LDS by the block: read
+// through a pointer into global memory, every field used after a store
+// would be fetched again (the compiler cannot tell that the stores leave
+// them alone); in LDS they are cheap to reread.
+template <int T>
+__device__ __forceinline__ const Params &params_lds(const Params *src, Params *dst) {
+    static_assert(sizeof(Params) % 4 == 0, "Params is copied as 32-bit words");
+    constexpr int n = (int)(sizeof(Params) / 4);
+    for (int t = threadIdx.x; t < n; t += T) reinterpret_cast<int *>(dst)[t] = reinterpret_cast<const int *>(src)[t];
+    __syncthreads();
+    return *dst;
+}
+
 // ------------------------------------------------------------------ batched persistent kernel
 // One workgroup owns a bin of whole instances and runs all K iterations of
 // each of them; the three phases of an iteration are separated by
@@ -984,12 +997,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const Params *insts, const int 
                                                   int K, int first) {
     __shared__ float4 zs[kBatchLdsNodes];
     __shared__ int len[2];
+    __shared__ Params sp;
     const int g = blockIdx.x;
     const int q0 = bin_start[g], q1 = bin_start[g + 1];
     for (int it = 0; it < K; ++it) {
         const bool fst = first && it == 0;
         for (int q = q0; q < q1; ++q) {
-            const Params &P = insts[bin_items[q]];
+            const Params &P = params_lds<BLOCK>(insts + bin_items[q], &sp);
             if (P.dim == 2) {
                 if (fst) batch_instance<2, M_FIRST, BLOCK>(P, zs, len);
                 else batch_instance<2, M_FUSED, BLOCK>(P, zs, len);
@@ -1014,8 +1028,9 @@ __global__ void k_reset_counters(Params P) {
 // the same bitwise evolution.
 template <int MODE, bool DENSE>
 __global__ __launch_bounds__(kBlock) void kp_stream(const Params *insts, const int2 *map) {
+    __shared__ Params sp;
     const int2 m = map[blockIdx.x];
-    const Params &P = insts[m.x];
+    const Params &P = params_lds<kBlock>(insts + m.x, &sp);
     if (P.dim == 2) stream_block<2, MODE, DENSE>(P, m.y);
     else stream_block<3, MODE, DENSE>(P, m.y);
 }
@@ -1023,15 +1038,17 @@ __global__ __launch_bounds__(kBlock) void kp_stream(const Params *insts, const i
 // map: (instance, qb | nqb << 16), block qb of the nqb that share its queue
 template <int MODE>
 __global__ __launch_bounds__(64) void kp_queue(const Params *insts, const int2 *map) {
+    __shared__ Params sp;
     const int2 m = map[blockIdx.x];
-    const Params &P = insts[m.x];
+    const Params &P = params_lds<64>(insts + m.x, &sp);
     if (P.dim == 2) queue_block<2, MODE>(P, m.y & 0xffff, m.y >> 16);
     else queue_block<3, MODE>(P, m.y & 0xffff, m.y >> 16);
 }
 
 __global__ __launch_bounds__(kBlock) void kp_nodes(const Params *insts, const int2 *map) {
+    __shared__ Params sp;
     const int2 m = map[blockIdx.x];
-    const Params &P = insts[m.x];
+    const Params &P = params_lds<kBlock>(insts + m.x, &sp);
     if (P.dim == 2) nodes_block<2>(P, m.y);
     else nodes_block<3>(P, m.y);
 }

@@ -54,11 +54,13 @@ def test_admm_full_run_matches_reference():
     assert O.min_clearance(inst.radii, zg) > min(P.min_clearance(), 0.0) - 5e-5
 
 
-def test_admm_batch_equals_plain():
+@pytest.mark.parametrize("block", [256, 0])
+def test_admm_batch_equals_plain(block):
     import torch
     from paper_1311_4527_amd.twa import Batch, Solver
     insts = I.conf_batch(6, base_seed=31, p_range=(4, 24))
     B = Batch(insts, flags=_flags())
+    B.twa_batch_config(block, len(insts))
     B.twa_batch_iterate(30)
     for i, inst in enumerate(insts):
         S = Solver.from_instance(inst, flags=_flags())

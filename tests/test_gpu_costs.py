@@ -85,11 +85,13 @@ def test_feasibility_restart_from_an_early_stop():
     assert free is not None
 
 
-def test_batch_equals_plain_with_velocity_limits():
+@pytest.mark.parametrize("block", [256, 0])
+def test_batch_equals_plain_with_velocity_limits(block):
     import torch
     from paper_1311_4527_amd.twa import Batch, Solver
     insts = [_limited(i, 1.4) for i in I.conf_batch(6, base_seed=77, p_range=(4, 20))]
     B = Batch(insts, flags=_flag(O.COST_MAXVEL))
+    B.twa_batch_config(block, len(insts))
     B.twa_batch_iterate(40)
     for i, inst in enumerate(insts):
         S = Solver.from_instance(inst, flags=_flag(O.COST_MAXVEL))
