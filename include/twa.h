@@ -143,10 +143,14 @@ twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm);
 /* Run k >= 0 iterations (App. B steps 1-7), asynchronously. */
 twa_status twa_iterate(twa_solver *s, int k);
 
-/* As twa_iterate, and records HIP events around every launch on the
- * solver's stream; synchronises and writes the summed device time in
- * milliseconds of each kernel to kernel_ms (host array of 3: factor stream,
- * queued minimisers, node consensus). */
+/* As twa_iterate, and times the kernels with HIP events on the solver's
+ * stream; synchronises and writes the device time in milliseconds of each
+ * kernel summed over the k iterations to kernel_ms (host array of 3: factor
+ * stream, queued minimisers, node consensus).  The last min(k, 4)
+ * iterations are launched on their own with events around every kernel
+ * (an event recorded on the stream slows every later launch of the call, so
+ * the captured graph replays before them carry none); their mean times
+ * stand for all k iterations. */
 twa_status twa_iterate_timed(twa_solver *s, int k, double *kernel_ms);
 
 /* Current consensus positions z [p][eta+1][dim]. */

@@ -91,12 +91,11 @@ struct twa_solver {
     int nblocks_queue = 0;
     // event timing (twa_iterate_timed): 1 = a new event per mark, 2 = the
     // preallocated events of the graph being captured
-    std::vector<hipEvent_t> events;
+    std::vector<hipEvent_t> events; // kept for the solver's life and reused
+    size_t events_used = 0;
     int timing = 0;
-    // HIP graphs of kGraphIters fused iterations (plain, and with events)
-    hipGraphExec_t graph = nullptr, graph_timed = nullptr;
-    std::vector<hipEvent_t> gevents;
-    size_t gev_next = 0;
+    // HIP graph of kGraphIters fused iterations
+    hipGraphExec_t graph = nullptr;
     bool graph_failed = false;
     // TWA_F_TAPE: the state the differentiated run starts from (canonical
     // layouts), saved by create / set_init / set_state

@@ -1168,16 +1168,21 @@ using twa_rt::rho_at;
 namespace {
 
 constexpr int kGraphIters = 32;
+// twa_iterate_timed times its last kTimedTail iterations, launched on their
+// own with events around their kernels: once an event is recorded on the
+// stream, every later launch of the same call runs slower (graph replays by
+// about a third), so no event comes before the untimed replays.
+constexpr int kTimedTail = 4;
 
 void mark(twa_solver *s, int slot) {
     (void)slot;
     if (s->timing == 1) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
-        (void)hipEventRecord(e, s->stream);
-        s->events.push_back(e);
-    } else if (s->timing == 2 && s->gev_next < s->gevents.size()) {
-        (void)hipEventRecord(s->gevents[s->gev_next++], s->stream);
+        if (s->events_used == s->events.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            s->events.push_back(e);
+        }
+        (void)hipEventRecord(s->events[s->events_used++], s->stream);
     }
 }
 
@@ -1256,29 +1261,20 @@ twa_status run_iteration(twa_solver *s, int mode, float rho, float rho_prev) {
 }
 
 
-// Capture kGraphIters fused iterations at the steady rho0 into a graph
-// (timed: with an event before and after every launch).  Returns false if
-// the stream cannot be captured (e.g. the legacy default stream).
-bool capture_graph(twa_solver *s, bool timed) {
-    hipGraphExec_t *slot = timed ? &s->graph_timed : &s->graph;
+// Capture kGraphIters fused iterations at the steady rho0 into a graph.
+// Returns false if the stream cannot be captured (e.g. the legacy default
+// stream).
+bool capture_graph(twa_solver *s) {
+    hipGraphExec_t *slot = &s->graph;
     if (*slot) return true;
     if (s->graph_failed) return false;
-    if (timed && s->gevents.empty()) {
-        s->gevents.resize((size_t)kGraphIters * 4);
-        for (auto &e : s->gevents)
-            if (hipEventCreate(&e) != hipSuccess) {
-                s->graph_failed = true;
-                return false;
-            }
-    }
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
         s->graph_failed = true;
         return false;
     }
-    s->timing = timed ? 2 : 0;
-    s->gev_next = 0;
+    s->timing = 0;
     bool ok = true;
     for (int it = 0; it < kGraphIters && ok; ++it) ok = run_iteration(s, M_FUSED, s->rho0, s->rho0) == TWA_OK;
     s->timing = 0;
@@ -1295,31 +1291,20 @@ bool capture_graph(twa_solver *s, bool timed) {
     return ok;
 }
 
-// Run k iterations; graph replays where possible.  acc (timed) collects the
-// device milliseconds of the three kernels.
-twa_status iterate_impl(twa_solver *s, int k, double *acc) {
+// Run k iterations; graph replays where possible.  timed: the last
+// kTimedTail iterations are launched on their own, with events.
+twa_status iterate_impl(twa_solver *s, int k, bool timed) {
+    const int tail = timed ? std::min(k, kTimedTail) : 0;
     while (k > 0) {
-        bool steady = s->pending && s->iter - 1 >= s->n_warm && !s->dbg_x;
-        if (steady && k >= kGraphIters && capture_graph(s, acc != nullptr)) {
-            if (acc) {
-                HIP_TRY(s, hipGraphLaunch(s->graph_timed, s->stream));
-                HIP_TRY(s, hipStreamSynchronize(s->stream));
-                for (int it = 0; it < kGraphIters; ++it)
-                    for (int kk = 0; kk < 3; ++kk) {
-                        float ms = 0.f;
-                        if (hipEventElapsedTime(&ms, s->gevents[4 * it + kk], s->gevents[4 * it + kk + 1]) ==
-                            hipSuccess)
-                            acc[kk] += ms;
-                    }
-            } else {
-                HIP_TRY(s, hipGraphLaunch(s->graph, s->stream));
-            }
+        const bool steady = s->pending && s->iter - 1 >= s->n_warm && !s->dbg_x;
+        if (steady && k - tail >= kGraphIters && capture_graph(s)) {
+            HIP_TRY(s, hipGraphLaunch(s->graph, s->stream));
             s->iter += kGraphIters;
             k -= kGraphIters;
             continue;
         }
         float rho = rho_at(s, s->iter);
-        if (acc) s->timing = 1;
+        if (k <= tail) s->timing = 1;
         twa_status st;
         if (!s->pending) st = run_iteration(s, M_FIRST, rho, rho);
         else st = run_iteration(s, M_FUSED, rho, rho_at(s, s->iter - 1));
@@ -1419,8 +1404,7 @@ void twa_destroy(twa_solver *s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
-    if (s->graph_timed) (void)hipGraphExecDestroy(s->graph_timed);
-    for (hipEvent_t e : s->gevents) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     for (void *p : s->allocs) (void)hipFree(p);
     delete s;
 }
@@ -1732,27 +1716,29 @@ twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm) {
 twa_status twa_iterate(twa_solver *s, int k) {
     TRY(check_alive(s));
     if (k < 0) return fail(s, TWA_E_INVALID, "k must be >= 0");
-    return iterate_impl(s, k, nullptr);
+    return iterate_impl(s, k, false);
 }
 
 twa_status twa_iterate_timed(twa_solver *s, int k, double *kernel_ms) {
     TRY(check_alive(s));
     if (!kernel_ms) return fail(s, TWA_E_INVALID, "null kernel_ms");
     if (k < 0) return fail(s, TWA_E_INVALID, "k must be >= 0");
-    s->events.clear();
+    s->events_used = 0;
     double acc[3] = {0, 0, 0};
-    twa_status st = iterate_impl(s, k, acc);
+    twa_status st = iterate_impl(s, k, true);
     hipError_t e = hipStreamSynchronize(s->stream);
-    // eager iterations: four marks each (before stream, queue, nodes; after nodes)
-    for (size_t q = 0; q + 3 < s->events.size() && e == hipSuccess; q += 4) {
+    // timed iterations: four marks each (before stream, queue, nodes; after nodes)
+    long long timed = 0;
+    for (size_t q = 0; q + 3 < s->events_used && e == hipSuccess; q += 4, ++timed) {
         for (int kk = 0; kk < 3; ++kk) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, s->events[q + kk], s->events[q + kk + 1]) == hipSuccess) acc[kk] += ms;
         }
     }
-    for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
-    s->events.clear();
-    for (int kk = 0; kk < 3; ++kk) kernel_ms[kk] = acc[kk];
+    s->events_used = 0;
+    // the timed iterations stand for all k
+    const double scale = timed > 0 ? (double)k / (double)timed : 0.0;
+    for (int kk = 0; kk < 3; ++kk) kernel_ms[kk] = acc[kk] * scale;
     if (st != TWA_OK) return st;
     if (e != hipSuccess) return fail(s, TWA_E_DEVICE, std::string("timed iterate: ") + hipGetErrorString(e));
     return TWA_OK;
