@@ -39,12 +39,12 @@
  *   - start and goal are constants (Sec. 3) yet equality nodes (Sec. 3.3):
  *     each gets a unary factor x = const with weight infinity.
  *   - weight infinity is taken as the exact limit; weight zero is replaced by
- *     a small equal value (App. C, D, E: "small equal values").
+ *     a small value shared by both weights (App. C, D, E).
  *   - the capsule support point P(theta) uses <x_R - x_L, n(theta)> >= 0.
  *   - exact ties of the argmin are broken deterministically: lowest energy,
  *     then tangent before boundary candidates, then smallest theta in
  *     [0, 2 pi).  The paper draws uniformly at random (App. B, step 2).
- *   - non-collision is "distance >= r_i + r_j" (Sec. 3.1 footnote), so a
+ *   - non-collision means distance >= r_i + r_j (Sec. 3.1 footnote), so a
  *     collision factor is active iff the closest approach is < r_i + r_j.
  */
 #include <math.h>

@@ -12,7 +12,7 @@
 // (a) a stationary point of a smooth piece where both ends are pushed (the
 // paper's tangent-slab family, App. I), (b) the outward normal of the point
 // of R nearest to one end while the other end is already clear (the
-// paper's "one spring relaxed" configuration), or (c) a kink of h (slab
+// paper's configuration with one spring at rest), or (c) a kink of h (slab
 // resting on a flat side of the wall).  Candidates of each kind are
 // enumerated in closed form or by a bracketed 1-D root solve, and the one
 // of least F wins.  The stationary points of a piece are Lagrange points of
