@@ -434,6 +434,47 @@ TWA_HD f2 closest_on_seg(f2 q, f2 a, f2 b) {
     return add(a, scl(d, t));
 }
 
+// Best candidate so far of the capsule minimiser: least F, the earliest
+// candidate on ties.
+struct CapBest {
+    f2 u = f2{1.f, 0.f};
+    float F = INFINITY;
+    int kind = CH_NONE, ctr = 0;
+};
+
+// Candidates of smooth piece pc (the arc around C.a, or C.b) in their fixed
+// order: the global stationary point of the piece's quadratic (and its
+// mirror in the hard case), and the two middle ones when the global point
+// lies on the wrong half-circle.
+TWA_HD void capsule_piece(const Capsule &C, f2 n0, f2 n1, float w0, float w1, int pc, f2 d, bool seg, CapBest &bb) {
+    auto consider = [&](f2 u) {
+        float Fk = cap_F(C, u, n0, n1, w0, w1);
+        if (Fk < bb.F || bb.kind == CH_NONE) {
+            bb.F = Fk;
+            bb.u = u;
+            bb.kind = CH_T;
+            bb.ctr = pc;
+        }
+    };
+    f2 c = pc ? C.b : C.a;
+    Eig2 g = piece_quadratic(sub(n0, c), sub(n1, c), w0, w1, C.r);
+    f2 t0, alt, mid[2];
+    int k = trs_global(g, &t0, &alt);
+    consider(t0);
+    if (k == 2) consider(alt);
+    // the piece's other local minimum can only matter when its global one
+    // lies on the half-circle where the other end cap is the support
+    float side = dot(d, t0);
+    bool valid = !seg || (pc ? side >= 0.f : side <= 0.f);
+    if (!valid) {
+        int nm = trs_middle(g, mid);
+        for (int q = 0; q < nm; ++q) consider(mid[q]);
+    }
+}
+
+TWA_HD void capsule_finish(const Capsule C, f2 n0, f2 n1, float w0, float w1, f2 d, float L2, bool seg, f2 sw,
+                           CapBest &bb, f2 &x0, f2 &x1, Choice *ch);
+
 TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int k0, int k1, f2 &x0, f2 &x1,
                          Choice *ch = nullptr) {
     bool i0 = k0 == W_INF, i1 = k1 == W_INF;
@@ -494,9 +535,17 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
         }
         return;
     }
-    f2 best = mk(1.f, 0.f);
-    int bk = CH_NONE, bc = 0;
-    float bF = INFINITY;
+    CapBest bb;
+    // (a) stationary points of each smooth piece
+    for (int pc = 0; pc < (seg ? 2 : 1); ++pc) capsule_piece(C, n0, n1, w0, w1, pc, d, seg, bb);
+    capsule_finish(C, n0, n1, w0, w1, d, L2, seg, sw, bb, x0, x1, ch);
+}
+
+TWA_HD void capsule_finish(const Capsule C, f2 n0, f2 n1, float w0, float w1, f2 d, float L2, bool seg, f2 sw,
+                           CapBest &bb, f2 &x0, f2 &x1, Choice *ch) {
+    f2 &best = bb.u;
+    int &bk = bb.kind, &bc = bb.ctr;
+    float &bF = bb.F;
     auto consider = [&](f2 u, int kind, int ctr) {
         float Fk = cap_F(C, u, n0, n1, w0, w1);
         if (Fk < bF || bk == CH_NONE) {
@@ -506,23 +555,6 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
             bc = ctr;
         }
     };
-    // (a) stationary points of each smooth piece
-    for (int pc = 0; pc < (seg ? 2 : 1); ++pc) {
-        f2 c = pc ? C.b : C.a;
-        Eig2 g = piece_quadratic(sub(n0, c), sub(n1, c), w0, w1, C.r);
-        f2 t0, alt, mid[2];
-        int k = trs_global(g, &t0, &alt);
-        consider(t0, CH_T, pc);
-        if (k == 2) consider(alt, CH_T, pc);
-        // the piece's other local minimum can only matter when its global
-        // one lies on the half-circle where the other end cap is the support
-        float side = dot(d, t0);
-        bool valid = !seg || (pc ? side >= 0.f : side <= 0.f);
-        if (!valid) {
-            int nm = trs_middle(g, mid);
-            for (int q = 0; q < nm; ++q) consider(mid[q], CH_T, pc);
-        }
-    }
     // (c) kinks: slab against a flat side
     if (seg) {
         consider(sw, CH_FLAT, 0);

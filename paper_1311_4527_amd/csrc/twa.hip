@@ -677,9 +677,42 @@ __device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsign
     return act;
 }
 
-// Queued wall factor (entry e).
+// The same minimiser on two lanes (lanes 2k and 2k+1 hold the same factor,
+// `piece` = lane & 1): each lane solves one smooth piece of the capsule, the
+// two results meet by a lane exchange, and both lanes finish identically.
+// Bitwise equal to capsule_prox: the exchange keeps piece 0's candidate on
+// equal F, as the sequential order does.  Device only; both lanes of a pair
+// must call it together.
+__device__ __forceinline__ void capsule_prox_pair(const Capsule C, f2 n0, f2 n1, float w0, float w1, int k0, int k1,
+                                                  int piece, f2 &x0, f2 &x1) {
+    bool i0 = k0 == W_INF, i1 = k1 == W_INF;
+    if ((i0 && i1) || i0 || i1) {
+        capsule_prox(C, n0, n1, w0, w1, k0, k1, x0, x1);
+        return;
+    }
+    f2 d = sub(C.b, C.a);
+    float L2 = dot(d, d);
+    bool seg = L2 > 0.f;
+    f2 sw = seg ? scl(perp(d), inv_sqrt(L2)) : mk(0.f, 1.f);
+    CapBest mine;
+    if (piece == 0 || seg) capsule_piece(C, n0, n1, w0, w1, piece, d, seg, mine);
+    CapBest other;
+    other.F = __shfl_xor(mine.F, 1);
+    other.u.x = __shfl_xor(mine.u.x, 1);
+    other.u.y = __shfl_xor(mine.u.y, 1);
+    other.kind = __shfl_xor(mine.kind, 1);
+    other.ctr = __shfl_xor(mine.ctr, 1);
+    const CapBest &a = piece ? other : mine, &b = piece ? mine : other;
+    CapBest bb = a;
+    if (b.kind != CH_NONE && (b.F < bb.F || bb.kind == CH_NONE)) bb = b;
+    capsule_finish(C, n0, n1, w0, w1, d, L2, seg, sw, bb, x0, x1, nullptr);
+}
+
+// Queued wall factor (entry e).  piece < 0: one lane; 0 or 1: the two lanes
+// of a pair share the minimiser (capsule_prox_pair) and lane 0 writes.
 template <int MODE>
-__device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsigned e) {
+__device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsigned e, int piece) {
+    const bool writer = piece <= 0;
     const bool dense = P.dense != 0;
     long long f = e & kIdx;
     bool prev = (e & kPrev) != 0;
@@ -702,7 +735,7 @@ __device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsign
         u.z = (kb == W_STD) ? u.z + P.step_prev * (x1.x - cb.x) : 0.f;
         u.w = (kb == W_STD) ? u.w + P.step_prev * (x1.y - cb.y) : 0.f;
         if (MODE == M_FINAL) {
-            P.u_wall[f] = u;
+            if (writer) P.u_wall[f] = u;
             return false;
         }
     } else if (MODE == M_FIRST) {
@@ -712,7 +745,11 @@ __device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsign
     bool act = segseg_sq(n0, n1, Cw.a, Cw.b) < Cw.r * Cw.r;
     f2 x0 = n0, x1 = n1;
     if (act) {
-        capsule_prox(Cw, n0, n1, wval(ka, P.rho), wval(kb, P.rho), ka, kb, x0, x1);
+        if (piece < 0) capsule_prox(Cw, n0, n1, wval(ka, P.rho), wval(kb, P.rho), ka, kb, x0, x1);
+        else capsule_prox_pair(Cw, n0, n1, wval(ka, P.rho), wval(kb, P.rho), ka, kb, piece, x0, x1);
+    }
+    if (!writer) return act;
+    if (act) {
         P.x_wall[f] = make_float4(x0.x, x0.y, x1.x, x1.y);
         float m0[2] = {x0.x + u.x, x0.y + u.y}, m1[2] = {x1.x + u.z, x1.y + u.w};
         contribute(P, na, 0, m0, 2);
@@ -817,12 +854,14 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
 
 // One queue entry per lane of a wave-uniform loop: collision entries first,
 // wall entries from the next multiple of 64 (a wave never mixes the two
-// minimisers, whose run times differ several-fold).
+// minimisers, whose run times differ several-fold); piece: which lane of a
+// wall entry's pair (-1: the entry has one lane).
 template <int D, int MODE>
-__device__ __forceinline__ void queue_entry(const Params &P, const Rec &Z, bool is_coll, bool is_wall, unsigned e) {
+__device__ __forceinline__ void queue_entry(const Params &P, const Rec &Z, bool is_coll, bool is_wall, unsigned e,
+                                            int piece) {
     bool ac = false, aw = false;
     if (is_coll) ac = coll_queue<D, MODE>(P, Z, e);
-    else if (is_wall) aw = wall_queue<MODE>(P, Z, e);
+    else if (is_wall) aw = wall_queue<MODE>(P, Z, e, piece) && piece <= 0;
     count_wave(&P.counters[2], ac);
     count_wave(&P.counters[3], aw);
 }
@@ -845,7 +884,8 @@ __device__ __forceinline__ void queue_block(const Params &P, long long qb, long 
     const int nqc = __shfl(v, kShards - 1);
     __syncthreads();
     const int nqw = P.counters[1];
-    const long long wall0 = ((long long)nqc + 63) & ~63LL, total = wall0 + nqw;
+    // wall entries take two lanes each (capsule_prox_pair)
+    const long long wall0 = ((long long)nqc + 63) & ~63LL, total = wall0 + 2LL * nqw;
     const long long stride = nqb * 64;
     const Rec Z{P.zr_cur, P.zr_prev};
     for (long long t0 = qb * 64; t0 < total; t0 += stride) {
@@ -861,9 +901,9 @@ __device__ __forceinline__ void queue_block(const Params &P, long long qb, long 
             }
             e = P.qc[(long long)lo * P.qcap + (t - pre[lo])];
         } else if (is_wall) {
-            e = P.qw[t - wall0];
+            e = P.qw[(t - wall0) >> 1];
         }
-        queue_entry<D, MODE>(P, Z, is_coll, is_wall, e);
+        queue_entry<D, MODE>(P, Z, is_coll, is_wall, e, (int)((t - wall0) & 1));
     }
 }
 
@@ -886,10 +926,27 @@ __device__ __forceinline__ void close_counters(const Params &P, int shards) {
     P.counters[1] = P.counters[2] = P.counters[3] = 0;
 }
 
+// close_counters by the first wave of a block, one lane per queue shard
+__device__ __forceinline__ void close_counters_wave(const Params &P) {
+    const int lane = threadIdx.x & 63;
+    int v = 0;
+    if (lane < kShards) {
+        v = P.qcnt[lane * kQueueStride];
+        P.qcnt[lane * kQueueStride] = 0;
+    }
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    if (lane == 0) {
+        P.stats[0] = P.counters[2];
+        P.stats[1] = P.counters[3];
+        P.stats[2] = v + P.counters[1];
+        P.counters[1] = P.counters[2] = P.counters[3] = 0;
+    }
+}
+
 template <int D>
 __device__ __forceinline__ void nodes_block(const Params &P, long long b) {
     long long nd = b * kBlock + threadIdx.x;
-    if (nd == 0) close_counters(P, kShards);
+    if (b == 0 && threadIdx.x < 64) close_counters_wave(P);
     if (nd < P.N) node_update<D>(P, nd);
 }
 
@@ -980,7 +1037,7 @@ __device__ __forceinline__ void batch_instance(const Params &P, float4 *zs, int 
     for (long long t0 = threadIdx.x & ~63; t0 < total; t0 += BLOCK) {
         const long long t = t0 + (threadIdx.x & 63);
         const bool is_coll = t < nqc, is_wall = t >= wall0 && t < total;
-        queue_entry<D, MODE>(P, Z, is_coll, is_wall, is_coll ? P.qc[t] : is_wall ? P.qw[t - wall0] : 0u);
+        queue_entry<D, MODE>(P, Z, is_coll, is_wall, is_coll ? P.qc[t] : is_wall ? P.qw[t - wall0] : 0u, -1);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
