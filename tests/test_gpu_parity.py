@@ -188,6 +188,29 @@ def test_deterministic_replay():
     assert torch.equal(A.twa_get_trajectories(), B.twa_get_trajectories())
 
 
+@pytest.mark.parametrize("k", [3, 70, 200])
+def test_timed_iterations_match_untimed(k):
+    """twa_iterate_timed runs the same iterations (graph replays, then the
+    timed tail launched on its own) and reports positive kernel times that
+    add up to no more than the wall time of the call."""
+    import time
+    import torch
+    inst = I.conf_swap100(0)
+    A = _solver(inst)
+    B = _solver(inst)
+    A.twa_iterate(40)
+    B.twa_iterate(40)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = A.twa_iterate_timed(k)
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    B.twa_iterate(k)
+    assert torch.equal(A.twa_get_trajectories(), B.twa_get_trajectories())
+    assert A.twa_get_stats()["iter"] == B.twa_get_stats()["iter"] == 40 + k
+    assert all(m > 0 for m in ms)
+    assert sum(ms) <= 1.5 * wall_ms + 1.0
+
+
 def test_full_solve_small_swap():
     """Collision-free and objective within 1e-3 of the reference after the
     same number of iterations (p=8 circle swap)."""
