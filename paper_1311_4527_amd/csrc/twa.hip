@@ -2,21 +2,27 @@
 // message-passing trajectory planner behind the C ABI of include/twa.h.
 //
 // One iteration (App. B, steps 1-7) is three launches on the solver stream:
-//   k_stream  one lane per factor, coalesced streams.  Collision and wall
-//             factors: closest-approach / segment-distance activity test on
-//             n = z - u (Sec. 3.3.1-3.3.2 weight rule); factors that are
-//             active, or were active last iteration, are appended to a
-//             work queue with one wave-aggregated atomic.  Energy and fixed
-//             factors are always active and are finished here.
-//   k_queue   one lane per queued factor: the full non-convex minimiser
-//             (App. C, D, I), the u update of the previous iteration
-//             (fused, see below), m = x + u, and the consensus sums.
+//   k_stream  coalesced walk over all factors.  Collision factors by
+//             columns: a wave holds one chunk of 64 pairs (i, j0..j0+63) of
+//             the pair triangle across several break-point intervals; wall,
+//             energy, velocity-limit and fixed factors one lane each.
+//             Collision and wall factors get the closest-approach /
+//             segment-distance activity test on n = z - u (Sec. 3.3.1-3.3.2
+//             weight rule); factors that are active, or were active last
+//             iteration, are appended to a work queue (one wave-aggregated
+//             atomic, the collision queue sharded over 32 counters).
+//             Energy, velocity-limit and fixed factors finish here.
+//   k_queue   one wave per workgroup over the queue: the full non-convex
+//             minimiser (App. C, D, I; a wall factor on two lanes), the u
+//             update of the previous iteration (fused, see below),
+//             m = x + u, and the consensus sums.
 //   k_nodes   one lane per break-point node: z = weighted mean (step 5),
 //             <-rho (step 6), clear the sums.
 // The u update (step 7) of iteration k needs z^{k+1}, so it is deferred
-// into the next iteration's k_stream/k_queue: they recompute x^{k} from the
-// saved (z^{k-1}, u^{k-1}) -- bitwise the same arithmetic -- and update u
-// in registers, so u is read once and written once per iteration.
+// into the next iteration: the queue keeps x^k of the factors active in
+// iteration k, the energy factors recompute it from (z^{k-1}, u^{k-1}) --
+// bitwise the same arithmetic -- and u is updated in registers, so it is
+// read once and written once per iteration.
 // Consensus sums are accumulated as exact 64-bit fixed-point integers with
 // atomics, so the result does not depend on the order of the additions.
 #include <hip/hip_runtime.h>
