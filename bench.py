@@ -185,6 +185,27 @@ def run_batched(K, warmup):
                 autotune=dict(block=block, groups=groups, candidates=log))
 
 
+def profile_batched(K, warmup=50, block=0, groups=1):
+    """The 256-instance batch in one launch form only (default: phased), K
+    iterations after a warm-up, for a kernel trace."""
+    import torch
+    from paper_1311_4527_amd import instances as I
+    from paper_1311_4527_amd.twa import Batch
+    insts = I.conf_batch()
+    F = sum(i.counts()["factors"] for i in insts)
+    B = Batch(insts)
+    B.twa_batch_config(block, groups)
+    B.twa_batch_iterate(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.twa_batch_iterate(K)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    B.close()
+    return dict(instances=len(insts), factors=F, iterations=K, block=block, groups=groups,
+                value=F * K / t, unit="factor-updates/s", us_per_iteration=t / K * 1e6)
+
+
 def min_clearance_pairs(radii, z):
     """Smallest closest-approach distance minus r_i + r_j over every pair and
     segment of trajectories z [p][eta+1][dim] (constant velocity per segment)."""
@@ -390,6 +411,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (for hardware-counter scaling)")
+    ap.add_argument("--leg", choices=["batched", "adjoint"], default=None,
+                    help="only run one side leg, without its comparison runs (for profiling)")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -407,6 +430,12 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.leg == "batched":
+        print(json.dumps(profile_batched(args.batch_steps)), flush=True)
+        return
+    if args.leg == "adjoint":
+        print(json.dumps(run_adjoint(500)), flush=True)
+        return
     inst = workload(args.workload)
     c = inst.counts()
     F = c["factors"]
