@@ -2059,14 +2059,21 @@ twa_status twa_batch_create(int n, const twa_instance *inst, unsigned flags, voi
     // blocks, and one queue block per 256 factors (1..64: crowded instances
     // queue a good share of their factors, and a block's entries beyond the
     // first 64 wait for a whole minimiser each)
+    // Queue blocks are ordered block-major (every instance's first block,
+    // then every instance's second...): an instance's first blocks hold its
+    // entries, and consecutive blocks land on different compute units, so
+    // the busy ones spread over the chip instead of stacking up.
     std::vector<int2> ms, mq, mn;
+    std::vector<int> nqb(n);
     for (int i = 0; i < n; ++i) {
         const twa_solver *s = b->solvers[i];
         for (long long lb = 0; lb < s->nblocks_stream; ++lb) ms.push_back(make_int2(i, (int)lb));
-        const int nqb = (int)std::min<long long>(64, std::max<long long>(1, (s->P.Fc + s->P.Fw + 255) / 256));
-        for (int qb = 0; qb < nqb; ++qb) mq.push_back(make_int2(i, qb | (nqb << 16)));
+        nqb[i] = (int)std::min<long long>(64, std::max<long long>(1, (s->P.Fc + s->P.Fw + 255) / 256));
         for (long long lb = 0; lb < (s->P.N + kBlock - 1) / kBlock; ++lb) mn.push_back(make_int2(i, (int)lb));
     }
+    for (int qb = 0; qb < 64; ++qb)
+        for (int i = 0; i < n; ++i)
+            if (qb < nqb[i]) mq.push_back(make_int2(i, qb | (nqb[i] << 16)));
     b->n_stream = (int)ms.size();
     b->n_queue = (int)mq.size();
     b->n_nodes = (int)mn.size();
