@@ -278,8 +278,9 @@ class _Borrowed(Solver):
 
 
 class Batch:
-    """Many independent instances advanced by one persistent launch
-    (twa_batch_create ... twa_batch_destroy)."""
+    """Many independent instances advanced together (twa_batch_create ...
+    twa_batch_destroy): by one persistent launch, or by one launch per phase
+    over all instances (twa_batch_config(0, 1))."""
 
     def __init__(self, instances, flags=0, stream: Optional[torch.cuda.Stream] = None, device="cuda"):
         lib = load_library()
@@ -325,6 +326,8 @@ class Batch:
         return len(self.instances)
 
     def twa_batch_config(self, block: int, groups: int):
+        """block 256 / 512 / 1024 lanes with `groups` bins: the persistent
+        kernel; block 0: the phased form (groups ignored)."""
         self._check(load_library().twa_batch_config(self.h, int(block), int(groups)))
 
     def twa_batch_iterate(self, k: int):
