@@ -366,3 +366,33 @@ def test_minimum_velocity_coinciding_ends():
     p = np.array([0.4, -0.2])
     act, xl, xh = O.prox_vel(p, p, 1.0, 3.0, 2.0, True)
     assert act and np.allclose(xl - xh, [2.0, 0.0]) and np.allclose((xl + 3 * xh) / 4, p)
+
+
+def _golden_rows(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        tok = line.split()
+        w = lambda t: np.inf if t == "inf" else float(t)
+        yield dict(kind=tok[0], wl=w(tok[1]), wh=w(tok[2]), C=float(tok[3]),
+                   nl=np.array([float(tok[4]), float(tok[5])]), nh=np.array([float(tok[6]), float(tok[7])]),
+                   xl=np.array([float(tok[8]), float(tok[9])]), xh=np.array([float(tok[10]), float(tok[11])]),
+                   binding=tok[12] == "1", src=" ".join(tok[13:]))
+
+
+def test_closed_forms_match_hand_worked_values():
+    """tests/golden/closed_forms.txt: energy (App. E), maximum and minimum
+    velocity (App. F, G) minimisers on hand-derived exact cases."""
+    rows = list(_golden_rows("closed_forms.txt"))
+    assert len(rows) >= 9
+    for r in rows:
+        if r["kind"] == "energy":
+            xl, xh = O.prox_energy(r["nl"], r["nh"], r["wl"], r["wh"], r["C"])
+            binding = True
+        else:
+            binding, xl, xh = O.prox_vel(r["nl"], r["nh"], r["wl"], r["wh"], r["C"], r["kind"] == "minvel")
+        assert binding == r["binding"], r["src"]
+        assert np.allclose(xl, r["xl"], atol=1e-12) and np.allclose(xh, r["xh"], atol=1e-12), (r["src"], xl, xh)
