@@ -244,14 +244,16 @@ def test_full_solve_swap100():
     assert cg > min(cr, 0.0) - 5e-5, (cg, cr)
 
 
-def test_parity_large_box_one_iteration():
+@pytest.mark.parametrize("flags", [1, 0])
+def test_parity_large_box_one_iteration(flags):
     """The p=1024, eta=16, 32-wall workload (8.4 M collision factors) in the
-    launch configuration of the benchmark: one iteration from the straight-
-    line state and one from an advanced reference state, element-wise."""
+    launch configuration of the benchmark (dense, and activity bits): one
+    iteration from the straight-line state and one from an advanced
+    reference state, element-wise."""
     inst = I.conf_box1024()
     P = O.Planner(inst)
     z, u, lr = P.get_state()
-    S = _solver(inst, flags=0)
+    S = _solver(inst, flags=flags)
     one_iteration_parity(inst, z, u, lr, 0, solver=S)
     P.iterate(8)
     z, u, lr = P.get_state()
