@@ -135,6 +135,27 @@ def test_parity_ragged_tail_sizes():
             one_iteration_parity(inst, z, u, lr, k, flags=p % 2)
 
 
+@pytest.mark.parametrize("eta,W,dim", [(1, 0, 2), (4, 3, 2), (3, 0, 3)])
+def test_single_agent(eta, W, dim):
+    """Degenerate instance without any collision factor (p = 1): parity of
+    single iterations against the reference."""
+    inst = I.random_box(1, 0.05, eta, n_walls=W, dim=dim, sigma=1e-2, seed=3 + eta, alpha=0.1, C=1.0 / eta)
+    for k, z, u, lr in _reference_states(inst, [0, 3]):
+        one_iteration_parity(inst, z, u, lr, k)
+
+
+def test_single_agent_reaches_the_straight_line():
+    """One agent in free space from a noisy start reaches the straight line
+    between its end points (App. A's single-agent case)."""
+    inst = I.circle_swap(1, 0.1, 4, sigma=0.3, seed=1, alpha=1.0, C=1.0)
+    S = _solver(inst)
+    S.twa_iterate(400)
+    z = S.twa_get_trajectories().cpu().numpy().astype(np.float64)
+    s = np.arange(5) / 4
+    line = inst.x0[:, None, :] + s[None, :, None] * (inst.xT - inst.x0)[:, None, :]
+    assert np.abs(z - line).max() < 1e-5
+
+
 def test_fused_matches_stepwise():
     """k iterations in a row (u update fused into the next iteration) equal k
     single iterations with the state exported and re-imported in between."""

@@ -87,8 +87,8 @@ def test_straight_line_fixed_point():
 
 
 def test_single_agent_straight_line():
-    """One agent in free space reaches the straight line (paper, App. A:
-    'the optimal straight-line solution in 200 iterations')."""
+    """One agent in free space reaches the straight line (App. A reports
+    the straight-line optimum after about 200 iterations)."""
     inst = I.circle_swap(1, 0.1, 4, sigma=0.3, seed=1, alpha=1.0, C=1.0)
     P = O.Planner(inst)
     P.iterate(400)
