@@ -68,7 +68,7 @@ enum { TOR_COST_ENERGY = 0, TOR_COST_NONE = 1, TOR_COST_MAXVEL = 2, TOR_COST_MIN
  * rho0; the agent-agent and agent-wall factors with their start ends fixed
  * are eq. minimizer_rvo_coll and eq. minimizer_rvo_wall as they stand. */
 
-/* Relative size of the "small equal value" that replaces a zero weight. */
+/* Relative size of the small value shared by both weights when a zero weight is replaced (App. C-E). */
 #define TOR_ZERO_WEIGHT 1e-9
 
 /* ------------------------------------------------------------------------ */
