@@ -394,9 +394,43 @@ def cpu_baseline(inst, budget_s=12.0):
     F = inst.counts()["factors"]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = min(cores, os.cpu_count() or cores)
-    return dict(value=F * n / dt, unit="factor-updates/s", cores=cores, kind="oracle",
-                sample=f"{n} reference iterations (after 1 untimed) of the same p=1024, eta=16, 32-wall "
-                       f"instance from its straight-line start, {dt:.1f} s wall")
+    out = dict(value=F * n / dt, unit="factor-updates/s", cores=cores, kind="oracle",
+               sample=f"{n} reference iterations (after 1 untimed) of the same p=1024, eta=16, 32-wall "
+                      f"instance from its straight-line start, {dt:.1f} s wall")
+    # the two small circle swaps, beside the GPU's small_workloads leg
+    small = {}
+    for name, K in (("swap8", 2000), ("swap100", 100)):
+        si = workload(name)
+        Ps = O.Planner(si)
+        t0 = time.perf_counter()
+        Ps.iterate(K)
+        ds = time.perf_counter() - t0
+        small[name] = dict(iterations=K, iterations_per_s=K / ds,
+                           factor_updates_per_s=si.counts()["factors"] * K / ds)
+    out["small_workloads"] = small
+    return out
+
+
+def run_small(warmup=50):
+    """The circle swaps of 8 agents (eta=4, 2000 iterations) and 100 agents
+    (eta=8, 5000 iterations): launch- and latency-bound, so iterations/s."""
+    import torch
+    from paper_1311_4527_amd.twa import Solver
+    out = {}
+    for name, K in (("swap8", 2000), ("swap100", 5000)):
+        inst = workload(name)
+        S = Solver.from_instance(inst)
+        S.twa_iterate(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.twa_iterate(K)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = dict(p=inst.p, eta=inst.eta, iterations=K, iterations_per_s=K / dt,
+                         factor_updates_per_s=inst.counts()["factors"] * K / dt,
+                         objective=objective(inst, S.twa_get_trajectories().cpu().numpy()))
+        S.close()
+    return out
 
 
 def main():
@@ -462,6 +496,9 @@ def main():
         print(f"# variant {other}: {out['variants'][other]['value']:.4g}", file=sys.stderr, flush=True)
         out["batched"] = run_batched(args.batch_steps, 50)
         print(f"# batched: {out['batched']['value']:.4g} (x{out['batched']['speedup']:.1f} vs sequential)",
+              file=sys.stderr, flush=True)
+        out["small_workloads"] = run_small()
+        print(f"# small: {[(k, round(v['iterations_per_s'])) for k, v in out['small_workloads'].items()]} iterations/s",
               file=sys.stderr, flush=True)
         out["admm_vs_twa"] = run_admm_vs_twa()
         print(f"# admm vs twa: {[(r['p'], r['twa']['iterations_to_collision_free'], r['admm']['iterations_to_collision_free']) for r in out['admm_vs_twa']]}",
