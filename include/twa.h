@@ -140,7 +140,10 @@ twa_status twa_set_init(twa_solver *s, const float *z);
  * create-time rho0 (Sec. 4 uses a small rho0 for 20 iterations). */
 twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm);
 
-/* Run k >= 0 iterations (App. B steps 1-7), asynchronously. */
+/* Run k >= 0 iterations (App. B steps 1-7), asynchronously.  Iterations at
+ * the steady rho0 are replayed from a HIP graph of 32; an instance of at most
+ * 256 collision + wall factors runs them in one persistent single-workgroup
+ * launch instead (bitwise the same iterations). */
 twa_status twa_iterate(twa_solver *s, int k);
 
 /* As twa_iterate, and times the kernels with HIP events on the solver's

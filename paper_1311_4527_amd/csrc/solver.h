@@ -97,6 +97,10 @@ struct twa_solver {
     // HIP graph of kGraphIters fused iterations
     hipGraphExec_t graph = nullptr;
     bool graph_failed = false;
+    // tiny instances: the persistent batched kernel on this one instance
+    // (a device copy of the parameters and its one-bin layout)
+    twa_rt::Params *tiny_params = nullptr;
+    int *tiny_bins = nullptr;
     // TWA_F_TAPE: the state the differentiated run starts from (canonical
     // layouts), saved by create / set_init / set_state
     float *origin_z = nullptr, *origin_u = nullptr;

@@ -1354,10 +1354,52 @@ bool capture_graph(twa_solver *s) {
     return ok;
 }
 
+// Instances this small (collision + wall factors) run untimed iterations
+// in the persistent batched kernel, one workgroup, all iterations of a call
+// in one launch: three launches per iteration would cost more than the work.
+constexpr long long kTinyFactors = 256;
+constexpr int kTinyBlock = 512, kTinyChunk = 4096; // iterations per launch at most
+
+bool tiny(const twa_solver *s) { return s->P.Fc + s->P.Fw <= kTinyFactors; }
+
+// k iterations of a tiny instance at the steady rho0 (bitwise the plain
+// iterations: the same per-factor code).
+twa_status iterate_tiny(twa_solver *s, int k) {
+    if (!s->tiny_params) {
+        Params c = s->P;
+        c.rho = c.rho_prev = s->rho0;
+        c.step = c.step_prev = s->alpha / s->rho0;
+        c.dbg_x = nullptr;
+        c.dbg_rho = nullptr;
+        const int bins[3] = {0, 1, 0}; // bin_start {0, 1}, bin_items {0}
+        TRY(dev_alloc(s, &s->tiny_params, 1));
+        TRY(dev_alloc(s, &s->tiny_bins, 3));
+        HIP_TRY(s, hipMemcpyAsync(s->tiny_params, &c, sizeof(Params), hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(s, hipMemcpyAsync(s->tiny_bins, bins, sizeof(bins), hipMemcpyHostToDevice, s->stream));
+    }
+    while (k > 0) {
+        const int n = std::min(k, kTinyChunk);
+        hipLaunchKernelGGL(k_batch<kTinyBlock>, dim3(1), dim3(kTinyBlock), 0, s->stream,
+                           (const Params *)s->tiny_params, (const int *)s->tiny_bins, (const int *)s->tiny_bins + 2, n,
+                           s->pending ? 0 : 1);
+        HIP_TRY(s, hipGetLastError());
+        s->pending = true;
+        s->iter += n;
+        k -= n;
+    }
+    return TWA_OK;
+}
+
 // Run k iterations; graph replays where possible.  timed: the last
 // kTimedTail iterations are launched on their own, with events.
 twa_status iterate_impl(twa_solver *s, int k, bool timed) {
     const int tail = timed ? std::min(k, kTimedTail) : 0;
+    // (steady rho0 throughout, the previous iteration's weights included)
+    const bool settled = s->iter >= s->n_warm && (!s->pending || s->iter - 1 >= s->n_warm);
+    if (tiny(s) && k - tail > 0 && settled && !s->dbg_x) {
+        TRY(iterate_tiny(s, k - tail));
+        k = tail;
+    }
     while (k > 0) {
         const bool steady = s->pending && s->iter - 1 >= s->n_warm && !s->dbg_x;
         if (steady && k - tail >= kGraphIters && capture_graph(s)) {

@@ -1,0 +1,98 @@
+"""Instances of at most 256 collision + wall factors: untimed iterations run
+in the persistent one-workgroup kernel, all iterations of a call in one
+launch.  The per-factor code is the plain kernels', so the state after any
+mix of such calls and plain iterations must equal, bit for bit, the state
+after plain iterations alone (twa_iterate_timed launches its last four
+iterations on their own, through the plain kernels, so calls of four timed
+iterations run plain throughout)."""
+import pytest
+
+from paper_1311_4527_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+F_DENSE, F_ADMM, F_NONE, F_MAXVEL, F_MINVEL = 1, 4, 8, 16, 32
+
+CASES = {
+    "swap8_2d": lambda: I.conf_small(0),                                # 112 collision factors
+    "swap6_3d": lambda: I.circle_swap(6, 0.05, 4, dim=3, seed=3),       # 60
+    "box8_walls": lambda: I.conf_box1024(seed=5, p=8, eta=4, n_walls=4),  # 112 + 128 wall factors
+}
+
+
+def _state(S):
+    import torch
+    z, u, lr, it = S.twa_get_state()
+    torch.cuda.synchronize()
+    return z.cpu(), u.cpu(), lr.cpu(), it
+
+
+def _plain(S, k):
+    assert k % 4 == 0
+    for _ in range(k // 4):
+        S.twa_iterate_timed(4)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("flags", [0, F_DENSE, F_ADMM, F_NONE, F_MAXVEL, F_MINVEL])
+def test_tiny_equals_plain(case, flags):
+    import torch
+    from paper_1311_4527_amd.twa import Solver
+    inst = CASES[case]()
+    c = inst.counts()
+    assert c["coll"] + c["wall"] <= 256
+    A = Solver.from_instance(inst, flags=flags)
+    B = Solver.from_instance(inst, flags=flags)
+    A.twa_iterate(37)            # from the initial state
+    A.twa_iterate_timed(3)       # plain iterations in between
+    A.twa_iterate(260)           # a pending state carried into the kernel
+    _plain(B, 300)
+    za, ua, la, ia = _state(A)
+    zb, ub, lb, ib = _state(B)
+    assert ia == ib == 300
+    assert torch.equal(za, zb)
+    assert torch.equal(ua, ub)
+    assert torch.equal(la, lb)
+    sa, sb = A.twa_get_stats(), B.twa_get_stats()
+    assert sa == sb
+    A.close()
+    B.close()
+
+
+def test_tiny_after_warm_up_schedule():
+    """Warm-up iterations (rho0_init) run plain; later calls take the kernel
+    at rho0, the first of them with a previous iteration at rho0 too."""
+    import torch
+    from paper_1311_4527_amd.twa import Solver
+    inst = I.conf_small(1)
+    A = Solver.from_instance(inst)
+    B = Solver.from_instance(inst)
+    for S in (A, B):
+        S.twa_set_schedule(0.25, 12)
+    A.twa_iterate(12)   # the warm-up
+    A.twa_iterate(1)    # previous iteration in the warm-up: plain
+    A.twa_iterate(199)
+    _plain(B, 212)
+    za, ua, la, _ = _state(A)
+    zb, ub, lb, _ = _state(B)
+    assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb)
+    A.close()
+    B.close()
+
+
+def test_tiny_long_call_spans_launches():
+    """More iterations than one launch of the kernel runs (4096)."""
+    import torch
+    from paper_1311_4527_amd.twa import Solver
+    inst = I.conf_small(2)
+    A = Solver.from_instance(inst)
+    B = Solver.from_instance(inst)
+    A.twa_iterate(5000)
+    for _ in range(5):
+        B.twa_iterate(1000)
+    za, ua, la, ia = _state(A)
+    zb, ub, lb, ib = _state(B)
+    assert ia == ib == 5000
+    assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb)
+    A.close()
+    B.close()
