@@ -389,21 +389,26 @@ TWA_HD void disk_prox(f2 m0, f2 m1, float w0, float w1, int k0, int k1, float R,
             bk = kind;
         }
     };
-    f2 t0, alt;
-    int nt = trs_global(g, &t0, &alt);
-    consider(t0, CH_T);
-    if (nt == 2) consider(alt, CH_T);
-    // one end pushed straight out while the other is clear: the stationary
-    // point of the one-sided piece (with both ends pushed the tangent
-    // family above already holds the minimum)
+    // one end pushed straight out while the other is clear: when valid it
+    // is the minimiser outright (that end moves the least any feasible
+    // configuration can move it, the other not at all), taken without
+    // comparing F, which rounding decides wrongly when the tangent family's
+    // root lies within ~1e-4 rad of it (F is stationary there).  Otherwise
+    // both ends are pushed and the tangent family holds the minimum.
     float q0 = dot(m0, m0), q1 = dot(m1, m1);
     if (q0 > 0.f && q0 < R * R) {
         f2 u = scl(m0, inv_sqrt(q0));
         if (dot(m1, u) >= R) consider(u, CH_R0);
     }
-    if (q1 > 0.f && q1 < R * R) {
+    if (bk == CH_NONE && q1 > 0.f && q1 < R * R) {
         f2 u = scl(m1, inv_sqrt(q1));
         if (dot(m0, u) >= R) consider(u, CH_R1);
+    }
+    if (bk == CH_NONE) {
+        f2 t0, alt;
+        int nt = trs_global(g, &t0, &alt);
+        consider(t0, CH_T);
+        if (nt == 2) consider(alt, CH_T);
     }
     v0 = add(m0, scl(best, pos(R - dot(m0, best))));
     v1 = add(m1, scl(best, pos(R - dot(m1, best))));
@@ -494,14 +499,24 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
     f2 sw = seg ? scl(perp(d), inv_sqrt(L2)) : mk(0.f, 1.f);
     if (i0 || i1) {
         // one end certain: the other moves along normals u visible from it
+        // (<q, u> >= h(u)).  A tangent normal from q to the circle at one
+        // end of the segment has q on its line, so it is visible exactly
+        // when that end is the support in direction u: the sign of <d, u>,
+        // tested with a slack of a few roundings of |d| only.  The other
+        // candidates are tested as they stand.
         f2 q = i0 ? n0 : n1, m = i0 ? n1 : n0;
-        float tol = 1e-5f * (fabsf(q.x) + fabsf(q.y) + C.r);
+        const float dtol = 1e-6f * (fabsf(d.x) + fabsf(d.y));
         f2 best = mk(1.f, 0.f);
         int bk = CH_NONE, bc = 0;
         float bg = INFINITY;
         auto consider = [&](f2 u, int kind, int ctr) {
             float h = cap_h(C, u);
-            if (dot(q, u) < h - tol) return; // not visible from the certain end
+            if (kind == CH_TAN) {
+                float side = dot(d, u); // > 0: the end b supports direction u
+                if (ctr ? side < -dtol : side > dtol) return;
+            } else if (dot(q, u) < h) {
+                return; // not visible from the certain end
+            }
             float g = pos(h - dot(m, u));
             if (g < bg) {
                 bg = g;
@@ -510,20 +525,41 @@ TWA_HD void capsule_prox(const Capsule C, f2 n0, f2 n1, float w0, float w1, int 
                 bc = ctr;
             }
         };
-        f2 tn[2];
-        int nt = tangent_normals(q, C.a, C.r, tn);
-        for (int k = 0; k < nt; ++k) consider(tn[k], CH_TAN, 0);
-        if (seg) {
-            nt = tangent_normals(q, C.b, C.r, tn);
-            for (int k = 0; k < nt; ++k) consider(tn[k], CH_TAN, 1);
+        // m's nearest boundary point, when visible from q, is the minimiser
+        // outright (m must move at least that far, and q stays), so rounding
+        // gets no say between it and a candidate of nearly the same direction
+        {
+            float tpar = seg ? fminf(fmaxf(dot(sub(m, C.a), d) / L2, 0.f), 1.f) : 0.f;
+            f2 t = sub(m, closest_on_seg(m, C.a, C.b));
+            float tt = dot(t, t);
+            if (tt > 0.f) {
+                const bool flat = seg && tpar > 0.f && tpar < 1.f;
+                f2 u = flat ? (dot(t, sw) >= 0.f ? sw : scl(sw, -1.f)) : scl(t, inv_sqrt(tt));
+                float h = cap_h(C, u);
+                if (dot(q, u) >= h) {
+                    bg = pos(h - dot(m, u));
+                    best = u;
+                    bk = flat ? CH_FLAT : CH_RADF;
+                    bc = (seg && tpar >= 1.f) ? 1 : 0;
+                }
+            }
         }
-        f2 t0 = sub(m, C.a);
-        if (dot(t0, t0) > 0.f) consider(scl(t0, inv_sqrt(dot(t0, t0))), CH_RADF, 0);
-        if (seg) {
-            f2 t1 = sub(m, C.b);
-            if (dot(t1, t1) > 0.f) consider(scl(t1, inv_sqrt(dot(t1, t1))), CH_RADF, 1);
-            consider(sw, CH_FLAT, 0);
-            consider(scl(sw, -1.f), CH_FLAT, 0);
+        if (bk == CH_NONE) {
+            f2 tn[2];
+            int nt = tangent_normals(q, C.a, C.r, tn);
+            for (int k = 0; k < nt; ++k) consider(tn[k], CH_TAN, 0);
+            if (seg) {
+                nt = tangent_normals(q, C.b, C.r, tn);
+                for (int k = 0; k < nt; ++k) consider(tn[k], CH_TAN, 1);
+            }
+            f2 t0 = sub(m, C.a);
+            if (dot(t0, t0) > 0.f) consider(scl(t0, inv_sqrt(dot(t0, t0))), CH_RADF, 0);
+            if (seg) {
+                f2 t1 = sub(m, C.b);
+                if (dot(t1, t1) > 0.f) consider(scl(t1, inv_sqrt(dot(t1, t1))), CH_RADF, 1);
+                consider(sw, CH_FLAT, 0);
+                consider(scl(sw, -1.f), CH_FLAT, 0);
+            }
         }
         f2 xm = (bg < INFINITY) ? add(m, scl(best, bg)) : m;
         x0 = i0 ? n0 : xm;
@@ -560,7 +596,12 @@ TWA_HD void capsule_finish(const Capsule C, f2 n0, f2 n1, float w0, float w1, f2
         consider(sw, CH_FLAT, 0);
         consider(scl(sw, -1.f), CH_FLAT, 0);
     }
-    // (b) nearest boundary point of one end while the other end is clear
+    // (b) nearest boundary point of one end while the other end is clear.
+    // When it exists it is the minimiser outright: every feasible
+    // configuration moves that end at least to the capsule's boundary, and
+    // this one moves nothing else.  It is taken without comparing F, which
+    // rounding decides wrongly when another candidate's direction lies
+    // within a few 1e-4 of it (F is stationary there) while its x differs.
     for (int e = 0; e < 2; ++e) {
         f2 n = e ? n1 : n0, other = e ? n0 : n1;
         float tpar = seg ? fminf(fmaxf(dot(sub(n, C.a), d) / L2, 0.f), 1.f) : 0.f;
@@ -568,9 +609,16 @@ TWA_HD void capsule_finish(const Capsule C, f2 n0, f2 n1, float w0, float w1, f2
         f2 t = sub(n, c);
         float tt = dot(t, t);
         if (tt > 0.f && tt < C.r * C.r) {
-            f2 u = scl(t, inv_sqrt(tt));
-            if (dot(other, u) >= cap_h(C, u))
-                consider(u, (tpar > 0.f && tpar < 1.f) ? CH_FLAT : (e ? CH_R1 : CH_R0), (seg && tpar >= 1.f) ? 1 : 0);
+            // against the flat side the normal is +-sw exactly (n - c is
+            // short and carries the rounding of c when n is near the segment)
+            const bool flat = seg && tpar > 0.f && tpar < 1.f;
+            f2 u = flat ? (dot(t, sw) >= 0.f ? sw : scl(sw, -1.f)) : scl(t, inv_sqrt(tt));
+            if (dot(other, u) >= cap_h(C, u)) {
+                best = u;
+                bk = flat ? CH_FLAT : (e ? CH_R1 : CH_R0);
+                bc = (seg && tpar >= 1.f) ? 1 : 0;
+                break;
+            }
         }
     }
     float h = cap_h(C, best);

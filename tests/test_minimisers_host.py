@@ -7,6 +7,7 @@ may choose differently) are counted and skipped.
 """
 import ctypes as ct
 import os
+import zlib
 import subprocess
 import tempfile
 
@@ -47,6 +48,11 @@ def _ref_lib():
     return L
 
 
+def _seed(*key):
+    """A fixed seed per parametrisation (hash() of strings changes per process)."""
+    return zlib.crc32(repr(key).encode())
+
+
 def _f32(a):
     return np.ascontiguousarray(np.asarray(a, np.float32))
 
@@ -82,6 +88,13 @@ def _close(a, b):
     return np.all(np.abs(a - b) <= TOL * np.maximum(np.abs(b), 1.0))
 
 
+def _sensitivity(fn, v, ref, draws=16):
+    """Largest change of fn's FP64 answer when every input moves by up to
+    one FP32 unit in the last place (relative 2^-24), over seeded draws."""
+    rng = np.random.default_rng(1)
+    return max(np.abs(fn(v * (1 + rng.uniform(-1, 1, v.shape) * 2.0 ** -24)) - ref).max() for _ in range(draws))
+
+
 WEIGHTS = {"std": ([1.0] * 4, [1] * 4), "inf_lo": ([0.0, 1.0, 0.0, 1.0], [2, 1, 2, 1]),
            "inf_hi": ([1.0, 0.0, 1.0, 0.0], [1, 2, 1, 2]), "unequal": (None, [1] * 4)}
 
@@ -90,9 +103,9 @@ WEIGHTS = {"std": ([1.0] * 4, [1] * 4), "inf_lo": ([0.0, 1.0, 0.0, 1.0], [2, 1, 
 @pytest.mark.parametrize("wmode", list(WEIGHTS))
 @pytest.mark.parametrize("scale", [1.0, 0.01])
 def test_coll_matches_reference(H, dim, wmode, scale):
-    rng = np.random.default_rng(hash((dim, wmode, scale)) % 2**32)
+    rng = np.random.default_rng(_seed(dim, wmode, scale))
     R = 0.5 * scale
-    checked = ties = 0
+    checked = ties = conditioned = 0
     for _ in range(3000):
         n = _f32(rng.normal(0, 0.4 * scale, size=(4, dim))).astype(np.float64)
         w, k = WEIGHTS[wmode]
@@ -112,17 +125,26 @@ def test_coll_matches_reference(H, dim, wmode, scale):
         x = np.zeros(4 * dim, np.float32)
         H.h_coll(dim, _f32(n.reshape(-1)).ctypes.data_as(_fp), _f32(w).ctypes.data_as(_fp),
                  np.ascontiguousarray(k, np.int32).ctypes.data_as(_i32), R, x.ctypes.data_as(_fp))
-        assert _close(x.astype(np.float64), xr), (n, w, k, x, xr)
+        ok = _close(x.astype(np.float64), xr)
+        if not ok:
+            # an ill-conditioned case: the FP32 minimiser rounds its inputs
+            # and a handful of intermediates, each about one unit in the last
+            # place, so it may differ by several times what one such
+            # perturbation of the inputs moves the FP64 answer by (8 allowed)
+            dev = _sensitivity(lambda m: ref_coll(m, wref, R)[1], n, xr)
+            ok = np.abs(x - xr).max() <= 8 * dev
+            conditioned += 1
+        assert ok, (n, w, k, x, xr)
         checked += 1
         if checked >= 300:
             break
-    assert checked >= 100 and ties <= 0.02 * checked
+    assert checked >= 100 and ties <= 0.02 * checked and conditioned <= 0.01 * checked
 
 
 @pytest.mark.parametrize("wmode", ["std", "inf0", "inf1", "unequal"])
 @pytest.mark.parametrize("scale", [1.0, 0.02])
 def test_capsule_matches_reference(H, wmode, scale):
-    rng = np.random.default_rng(hash((wmode, scale)) % 2**32)
+    rng = np.random.default_rng(_seed(wmode, scale))
     checked = ties = 0
     for _ in range(4000):
         r = float(np.float32(rng.uniform(0.05, 0.3) * scale))
@@ -189,7 +211,7 @@ def _vjp_close(g, want, tol=2e-4):
 @pytest.mark.parametrize("scale", [1.0, 0.01])
 def test_coll_vjp_matches_reference_differences(H, wmode, scale):
     H.h_coll_vjp.argtypes = [_fp, _fp, _i32, ct.c_float, _fp, _fp, _fp]
-    rng = np.random.default_rng(hash(("vjp", wmode, scale)) % 2**32)
+    rng = np.random.default_rng(_seed("vjp", wmode, scale))
     R = 0.5 * scale
     checked = 0
     for _ in range(4000):
@@ -230,7 +252,7 @@ def test_coll_vjp_matches_reference_differences(H, wmode, scale):
 @pytest.mark.parametrize("wmode", ["std", "inf0", "inf1", "unequal"])
 def test_capsule_vjp_matches_reference_differences(H, wmode):
     H.h_capsule_vjp.argtypes = [_fp, ct.c_float, _fp, ct.c_float, ct.c_float, ct.c_int, ct.c_int, _fp, _fp, _fp]
-    rng = np.random.default_rng(hash(("cvjp", wmode)) % 2**32)
+    rng = np.random.default_rng(_seed("cvjp", wmode))
     checked = 0
     for _ in range(6000):
         r = float(np.float32(rng.uniform(0.05, 0.3)))
@@ -343,7 +365,7 @@ def test_velocity_minimiser_matches_reference(H, minimum, wmode):
     H.h_vel.argtypes = [ct.c_int, _fp, _fp, ct.c_float, ct.c_float, ct.c_int, ct.c_int, ct.c_float, ct.c_int, _fp,
                         _fp]
     H.h_vel.restype = ct.c_int
-    rng = np.random.default_rng(hash(("vel", minimum, wmode)) % 2**32)
+    rng = np.random.default_rng(_seed("vel", minimum, wmode))
     for _ in range(300):
         dim = int(rng.choice([2, 3]))
         nl = _f32(rng.normal(0, 1, dim)).astype(np.float64)
