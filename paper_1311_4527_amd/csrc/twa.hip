@@ -1362,21 +1362,27 @@ constexpr int kTinyBlock = 512, kTinyChunk = 4096; // iterations per launch at m
 
 bool tiny(const twa_solver *s) { return s->P.Fc + s->P.Fw <= kTinyFactors; }
 
+// The device copy of a tiny instance's parameters that the persistent kernel
+// reads (at the steady rho0, no debug capture) and its one-bin layout; made
+// at create, so that iterating allocates and uploads nothing.
+twa_status prepare_tiny(twa_solver *s) {
+    Params c = s->P;
+    c.rho = c.rho_prev = s->rho0;
+    c.step = c.step_prev = s->alpha / s->rho0;
+    c.dbg_x = nullptr;
+    c.dbg_rho = nullptr;
+    const int bins[3] = {0, 1, 0}; // bin_start {0, 1}, bin_items {0}
+    TRY(dev_alloc(s, &s->tiny_params, 1));
+    TRY(dev_alloc(s, &s->tiny_bins, 3));
+    HIP_TRY(s, hipMemcpyAsync(s->tiny_params, &c, sizeof(Params), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(s->tiny_bins, bins, sizeof(bins), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream)); // the sources are on this stack
+    return TWA_OK;
+}
+
 // k iterations of a tiny instance at the steady rho0 (bitwise the plain
 // iterations: the same per-factor code).
 twa_status iterate_tiny(twa_solver *s, int k) {
-    if (!s->tiny_params) {
-        Params c = s->P;
-        c.rho = c.rho_prev = s->rho0;
-        c.step = c.step_prev = s->alpha / s->rho0;
-        c.dbg_x = nullptr;
-        c.dbg_rho = nullptr;
-        const int bins[3] = {0, 1, 0}; // bin_start {0, 1}, bin_items {0}
-        TRY(dev_alloc(s, &s->tiny_params, 1));
-        TRY(dev_alloc(s, &s->tiny_bins, 3));
-        HIP_TRY(s, hipMemcpyAsync(s->tiny_params, &c, sizeof(Params), hipMemcpyHostToDevice, s->stream));
-        HIP_TRY(s, hipMemcpyAsync(s->tiny_bins, bins, sizeof(bins), hipMemcpyHostToDevice, s->stream));
-    }
     while (k > 0) {
         const int n = std::min(k, kTinyChunk);
         hipLaunchKernelGGL(k_batch<kTinyBlock>, dim3(1), dim3(kTinyBlock), 0, s->stream,
@@ -1396,7 +1402,7 @@ twa_status iterate_impl(twa_solver *s, int k, bool timed) {
     const int tail = timed ? std::min(k, kTimedTail) : 0;
     // (steady rho0 throughout, the previous iteration's weights included)
     const bool settled = s->iter >= s->n_warm && (!s->pending || s->iter - 1 >= s->n_warm);
-    if (tiny(s) && k - tail > 0 && settled && !s->dbg_x) {
+    if (s->tiny_params && k - tail > 0 && settled && !s->dbg_x) {
         TRY(iterate_tiny(s, k - tail));
         k = tail;
     }
@@ -1785,6 +1791,10 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     }
     if (reset_state_buffers(s) != TWA_OK) return bail(TWA_E_DEVICE);
     if (save_origin(s) != TWA_OK) return bail(TWA_E_DEVICE);
+    if (tiny(s)) {
+        const twa_status st = prepare_tiny(s);
+        if (st != TWA_OK) return bail(st);
+    }
     if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(TWA_E_DEVICE);
     *out = s;
     return TWA_OK;
