@@ -150,10 +150,11 @@ twa_status twa_iterate(twa_solver *s, int k);
  * stream; synchronises and writes the device time in milliseconds of each
  * kernel summed over the k iterations to kernel_ms (host array of 3: factor
  * stream, queued minimisers, node consensus).  The last min(k, 4)
- * iterations are launched on their own with events around every kernel
- * (an event recorded on the stream slows every later launch of the call, so
- * the captured graph replays before them carry none); their mean times
- * stand for all k iterations. */
+ * iterations are launched on their own, every kernel with a start and a stop
+ * event attached to its dispatch (hipExtLaunchKernel), so each pair spans
+ * the kernel alone (an event recorded on the stream slows every later launch
+ * of the call, so the captured graph replays before them carry none); their
+ * mean times stand for all k iterations. */
 twa_status twa_iterate_timed(twa_solver *s, int k, double *kernel_ms);
 
 /* Current consensus positions z [p][eta+1][dim]. */

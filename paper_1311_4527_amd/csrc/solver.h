@@ -89,8 +89,8 @@ struct twa_solver {
     unsigned char *dbg_rho = nullptr;
     long long nblocks_stream = 0;
     int nblocks_queue = 0;
-    // event timing (twa_iterate_timed): 1 = a new event per mark, 2 = the
-    // preallocated events of the graph being captured
+    // event timing (twa_iterate_timed): 1 = kernels launched now take a
+    // start and a stop event from the pool
     std::vector<hipEvent_t> events; // kept for the solver's life and reused
     size_t events_used = 0;
     int timing = 0;

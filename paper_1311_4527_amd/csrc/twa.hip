@@ -26,6 +26,7 @@
 // Consensus sums are accumulated as exact 64-bit fixed-point integers with
 // atomics, so the result does not depend on the order of the additions.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -1232,21 +1233,33 @@ namespace {
 
 constexpr int kGraphIters = 32;
 // twa_iterate_timed times its last kTimedTail iterations, launched on their
-// own with events around their kernels: once an event is recorded on the
-// stream, every later launch of the same call runs slower (graph replays by
-// about a third), so no event comes before the untimed replays.
+// own, each kernel with a start and a stop event attached to its own dispatch
+// (hipExtLaunchKernel), so an event pair spans the kernel alone.  Once an
+// event is recorded on the stream, every later launch of the same call runs
+// slower (graph replays by about a third), so no event comes before the
+// untimed replays.
 constexpr int kTimedTail = 4;
 
-void mark(twa_solver *s, int slot) {
-    (void)slot;
-    if (s->timing == 1) {
-        if (s->events_used == s->events.size()) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return;
-            s->events.push_back(e);
-        }
-        (void)hipEventRecord(s->events[s->events_used++], s->stream);
+// Two events of the solver's pool for the next timed kernel (false: none).
+bool take_events(twa_solver *s, hipEvent_t *e0, hipEvent_t *e1) {
+    while (s->events.size() < s->events_used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return false;
+        s->events.push_back(e);
     }
+    *e0 = s->events[s->events_used++];
+    *e1 = s->events[s->events_used++];
+    return true;
+}
+
+// Launch one kernel on the solver's stream; while timing, with events.
+template <typename Kern, typename... Args>
+void launch(twa_solver *s, Kern kernel, dim3 grid, dim3 block, Args... args) {
+    hipEvent_t e0, e1;
+    if (s->timing == 1 && take_events(s, &e0, &e1))
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s->stream, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s->stream, args...);
 }
 
 
@@ -1274,38 +1287,27 @@ twa_status to_host(twa_solver *s, std::vector<T> &dst, const T *src, size_t coun
 }
 
 
-void mark(twa_solver *s, int slot);
-
 template <int D>
 twa_status launch_iteration(twa_solver *s, int mode) {
     Params P = s->P;
-    long long g = s->nblocks_stream;
-    int gq = s->nblocks_queue;
+    const dim3 g((unsigned)s->nblocks_stream), gq(s->nblocks_queue), gn((unsigned)((P.N + kBlock - 1) / kBlock));
     if (mode == M_FIRST) {
-        mark(s, 0);
-        if (P.dense) hipLaunchKernelGGL((k_stream<D, M_FIRST, true>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
-        else hipLaunchKernelGGL((k_stream<D, M_FIRST, false>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
-        mark(s, 1);
-        hipLaunchKernelGGL((k_queue<D, M_FIRST>), dim3(gq), dim3(64), 0, s->stream, P);
-        mark(s, 2);
+        if (P.dense) launch(s, k_stream<D, M_FIRST, true>, g, dim3(kBlock), P);
+        else launch(s, k_stream<D, M_FIRST, false>, g, dim3(kBlock), P);
+        launch(s, k_queue<D, M_FIRST>, gq, dim3(64), P);
     } else if (mode == M_FUSED) {
-        mark(s, 0);
-        if (P.dense) hipLaunchKernelGGL((k_stream<D, M_FUSED, true>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
-        else hipLaunchKernelGGL((k_stream<D, M_FUSED, false>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
-        mark(s, 1);
-        hipLaunchKernelGGL((k_queue<D, M_FUSED>), dim3(gq), dim3(64), 0, s->stream, P);
-        mark(s, 2);
+        if (P.dense) launch(s, k_stream<D, M_FUSED, true>, g, dim3(kBlock), P);
+        else launch(s, k_stream<D, M_FUSED, false>, g, dim3(kBlock), P);
+        launch(s, k_queue<D, M_FUSED>, gq, dim3(64), P);
     } else {
-        if (P.dense) hipLaunchKernelGGL((k_stream<D, M_FINAL, true>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
-        else hipLaunchKernelGGL((k_stream<D, M_FINAL, false>), dim3((unsigned)g), dim3(kBlock), 0, s->stream, P);
-        hipLaunchKernelGGL((k_queue<D, M_FINAL>), dim3(gq), dim3(64), 0, s->stream, P);
+        if (P.dense) hipLaunchKernelGGL((k_stream<D, M_FINAL, true>), g, dim3(kBlock), 0, s->stream, P);
+        else hipLaunchKernelGGL((k_stream<D, M_FINAL, false>), g, dim3(kBlock), 0, s->stream, P);
+        hipLaunchKernelGGL((k_queue<D, M_FINAL>), gq, dim3(64), 0, s->stream, P);
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s->stream, P);
         HIP_TRY(s, hipGetLastError());
         return TWA_OK;
     }
-    unsigned nb = (unsigned)((P.N + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_nodes<D>), dim3(nb), dim3(kBlock), 0, s->stream, P);
-    mark(s, 3);
+    launch(s, k_nodes<D>, gn, dim3(kBlock), P);
     HIP_TRY(s, hipGetLastError());
     return TWA_OK;
 }
@@ -1842,12 +1844,13 @@ twa_status twa_iterate_timed(twa_solver *s, int k, double *kernel_ms) {
     double acc[3] = {0, 0, 0};
     twa_status st = iterate_impl(s, k, true);
     hipError_t e = hipStreamSynchronize(s->stream);
-    // timed iterations: four marks each (before stream, queue, nodes; after nodes)
+    // timed iterations: a start and a stop event for each of the three kernels
     long long timed = 0;
-    for (size_t q = 0; q + 3 < s->events_used && e == hipSuccess; q += 4, ++timed) {
+    for (size_t q = 0; q + 5 < s->events_used && e == hipSuccess; q += 6, ++timed) {
         for (int kk = 0; kk < 3; ++kk) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, s->events[q + kk], s->events[q + kk + 1]) == hipSuccess) acc[kk] += ms;
+            if (hipEventElapsedTime(&ms, s->events[q + 2 * kk], s->events[q + 2 * kk + 1]) == hipSuccess)
+                acc[kk] += ms;
         }
     }
     s->events_used = 0;
