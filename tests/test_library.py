@@ -94,3 +94,40 @@ def test_create_rejects_flag_combinations(lib):
         st = lib.twa_create(4, eta, 2, dummy, dummy, dummy, 0, None, dummy, ct.c_float(1.0), ct.c_float(0.1), flags,
                             None, ct.byref(out))
         assert st == 1 and not out.value
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures the one-GPU hot path; --gpus above 1 exits with
+    a message instead of timing anything."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
+
+
+def test_bench_traffic_digest_tracks_the_sources(tmp_path, monkeypatch):
+    """Counter-based traffic is reported only for the kernel sources it was
+    taken on: any change to the code (comments aside) turns it off."""
+    import importlib
+    import shutil
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    bench = importlib.import_module("bench")
+    d = bench.kernel_sources_digest()
+    for rel in bench.KERNEL_SOURCES:
+        dst = tmp_path / rel
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        shutil.copy(os.path.join(root, rel), dst)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.kernel_sources_digest() == d
+    p = tmp_path / bench.KERNEL_SOURCES[0]
+    p.write_text(p.read_text() + "\n// a comment changes nothing\n")
+    assert bench.kernel_sources_digest() == d
+    p.write_text(p.read_text() + "\nstatic int twa_extra_symbol;\n")
+    assert bench.kernel_sources_digest() != d
+    for variant in bench.MEASURED_TRAFFIC:
+        assert bench.measured_traffic(variant) is None
