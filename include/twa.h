@@ -178,6 +178,22 @@ twa_status twa_capture_next(twa_solver *s, float *x_out, unsigned char *rho_out)
 /* Counters of the last iteration (host struct; synchronises the stream). */
 twa_status twa_get_stats(twa_solver *s, twa_stats *out);
 
+/* Measures of the current break-points z, in double precision from the FP32
+ * positions (host pointers, any may be NULL; synchronises the stream):
+ *   objective      sum over agents i and intervals s of C[i][s] |z_i(s+1) -
+ *                  z_i(s)|^2, the energy cost of Sec. 3.1 (evaluated with the
+ *                  create-time C whatever the cost mode);
+ *   min_clearance  the smallest of: closest approach of agents i and j moving
+ *                  at constant velocity over an interval minus r_i + r_j
+ *                  (Sec. 2), over every pair and interval; distance of agent
+ *                  i's interval segment to a wall minus r_i (Sec. 3.2, planar)
+ *                  over every interval and wall; +infinity with neither;
+ *   max_move       the largest distance a break-point moved in the last
+ *                  iteration (0 after create, set_init or set_state).
+ * Computed on the device; allocates nothing (its 24-byte buffer is made at
+ * create). */
+twa_status twa_get_quality(twa_solver *s, double *objective, double *min_clearance, double *max_move);
+
 /* Sizes: factors and edges in canonical order (host pointers). */
 twa_status twa_sizes(const twa_solver *s, long long *n_factors, long long *n_edges);
 

@@ -81,6 +81,7 @@ struct twa_solver {
     hipStream_t stream = nullptr;
     twa_rt::Params P{};
     int *stats_dev = nullptr;
+    double *quality_dev = nullptr; // twa_get_quality: objective, largest move, clearance key
     int *bad_dev = nullptr;
     std::vector<void *> allocs;
     std::string err;

@@ -1147,6 +1147,119 @@ __global__ void k_z_export(const float4 *zr, float *z, unsigned char *lrho, int 
     }
     if (lrho) lrho[t] = (unsigned char)(int)r.w;
 }
+
+// ------------------------------------------------------------------ quality
+// Measures of the current break-points z, in double precision from the FP32
+// node records: the energy objective sum C_is |z_i(s+1) - z_i(s)|^2 (Sec. 3.1),
+// the smallest clearance over every pair and interval (closest approach of
+// the two constant-velocity agents minus r_i + r_j, Sec. 2) and over every
+// interval and wall (segment distance minus r_i, Sec. 3.2), and the largest
+// move of a break-point in the last iteration.
+
+// unsigned key whose order is the order of the doubles (for atomicMin)
+__device__ __forceinline__ unsigned long long order_key(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// one workgroup of 1024 lanes: objective and largest move, reduced in a
+// fixed order; also arms the clearance minimum for k_quality_clearance
+__global__ __launch_bounds__(1024) void k_quality_sums(const float4 *zr, const float4 *zp, const float *C, int p,
+                                                       int eta, double *out, unsigned long long *min_key) {
+    __shared__ double part[2][1024];
+    double obj = 0.0, mv = 0.0;
+    const long long S = (long long)p * eta, N = (long long)p * (eta + 1);
+    for (long long t = threadIdx.x; t < S; t += 1024) {
+        const int i = (int)(t / eta), s = (int)(t % eta);
+        const float4 a = zr[(long long)s * p + i], b = zr[(long long)(s + 1) * p + i];
+        const double dx = (double)b.x - a.x, dy = (double)b.y - a.y, dz = (double)b.z - a.z;
+        obj += (double)C[t] * (dx * dx + dy * dy + dz * dz);
+    }
+    for (long long nd = threadIdx.x; nd < N; nd += 1024) {
+        const float4 a = zr[nd], b = zp[nd];
+        const double dx = (double)a.x - b.x, dy = (double)a.y - b.y, dz = (double)a.z - b.z;
+        mv = fmax(mv, sqrt(dx * dx + dy * dy + dz * dz));
+    }
+    part[0][threadIdx.x] = obj;
+    part[1][threadIdx.x] = mv;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            part[0][threadIdx.x] += part[0][threadIdx.x + h];
+            part[1][threadIdx.x] = fmax(part[1][threadIdx.x], part[1][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = part[0][0];
+        out[1] = part[1][0];
+        *min_key = order_key(INFINITY);
+    }
+}
+
+// squared distance from q to the segment [a, b] (planar)
+__device__ __forceinline__ double pt_seg2(double qx, double qy, double ax, double ay, double bx, double by) {
+    const double ex = bx - ax, ey = by - ay, ee = ex * ex + ey * ey;
+    double t = 0.0;
+    if (ee > 0.0) t = fmin(fmax(((qx - ax) * ex + (qy - ay) * ey) / ee, 0.0), 1.0);
+    const double vx = qx - (ax + t * ex), vy = qy - (ay + t * ey);
+    return vx * vx + vy * vy;
+}
+
+// twice the signed area of (a, b, c)
+__device__ __forceinline__ double cross3(double ax, double ay, double bx, double by, double cx, double cy) {
+    return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+}
+
+// rows (s, i) of the pair triangle, one per workgroup pass; lanes over j > i
+// and over the walls; one atomicMin per workgroup
+__global__ __launch_bounds__(256) void k_quality_clearance(const float4 *zr, const float *radii, const float4 *walls,
+                                                           int p, int eta, int W, int dim,
+                                                           unsigned long long *min_key) {
+    __shared__ double wmin[4];
+    double best = INFINITY;
+    const long long rows = (long long)p * eta;
+    for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int s = (int)(row / p), i = (int)(row % p);
+        const float4 ai = zr[(long long)s * p + i], bi = zr[(long long)(s + 1) * p + i];
+        const double ri = radii[i];
+        for (int j = i + 1 + (int)threadIdx.x; j < p; j += 256) {
+            const float4 aj = zr[(long long)s * p + j], bj = zr[(long long)(s + 1) * p + j];
+            // relative position at the interval's ends; closest approach over the interval
+            const double d0x = (double)aj.x - ai.x, d0y = (double)aj.y - ai.y, d0z = (double)aj.z - ai.z;
+            const double ex = ((double)bj.x - bi.x) - d0x, ey = ((double)bj.y - bi.y) - d0y,
+                         ez = ((double)bj.z - bi.z) - d0z;
+            const double ee = ex * ex + ey * ey + ez * ez;
+            double a = 0.0;
+            if (ee > 0.0) a = fmin(fmax(-(d0x * ex + d0y * ey + d0z * ez) / ee, 0.0), 1.0);
+            const double vx = d0x + a * ex, vy = d0y + a * ey, vz = d0z + a * ez;
+            best = fmin(best, sqrt(vx * vx + vy * vy + vz * vz) - (ri + (double)radii[j]));
+        }
+        if (dim == 2) {
+            for (int w = (int)threadIdx.x; w < W; w += 256) {
+                const float4 wl = walls[w];
+                const double px = ai.x, py = ai.y, qx = bi.x, qy = bi.y;
+                const double o1 = cross3(px, py, qx, qy, wl.x, wl.y), o2 = cross3(px, py, qx, qy, wl.z, wl.w);
+                const double o3 = cross3(wl.x, wl.y, wl.z, wl.w, px, py), o4 = cross3(wl.x, wl.y, wl.z, wl.w, qx, qy);
+                double d2;
+                if (o1 * o2 < 0.0 && o3 * o4 < 0.0) {
+                    d2 = 0.0; // proper crossing
+                } else {
+                    d2 = fmin(fmin(pt_seg2(px, py, wl.x, wl.y, wl.z, wl.w), pt_seg2(qx, qy, wl.x, wl.y, wl.z, wl.w)),
+                              fmin(pt_seg2(wl.x, wl.y, px, py, qx, qy), pt_seg2(wl.z, wl.w, px, py, qx, qy)));
+                }
+                best = fmin(best, sqrt(d2) - ri);
+            }
+        }
+    }
+    for (int d = 32; d >= 1; d >>= 1) best = fmin(best, __shfl_xor(best, d));
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double m = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+        atomicMin(min_key, order_key(m));
+    }
+}
 // u: canonical [E][dim] <-> per-kind layouts.  dir 0: import, 1: export
 __global__ void k_u_convert(Params P, float *u, int D, int dir) {
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1709,7 +1822,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         dev_alloc(s, &P.x_wall, (size_t)std::max<long long>(1, Fw)) ||
         dev_alloc(s, &wbc_d, (size_t)std::max<long long>(1, (Fc + 63) / 64)) ||
         dev_alloc(s, &wbw_d, (size_t)std::max<long long>(1, (Fw + 63) / 64)) ||
-        dev_alloc(s, &s->stats_dev, 4) || dev_alloc(s, &s->bad_dev, 1))
+        dev_alloc(s, &s->stats_dev, 4) || dev_alloc(s, &s->bad_dev, 1) || dev_alloc(s, &s->quality_dev, 3))
         return bail(TWA_E_NOMEM);
     unsigned long long *chunk_d;
     int *rowchunk_d;
@@ -1912,6 +2025,30 @@ twa_status twa_get_stats(twa_solver *s, twa_stats *out) {
     out->active_coll = h[0];
     out->active_wall = h[1];
     out->queued = h[2];
+    return TWA_OK;
+}
+
+twa_status twa_get_quality(twa_solver *s, double *objective, double *min_clearance, double *max_move) {
+    TRY(check_alive(s));
+    const Params &P = s->P;
+    unsigned long long *min_key = reinterpret_cast<unsigned long long *>(s->quality_dev + 2);
+    hipLaunchKernelGGL(k_quality_sums, dim3(1), dim3(1024), 0, s->stream, (const float4 *)P.zr_cur,
+                       (const float4 *)P.zr_prev, P.C, s->p, s->eta, s->quality_dev, min_key);
+    const long long rows = (long long)s->p * s->eta;
+    hipLaunchKernelGGL(k_quality_clearance, dim3((unsigned)std::min<long long>(rows, 8192)), dim3(256), 0, s->stream,
+                       (const float4 *)P.zr_cur, P.radii, P.walls, s->p, s->eta, s->W, s->dim, min_key);
+    HIP_TRY(s, hipGetLastError());
+    double h[3];
+    HIP_TRY(s, hipMemcpyAsync(h, s->quality_dev, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    unsigned long long k;
+    std::memcpy(&k, &h[2], sizeof(k));
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    double m;
+    std::memcpy(&m, &b, sizeof(m));
+    if (objective) *objective = h[0];
+    if (max_move) *max_move = h[1];
+    if (min_clearance) *min_clearance = m;
     return TWA_OK;
 }
 

@@ -77,6 +77,8 @@ def load_library():
     lib.twa_get_stats.argtypes = [_vp, ct.POINTER(_Stats)]
     lib.twa_sizes.restype = ct.c_int
     lib.twa_sizes.argtypes = [_vp, ct.POINTER(ct.c_longlong), ct.POINTER(ct.c_longlong)]
+    lib.twa_get_quality.restype = ct.c_int
+    lib.twa_get_quality.argtypes = [_vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
     lib.twa_check_finite.restype = ct.c_int
     lib.twa_check_finite.argtypes = [_vp]
     lib.twa_backward.restype = ct.c_int
@@ -226,6 +228,13 @@ class Solver:
         s = _Stats()
         self._check(load_library().twa_get_stats(self.h, ct.byref(s)))
         return dict(iter=s.iter, active_coll=s.active_coll, active_wall=s.active_wall, queued=s.queued)
+
+    def twa_get_quality(self) -> dict:
+        """Energy objective, smallest clearance and largest last move of the
+        current break-points, computed on the device (synchronises)."""
+        o, c, m = ct.c_double(), ct.c_double(), ct.c_double()
+        self._check(load_library().twa_get_quality(self.h, ct.byref(o), ct.byref(c), ct.byref(m)))
+        return dict(objective=o.value, min_clearance=c.value, max_move=m.value)
 
     def twa_check_finite(self):
         self._check(load_library().twa_check_finite(self.h))
