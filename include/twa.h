@@ -191,7 +191,8 @@ twa_status twa_get_stats(twa_solver *s, twa_stats *out);
  *   max_move       the largest distance a break-point moved in the last
  *                  iteration (0 after create, set_init or set_state).
  * Computed on the device; allocates nothing (its 24-byte buffer is made at
- * create). */
+ * create).  Non-finite positions drop out of the minimum and the maximum
+ * (twa_check_finite reports them). */
 twa_status twa_get_quality(twa_solver *s, double *objective, double *min_clearance, double *max_move);
 
 /* Sizes: factors and edges in canonical order (host pointers). */
