@@ -179,3 +179,30 @@ def test_full_size_adjoint_runs_and_is_linear():
         scale = max(np.abs(c).max(), 1e-12)
         assert np.abs(a + 2 * b - c).max() <= 1e-4 * scale
     S.close()
+
+
+@pytest.mark.parametrize("case", ["swap100", "box64_walls", "swap8_tiny"])
+@pytest.mark.parametrize("flags", [0, 1])
+def test_reading_the_state_leaves_the_run_unchanged(case, flags):
+    """The reverse sweep recomputes each segment reading the state after every
+    iteration (twa_get_state settles the deferred u update, and the next
+    iteration starts afresh); the states it linearises about must be the
+    forward run's own, bit for bit."""
+    import torch
+    from paper_1311_4527_amd.twa import Solver
+    inst = {"swap100": lambda: I.conf_swap100(0),
+            "box64_walls": lambda: I.conf_box1024(seed=9, p=64, eta=8, n_walls=4),
+            "swap8_tiny": lambda: I.conf_small(0)}[case]()
+    A = Solver.from_instance(inst, flags=flags)
+    B = Solver.from_instance(inst, flags=flags)
+    A.twa_iterate(100)
+    for _ in range(100):
+        B.twa_iterate(1)
+        B.twa_get_state()
+    za, ua, la, ia = A.twa_get_state()
+    zb, ub, lb, ib = B.twa_get_state()
+    torch.cuda.synchronize()
+    assert ia == ib == 100
+    assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb)
+    A.close()
+    B.close()
