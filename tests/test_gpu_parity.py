@@ -279,3 +279,17 @@ def test_parity_large_box_one_iteration(flags):
     P.iterate(8)
     z, u, lr = P.get_state()
     one_iteration_parity(inst, z, u, lr, 8, solver=S)
+
+
+@pytest.mark.parametrize("flags", [1, 0])
+def test_parity_many_agents_one_iteration(flags):
+    """4096 agents, eta = 3, four short walls: 25.2 M collision factors, past
+    2^24 factor indices and 4x the 1024-agent box's agent count (pair rows,
+    chunk tables and queue entries at their larger sizes), element-wise
+    against the reference from the straight-line state."""
+    inst = I.random_box(4096, 0.002, 3, n_walls=4, min_sep=0.005, wall_len=(0.01, 0.03), seed=77)
+    assert inst.counts()["coll"] > 2 ** 24
+    P = O.Planner(inst)
+    z, u, lr = P.get_state()
+    del P
+    one_iteration_parity(inst, z, u, lr, 0, flags=flags)
