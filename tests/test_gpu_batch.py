@@ -94,3 +94,29 @@ def test_autotuner_picks_a_candidate(tmp_path, monkeypatch):
     b, g = AT.tune(B, iters=3, log=log)
     assert (b, g) in AT.candidates(10) and len(log) == len(AT.candidates(10))
     assert AT.tune(B, iters=3) == (b, g)   # cached
+
+
+@pytest.mark.parametrize("block,groups,flags", [(256, 3, 0), (1024, 1, 1), (0, 1, 0), (0, 1, 1)])
+def test_batch_with_degenerate_members(block, groups, flags):
+    """Members with no collision factor (one agent), one interval (eta = 1),
+    two agents, a 3-D triple and a long-row box with walls, in one batch:
+    each evolves bitwise as in its own solver."""
+    import torch
+    from paper_1311_4527_amd.twa import Batch, Solver
+    insts = [I.conf_box1024(seed=3, p=1, eta=1, n_walls=2), I.circle_swap(1, 0.05, 5, seed=1),
+             I.circle_swap(2, 0.05, 1, seed=2), I.circle_swap(3, 0.05, 2, dim=3, seed=3),
+             I.conf_box1024(seed=4, p=70, eta=4, n_walls=3), I.conf_small(0)]
+    B = Batch(insts, flags=flags)
+    B.twa_batch_config(block, groups)
+    B.twa_batch_iterate(30)
+    B.twa_batch_iterate(7)
+    for i, inst in enumerate(insts):
+        S = Solver.from_instance(inst, flags=flags)
+        S.twa_iterate(37)
+        a, b = B.twa_batch_get_trajectories(i), S.twa_get_trajectories()
+        assert torch.equal(a, b), (i, inst.name, (a - b).abs().max().item())
+        za, ua, la, ka = B.twa_batch_solver(i).twa_get_state()
+        zb, ub, lb, kb = S.twa_get_state()
+        assert ka == kb == 37 and torch.equal(ua, ub) and torch.equal(la, lb)
+        S.close()
+    B.close()
