@@ -67,6 +67,10 @@ def workload(name):
         return I.conf_swap100(0)
     if name == "swap8":
         return I.conf_small(0)
+    if name == "single1":
+        # one agent in free space from a noisy start (eta=8): the optimum is
+        # the straight line between its end points
+        return I.circle_swap(1, 0.1, 8, sigma=0.3, seed=1, alpha=1.0, C=1.0, name="single1_eta8_s1")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -398,7 +402,7 @@ def cpu_baseline(inst, budget_s=12.0):
                       f"instance from its straight-line start, {dt:.1f} s wall")
     # the two small circle swaps, beside the GPU's small_workloads leg
     small = {}
-    for name, K in (("swap8", 2000), ("swap100", 100)):
+    for name, K in (("swap8", 2000), ("swap100", 100), ("single1", 200)):
         si = workload(name)
         Ps = O.Planner(si)
         t0 = time.perf_counter()
@@ -429,6 +433,22 @@ def run_small(warmup=50):
                          factor_updates_per_s=inst.counts()["factors"] * K / dt,
                          objective=objective(inst, S.twa_get_trajectories().cpu().numpy()))
         S.close()
+    # one agent in free space, 200 iterations from a fresh solver (the
+    # convergence run the paper times on its own single-agent example)
+    import numpy as np
+    inst = workload("single1")
+    S = Solver.from_instance(inst)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.twa_iterate(200)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    z = S.twa_get_trajectories().cpu().numpy().astype(np.float64)
+    s = np.arange(inst.eta + 1) / inst.eta
+    line = inst.x0[:, None, :] + s[None, :, None] * (inst.xT - inst.x0)[:, None, :]
+    out["single1"] = dict(p=1, eta=inst.eta, iterations=200, ms=dt * 1e3, iterations_per_s=200 / dt,
+                          max_distance_to_line=float(np.abs(z - line).max()))
+    S.close()
     return out
 
 
