@@ -66,3 +66,11 @@ def test_admm_batch_equals_plain(block):
         S = Solver.from_instance(inst, flags=_flags())
         S.twa_iterate(30)
         assert torch.equal(B.twa_batch_get_trajectories(i), S.twa_get_trajectories())
+
+
+def test_admm_one_iteration_parity_many_chunks():
+    """150 agents with walls: rows of the pair triangle span up to three
+    64-pair chunks plus a ragged tail, in ADMM's dense layout."""
+    inst = I.random_box(150, 0.01, 6, n_walls=8, sigma=1e-2, seed=12, alpha=0.1, C=1 / 900)
+    for k, z, u, lr in _reference_states(inst, [0, 4, 40], mode=O.MODE_ADMM):
+        one_iteration_parity(inst, z, u, lr, k, flags=_flags(), mode=O.MODE_ADMM)

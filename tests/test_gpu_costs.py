@@ -97,3 +97,17 @@ def test_batch_equals_plain_with_velocity_limits(block):
         S = Solver.from_instance(inst, flags=_flag(O.COST_MAXVEL))
         S.twa_iterate(40)
         assert torch.equal(B.twa_batch_get_trajectories(i), S.twa_get_trajectories())
+
+
+@pytest.mark.parametrize("cost,factor", CASES)
+@pytest.mark.parametrize("dense", [0, 1])
+def test_one_iteration_parity_many_chunks(cost, factor, dense):
+    """140 agents with walls (multi-chunk rows and a ragged tail) for each
+    per-segment factor, both layouts."""
+    from paper_1311_4527_amd.twa import TWA_F_DENSE
+    inst = I.random_box(140, 0.01, 5, n_walls=6, sigma=1e-2, seed=21, alpha=0.1, C=1.0)
+    if factor is not None:
+        _limited(inst, factor)
+    flags = _flag(cost) | (TWA_F_DENSE if dense else 0)
+    for k, z, u, lr in _reference_states(inst, [0, 6, 50], cost=cost):
+        one_iteration_parity(inst, z, u, lr, k, flags=flags, cost=cost)

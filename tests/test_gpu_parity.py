@@ -118,6 +118,14 @@ def test_parity_3d(dim):
         one_iteration_parity(box, z, u, lr, k, 1)
 
 
+@pytest.mark.parametrize("flags", [0, 1])
+def test_parity_3d_many_chunks(flags):
+    """200 agents in 3-D (multi-chunk rows, a ragged tail of 8), both layouts."""
+    inst = I.random_box(200, 0.01, 6, dim=3, sigma=1e-2, seed=13, alpha=0.1, C=1 / 1200)
+    for k, z, u, lr in _reference_states(inst, [0, 6, 40]):
+        one_iteration_parity(inst, z, u, lr, k, flags)
+
+
 def test_parity_random_states():
     """Synthetic states (random u on random factors) exercise minimiser
     branches the trajectories above may not reach."""
