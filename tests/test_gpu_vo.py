@@ -32,6 +32,19 @@ def test_vo_one_iteration_parity():
         one_iteration_parity(inst, z, u, lr, k, flags=_flags(), cost=O.COST_VO)
 
 
+def test_vo_one_iteration_parity_many_agents():
+    """150 agents (eta = 1, so the column walk over 64-pair chunks with a
+    ragged tail) heading inwards until neighbours come into contact."""
+    p, r = 150, 0.007
+    rng = np.random.default_rng(3)
+    ang = 2 * np.pi * np.arange(p) / p + rng.normal(0, 1e-3, p)  # spacing 0.0167 > 2r at the start
+    pos = np.stack([np.cos(ang), np.sin(ang)], 1) * 0.4
+    xref = pos * 0.75 + rng.normal(0, 1e-3, (p, 2))  # spacing 0.0126 < 2r at the references
+    inst = _vo_epoch_instance(pos, xref, np.full(p, r), 0.1 * (1 + 0.001 * np.arange(p)))
+    for k, z, u, lr in _reference_states(inst, [0, 5, 60], cost=O.COST_VO):
+        one_iteration_parity(inst, z, u, lr, k, flags=_flags(), cost=O.COST_VO)
+
+
 def test_vo_one_iteration_parity_walls():
     x0 = np.array([[0.2, 0.2], [0.8, 0.2], [0.5, 0.8]])
     xref = np.array([[0.8, 0.5], [0.2, 0.5], [0.5, 0.3]])
