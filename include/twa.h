@@ -104,6 +104,12 @@ typedef struct {
     long long active_coll;   /* collision factors with weight rho0, last iteration */
     long long active_wall;   /* wall factors with weight rho0, last iteration */
     long long queued;        /* factors that went through a full minimiser, last iteration */
+    double residual;         /* primal residual of the last iteration: max |x - z| over the edges
+                                whose u it updated (both weights rho0, App. B step 7); 0 when no
+                                iteration ran since the state was set */
+    double objective;        /* energy objective of z, as twa_get_quality */
+    double min_clearance;    /* smallest clearance of z, as twa_get_quality */
+    long long graph_iterations; /* iterations run so far from replayed HIP graphs */
 } twa_stats;
 
 /*
@@ -120,7 +126,12 @@ typedef struct {
  *   rho0 > 0           standard weight; alpha > 0 step (App. B step 7 uses
  *                      alpha/rho0).
  *   flags              TWA_F_* above.
- *   hip_stream         hipStream_t on which every call runs (NULL = default).
+ *   hip_stream         hipStream_t on which every call runs.  NULL: the solver
+ *                      makes its own stream with the default flags, which
+ *                      orders itself with the null stream both ways (work the
+ *                      caller queues on the null stream before or after a call
+ *                      stays in order) and, unlike the null stream, can be
+ *                      captured into the graphs twa_iterate replays.
  * Starts must be pairwise >= r_i + r_j apart, and so must goals; no start or
  * goal may lie within r_i of a wall (TWA_E_INFEASIBLE otherwise; overlaps up
  * to 1e-5 relative, the rounding of positions left in contact, are accepted).
@@ -141,15 +152,16 @@ twa_status twa_set_init(twa_solver *s, const float *z);
 twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm);
 
 /* Run k >= 0 iterations (App. B steps 1-7), asynchronously.  Iterations at
- * the steady rho0 are replayed from a HIP graph of 32; an instance of at most
- * 256 collision + wall factors runs them in one persistent single-workgroup
- * launch instead (bitwise the same iterations). */
+ * the steady rho0 are replayed from HIP graphs of 32, 16, ..., 1 iterations
+ * (captured together the first time, so any k replays); an instance of at
+ * most 256 collision + wall factors runs them in one persistent
+ * single-workgroup launch instead (bitwise the same iterations). */
 twa_status twa_iterate(twa_solver *s, int k);
 
 /* As twa_iterate, and times the kernels with HIP events on the solver's
  * stream; synchronises and writes the device time in milliseconds of each
  * kernel summed over the k iterations to kernel_ms (host array of 3: factor
- * stream, queued minimisers, node consensus).  The last min(k, 4)
+ * stream, queued minimisers, node consensus).  The last min(k, 2)
  * iterations are launched on their own, every kernel with a start and a stop
  * event attached to its dispatch (hipExtLaunchKernel), so each pair spans
  * the kernel alone (an event recorded on the stream slows every later launch
@@ -175,7 +187,11 @@ twa_status twa_set_state(twa_solver *s, const float *z, const float *u, const un
  * until that iteration has run. */
 twa_status twa_capture_next(twa_solver *s, float *x_out, unsigned char *rho_out);
 
-/* Counters of the last iteration (host struct; synchronises the stream). */
+/* Counters and measures of the last iteration (host struct; synchronises
+ * the stream).  Settles the pending u update of the last iteration (the next
+ * iteration is bitwise the same either way).  Returns TWA_E_NUMERIC, with the
+ * struct filled, when a consensus sum left its fixed-point range since the
+ * state was set (see twa_check_finite). */
 twa_status twa_get_stats(twa_solver *s, twa_stats *out);
 
 /* Measures of the current break-points z, in double precision from the FP32
@@ -198,8 +214,19 @@ twa_status twa_get_quality(twa_solver *s, double *objective, double *min_clearan
 /* Sizes: factors and edges in canonical order (host pointers). */
 twa_status twa_sizes(const twa_solver *s, long long *n_factors, long long *n_edges);
 
-/* Scan z and u for NaN/Inf (synchronises): TWA_E_NUMERIC if any. */
+/* Scan z and u for NaN/Inf (synchronises): TWA_E_NUMERIC if any, or if a
+ * consensus contribution since the state was last set (create, set_init,
+ * set_state) was non-finite or beyond the fixed-point range of the node sums
+ * (see twa_consensus_scale): the iterates diverged and z may be wrong. */
 twa_status twa_check_finite(twa_solver *s);
+
+/* The fixed-point scale of the consensus sums that twa_create picks for p
+ * agents, n_walls walls and coordinates of magnitude at most coord_max (>= 1;
+ * twa_create uses the largest |coordinate| of starts, goals and walls, at
+ * least 1), and the largest |m| one edge may contribute before the overflow
+ * flag of twa_check_finite is raised.  Host only (no device needed):
+ * TWA_E_INVALID on bad arguments. */
+twa_status twa_consensus_scale(int p, int n_walls, double coord_max, double *scale, double *limit);
 
 /*
  * Reverse-mode gradient of a loss L(z^K) of the trajectories after the run

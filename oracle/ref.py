@@ -66,6 +66,14 @@ def _load():
     lib.tor_iterate.argtypes = [ct.c_void_p, ct.c_long]
     lib.tor_get_margins.restype = None
     lib.tor_get_margins.argtypes = [ct.c_void_p, _dp, _dp]
+    lib.tor_override_next.restype = None
+    lib.tor_override_next.argtypes = [ct.c_void_p, ct.c_long, ct.POINTER(ct.c_long), _dp, _u8]
+    lib.tor_prox_capsule_gap.restype = ct.c_int
+    lib.tor_prox_capsule_gap.argtypes = [_dp, _dp, ct.c_double, _dp, _dp, ct.c_double, ct.c_double, _dp, _dp,
+                                         _ip, _dp, _dp]
+    lib.tor_prox_coll_gap.restype = ct.c_int
+    lib.tor_prox_coll_gap.argtypes = [_dp, _dp, _dp, _dp, ct.c_double, ct.c_double, ct.c_double, ct.c_double,
+                                      ct.c_double, ct.c_int, _dp, _dp, _dp, _dp, _ip, _dp, _dp]
     lib.tor_tape.restype = ct.c_long
     lib.tor_tape.argtypes = [ct.c_void_p, ct.c_long]
     lib.tor_backward.restype = None
@@ -156,6 +164,35 @@ def prox_coll(nl, nh, nlp, nhp, wl, wh, wlp, whp, R):
     return (bool(act), *outs, kind.value, th.value)
 
 
+def prox_capsule_gap(xL, xR, r, n0, n1, w0, w1) -> float:
+    """Relative energy gap between the agent-wall minimiser's chosen
+    configuration and the best distinct runner-up candidate (inf when the
+    factor is inactive or has a single candidate): a near-tie diagnostic."""
+    arrs = [_d(v) for v in (xL, xR, n0, n1)]
+    x0 = np.zeros(2)
+    x1 = np.zeros(2)
+    kind = ct.c_int(0)
+    th = ct.c_double(0)
+    gap = ct.c_double(0)
+    _load().tor_prox_capsule_gap(arrs[0][1], arrs[1][1], float(r), arrs[2][1], arrs[3][1], _w(w0), _w(w1),
+                                 x0.ctypes.data_as(_dp), x1.ctypes.data_as(_dp), ct.byref(kind), ct.byref(th),
+                                 ct.byref(gap))
+    return gap.value
+
+
+def prox_coll_gap(nl, nh, nlp, nhp, wl, wh, wlp, whp, R) -> float:
+    """As prox_capsule_gap, for the agent-agent minimiser."""
+    arrs = [_d(v) for v in (nl, nh, nlp, nhp)]
+    dim = arrs[0][0].shape[0]
+    outs = [np.zeros(dim) for _ in range(4)]
+    kind = ct.c_int(0)
+    th = ct.c_double(0)
+    gap = ct.c_double(0)
+    _load().tor_prox_coll_gap(*[a[1] for a in arrs], _w(wl), _w(wh), _w(wlp), _w(whp), float(R), dim,
+                              *[o.ctypes.data_as(_dp) for o in outs], ct.byref(kind), ct.byref(th), ct.byref(gap))
+    return gap.value
+
+
 def min_clearance(radii, z, walls=None) -> float:
     """min over segment pairs of (closest approach - r_i - r_j) and over
     segment/wall pairs of (distance - r_i); z is [p][eta+1][dim]."""
@@ -236,6 +273,18 @@ class Planner:
 
     def iterate(self, k: int):
         _load().tor_iterate(self.h, int(k))
+
+    def override_next(self, factors, x, rho):
+        """Test support: in the next iteration only, the listed factors emit
+        the given x (their edges in canonical order, factors in the listed
+        order) and ->rho instead of running their minimiser."""
+        f = np.ascontiguousarray(factors, dtype=np.int64).ravel()
+        xx = np.ascontiguousarray(x, dtype=np.float64).ravel()
+        rr = np.ascontiguousarray(rho, dtype=np.uint8).ravel()
+        if f.size == 0:
+            return
+        _load().tor_override_next(self.h, int(f.size), f.ctypes.data_as(ct.POINTER(ct.c_long)),
+                                  xx.ctypes.data_as(_dp), rr.ctypes.data_as(_u8))
 
     def tape(self, k: int):
         """Run k iterations keeping every state for :meth:`backward`."""

@@ -862,6 +862,10 @@ typedef struct {
     double *act_margin;   /* |closest approach - R| / R of the last activity test, per factor */
     double *tie_margin;   /* relative energy gap to the runner-up candidate, per factor */
     int cost;             /* TOR_COST_*: what the per-segment factors are */
+    /* test support: minimiser outputs given for the next iteration */
+    long *ovr;            /* [F] offset of the factor's x in ovr_x, or -1 (NULL: none) */
+    double *ovr_x;        /* per listed factor: its edges' x, canonical order */
+    unsigned char *ovr_rho; /* [F] ->rho of a listed factor */
 } tor_t;
 
 static long node_id(const tor_t *T, int i, int s) { return (long)i * (T->eta + 1) + s; }
@@ -972,6 +976,7 @@ void tor_destroy(void *h) {
     free(T->z), free(T->u), free(T->x), free(T->n), free(T->m), free(T->rout), free(T->rin);
     free(T->act_margin), free(T->tie_margin);
     free(T->tape_z), free(T->tape_u), free(T->tape_rin), free(T->tape_rout), free(T->tape_rin_next);
+    free(T->ovr), free(T->ovr_x), free(T->ovr_rho);
     free(T);
 }
 
@@ -1018,6 +1023,34 @@ void tor_get_margins(void *h, double *act_margin, double *tie_margin) {
     if (tie_margin) memcpy(tie_margin, T->tie_margin, sizeof(double) * T->F);
 }
 
+/* Test support, not a step of the method: for the next iteration only, the
+ * listed factors skip their minimiser and emit the given x (each factor's
+ * edges in canonical order, dim values per edge, factors one after another in
+ * the order listed) and ->rho; m, z, <-rho and u then follow App. B as usual.
+ * Lets a test follow the iteration after a factor whose argmin is a near-tie
+ * took the other (equally good) candidate. */
+void tor_override_next(void *h, long nf, const long *factors, const double *x, const unsigned char *rho) {
+    tor_t *T = (tor_t *)h;
+    free(T->ovr), free(T->ovr_x), free(T->ovr_rho);
+    T->ovr = NULL, T->ovr_x = NULL, T->ovr_rho = NULL;
+    if (nf <= 0) return;
+    long nx = 0;
+    for (long q = 0; q < nf; q++) nx += (T->fe0[factors[q] + 1] - T->fe0[factors[q]]) * T->dim;
+    T->ovr = (long *)malloc(sizeof(long) * T->F);
+    T->ovr_x = (double *)malloc(sizeof(double) * (size_t)nx);
+    T->ovr_rho = (unsigned char *)malloc((size_t)T->F);
+    for (long f = 0; f < T->F; f++) T->ovr[f] = -1;
+    long off = 0;
+    for (long q = 0; q < nf; q++) {
+        long f = factors[q];
+        long n = (T->fe0[f + 1] - T->fe0[f]) * T->dim;
+        T->ovr[f] = off; /* where factor f's x starts in ovr_x */
+        T->ovr_rho[f] = rho[q];
+        memcpy(T->ovr_x + off, x + off, sizeof(double) * (size_t)n);
+        off += n;
+    }
+}
+
 static double weight_value(const tor_t *T, unsigned char w, double rho) {
     (void)T;
     if (w == TOR_INF) return INFINITY;
@@ -1032,6 +1065,13 @@ static void run_factor(tor_t *T, long f, double rho) {
     int t = T->ftype[f];
     double *n = T->n, *x = T->x;
     unsigned char out = TOR_STD;
+    if (T->ovr && T->ovr[f] >= 0) {
+        /* outputs given for this iteration (tor_override_next) */
+        long ne = T->fe0[f + 1] - e;
+        memcpy(x + e * dim, T->ovr_x + T->ovr[f], sizeof(double) * (size_t)(ne * dim));
+        for (long q = 0; q < ne; q++) T->rout[e + q] = T->ovr_rho[f];
+        return;
+    }
     if (t == TOR_F_FIXED && T->cost == TOR_COST_VO && T->fs[f] != 0) {
         /* VO cost: the energy minimiser with its first end certain at x^ref */
         int i = T->fa[f];
@@ -1154,6 +1194,7 @@ static void one_iteration(tor_t *T) {
             for (int k = 0; k < dim; k++) T->u[e * dim + k] = 0;
         }
     }
+    if (T->ovr) tor_override_next(T, 0, NULL, NULL, NULL); /* one iteration only */
     if (T->taping && T->tape_len < T->tape_cap) {
         memcpy(T->tape_rout + T->tape_len * E, T->rout, E);
         memcpy(T->tape_rin_next, T->rin, E);

@@ -44,7 +44,7 @@ struct Params {
     unsigned *qc, *qw;
     int *qcnt;        // collision queue shard lengths, shard q at [q * kQueueStride]
     long long qcap;   // entries per collision queue shard
-    int *counters; // [1] qw length, [2] active coll, [3] active wall
+    int *counters; // [1] qw length, [2] active coll, [3] active wall, [5] consensus overflow (sticky)
     int *stats;    // last iteration: active coll, active wall, queued
     unsigned long long *acc; // [2 kinds][dim][N]  kind 0 = std, 1 = inf
     int *cnt;                // [2][N]
@@ -56,6 +56,8 @@ struct Params {
     long long N;
     double scale;
     float scalef;
+    float sat_lim;   // largest |m| * scale one contribution may carry: degree of it cannot overflow int64
+    unsigned *resid; // primal residual max |x - z| of the u updates run by the finalizing pass (float bits)
     float rho, step;      // this iteration: weight value of rho0, alpha/rho0
     float rho_prev, step_prev;
     int dense;
@@ -82,6 +84,8 @@ struct twa_solver {
     twa_rt::Params P{};
     int *stats_dev = nullptr;
     double *quality_dev = nullptr; // twa_get_quality: objective, largest move, clearance key
+    unsigned *resid_dev = nullptr;  // residual of the last finalized iteration (float bits)
+    bool resid_valid = false;       // resid_dev holds the last iteration's residual
     int *bad_dev = nullptr;
     std::vector<void *> allocs;
     std::string err;
@@ -95,9 +99,13 @@ struct twa_solver {
     std::vector<hipEvent_t> events; // kept for the solver's life and reused
     size_t events_used = 0;
     int timing = 0;
-    // HIP graph of kGraphIters fused iterations
-    hipGraphExec_t graph = nullptr;
+    // HIP graphs of 1, 2, 4, ... kGraphIters fused iterations (graphs[b]
+    // holds 2^b), so any count of steady iterations replays
+    static constexpr int kGraphSizes = 6;
+    hipGraphExec_t graphs[kGraphSizes] = {};
     bool graph_failed = false;
+    long long graph_iters = 0;  // iterations run from graph replays
+    hipStream_t own_stream = nullptr; // made at create when the caller passes the null stream
     // tiny instances: the persistent batched kernel on this one instance
     // (a device copy of the parameters and its one-bin layout)
     twa_rt::Params *tiny_params = nullptr;

@@ -94,13 +94,28 @@ __device__ __forceinline__ void count_wave(int *ctr, bool pred) {
     if (mask && __lane_id() == __ffsll((long long)mask) - 1) atomicAdd(ctr, __popcll(mask));
 }
 
+// One edge's m into the exact fixed-point consensus sums of its node.  A
+// value beyond the headroom (or not finite) raises the sticky overflow flag
+// that twa_check_finite and twa_get_stats report: up to a node's degree of
+// contributions below sat_lim cannot wrap the 64-bit sum.
 __device__ __forceinline__ void contribute(const Params &P, long long node, int kind, const float *m, int D) {
     for (int k = 0; k < D; ++k) {
-        float v = fminf(fmaxf(m[k] * P.scalef, -4.0e18f), 4.0e18f);
+        float v = m[k] * P.scalef;
+        if (!(fabsf(v) <= P.sat_lim)) P.counters[5] = 1;
+        v = fminf(fmaxf(v, -4.0e18f), 4.0e18f);
         long long q = __float2ll_rn(v);
         atomicAdd(&P.acc[((long long)kind * D + k) * P.N + node], (unsigned long long)q);
     }
     atomicAdd(&P.cnt[(long long)kind * P.N + node], 1);
+}
+
+// Finalizing pass only: fold |x - z| of an edge whose u is updated (both
+// weights rho0) into the residual maximum (non-negative floats order as
+// their bit patterns).
+__device__ __forceinline__ void residual(const Params &P, const float *x, const float *z, int D) {
+    float d2 = 0.f;
+    for (int c = 0; c < D; ++c) d2 += (x[c] - z[c]) * (x[c] - z[c]);
+    atomicMax(P.resid, __float_as_uint(sqrtf(d2)));
 }
 
 // (s, i, j) of factor f0 + k given (s, i, j) of f0: walk along the rows of
@@ -515,7 +530,11 @@ __device__ __forceinline__ void energy_stream(const Params &P, const Rec &Z, lon
             u[D + c] = (sent && kb == W_STD) ? u[D + c] + P.step_prev * (xk[D + c] - zc[D + c]) : 0.f;
         }
         for (int q = 0; q < 2 * D; ++q) up[q] = u[q];
-        if (MODE == M_FINAL) return;
+        if (MODE == M_FINAL) {
+            if (sent && ka == W_STD) residual(P, xk, zc, D);
+            if (sent && kb == W_STD) residual(P, xk + D, zc + D, D);
+            return;
+        }
     }
     float x[6], m[6];
     for (int q = 0; q < 2 * D; ++q) n[q] = zc[q] - u[q];
@@ -564,7 +583,10 @@ __device__ __forceinline__ void vo_goal_stream(const Params &P, const Rec &Z, lo
         for (int c = 0; c < D; ++c) n[c] = zp[c] - u[c];
         vo_cost_prox<D>(xr, C, n, wcode(rp), P.rho_prev, xk);
         for (int c = 0; c < D; ++c) u[c] = (k == W_STD) ? u[c] + P.step_prev * (xk[c] - zc[c]) : 0.f, up[c] = u[c];
-        if (MODE == M_FINAL) return;
+        if (MODE == M_FINAL) {
+            if (k == W_STD) residual(P, xk, zc, D);
+            return;
+        }
     }
     for (int c = 0; c < D; ++c) n[c] = zc[c] - u[c];
     vo_cost_prox<D>(xr, C, n, k, P.rho, x);
@@ -597,6 +619,7 @@ __device__ __forceinline__ void fixed_stream(const Params &P, const Rec &Z, long
             float zc[3];
             node_xyz(Z.cur[nd], zc, D);
             for (int c = 0; c < D; ++c) u[c] = u[c] + P.step_prev * (x[c] - zc[c]), up[c] = u[c];
+            if (MODE == M_FINAL) residual(P, x, zc, D);
         } else {
             // ->rho^{k-1} = infinity, so u^k = 0
             for (int c = 0; c < D; ++c) u[c] = 0.f, up[c] = 0.f;
@@ -643,6 +666,8 @@ __device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsign
                     (k[q] == W_STD) ? u[q * D + c] + P.step_prev * (x[q * D + c] - zc[q * D + c]) : 0.f;
         if (MODE == M_FINAL) {
             store_u_coll<D>(P, f, u);
+            for (int q = 0; q < 4; ++q)
+                if (k[q] == W_STD) residual(P, x + q * D, zc + q * D, D);
             return false;
         }
     } else if (MODE == M_FIRST) {
@@ -742,7 +767,12 @@ __device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsign
         u.z = (kb == W_STD) ? u.z + P.step_prev * (x1.x - cb.x) : 0.f;
         u.w = (kb == W_STD) ? u.w + P.step_prev * (x1.y - cb.y) : 0.f;
         if (MODE == M_FINAL) {
-            if (writer) P.u_wall[f] = u;
+            if (writer) {
+                P.u_wall[f] = u;
+                const float za[2] = {ca.x, ca.y}, zb[2] = {cb.x, cb.y}, xa[2] = {x0.x, x0.y}, xb[2] = {x1.x, x1.y};
+                if (ka == W_STD) residual(P, xa, za, 2);
+                if (kb == W_STD) residual(P, xb, zb, 2);
+            }
             return false;
         }
     } else if (MODE == M_FIRST) {
@@ -1344,14 +1374,14 @@ using twa_rt::rho_at;
 
 namespace {
 
-constexpr int kGraphIters = 32;
+constexpr int kGraphIters = 1 << (twa_solver::kGraphSizes - 1); // largest graph: 32 iterations
 // twa_iterate_timed times its last kTimedTail iterations, launched on their
 // own, each kernel with a start and a stop event attached to its own dispatch
 // (hipExtLaunchKernel), so an event pair spans the kernel alone.  Once an
 // event is recorded on the stream, every later launch of the same call runs
 // slower (graph replays by about a third), so no event comes before the
 // untimed replays.
-constexpr int kTimedTail = 4;
+constexpr int kTimedTail = 2;
 
 // Two events of the solver's pool for the next timed kernel (false: none).
 bool take_events(twa_solver *s, hipEvent_t *e0, hipEvent_t *e1) {
@@ -1439,29 +1469,32 @@ twa_status run_iteration(twa_solver *s, int mode, float rho, float rho_prev) {
 }
 
 
-// Capture kGraphIters fused iterations at the steady rho0 into a graph.
-// Returns false if the stream cannot be captured (e.g. the legacy default
-// stream).
-bool capture_graph(twa_solver *s) {
-    hipGraphExec_t *slot = &s->graph;
-    if (*slot) return true;
+// Capture graphs of 1, 2, 4, ..., kGraphIters fused iterations at the steady
+// rho0, all at once (the first time a steady iteration is run), so later
+// calls of any length replay without capturing.  Returns false if the
+// stream cannot be captured.
+bool capture_graphs(twa_solver *s) {
+    if (s->graphs[0]) return true;
     if (s->graph_failed) return false;
-    hipGraph_t g = nullptr;
-    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        (void)hipGetLastError();
-        s->graph_failed = true;
-        return false;
-    }
-    s->timing = 0;
     bool ok = true;
-    for (int it = 0; it < kGraphIters && ok; ++it) ok = run_iteration(s, M_FUSED, s->rho0, s->rho0) == TWA_OK;
-    s->timing = 0;
-    ok = (hipStreamEndCapture(s->stream, &g) == hipSuccess) && ok && g != nullptr;
-    if (ok) ok = hipGraphInstantiate(slot, g, nullptr, nullptr, 0) == hipSuccess;
-    if (g) (void)hipGraphDestroy(g);
+    for (int b = 0; b < twa_solver::kGraphSizes && ok; ++b) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            ok = false;
+            break;
+        }
+        s->timing = 0;
+        for (int it = 0; it < (1 << b) && ok; ++it) ok = run_iteration(s, M_FUSED, s->rho0, s->rho0) == TWA_OK;
+        ok = (hipStreamEndCapture(s->stream, &g) == hipSuccess) && ok && g != nullptr;
+        if (ok) ok = hipGraphInstantiate(&s->graphs[b], g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+    }
     if (!ok) {
         (void)hipGetLastError();
-        *slot = nullptr;
+        for (hipGraphExec_t &e : s->graphs) {
+            if (e) (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
         s->graph_failed = true;
         s->err.clear();
         s->latched = TWA_OK;
@@ -1523,10 +1556,14 @@ twa_status iterate_impl(twa_solver *s, int k, bool timed) {
     }
     while (k > 0) {
         const bool steady = s->pending && s->iter - 1 >= s->n_warm && !s->dbg_x;
-        if (steady && k - tail >= kGraphIters && capture_graph(s)) {
-            HIP_TRY(s, hipGraphLaunch(s->graph, s->stream));
-            s->iter += kGraphIters;
-            k -= kGraphIters;
+        if (steady && k - tail > 0 && capture_graphs(s)) {
+            // the largest captured chunk that fits before the timed tail
+            int b = twa_solver::kGraphSizes - 1;
+            while ((1 << b) > k - tail) --b;
+            HIP_TRY(s, hipGraphLaunch(s->graphs[b], s->stream));
+            s->iter += 1 << b;
+            s->graph_iters += 1 << b;
+            k -= 1 << b;
             continue;
         }
         float rho = rho_at(s, s->iter);
@@ -1548,8 +1585,10 @@ twa_status iterate_impl(twa_solver *s, int k, bool timed) {
 // pending -> canonical: materialise u^k
 twa_status finalize(twa_solver *s) {
     if (!s->pending) return TWA_OK;
+    HIP_TRY(s, hipMemsetAsync(s->resid_dev, 0, sizeof(unsigned), s->stream));
     TRY(run_iteration(s, M_FINAL, rho_at(s, s->iter), rho_at(s, s->iter - 1)));
     s->pending = false;
+    s->resid_valid = true;
     return TWA_OK;
 }
 
@@ -1568,6 +1607,7 @@ twa_status reset_state_buffers(twa_solver *s) {
     HIP_TRY(s, hipMemsetAsync(P.qcnt, 0, sizeof(int) * kShards * kQueueStride, s->stream));
     HIP_TRY(s, hipMemsetAsync(s->stats_dev, 0, sizeof(int) * 4, s->stream));
     s->pending = false;
+    s->resid_valid = false;
     return TWA_OK;
 }
 
@@ -1588,6 +1628,20 @@ twa_status save_origin(twa_solver *s) {
     HIP_TRY(s, hipGetLastError());
     s->origin_iter = s->iter;
     return TWA_OK;
+}
+
+// Fixed-point scale of the consensus sums: a power of two such that the
+// contributions of every edge of a node (degree 2(p-1) + 2 + 2 n_walls + 1),
+// each with |m| <= 8 coord_max, sum below 2^62 (capped at 2^44, far below
+// FP32's resolution at unit scale).  *limit: the largest |m| one contribution
+// may carry before the overflow flag is raised (degree of them stay below
+// 2^62 in magnitude, so the int64 sum cannot wrap).
+void consensus_scale(int p, int n_walls, double coord_max, double *scale, double *limit) {
+    const long long deg = 2LL * (p - 1) + 2 + 2LL * n_walls + 1;
+    const double lim = std::ldexp(1.0, 62) / (8.0 * coord_max * (double)deg);
+    const int S = std::min((int)std::floor(std::log2(lim)), 44);
+    *scale = std::ldexp(1.0, S);
+    *limit = std::ldexp(1.0, 62) / ((double)deg * *scale);
 }
 
 bool finite_all(const std::vector<float> &v) {
@@ -1629,9 +1683,11 @@ const char *twa_last_error(const twa_solver *s) { return s ? s->err.c_str() : "n
 void twa_destroy(twa_solver *s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    if (s->graph) (void)hipGraphExecDestroy(s->graph);
+    for (hipGraphExec_t e : s->graphs)
+        if (e) (void)hipGraphExecDestroy(e);
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     for (void *p : s->allocs) (void)hipFree(p);
+    if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s;
 }
 
@@ -1688,6 +1744,17 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     }
     s->p = p, s->eta = eta, s->dim = dim, s->W = n_walls;
     s->rho0 = s->rho0_init = rho0, s->alpha = alpha, s->flags = flags;
+    if (!s->stream) {
+        // The null stream cannot be captured into graphs.  A stream made with
+        // the default flags orders itself with the null stream both ways, so
+        // the caller's null-stream work and the solver's stay in order.
+        if (hipStreamCreate(&s->own_stream) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(s, TWA_E_DEVICE, "hipStreamCreate failed");
+            return bail(TWA_E_DEVICE);
+        }
+        s->stream = s->own_stream;
+    }
     // --- host copies for validation
     std::vector<float> hr, h0, hT, hw, hC;
     if (to_host(s, hr, radii, p) || to_host(s, h0, x0, (size_t)p * dim) || to_host(s, hT, xT, (size_t)p * dim) ||
@@ -1796,13 +1863,13 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
              : (flags & TWA_F_COST_MINVEL) ? COST_MINVEL
                                            : COST_ENERGY;
     P.dense = ((flags & TWA_F_DENSE) || P.admm) ? 1 : 0;
-    // fixed-point scale: |m| * scale * (degree + 1) stays below 2^62
-    long long deg = 2LL * (p - 1) + 2 + 2LL * n_walls + 1;
-    double lim = std::ldexp(1.0, 62) / (8.0 * Lmax * (double)deg);
-    int S = (int)std::floor(std::log2(lim));
-    S = std::min(S, 44);
-    P.scale = std::ldexp(1.0, S);
-    P.scalef = (float)P.scale;
+    {
+        double lim_m = 0;
+        consensus_scale(p, n_walls, Lmax, &P.scale, &lim_m);
+        P.scalef = (float)P.scale;
+        // per contribution, in scaled units, rounded down to a float
+        P.sat_lim = std::nextafter((float)(lim_m * P.scale), 0.f);
+    }
     float *radii_d, *C_d;
     float4 *walls_d, *xfix_d;
     unsigned long long *wbc_d, *wbw_d;
@@ -1822,7 +1889,8 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         dev_alloc(s, &P.x_wall, (size_t)std::max<long long>(1, Fw)) ||
         dev_alloc(s, &wbc_d, (size_t)std::max<long long>(1, (Fc + 63) / 64)) ||
         dev_alloc(s, &wbw_d, (size_t)std::max<long long>(1, (Fw + 63) / 64)) ||
-        dev_alloc(s, &s->stats_dev, 4) || dev_alloc(s, &s->bad_dev, 1) || dev_alloc(s, &s->quality_dev, 3))
+        dev_alloc(s, &s->stats_dev, 4) || dev_alloc(s, &s->bad_dev, 1) || dev_alloc(s, &s->quality_dev, 3) ||
+        dev_alloc(s, &s->resid_dev, 1))
         return bail(TWA_E_NOMEM);
     unsigned long long *chunk_d;
     int *rowchunk_d;
@@ -1853,6 +1921,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
                         hwbw[f >> 6] = ((unsigned long long)s2 << 48) | ((unsigned long long)i << 24) | (unsigned long long)w;
     }
     P.stats = s->stats_dev;
+    P.resid = s->resid_dev;
     P.rho = P.rho_prev = rho0;
     P.step = P.step_prev = alpha / rho0;
     // constants
@@ -2018,13 +2087,26 @@ twa_status twa_set_state(twa_solver *s, const float *z, const float *u, const un
 twa_status twa_get_stats(twa_solver *s, twa_stats *out) {
     TRY(check_alive(s));
     if (!out) return fail(s, TWA_E_INVALID, "null stats");
+    TRY(finalize(s));
     int h[4] = {0, 0, 0, 0};
+    unsigned r = 0;
+    int overflow = 0;
     HIP_TRY(s, hipMemcpyAsync(h, s->stats_dev, sizeof(int) * 3, hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    HIP_TRY(s, hipMemcpyAsync(&r, s->resid_dev, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(&overflow, s->P.counters + 5, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    double obj = 0, clr = 0;
+    TRY(twa_get_quality(s, &obj, &clr, nullptr)); // synchronises
     out->iter = s->iter;
     out->active_coll = h[0];
     out->active_wall = h[1];
     out->queued = h[2];
+    float rf;
+    std::memcpy(&rf, &r, sizeof(rf));
+    out->residual = s->resid_valid ? (double)rf : 0.0;
+    out->objective = obj;
+    out->min_clearance = clr;
+    out->graph_iterations = s->graph_iters;
+    if (overflow) return fail(s, TWA_E_NUMERIC, "consensus sum beyond its fixed-point range (diverging iterates)");
     return TWA_OK;
 }
 
@@ -2052,6 +2134,13 @@ twa_status twa_get_quality(twa_solver *s, double *objective, double *min_clearan
     return TWA_OK;
 }
 
+twa_status twa_consensus_scale(int p, int n_walls, double coord_max, double *scale, double *limit) {
+    if (p < 1 || n_walls < 0 || !(coord_max >= 1.0) || !std::isfinite(coord_max) || !scale || !limit)
+        return TWA_E_INVALID;
+    consensus_scale(p, n_walls, coord_max, scale, limit);
+    return TWA_OK;
+}
+
 twa_status twa_sizes(const twa_solver *s, long long *n_factors, long long *n_edges) {
     if (!s) return TWA_E_INVALID;
     const Params &P = s->P;
@@ -2072,10 +2161,12 @@ twa_status twa_check_finite(twa_solver *s) {
     hipLaunchKernelGGL(k_finite, dim3(1), dim3(256), 0, s->stream, (const float4 *)s->P.zr_cur, 0LL,
                        (const float *)s->P.u_energy, (long long)(2 * s->dim * s->P.Fe), s->bad_dev);
     HIP_TRY(s, hipGetLastError());
-    int bad = 0;
+    int bad = 0, overflow = 0;
     HIP_TRY(s, hipMemcpyAsync(&bad, s->bad_dev, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(&overflow, s->P.counters + 5, sizeof(int), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     if (bad) return fail(s, TWA_E_NUMERIC, "non-finite value in z or u");
+    if (overflow) return fail(s, TWA_E_NUMERIC, "consensus sum beyond its fixed-point range (diverging iterates)");
     return TWA_OK;
 }
 
@@ -2099,6 +2190,8 @@ struct twa_batch {
     twa_status latched = TWA_OK;
     hipGraphExec_t gexec = nullptr;
     int g_k = -1, g_first = -1;
+    std::vector<Params> hparams;       // host copy of insts_dev
+    hipStream_t own_stream = nullptr;  // made when the caller passes the null stream
 };
 
 namespace {
@@ -2209,6 +2302,7 @@ void twa_batch_destroy(twa_batch *b) {
     if (b->bin_items_dev) (void)hipFree(b->bin_items_dev);
     if (b->map_dev) (void)hipFree(b->map_dev);
     if (b->pexec) (void)hipGraphExecDestroy(b->pexec);
+    if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
     delete b;
 }
 
@@ -2218,11 +2312,20 @@ twa_status twa_batch_create(int n, const twa_instance *inst, unsigned flags, voi
     twa_batch *b = new (std::nothrow) twa_batch();
     if (!b) return TWA_E_NOMEM;
     b->stream = static_cast<hipStream_t>(hip_stream);
+    if (!b->stream) {
+        // as twa_create: a capturable stream ordered with the null stream
+        if (hipStreamCreate(&b->own_stream) != hipSuccess) {
+            (void)hipGetLastError();
+            delete b;
+            return TWA_E_DEVICE;
+        }
+        b->stream = b->own_stream;
+    }
     for (int i = 0; i < n; ++i) {
         const twa_instance &I = inst[i];
         twa_solver *s = nullptr;
         twa_status st = twa_create(I.p, I.eta, I.dim, I.radii, I.x0, I.xT, I.n_walls, I.walls, I.C, I.rho0, I.alpha,
-                                   flags, hip_stream, &s);
+                                   flags, b->stream, &s);
         if (st == TWA_OK && I.z0) {
             st = twa_set_init(s, I.z0);
             if (st != TWA_OK) twa_destroy(s);
@@ -2241,7 +2344,8 @@ twa_status twa_batch_create(int n, const twa_instance *inst, unsigned flags, voi
         twa_batch_destroy(b);
         return TWA_E_NOMEM;
     }
-    std::vector<Params> h(n);
+    std::vector<Params> &h = b->hparams;
+    h.resize(n);
     for (int i = 0; i < n; ++i) {
         h[i] = b->solvers[i]->P;
         h[i].dbg_x = nullptr;
@@ -2309,17 +2413,46 @@ twa_status twa_batch_iterate(twa_batch *b, int k) {
     if (b->latched != TWA_OK) return b->latched;
     if (k < 0) return bfail(b, TWA_E_INVALID, "k must be >= 0");
     if (k == 0) return TWA_OK;
-    bool any_pending = false, all_pending = true;
+    bool any_pending = false, all_pending = true, dbg = false;
     for (twa_solver *s : b->solvers) {
         if (s->latched != TWA_OK) return bfail(b, s->latched, "an instance has a latched device error");
         if (s->n_warm > 0 && s->iter < s->n_warm) return bfail(b, TWA_E_STATE, "batched instances take no rho0 schedule");
+        // an iteration run at the warm-up rho0 whose u update is still
+        // pending: settle it with its own weight and step (the batched
+        // kernels run the steady rho0 only)
+        if (s->pending && s->iter - 1 < s->n_warm && finalize(s) != TWA_OK)
+            return bfail(b, TWA_E_DEVICE, "finalize: " + s->err);
         any_pending |= s->pending;
         all_pending &= s->pending;
+        dbg |= s->dbg_x != nullptr;
     }
     if (any_pending && !all_pending)
         for (twa_solver *s : b->solvers)
             if (finalize(s) != TWA_OK) return bfail(b, TWA_E_DEVICE, "finalize: " + s->err);
     int first = all_pending ? 0 : 1;
+    if (dbg) {
+        // twa_capture_next on a member: its first iteration runs on its own
+        // launch with the capture buffers in the parameters the kernels read
+        std::vector<Params> h = b->hparams;
+        for (size_t i = 0; i < h.size(); ++i) {
+            h[i].dbg_x = b->solvers[i]->dbg_x;
+            h[i].dbg_rho = b->solvers[i]->dbg_rho;
+        }
+        BHIP_TRY(b, hipMemcpyAsync(b->insts_dev, h.data(), sizeof(Params) * h.size(), hipMemcpyHostToDevice, b->stream));
+        launch_batch(b, 1, first);
+        BHIP_TRY(b, hipGetLastError());
+        BHIP_TRY(b, hipMemcpyAsync(b->insts_dev, b->hparams.data(), sizeof(Params) * h.size(), hipMemcpyHostToDevice,
+                                   b->stream));
+        BHIP_TRY(b, hipStreamSynchronize(b->stream)); // h lives on this stack
+        for (twa_solver *s : b->solvers) {
+            s->dbg_x = nullptr;
+            s->dbg_rho = nullptr;
+            s->pending = true;
+            s->iter += 1;
+        }
+        first = 0;
+        if (--k == 0) return TWA_OK;
+    }
     if (b->block == 0) {
         // phased form: a first iteration on its own, then a captured graph
         // of kPhasedChunk iterations replayed, then the rest launched directly

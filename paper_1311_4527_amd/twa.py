@@ -39,7 +39,8 @@ class TWAError(RuntimeError):
 
 class _Stats(ct.Structure):
     _fields_ = [("iter", ct.c_longlong), ("active_coll", ct.c_longlong), ("active_wall", ct.c_longlong),
-                ("queued", ct.c_longlong)]
+                ("queued", ct.c_longlong), ("residual", ct.c_double), ("objective", ct.c_double),
+                ("min_clearance", ct.c_double), ("graph_iterations", ct.c_longlong)]
 
 
 _lib = None
@@ -81,6 +82,9 @@ def load_library():
     lib.twa_get_quality.argtypes = [_vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
     lib.twa_check_finite.restype = ct.c_int
     lib.twa_check_finite.argtypes = [_vp]
+    lib.twa_consensus_scale.restype = ct.c_int
+    lib.twa_consensus_scale.argtypes = [ct.c_int, ct.c_int, ct.c_double, ct.POINTER(ct.c_double),
+                                        ct.POINTER(ct.c_double)]
     lib.twa_backward.restype = ct.c_int
     lib.twa_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     lib.twa_last_error.restype = ct.c_char_p
@@ -227,7 +231,9 @@ class Solver:
     def twa_get_stats(self) -> dict:
         s = _Stats()
         self._check(load_library().twa_get_stats(self.h, ct.byref(s)))
-        return dict(iter=s.iter, active_coll=s.active_coll, active_wall=s.active_wall, queued=s.queued)
+        return dict(iter=s.iter, active_coll=s.active_coll, active_wall=s.active_wall, queued=s.queued,
+                    residual=s.residual, objective=s.objective, min_clearance=s.min_clearance,
+                    graph_iterations=s.graph_iterations)
 
     def twa_get_quality(self) -> dict:
         """Energy objective, smallest clearance and largest last move of the
@@ -366,3 +372,13 @@ class Batch:
 
 def twa_version() -> str:
     return load_library().twa_version().decode()
+
+
+def twa_consensus_scale(p: int, n_walls: int, coord_max: float):
+    """(scale, limit) of the fixed-point consensus sums twa_create picks
+    (host only)."""
+    sc, lim = ct.c_double(), ct.c_double()
+    st = load_library().twa_consensus_scale(int(p), int(n_walls), float(coord_max), ct.byref(sc), ct.byref(lim))
+    if st != TWA_OK:
+        raise TWAError(st, "twa_consensus_scale")
+    return sc.value, lim.value

@@ -62,25 +62,63 @@ def test_batch_dense_equals_skip():
         assert torch.equal(A.twa_batch_get_trajectories(i), D.twa_batch_get_trajectories(i))
 
 
-def test_batch_against_reference_one_iteration():
-    """Instance by instance, one batched iteration equals the FP64 reference
-    to the single-iteration tolerance."""
+@pytest.mark.parametrize("block,groups", [(0, 1), (256, 6)])
+def test_batch_against_reference_one_iteration(block, groups):
+    """Instance by instance, the first batched iteration equals the FP64
+    reference by the single-iteration protocol: x per edge and ->rho per
+    factor (captured through the batch), z, <-rho and u; near-tied factors
+    validated and followed through, none skipped."""
+    import torch
     import oracle as O
     from paper_1311_4527_amd.twa import Batch
+    from tests.parity import compare_iteration
     insts = _mixed(6, seed=13)
     B = Batch(insts)
-    B.twa_batch_iterate(1)
+    B.twa_batch_config(block, groups)
+    bufs = []
     for i, inst in enumerate(insts):
-        P = O.Planner(inst)
-        z32 = inst.z0.astype(np.float32).astype(np.float64)
-        P.set_state(z32, np.zeros((P.E, inst.dim)), P.get_state()[2], 0)
-        P.iterate(1)
-        zr = P.trajectories()
-        zg = B.twa_batch_get_trajectories(i).cpu().numpy()
-        act, tie = P.margins()
-        if ((act < 1e-5) | (tie < 1e-5)).any():
-            continue
-        assert np.all(np.abs(zg - zr) <= 1e-5 * np.maximum(np.abs(zr), 1.0)), inst.name
+        S = B.twa_batch_solver(i)
+        x = torch.empty((S.n_edges, inst.dim), dtype=torch.float32, device="cuda")
+        r = torch.empty((S.n_factors,), dtype=torch.uint8, device="cuda")
+        S.twa_capture_next(x, r)
+        bufs.append((S, x, r))
+    B.twa_batch_iterate(1)
+    torch.cuda.synchronize()
+    checked = []
+    for inst, (S, x, r) in zip(insts, bufs):
+        z, u, l, it = S.twa_get_state()
+        assert it == 1
+        lr0 = O.Planner(inst).get_state()[2]
+        gpu = tuple(t.cpu().numpy() for t in (x, r, z, u, l))
+        compare_iteration(inst, inst.z0.astype(np.float32), np.zeros((S.n_edges, inst.dim), np.float32), lr0, 0,
+                          gpu)
+        checked.append(inst.name)
+    assert len(checked) == len(insts) and sum("swap" in n for n in checked) == 3, checked
+
+
+def test_batch_after_warm_up_equals_plain():
+    """A member that ran its warm-up schedule (Sec. 4's small rho0) through
+    its own solver, with the last warm-up iteration's u update still pending,
+    continues in the batch bitwise as in its own solver."""
+    import torch
+    from paper_1311_4527_amd.twa import Batch, Solver
+    insts = _mixed(4, seed=17)
+    B = Batch(insts)
+    plain = []
+    for i, inst in enumerate(insts):
+        M = B.twa_batch_solver(i)
+        M.twa_set_schedule(0.5, 3)
+        M.twa_iterate(3)
+        S = Solver.from_instance(inst)
+        S.twa_set_schedule(0.5, 3)
+        S.twa_iterate(3 + 20)
+        plain.append(S)
+    B.twa_batch_iterate(20)
+    for i, S in enumerate(plain):
+        za, ua, la, ka = B.twa_batch_solver(i).twa_get_state()
+        zb, ub, lb, kb = S.twa_get_state()
+        assert ka == kb == 23
+        assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb), insts[i].name
 
 
 def test_autotuner_picks_a_candidate(tmp_path, monkeypatch):

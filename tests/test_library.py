@@ -1,6 +1,7 @@
 """The C-ABI library loads and exports every symbol its header declares;
 argument validation that needs no device (no GPU)."""
 import ctypes as ct
+import math
 import os
 import re
 import subprocess
@@ -131,3 +132,29 @@ def test_bench_traffic_digest_tracks_the_sources(tmp_path, monkeypatch):
     assert bench.kernel_sources_digest() != d
     for variant in bench.MEASURED_TRAFFIC:
         assert bench.measured_traffic(variant) is None
+
+
+@pytest.mark.parametrize("p,nw,cmax", [(1, 0, 1.0), (8, 0, 1.0), (100, 0, 1.0), (1024, 32, 1.0), (4096, 4, 1.0),
+                                       (64, 8, 37.5), (5000, 0, 1e6)])
+def test_consensus_scale_headroom(lib, p, nw, cmax):
+    """The fixed-point consensus: a power-of-two scale (at most 2^44) such that
+    a node's degree of contributions, each within the overflow limit, sums
+    below 2^62 (no int64 wrap), while every m of at most 8 coord_max -- far
+    beyond any iterate that stays in the scene -- stays within the limit."""
+    lib.twa_consensus_scale.restype = ct.c_int
+    lib.twa_consensus_scale.argtypes = [ct.c_int, ct.c_int, ct.c_double, ct.POINTER(ct.c_double),
+                                        ct.POINTER(ct.c_double)]
+    sc, lim = ct.c_double(), ct.c_double()
+    assert lib.twa_consensus_scale(p, nw, cmax, ct.byref(sc), ct.byref(lim)) == 0
+    scale, limit = sc.value, lim.value
+    S = math.log2(scale)
+    assert S == int(S) and S <= 44
+    deg = 2 * (p - 1) + 2 + 2 * nw + 1       # collision, energy, wall and fixed edges of a node
+    assert deg * limit * scale <= 2.0 ** 62 * (1 + 1e-12)
+    assert limit >= 8 * cmax
+
+
+def test_consensus_scale_rejects_bad_arguments(lib):
+    sc, lim = ct.c_double(), ct.c_double()
+    for args in ((0, 0, 1.0), (4, -1, 1.0), (4, 0, 0.5), (4, 0, float("nan"))):
+        assert lib.twa_consensus_scale(*args, ct.byref(sc), ct.byref(lim)) == 1
