@@ -246,11 +246,15 @@ twa_status twa_consensus_scale(int p, int n_walls, double coord_max, double *sca
  *   dL_dz0 [p][eta+1][dim]  dL/dz^0 at the interior break-points (written;
  *                           0 at s = 0 and s = eta), or NULL.
  * All device arrays, caller-owned.  The initial u is held constant.
- * Checkpoints every ceil(sqrt(K)) iterations and recomputes one segment at
- * a time: about 2 sqrt(K) copies of (z, u, <-rho), allocated for the call
- * and freed before it returns (TWA_E_NOMEM if they do not fit).  The solver's
- * forward state is the same afterwards.  dim == 2 only (TWA_E_INVALID
- * otherwise); TWA_E_STATE without TWA_F_TAPE.  Synchronises the stream.
+ * Checkpoints every ceil(sqrt(K)) iterations (z and <-rho dense; u of the
+ * collision and wall factors sparse, as it is zero on every factor that sent
+ * weight 0) and recomputes one segment at a time, the factor kernels
+ * capturing each iteration's weights and the minimiser inputs of the
+ * factors that sent rho0.  Its buffers are allocated at the first call and
+ * kept, grown when a later call needs more, until twa_destroy (TWA_E_NOMEM
+ * if they do not fit).  The solver's forward state is the same afterwards.
+ * dim == 2 only (TWA_E_INVALID otherwise); TWA_E_STATE without TWA_F_TAPE.
+ * Synchronises the stream.
  */
 twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT, float *dL_dr,
                         float *dL_dz0);

@@ -11,17 +11,24 @@
 //        else 0                     (steps 5-7)
 // With every discrete decision held at the forward run's (the weights, the
 // minimiser candidate) the map is differentiable, and its transpose runs
-// backwards through the same steps:
+// backwards through the same steps, one reverse step per iteration:
+//   k_adj_accum    per captured factor (one that sent rho0): its edges' count
+//                  and kept cotangents du' per node
 //   k_adj_select   per node: the class of the mean, and
 //                  g = (dz' - s * sum of du' over kept edges) / |mean set|
-//   k_adj_factors  per factor: dx = s du'[kept] + g[in mean set],
-//                  dn = J_g^T dx (minimiser derivatives from prox.h),
-//                  du = du'[kept] + g[in mean set] - dn, radius and start /
+//   k_adj_factors  per fixed / energy factor and per captured factor:
+//                  dx = s du'[kept] + g[in mean set], dn = J_g^T dx (the
+//                  minimiser derivatives from prox.h), du = du'[kept] +
+//                  g[in mean set] - dn, dz += dn per node, radius and start /
 //                  goal cotangents
-//   k_adj_gather   per node: dz = sum of dn over the node's edges
-// State is read in the canonical layouts of the public header.  The forward
-// states come from the solver itself: checkpoints every ceil(sqrt(K))
-// iterations, and one segment at a time recomputed with every state kept.
+// A factor that sent weight 0 carries no cotangent in the energy mode (see
+// k_adj_accum), so a step's cost follows the active factors, not the edges.
+// The forward decisions come from the solver itself: checkpoints every
+// ceil(sqrt(K)) iterations (state in the canonical layouts, collision and
+// wall u kept sparse: by the u rule of App. B step 7 it is zero on every
+// factor that sent weight 0), and each segment recomputed with its weights
+// and the minimiser inputs n of the factors that sent rho0 captured by the
+// factor kernels themselves.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +41,7 @@
 #include "solver.h"
 
 using namespace twa;
+using twa_rt::AdjRec;
 using twa_rt::wval;
 
 namespace {
@@ -45,19 +53,22 @@ struct Adj {
     const float *radii;
     const float4 *walls;
     const float *C;
-    // forward state of iteration k (canonical layouts) and its decisions
-    const float *z;              // [N][2]
-    const float *u;              // [E][2]
+    // decisions of iteration k
     const unsigned char *l;      // [N] <-rho^k
     const unsigned char *rout;   // [F] ->rho^k
     const unsigned char *lnext;  // [N] <-rho^{k+1}
     float rho, step;             // rho0 of iteration k, alpha / rho0
     // cotangents
-    float *zb;           // [N][2] dL/dz^{k+1} in, dL/dz^k out (k_adj_gather)
-    float *ub;           // [E][2] dL/du^{k+1} in, dL/du^k out (k_adj_factors)
+    const float *zb_in;  // [N][2] dL/dz^{k+1}
+    float *zb_out;       // [N][2] dL/dz^k: zeroed, then accumulated
+    const float *ub_in;  // [E][2] dL/du^{k+1}
+    float *ub_out;       // [E][2] dL/du^k: zeroed, then written where nonzero
     float *g;            // [N][2]
     unsigned char *cls;  // [N] weight class of the node's mean
-    float *nb;           // [E][2] dL/dn
+    const int *cnt;      // [N] size of the node's mean set in iteration k (captured)
+    const float *S_in;   // [N][2] sum of dL/du^{k+1} over the kept edges of captured factors
+    float *S_next;       // [N][2] the same sum for iteration k-1, accumulated here
+    const unsigned char *rout_prev; // [F] ->rho^{k-1}, or null when k-1 is not captured yet
     float *dx0, *dxT;    // [p][2], accumulated
     double *drd;         // [p], accumulated
 };
@@ -68,103 +79,84 @@ __device__ __forceinline__ long long pair_index(int p, int a, int b) {
     return (long long)a * p - (long long)a * (a + 1) / 2 + (b - a - 1);
 }
 
-// Visit every edge of node (i, s) as fn(factor, edge); lanes of a wave
-// split the collision and wall edges, lane 0 takes the fixed and energy ones.
-template <class Fn>
-__device__ __forceinline__ void for_node_edges(const Adj &A, int i, int s, int lane, Fn fn) {
-    if (lane == 0) {
-        if (s == 0) fn(2LL * i, 2LL * i);
-        if (s == A.eta) fn(2LL * i + 1, 2LL * i + 1);
-        if (s > 0) {
-            long long fe = (long long)i * A.eta + s - 1;
-            fn(A.f_energy + fe, A.e_energy + 2 * fe + 1);
+// (i, j) of collision factor q of a break-point interval (row-major i < j)
+__device__ __forceinline__ void pair_of(int p, long long q, int &i, int &j) {
+    double b = 2.0 * p - 1.0;
+    i = (int)floor((b - sqrt(fmax(b * b - 8.0 * (double)q, 0.0))) * 0.5);
+    i = max(0, min(i, p - 2));
+    while (i > 0 && pair_index(p, i, i + 1) > q) --i;
+    while (i < p - 2 && pair_index(p, i + 1, i + 2) <= q) ++i;
+    j = (int)(q - pair_index(p, i, i + 1)) + i + 1;
+}
+
+// In the energy mode a collision or wall factor that sent weight 0 carries
+// no cotangent: its edges are neither kept by the u update (that needs rho0)
+// nor part of their node's mean (every node has a rho0 energy edge or an
+// infinite fixed one, so the all-zero case never arises).  A reverse step
+// therefore touches the fixed and energy edges and the captured factors only.
+
+// S_in for the first reverse step of a segment (the step after it, which
+// accumulates S for the others, belongs to the segment reversed before):
+// per captured factor, its kept edges' dL/du^{k+1} into its nodes
+__global__ __launch_bounds__(256) void k_adj_accum(Adj A, float *S, const AdjRec *pool, const unsigned *offs,
+                                                   unsigned cap) {
+    const unsigned b = offs[0], e = min(offs[1], cap);
+    for (unsigned t = b + blockIdx.x * blockDim.x + threadIdx.x; t < e; t += gridDim.x * blockDim.x) {
+        const AdjRec rec = pool[t];
+        long long nd[4], ed[4];
+        int ne;
+        if (!rec.wall) {
+            const long long fc = rec.f;
+            int s = (int)(fc / A.P2), i, j;
+            pair_of(A.p, fc - (long long)s * A.P2, i, j);
+            nd[0] = node_id(A, i, s), nd[1] = nd[0] + 1, nd[2] = node_id(A, j, s), nd[3] = nd[2] + 1;
+            const long long e0 = A.e_coll + 4 * fc;
+            for (int k = 0; k < 4; ++k) ed[k] = e0 + k;
+            ne = 4;
+        } else {
+            const long long fw = rec.f, per_s = (long long)A.p * A.W;
+            const int s = (int)(fw / per_s), i = (int)((fw - (long long)s * per_s) / A.W);
+            nd[0] = node_id(A, i, s), nd[1] = nd[0] + 1;
+            ed[0] = A.e_wall + 2 * fw, ed[1] = ed[0] + 1;
+            ne = 2;
         }
-        if (s < A.eta) {
-            long long fe = (long long)i * A.eta + s;
-            fn(A.f_energy + fe, A.e_energy + 2 * fe);
-        }
-    }
-    for (int j = lane; j < A.p; j += 64) {
-        if (j == i) continue;
-        int a = min(i, j), b = max(i, j);
-        int base = (i == a) ? 0 : 2;
-        long long pi = pair_index(A.p, a, b);
-        if (s < A.eta) {
-            long long fc = (long long)s * A.P2 + pi;
-            fn(A.f_coll + fc, A.e_coll + 4 * fc + base);
-        }
-        if (s > 0) {
-            long long fc = (long long)(s - 1) * A.P2 + pi;
-            fn(A.f_coll + fc, A.e_coll + 4 * fc + base + 1);
-        }
-    }
-    for (int w = lane; w < A.W; w += 64) {
-        if (s < A.eta) {
-            long long fw = ((long long)s * A.p + i) * A.W + w;
-            fn(A.f_wall + fw, A.e_wall + 2 * fw);
-        }
-        if (s > 0) {
-            long long fw = ((long long)(s - 1) * A.p + i) * A.W + w;
-            fn(A.f_wall + fw, A.e_wall + 2 * fw + 1);
-        }
+        for (int k = 0; k < ne; ++k)
+            if (A.lnext[nd[k]] == W_STD) {
+                atomicAdd(&S[2 * nd[k]], A.ub_in[2 * ed[k]]);
+                atomicAdd(&S[2 * nd[k] + 1], A.ub_in[2 * ed[k] + 1]);
+            }
     }
 }
 
-template <class T>
-__device__ __forceinline__ T wave_sum(T v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// one wave per node
+// per node: the class of its mean (infinite edges if any, else rho0 edges:
+// the <-rho code the node pass gave it) and g = (dz' - s * sum of du' over
+// kept edges) / |mean set|
 __global__ __launch_bounds__(256) void k_adj_select(Adj A) {
-    int lane = threadIdx.x & 63;
-    long long t = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= A.N) return;
-    int i = (int)(t / (A.eta + 1)), s = (int)(t % (A.eta + 1));
-    bool keep_node = A.lnext[t] == W_STD;
-    int ninf = 0, nstd = 0, deg = 0;
-    float sx = 0.f, sy = 0.f;
-    for_node_edges(A, i, s, lane, [&](long long f, long long e) {
-        int r = A.rout[f];
-        ninf += r == W_INF;
-        nstd += r == W_STD;
-        ++deg;
-        if (r == W_STD && keep_node) {
-            sx += A.ub[2 * e];
-            sy += A.ub[2 * e + 1];
+    const int i = (int)(t / (A.eta + 1)), s = (int)(t % (A.eta + 1));
+    const bool keep_node = A.lnext[t] == W_STD;
+    float sx = A.S_in[2 * t], sy = A.S_in[2 * t + 1];
+    auto edge = [&](long long f, long long e) {
+        if (A.rout[f] == W_STD && keep_node) {
+            sx += A.ub_in[2 * e];
+            sy += A.ub_in[2 * e + 1];
         }
-    });
-    ninf = wave_sum(ninf);
-    nstd = wave_sum(nstd);
-    deg = wave_sum(deg);
-    sx = wave_sum(sx);
-    sy = wave_sum(sy);
-    if (lane == 0) {
-        int cnt = ninf ? ninf : (nstd ? nstd : deg);
-        A.cls[t] = (unsigned char)(ninf ? W_INF : (nstd ? W_STD : W_ZERO));
-        A.g[2 * t] = (A.zb[2 * t] - A.step * sx) / (float)cnt;
-        A.g[2 * t + 1] = (A.zb[2 * t + 1] - A.step * sy) / (float)cnt;
+    };
+    if (s == 0) edge(2LL * i, 2LL * i);
+    if (s == A.eta) edge(2LL * i + 1, 2LL * i + 1);
+    if (s > 0) {
+        const long long fe = (long long)i * A.eta + s - 1;
+        edge(A.f_energy + fe, A.e_energy + 2 * fe + 1);
     }
-}
-
-// one wave per node: dz^k = sum of dn over the node's edges
-__global__ __launch_bounds__(256) void k_adj_gather(Adj A) {
-    int lane = threadIdx.x & 63;
-    long long t = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= A.N) return;
-    int i = (int)(t / (A.eta + 1)), s = (int)(t % (A.eta + 1));
-    float sx = 0.f, sy = 0.f;
-    for_node_edges(A, i, s, lane, [&](long long, long long e) {
-        sx += A.nb[2 * e];
-        sy += A.nb[2 * e + 1];
-    });
-    sx = wave_sum(sx);
-    sy = wave_sum(sy);
-    if (lane == 0) {
-        A.zb[2 * t] = sx;
-        A.zb[2 * t + 1] = sy;
+    if (s < A.eta) {
+        const long long fe = (long long)i * A.eta + s;
+        edge(A.f_energy + fe, A.e_energy + 2 * fe);
     }
+    const float cnt = (float)A.cnt[t];
+    A.cls[t] = A.lnext[t];
+    A.g[2 * t] = (A.zb_in[2 * t] - A.step * sx) / cnt;
+    A.g[2 * t + 1] = (A.zb_in[2 * t + 1] - A.step * sy) / cnt;
 }
 
 // dL/dx of edge e (node t) of a factor with weight r; also the part of
@@ -172,96 +164,92 @@ __global__ __launch_bounds__(256) void k_adj_gather(Adj A) {
 __device__ __forceinline__ void edge_xbar(const Adj &A, int r, long long t, long long e, f2 &xb, f2 &up) {
     bool keep = r == W_STD && A.lnext[t] == W_STD;
     int c = A.cls[t];
-    bool in_mean = c == W_INF ? r == W_INF : (c == W_STD ? r == W_STD : true);
-    f2 ubp = keep ? mk(A.ub[2 * e], A.ub[2 * e + 1]) : mk(0.f, 0.f);
+    bool in_mean = c == W_INF ? r == W_INF : r == W_STD;
+    f2 ubp = keep ? mk(A.ub_in[2 * e], A.ub_in[2 * e + 1]) : mk(0.f, 0.f);
     f2 gg = in_mean ? mk(A.g[2 * t], A.g[2 * t + 1]) : mk(0.f, 0.f);
     xb = add(scl(ubp, A.step), gg);
     up = add(ubp, gg);
 }
 
-__device__ __forceinline__ f2 edge_n(const Adj &A, long long t, long long e) {
-    return mk(A.z[2 * t] - A.u[2 * e], A.z[2 * t + 1] - A.u[2 * e + 1]);
+// dL/du^k of edge e and dL/dn into its node's dL/dz^k.  kept_prev: the edge
+// is kept by iteration k-1's u update (its factor sent rho0 there too and
+// the node keeps rho0), so its dL/du^k enters that step's sum S.
+__device__ __forceinline__ void edge_out(const Adj &A, long long t, long long e, f2 up, f2 nb, bool kept_prev = false) {
+    const f2 uo = mk(up.x - nb.x, up.y - nb.y);
+    A.ub_out[2 * e] = uo.x;
+    A.ub_out[2 * e + 1] = uo.y;
+    atomicAdd(&A.zb_out[2 * t], nb.x);
+    atomicAdd(&A.zb_out[2 * t + 1], nb.y);
+    if (kept_prev) {
+        atomicAdd(&A.S_next[2 * t], uo.x);
+        atomicAdd(&A.S_next[2 * t + 1], uo.y);
+    }
 }
 
-__device__ __forceinline__ void edge_out(const Adj &A, long long e, f2 up, f2 nb) {
-    A.ub[2 * e] = up.x - nb.x;
-    A.ub[2 * e + 1] = up.y - nb.y;
-    A.nb[2 * e] = nb.x;
-    A.nb[2 * e + 1] = nb.y;
-}
-
-// one lane per factor, canonical factor order
-__global__ __launch_bounds__(256) void k_adj_factors(Adj A) {
-    long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= A.F) return;
-    int r = A.rout[f];
+// A fixed or energy factor (canonical factor index f < f_coll).
+__device__ __forceinline__ void adj_small(const Adj &A, long long f) {
+    const int r = A.rout[f];
     if (f < A.f_energy) {
         // fixed start / goal factor: x is the constant itself
-        int i = (int)(f >> 1);
-        int s = (f & 1) ? A.eta : 0;
-        long long t = node_id(A, i, s), e = f;
+        const int i = (int)(f >> 1);
+        const int s = (f & 1) ? A.eta : 0;
+        const long long t = node_id(A, i, s), e = f;
         f2 xb, up;
         edge_xbar(A, r, t, e, xb, up);
         float *dst = (f & 1) ? A.dxT : A.dx0;
         dst[2 * i] += xb.x;
         dst[2 * i + 1] += xb.y;
-        edge_out(A, e, up, mk(0.f, 0.f));
-    } else if (f < A.f_coll) {
+        edge_out(A, t, e, up, mk(0.f, 0.f));
+    } else {
         // energy factor (App. E): linear in n
-        long long fe = f - A.f_energy;
-        int i = (int)(fe / A.eta), s = (int)(fe % A.eta);
-        long long t0 = node_id(A, i, s), t1 = t0 + 1;
-        long long e0 = A.e_energy + 2 * fe, e1 = e0 + 1;
+        const long long fe = f - A.f_energy;
+        const int i = (int)(fe / A.eta), s = (int)(fe % A.eta);
+        const long long t0 = node_id(A, i, s), t1 = t0 + 1;
+        const long long e0 = A.e_energy + 2 * fe, e1 = e0 + 1;
         f2 xb0, up0, xb1, up1;
         edge_xbar(A, r, t0, e0, xb0, up0);
         edge_xbar(A, r, t1, e1, xb1, up1);
-        int k0 = A.l[t0], k1 = A.l[t1];
-        float w0 = wval(k0, A.rho), w1 = wval(k1, A.rho);
-        float C = A.C[fe];
+        const int k0 = A.l[t0], k1 = A.l[t1];
+        const float w0 = wval(k0, A.rho), w1 = wval(k1, A.rho);
+        const float C = A.C[fe];
         float nb[4] = {0.f, 0.f, 0.f, 0.f};
         energy_vjp(w0, w1, k0, k1, C, xb0.x, xb1.x, nb[0], nb[2]);
         energy_vjp(w0, w1, k0, k1, C, xb0.y, xb1.y, nb[1], nb[3]);
-        edge_out(A, e0, up0, mk(nb[0], nb[1]));
-        edge_out(A, e1, up1, mk(nb[2], nb[3]));
-    } else if (f < A.f_wall) {
-        // collision factor (App. C): (s, i, j) from the triangular index
-        long long fc = f - A.f_coll;
-        int s = (int)(fc / A.P2);
-        long long q = fc - (long long)s * A.P2;
-        double b = 2.0 * A.p - 1.0;
-        int i = (int)floor((b - sqrt(fmax(b * b - 8.0 * (double)q, 0.0))) * 0.5);
-        i = max(0, min(i, A.p - 2));
-        while (i > 0 && pair_index(A.p, i, i + 1) > q) --i;
-        while (i < A.p - 2 && pair_index(A.p, i + 1, i + 2) <= q) ++i;
-        int j = (int)(q - pair_index(A.p, i, i + 1)) + i + 1;
+        edge_out(A, t0, e0, up0, mk(nb[0], nb[1]));
+        edge_out(A, t1, e1, up1, mk(nb[2], nb[3]));
+    }
+}
+
+// A collision or wall factor that sent rho0 (one captured record).
+__device__ __forceinline__ void adj_active(const Adj &A, const AdjRec &rec) {
+    if (!rec.wall) {
+        // collision factor (App. C)
+        const long long fc = rec.f;
+        int s = (int)(fc / A.P2), i, j;
+        pair_of(A.p, fc - (long long)s * A.P2, i, j);
         long long t[4] = {node_id(A, i, s), node_id(A, i, s + 1), node_id(A, j, s), node_id(A, j, s + 1)};
         long long e0 = A.e_coll + 4 * fc;
-        float xb[8], n[8], w[4], nbv[8];
+        float xb[8], w[4], nbv[8];
         int k[4];
         f2 up[4];
         for (int qq = 0; qq < 4; ++qq) {
             f2 x_b;
-            edge_xbar(A, r, t[qq], e0 + qq, x_b, up[qq]);
+            edge_xbar(A, W_STD, t[qq], e0 + qq, x_b, up[qq]);
             xb[2 * qq] = x_b.x, xb[2 * qq + 1] = x_b.y;
-            f2 nn = edge_n(A, t[qq], e0 + qq);
-            n[2 * qq] = nn.x, n[2 * qq + 1] = nn.y;
             k[qq] = A.l[t[qq]];
             w[qq] = wval(k[qq], A.rho);
         }
-        if (r == W_STD) {
-            for (int qq = 0; qq < 8; ++qq) nbv[qq] = 0.f;
-            float Rb = 0.f;
-            coll_vjp2(n, w, k, A.radii[i] + A.radii[j], xb, nbv, Rb);
-            atomicAdd(&A.drd[i], (double)Rb);
-            atomicAdd(&A.drd[j], (double)Rb);
-        } else {
-            // inactive: x = n
-            for (int qq = 0; qq < 8; ++qq) nbv[qq] = xb[qq];
-        }
-        for (int qq = 0; qq < 4; ++qq) edge_out(A, e0 + qq, up[qq], mk(nbv[2 * qq], nbv[2 * qq + 1]));
+        for (int qq = 0; qq < 8; ++qq) nbv[qq] = 0.f;
+        float Rb = 0.f;
+        coll_vjp2(rec.n, w, k, A.radii[i] + A.radii[j], xb, nbv, Rb);
+        atomicAdd(&A.drd[i], (double)Rb);
+        atomicAdd(&A.drd[j], (double)Rb);
+        const bool prev = A.rout_prev && A.rout_prev[A.f_coll + fc] == W_STD;
+        for (int qq = 0; qq < 4; ++qq)
+            edge_out(A, t[qq], e0 + qq, up[qq], mk(nbv[2 * qq], nbv[2 * qq + 1]), prev && A.l[t[qq]] == W_STD);
     } else {
         // wall factor (App. D)
-        long long fw = f - A.f_wall;
+        const long long fw = rec.f;
         long long per_s = (long long)A.p * A.W;
         int s = (int)(fw / per_s);
         long long q = fw - (long long)s * per_s;
@@ -269,27 +257,41 @@ __global__ __launch_bounds__(256) void k_adj_factors(Adj A) {
         long long t0 = node_id(A, i, s), t1 = t0 + 1;
         long long e0 = A.e_wall + 2 * fw, e1 = e0 + 1;
         f2 xb0, up0, xb1, up1;
-        edge_xbar(A, r, t0, e0, xb0, up0);
-        edge_xbar(A, r, t1, e1, xb1, up1);
-        f2 nb0 = xb0, nb1 = xb1;
-        if (r == W_STD) {
-            float4 wl = A.walls[wi];
-            Capsule Cw{mk(wl.x, wl.y), mk(wl.z, wl.w), A.radii[i]};
-            f2 n0 = edge_n(A, t0, e0), n1 = edge_n(A, t1, e1);
-            int k0 = A.l[t0], k1 = A.l[t1];
-            float w0 = wval(k0, A.rho), w1 = wval(k1, A.rho);
-            f2 x0, x1;
-            Choice ch;
-            capsule_prox(Cw, n0, n1, w0, w1, k0, k1, x0, x1, &ch);
-            nb0 = mk(0.f, 0.f);
-            nb1 = mk(0.f, 0.f);
-            float rb = 0.f;
-            capsule_vjp(Cw, n0, n1, w0, w1, k0, k1, ch, xb0, xb1, nb0, nb1, rb);
-            atomicAdd(&A.drd[i], (double)rb);
-        }
-        edge_out(A, e0, up0, nb0);
-        edge_out(A, e1, up1, nb1);
+        edge_xbar(A, W_STD, t0, e0, xb0, up0);
+        edge_xbar(A, W_STD, t1, e1, xb1, up1);
+        float4 wl = A.walls[wi];
+        Capsule Cw{mk(wl.x, wl.y), mk(wl.z, wl.w), A.radii[i]};
+        f2 n0 = mk(rec.n[0], rec.n[1]), n1 = mk(rec.n[2], rec.n[3]);
+        int k0 = A.l[t0], k1 = A.l[t1];
+        float w0 = wval(k0, A.rho), w1 = wval(k1, A.rho);
+        f2 x0, x1;
+        Choice ch;
+        capsule_prox(Cw, n0, n1, w0, w1, k0, k1, x0, x1, &ch);
+        f2 nb0 = mk(0.f, 0.f), nb1 = mk(0.f, 0.f);
+        float rb = 0.f;
+        capsule_vjp(Cw, n0, n1, w0, w1, k0, k1, ch, xb0, xb1, nb0, nb1, rb);
+        atomicAdd(&A.drd[i], (double)rb);
+        const bool prev = A.rout_prev && A.rout_prev[A.f_wall + fw] == W_STD;
+        edge_out(A, t0, e0, up0, nb0, prev && A.l[t0] == W_STD);
+        edge_out(A, t1, e1, up1, nb1, prev && A.l[t1] == W_STD);
     }
+}
+
+// The factors of one reverse step: blocks [0, nb_small) take the fixed and
+// energy factors one lane each; the rest stride over the captured records
+// [offs[0], offs[1]) (clipped to the pool's capacity), one lane each, so the
+// non-linear derivatives run in full waves.
+__global__ __launch_bounds__(256) void k_adj_factors(Adj A, unsigned nb_small, const AdjRec *pool, const unsigned *offs,
+                                                     unsigned cap) {
+    if (blockIdx.x < nb_small) {
+        const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+        if (f < A.f_coll) adj_small(A, f);
+        return;
+    }
+    const unsigned b = offs[0], e = min(offs[1], cap);
+    const unsigned nblk = gridDim.x - nb_small;
+    for (unsigned t = b + (blockIdx.x - nb_small) * blockDim.x + threadIdx.x; t < e; t += nblk * blockDim.x)
+        adj_active(A, pool[t]);
 }
 
 // z^0 cotangent: its end points are the start and goal
@@ -300,45 +302,360 @@ __global__ void k_adj_finish(Adj A, float *dz0, float *dr) {
         bool end = s == 0 || s == A.eta;
         if (end) {
             float *dst = s == 0 ? A.dx0 : A.dxT;
-            dst[2 * i] += A.zb[2 * t];
-            dst[2 * i + 1] += A.zb[2 * t + 1];
+            dst[2 * i] += A.zb_in[2 * t];
+            dst[2 * i + 1] += A.zb_in[2 * t + 1];
         }
         if (dz0) {
-            dz0[2 * t] = end ? 0.f : A.zb[2 * t];
-            dz0[2 * t + 1] = end ? 0.f : A.zb[2 * t + 1];
+            dz0[2 * t] = end ? 0.f : A.zb_in[2 * t];
+            dz0[2 * t + 1] = end ? 0.f : A.zb_in[2 * t + 1];
         }
     }
     if (t < A.p) dr[t] = (float)A.drd[t];
 }
 
-// device buffers of one twa_backward call, freed on every exit path
-struct Scratch {
-    std::vector<void *> ptrs;
-    ~Scratch() {
-        for (void *p : ptrs) (void)hipFree(p);
-    }
-    template <class T>
-    bool get(T **out, size_t count) {
-        void *p = nullptr;
-        if (hipMalloc(&p, std::max<size_t>(count * sizeof(T), 16)) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
+// A state with its collision / wall u sparse (a checkpoint): z, <-rho and
+// the u of the fixed and energy edges dense, then one record per collision
+// or wall factor with a nonzero u (its index among all factors and its
+// edges' u) in the record arena, from arena index *first to *end.
+struct Sparse {
+    float *z;          // [N][2]
+    unsigned char *l;  // [N]
+    float *u_small;    // [e_coll][2]: the fixed and energy edges
+    unsigned *first, *end; // device
+};
+
+// canonical dense u -> arena records of the collision / wall factors with a
+// nonzero u (appended at *cursor; those past cap are dropped, the cursor
+// still counts them)
+__global__ __launch_bounds__(256) void k_pack(const float *u, long long f_coll, long long nfac, long long e_coll,
+                                              long long Fc, AdjRec *arena, unsigned cap, unsigned *cursor) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool nz = false;
+    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (q < nfac) {
+        const bool wall = q >= Fc;
+        const long long e0 = wall ? e_coll + 4 * Fc + 2 * (q - Fc) : e_coll + 4 * q;
+        const int nv = wall ? 4 : 8;
+        for (int c = 0; c < nv; ++c) {
+            v[c] = u[2 * e0 + c];
+            nz = nz || v[c] != 0.f;
         }
-        ptrs.push_back(p);
-        *out = static_cast<T *>(p);
-        return true;
+    }
+    const unsigned long long mask = __ballot(nz);
+    if (mask == 0ull) return;
+    const int lane = __lane_id(), leader = __ffsll((long long)mask) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(cursor, (unsigned)__popcll(mask));
+    base = __shfl(base, leader);
+    const unsigned idx = base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+    if (nz && idx < cap) {
+        AdjRec r;
+        r.f = (unsigned)(f_coll + q);
+        r.wall = q >= Fc;
+        for (int c = 0; c < 8; ++c) r.n[c] = v[c];
+        arena[idx] = r;
+    }
+}
+
+// arena records [*first, *end) -> canonical dense u (zeroed before)
+__global__ __launch_bounds__(256) void k_unpack(float *u, long long f_coll, long long e_coll, long long Fc,
+                                                const AdjRec *arena, const unsigned *first, const unsigned *end,
+                                                unsigned cap) {
+    const unsigned b = *first, e = min(*end, cap);
+    for (unsigned t = b + blockIdx.x * blockDim.x + threadIdx.x; t < e; t += gridDim.x * blockDim.x) {
+        const AdjRec r = arena[t];
+        const long long q = (long long)r.f - f_coll;
+        const long long e0 = r.wall ? e_coll + 4 * Fc + 2 * (q - Fc) : e_coll + 4 * q;
+        const int nv = r.wall ? 4 : 8;
+        for (int c = 0; c < nv; ++c) u[2 * e0 + c] = r.n[c];
+    }
+}
+
+__global__ void k_copy_u32(unsigned *dst, const unsigned *src) { *dst = *src; }
+
+__global__ void k_fill_float(float *p, long long n) {
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+        p[t] = 0.f;
+}
+
+// ------------------------------------------------------------------ workspace
+// Bump allocation of one call's buffers from a region (the solver's own,
+// allocated at its first call and kept).  With base == nullptr it only adds
+// up the sizes.
+struct Region {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    template <class T>
+    T *take(size_t count) {
+        const size_t off = (used + 255) & ~(size_t)255;
+        const size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+        if (base && off + bytes > cap) return nullptr;
+        used = off + bytes;
+        return base ? reinterpret_cast<T *>(base + off) : reinterpret_cast<T *>(256);
     }
 };
 
-struct StateBuf {
-    float *z = nullptr, *u = nullptr;
-    unsigned char *l = nullptr;
+struct Shape {
+    long long N, E, F, K, L, ncp, len_max, e_small, nfac;
+    int p;
 };
 
-} // namespace
+Shape shape_of(const twa_solver *s) {
+    const twa_rt::Params &P = s->P;
+    Shape h;
+    h.N = P.N, h.E = P.e_wall + 2 * P.Fw, h.F = P.Ff + P.Fe + P.Fc + P.Fw, h.p = s->p;
+    h.e_small = P.e_coll, h.nfac = P.Fc + P.Fw;
+    h.K = s->iter - s->origin_iter;
+    h.L = std::max<long long>(1, (long long)std::ceil(std::sqrt((double)std::max<long long>(h.K, 0))));
+    h.ncp = h.K > 0 ? (h.K + h.L - 1) / h.L : 0;
+    h.len_max = std::min(h.L, std::max<long long>(h.K, 1));
+    return h;
+}
 
-extern "C" twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT, float *dL_dr,
-                                   float *dL_dz0) {
+// Everything a call needs besides the record arena and the capture pool.
+// Checkpoint c's arrays are slices c of the ck_* arrays (no host-side table).
+struct Buffers {
+    Sparse cur;                   // the forward state at the call, restored at the end
+    float *ck_z, *ck_us;          // [ncp][N][2], [ncp][e_small][2]
+    unsigned char *ck_l;          // [ncp][N]
+    unsigned *ck_first, *ck_end;  // [ncp]
+    float *u_tmp;                 // [E][2] dense u of a state being packed or unpacked
+    // two cotangent sets, alternately a reverse step's input and its output
+    // (the output is cleared in one memset): dL/du [E][2], dL/dz [N][2], and
+    // the per-node sum S [N][2] that the step after it reads
+    char *set[2];
+    size_t set_bytes;
+    float *g;                     // [N][2]
+    unsigned char *cls;           // [N]
+    double *drd;                  // [p]
+    unsigned *arena_cursor, *pool_cursor;
+    unsigned *offs;               // [len_max + 1] pool cursor before each iteration of a segment
+    unsigned char *rout;          // [len_max][F] ->rho of each iteration of a segment
+    unsigned char *lseg;          // [len_max + 1][N] <-rho before each iteration, and after the last
+    int *cntseg;                  // [len_max][N] size of each node's mean set in each iteration
+    AdjRec *arena, *pool;
+    unsigned arena_cap, pool_cap;
+};
+
+// Carve one cotangent set (see Buffers) from base; returns its size.
+size_t set_layout(const Shape &h, char *base, float **ub = nullptr, float **zb = nullptr, float **S = nullptr) {
+    Region R;
+    R.base = base;
+    R.cap = ~(size_t)0;
+    float *a = R.take<float>((size_t)h.E * 2);
+    float *b = R.take<float>((size_t)h.N * 2);
+    float *c = R.take<float>((size_t)h.N * 2);
+    if (ub) *ub = a, *zb = b, *S = c;
+    return R.used;
+}
+
+bool layout(Region &R, const Shape &h, Buffers &B) {
+    B.cur.z = R.take<float>((size_t)h.N * 2);
+    B.cur.l = R.take<unsigned char>((size_t)h.N);
+    B.cur.u_small = R.take<float>((size_t)h.e_small * 2);
+    B.cur.first = R.take<unsigned>(1);
+    B.cur.end = R.take<unsigned>(1);
+    const size_t nc = (size_t)std::max<long long>(h.ncp, 1);
+    B.ck_z = R.take<float>(nc * h.N * 2);
+    B.ck_us = R.take<float>(nc * h.e_small * 2);
+    B.ck_l = R.take<unsigned char>(nc * h.N);
+    B.ck_first = R.take<unsigned>(nc);
+    B.ck_end = R.take<unsigned>(nc);
+    B.u_tmp = R.take<float>((size_t)h.E * 2);
+    B.set_bytes = set_layout(h, nullptr);
+    B.set[0] = R.take<char>(B.set_bytes);
+    B.set[1] = R.take<char>(B.set_bytes);
+    B.g = R.take<float>((size_t)h.N * 2);
+    B.cls = R.take<unsigned char>((size_t)h.N);
+    B.drd = R.take<double>((size_t)h.p);
+    B.arena_cursor = R.take<unsigned>(1);
+    B.pool_cursor = R.take<unsigned>(1);
+    B.offs = R.take<unsigned>((size_t)h.len_max + 1);
+    B.rout = R.take<unsigned char>((size_t)h.len_max * h.F);
+    B.lseg = R.take<unsigned char>((size_t)(h.len_max + 1) * h.N);
+    B.cntseg = R.take<int>((size_t)h.len_max * h.N);
+    return B.cur.z && B.cur.l && B.cur.u_small && B.cur.first && B.cur.end && B.ck_z && B.ck_us && B.ck_l &&
+           B.ck_first && B.ck_end && B.u_tmp && B.set[0] && B.set[1] && B.g && B.cls && B.drd && B.arena_cursor &&
+           B.pool_cursor && B.offs && B.rout && B.lseg && B.cntseg;
+}
+
+Sparse ckpt(const Buffers &B, const Shape &h, long long c) {
+    Sparse q;
+    q.z = B.ck_z + c * h.N * 2;
+    q.l = B.ck_l + c * h.N;
+    q.u_small = B.ck_us + c * h.e_small * 2;
+    q.first = B.ck_first + c;
+    q.end = B.ck_end + c;
+    return q;
+}
+
+unsigned grid_for(unsigned long long n) { return (unsigned)std::max<unsigned long long>(1, std::min<unsigned long long>((n + 255) / 256, 1024)); }
+
+// the solver's current state into q: z and <-rho, the fixed and energy u
+// dense, the collision / wall u as arena records
+twa_status pack(twa_solver *s, const Shape &h, Buffers &B, const Sparse &q) {
+    long long it = 0;
+    TRY(twa_get_state(s, q.z, B.u_tmp, q.l, &it)); // settles the pending u update
+    HIP_TRY(s, hipMemcpyAsync(q.u_small, B.u_tmp, sizeof(float) * 2 * h.e_small, hipMemcpyDeviceToDevice, s->stream));
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s->stream, q.first, (const unsigned *)B.arena_cursor);
+    if (h.nfac > 0)
+        hipLaunchKernelGGL(k_pack, dim3((unsigned)((h.nfac + 255) / 256)), dim3(256), 0, s->stream,
+                           (const float *)B.u_tmp, s->P.f_coll, h.nfac, h.e_small, s->P.Fc, B.arena, B.arena_cap,
+                           B.arena_cursor);
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s->stream, q.end, (const unsigned *)B.arena_cursor);
+    HIP_TRY(s, hipGetLastError());
+    return TWA_OK;
+}
+
+// state q into the solver, at iteration k
+twa_status unpack(twa_solver *s, const Shape &h, Buffers &B, const Sparse &q, long long k) {
+    hipLaunchKernelGGL(k_fill_float, dim3(grid_for((unsigned long long)h.E * 2)), dim3(256), 0, s->stream, B.u_tmp,
+                       h.E * 2);
+    HIP_TRY(s, hipMemcpyAsync(B.u_tmp, q.u_small, sizeof(float) * 2 * h.e_small, hipMemcpyDeviceToDevice, s->stream));
+    hipLaunchKernelGGL(k_unpack, dim3(grid_for(B.arena_cap)), dim3(256), 0, s->stream, B.u_tmp, s->P.f_coll,
+                       h.e_small, s->P.Fc, (const AdjRec *)B.arena, (const unsigned *)q.first,
+                       (const unsigned *)q.end, B.arena_cap);
+    HIP_TRY(s, hipGetLastError());
+    return twa_rt::import_state(s, q.z, B.u_tmp, q.l, k);
+}
+
+// what made an attempt stop short
+enum { kDone = 0, kArenaFull = 1, kPoolFull = 2 };
+
+// One attempt of the whole computation with the buffers of B.  *outcome is
+// kDone, or which record store ran out (*need: the records it wanted); the
+// solver's forward state is restored either way.
+// grow_pool (may be null): make the capture pool hold `need` records, for
+// the segment to be recomputed once more; without it an overflow ends the
+// attempt.
+using GrowPool = twa_status (*)(twa_solver *s, Buffers &B, unsigned need);
+
+twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_dz, float *dL_dx0, float *dL_dxT,
+                    float *dL_dr, float *dL_dz0, int *outcome, unsigned *need, GrowPool grow_pool) {
+    const twa_rt::Params &P = s->P;
+    hipStream_t st = s->stream;
+    *outcome = kDone;
+    *need = 0;
+    HIP_TRY(s, hipMemsetAsync(B.arena_cursor, 0, sizeof(unsigned), st));
+    const long long cur_iter = s->iter, it0 = s->origin_iter;
+    TRY(pack(s, h, B, B.cur));
+    unsigned used = 0;
+    HIP_TRY(s, hipMemcpyAsync(&used, B.arena_cursor, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    HIP_TRY(s, hipStreamSynchronize(st));
+    if (used > B.arena_cap) {
+        // the forward state itself did not fit: nothing else was touched
+        *outcome = kArenaFull;
+        *need = used;
+        return TWA_OK;
+    }
+    // pass 1: checkpoints every L iterations from the run's start
+    if (h.K > 0) TRY(twa_rt::import_state(s, s->origin_z, s->origin_u, s->origin_l, it0));
+    for (long long c = 0; c < h.ncp; ++c) {
+        TRY(pack(s, h, B, ckpt(B, h, c)));
+        if (c + 1 < h.ncp) TRY(twa_iterate(s, (int)h.L));
+    }
+    HIP_TRY(s, hipMemcpyAsync(&used, B.arena_cursor, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    HIP_TRY(s, hipStreamSynchronize(st));
+    if (used > B.arena_cap) {
+        *outcome = kArenaFull;
+        *need = used;
+        return unpack(s, h, B, B.cur, cur_iter);
+    }
+
+    Adj A{};
+    A.p = s->p, A.eta = s->eta, A.W = s->W;
+    A.P2 = (long long)s->p * (s->p - 1) / 2, A.N = h.N, A.E = h.E, A.F = h.F;
+    A.e_energy = P.e_energy, A.e_coll = P.e_coll, A.e_wall = P.e_wall;
+    A.f_energy = P.f_energy, A.f_coll = P.f_coll, A.f_wall = P.f_wall;
+    A.radii = P.radii, A.walls = P.walls, A.C = P.C;
+    A.g = B.g, A.cls = B.cls, A.dx0 = dL_dx0, A.dxT = dL_dxT, A.drd = B.drd;
+    int in = 0; // the set holding dL/d(state after the step being reversed)
+    {
+        float *ub, *zb, *S;
+        set_layout(h, B.set[in], &ub, &zb, &S);
+        HIP_TRY(s, hipMemsetAsync(B.set[in], 0, B.set_bytes, st));
+        HIP_TRY(s, hipMemcpyAsync(zb, dL_dz, sizeof(float) * h.N * 2, hipMemcpyDeviceToDevice, st));
+    }
+    HIP_TRY(s, hipMemsetAsync(dL_dx0, 0, sizeof(float) * s->p * 2, st));
+    HIP_TRY(s, hipMemsetAsync(dL_dxT, 0, sizeof(float) * s->p * 2, st));
+    HIP_TRY(s, hipMemsetAsync(B.drd, 0, sizeof(double) * s->p, st));
+    const unsigned nb_nodes = (unsigned)((h.N + 255) / 256), nb_small = (unsigned)((P.f_coll + 255) / 256);
+    const unsigned nb_rec = 256; // blocks striding over the captured records
+
+    // pass 2: segments in reverse; recompute each capturing its decisions,
+    // then run it backwards
+    for (long long c = h.ncp - 1; c >= 0; --c) {
+        const long long k0 = it0 + c * h.L, len = std::min(h.L, h.K - c * h.L);
+    recompute:
+        TRY(unpack(s, h, B, ckpt(B, h, c), k0));
+        HIP_TRY(s, hipMemsetAsync(B.pool_cursor, 0, sizeof(unsigned), st));
+        HIP_TRY(s, hipMemsetAsync(B.offs, 0, sizeof(unsigned), st));
+        TRY(twa_rt::export_lrho(s, B.lseg));
+        for (long long t = 0; t < len; ++t) {
+            // the iteration's weights, its captured factors, and (from its
+            // node pass) the new <-rho codes, the mean-set sizes and the
+            // capture cursor
+            s->dbg_rho = B.rout + t * h.F;
+            s->adj_pool = B.pool;
+            s->adj_cursor = B.pool_cursor;
+            s->adj_cap = B.pool_cap;
+            s->adj_offs = B.offs + t + 1;
+            s->dbg_l = B.lseg + (t + 1) * h.N;
+            s->dbg_cnt = B.cntseg + t * h.N;
+            TRY(twa_iterate(s, 1));
+        }
+        HIP_TRY(s, hipMemcpyAsync(&used, B.pool_cursor, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        HIP_TRY(s, hipStreamSynchronize(st));
+        if (used > B.pool_cap) {
+            if (grow_pool) {
+                TRY(grow_pool(s, B, used));
+                goto recompute;
+            }
+            *outcome = kPoolFull;
+            *need = used;
+            return unpack(s, h, B, B.cur, cur_iter);
+        }
+        for (long long t = len - 1; t >= 0; --t) {
+            float *ub_in, *zb_in, *S_in, *ub_out, *zb_out, *S_out;
+            set_layout(h, B.set[in], &ub_in, &zb_in, &S_in);
+            set_layout(h, B.set[1 - in], &ub_out, &zb_out, &S_out);
+            A.ub_in = ub_in, A.zb_in = zb_in, A.S_in = S_in;
+            A.ub_out = ub_out, A.zb_out = zb_out, A.S_next = S_out;
+            A.l = B.lseg + t * h.N;
+            A.lnext = B.lseg + (t + 1) * h.N;
+            A.cnt = B.cntseg + t * h.N;
+            A.rout = B.rout + t * h.F;
+            A.rout_prev = t > 0 ? B.rout + (t - 1) * h.F : nullptr;
+            A.rho = twa_rt::rho_at(s, k0 + t);
+            A.step = s->alpha / A.rho;
+            const unsigned *offs = B.offs + t;
+            // the step after this one belongs to the segment reversed before
+            // (or is the loss): it could not accumulate this step's S
+            if (t == len - 1)
+                hipLaunchKernelGGL(k_adj_accum, dim3(nb_rec), dim3(256), 0, st, A, S_in, (const AdjRec *)B.pool, offs,
+                                   B.pool_cap);
+            HIP_TRY(s, hipMemsetAsync(B.set[1 - in], 0, B.set_bytes, st));
+            hipLaunchKernelGGL(k_adj_select, dim3(nb_nodes), dim3(256), 0, st, A);
+            hipLaunchKernelGGL(k_adj_factors, dim3(nb_small + nb_rec), dim3(256), 0, st, A, nb_small,
+                               (const AdjRec *)B.pool, offs, B.pool_cap);
+            HIP_TRY(s, hipGetLastError());
+            in = 1 - in;
+        }
+    }
+    {
+        float *ub, *zb, *S;
+        set_layout(h, B.set[in], &ub, &zb, &S);
+        A.zb_in = zb;
+    }
+    const long long nfin = std::max<long long>(h.N, s->p);
+    hipLaunchKernelGGL(k_adj_finish, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, st, A, dL_dz0, dL_dr);
+    HIP_TRY(s, hipGetLastError());
+    TRY(unpack(s, h, B, B.cur, cur_iter));
+    HIP_TRY(s, hipStreamSynchronize(st));
+    return TWA_OK;
+}
+
+twa_status check_args(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT, float *dL_dr) {
     using twa_rt::fail;
     TRY(twa_rt::check_alive(s));
     if (!(s->flags & TWA_F_TAPE)) return fail(s, TWA_E_STATE, "twa_backward needs TWA_F_TAPE at create");
@@ -346,86 +663,71 @@ extern "C" twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_
     if (s->P.admm) return fail(s, TWA_E_INVALID, "twa_backward supports the three-weight mode only");
     if (s->P.cost != 0) return fail(s, TWA_E_INVALID, "twa_backward supports the energy cost only");
     if (!dL_dz || !dL_dx0 || !dL_dxT || !dL_dr) return fail(s, TWA_E_INVALID, "null array argument");
-    const twa_rt::Params &P = s->P;
-    const long long N = P.N, E = P.e_wall + 2 * P.Fw, F = P.Ff + P.Fe + P.Fc + P.Fw;
-    const long long K = s->iter - s->origin_iter;
-    if (K < 0) return fail(s, TWA_E_STATE, "iteration count below the run's start");
-    const int D = 2;
-    const long long L = std::max<long long>(1, (long long)std::ceil(std::sqrt((double)K)));
-    const long long ncp = K > 0 ? (K + L - 1) / L : 0;
-
-    Scratch sc;
-    auto state_buf = [&](StateBuf &b) {
-        return sc.get(&b.z, (size_t)N * D) && sc.get(&b.u, (size_t)E * D) && sc.get(&b.l, (size_t)N);
-    };
-    StateBuf cur;
-    std::vector<StateBuf> ckpt((size_t)ncp), seg((size_t)std::min(L, K));
-    std::vector<unsigned char *> rout((size_t)std::min(L, K));
-    unsigned char *lnext = nullptr, *cls = nullptr;
-    float *xscr = nullptr, *zb = nullptr, *ub = nullptr, *g = nullptr, *nb = nullptr;
-    double *drd = nullptr;
-    bool ok = state_buf(cur) && sc.get(&lnext, (size_t)N) && sc.get(&cls, (size_t)N) &&
-              sc.get(&xscr, (size_t)E * D) && sc.get(&zb, (size_t)N * D) && sc.get(&ub, (size_t)E * D) &&
-              sc.get(&g, (size_t)N * D) && sc.get(&nb, (size_t)E * D) && sc.get(&drd, (size_t)s->p);
-    for (auto &b : ckpt) ok = ok && state_buf(b);
-    for (size_t q = 0; q < seg.size(); ++q) ok = ok && state_buf(seg[q]) && sc.get(&rout[q], (size_t)F);
-    if (!ok) return fail(s, TWA_E_NOMEM, "twa_backward: checkpoint allocation failed");
-
-    // keep the forward state to restore it at the end
-    long long cur_iter = 0;
-    TRY(twa_get_state(s, cur.z, cur.u, cur.l, &cur_iter));
-    const long long it0 = s->origin_iter;
-
-    // pass 1: checkpoints every L iterations from the run's start
-    if (K > 0) TRY(twa_rt::import_state(s, s->origin_z, s->origin_u, s->origin_l, it0));
-    for (long long c = 0; c < ncp; ++c) {
-        long long dummy;
-        TRY(twa_get_state(s, ckpt[c].z, ckpt[c].u, ckpt[c].l, &dummy));
-        if (c + 1 < ncp) TRY(twa_iterate(s, (int)L));
-    }
-
-    Adj A{};
-    A.p = s->p, A.eta = s->eta, A.W = s->W;
-    A.P2 = (long long)s->p * (s->p - 1) / 2, A.N = N, A.E = E, A.F = F;
-    A.e_energy = P.e_energy, A.e_coll = P.e_coll, A.e_wall = P.e_wall;
-    A.f_energy = P.f_energy, A.f_coll = P.f_coll, A.f_wall = P.f_wall;
-    A.radii = P.radii, A.walls = P.walls, A.C = P.C;
-    A.zb = zb, A.ub = ub, A.g = g, A.cls = cls, A.nb = nb, A.dx0 = dL_dx0, A.dxT = dL_dxT, A.drd = drd;
-    HIP_TRY(s, hipMemcpyAsync(zb, dL_dz, sizeof(float) * N * D, hipMemcpyDeviceToDevice, s->stream));
-    HIP_TRY(s, hipMemsetAsync(ub, 0, sizeof(float) * E * D, s->stream));
-    HIP_TRY(s, hipMemsetAsync(dL_dx0, 0, sizeof(float) * s->p * D, s->stream));
-    HIP_TRY(s, hipMemsetAsync(dL_dxT, 0, sizeof(float) * s->p * D, s->stream));
-    HIP_TRY(s, hipMemsetAsync(drd, 0, sizeof(double) * s->p, s->stream));
-    const unsigned nb_nodes = (unsigned)((N + 3) / 4), nb_fac = (unsigned)((F + 255) / 256);
-
-    // pass 2: segments in reverse; recompute each with every state kept
-    for (long long c = ncp - 1; c >= 0; --c) {
-        long long k0 = it0 + c * L, len = std::min(L, K - c * L);
-        TRY(twa_rt::import_state(s, ckpt[c].z, ckpt[c].u, ckpt[c].l, k0));
-        for (long long t = 0; t < len; ++t) {
-            long long dummy;
-            TRY(twa_get_state(s, seg[t].z, seg[t].u, seg[t].l, &dummy));
-            TRY(twa_capture_next(s, xscr, rout[t]));
-            TRY(twa_iterate(s, 1));
-        }
-        TRY(twa_get_state(s, nullptr, nullptr, lnext, nullptr));
-        for (long long t = len - 1; t >= 0; --t) {
-            A.z = seg[t].z, A.u = seg[t].u, A.l = seg[t].l, A.rout = rout[t];
-            A.lnext = (t + 1 < len) ? seg[t + 1].l : lnext;
-            A.rho = twa_rt::rho_at(s, k0 + t);
-            A.step = s->alpha / A.rho;
-            hipLaunchKernelGGL(k_adj_select, dim3(nb_nodes), dim3(256), 0, s->stream, A);
-            hipLaunchKernelGGL(k_adj_factors, dim3(nb_fac), dim3(256), 0, s->stream, A);
-            hipLaunchKernelGGL(k_adj_gather, dim3(nb_nodes), dim3(256), 0, s->stream, A);
-            HIP_TRY(s, hipGetLastError());
-        }
-    }
-    long long nfin = std::max<long long>(N, s->p);
-    hipLaunchKernelGGL(k_adj_finish, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, s->stream, A, dL_dz0,
-                       dL_dr);
-    HIP_TRY(s, hipGetLastError());
-    // restore the forward state
-    TRY(twa_rt::import_state(s, cur.z, cur.u, cur.l, cur_iter));
-    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    if (s->iter < s->origin_iter) return fail(s, TWA_E_STATE, "iteration count below the run's start");
     return TWA_OK;
+}
+
+twa_status ensure(twa_solver *s, void **buf, size_t *have, size_t want);
+
+// the allocating path's pool growth (a quarter to spare)
+twa_status grow_solver_pool(twa_solver *s, Buffers &B, unsigned need) {
+    const size_t want = std::min<size_t>((size_t)need * 5 / 4 + 1024, 0xffffffffu) * sizeof(AdjRec);
+    TRY(ensure(s, &s->adj_pool_mem, &s->adj_pool_bytes, want));
+    B.pool = static_cast<AdjRec *>(s->adj_pool_mem);
+    B.pool_cap = (unsigned)std::min<size_t>(s->adj_pool_bytes / sizeof(AdjRec), 0xffffffffu);
+    return TWA_OK;
+}
+
+// grow-only device buffer owned by the solver
+twa_status ensure(twa_solver *s, void **buf, size_t *have, size_t want) {
+    if (*have >= want) return TWA_OK;
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *have = 0;
+    if (hipMalloc(buf, want) != hipSuccess) {
+        (void)hipGetLastError();
+        *buf = nullptr;
+        return twa_rt::fail(s, TWA_E_NOMEM, "twa_backward: allocation of " + std::to_string(want) + " bytes failed");
+    }
+    *have = want;
+    return TWA_OK;
+}
+
+} // namespace
+
+extern "C" twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT, float *dL_dr,
+                                   float *dL_dz0) {
+    TRY(check_args(s, dL_dz, dL_dx0, dL_dxT, dL_dr));
+    const Shape h = shape_of(s);
+    Region sz;
+    Buffers B{};
+    layout(sz, h, B);
+    TRY(ensure(s, &s->adj_ws, &s->adj_ws_bytes, sz.used));
+    Region R;
+    R.base = static_cast<char *>(s->adj_ws);
+    R.cap = s->adj_ws_bytes;
+    layout(R, h, B);
+    // record stores: sized from the last iteration's queue, grown on demand
+    int queued = 0;
+    HIP_TRY(s, hipMemcpyAsync(&queued, s->stats_dev + 2, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(s, hipStreamSynchronize(s->stream));
+    const size_t per = 2 * (size_t)std::max(queued, 0) + 1024;
+    size_t want_arena = std::max<size_t>(s->adj_arena_bytes, (size_t)(h.ncp + 1) * per * sizeof(AdjRec));
+    size_t want_pool = std::max<size_t>(s->adj_pool_bytes, (size_t)h.len_max * per * sizeof(AdjRec));
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        const size_t cap_recs = (size_t)0xffffffffu * sizeof(AdjRec);
+        TRY(ensure(s, &s->adj_arena, &s->adj_arena_bytes, std::min(want_arena, cap_recs)));
+        TRY(ensure(s, &s->adj_pool_mem, &s->adj_pool_bytes, std::min(want_pool, cap_recs)));
+        B.arena = static_cast<AdjRec *>(s->adj_arena);
+        B.arena_cap = (unsigned)(s->adj_arena_bytes / sizeof(AdjRec));
+        B.pool = static_cast<AdjRec *>(s->adj_pool_mem);
+        B.pool_cap = (unsigned)(s->adj_pool_bytes / sizeof(AdjRec));
+        int outcome = kDone;
+        unsigned need = 0;
+        TRY(run_once(s, h, B, dL_dz, dL_dx0, dL_dxT, dL_dr, dL_dz0, &outcome, &need, grow_solver_pool));
+        if (outcome == kDone) return TWA_OK;
+        // the arena's need is exact (every checkpoint was counted): one more attempt
+        want_arena = (size_t)need * sizeof(AdjRec) * 5 / 4 + 4096;
+    }
+    return twa_rt::fail(s, TWA_E_NOMEM, "twa_backward: record stores kept overflowing");
 }

@@ -21,6 +21,14 @@ __host__ __device__ __forceinline__ float wval(int code, float rho) {
     return code == twa::W_STD ? rho : (code == twa::W_ZERO ? kZeroWeight * rho : 0.f);
 }
 
+// One active collision or wall factor of an iteration recomputed by
+// twa_backward: its index (within its kind) and the minimiser input n of its
+// edges (planar: 4 edges x 2 for a collision factor, 2 x 2 for a wall).
+struct AdjRec {
+    unsigned f, wall;
+    float n[8];
+};
+
 struct Params {
     int p, eta, W, dim;
     long long Fc, Fw, Fe, Ff;
@@ -67,6 +75,14 @@ struct Params {
     // debug capture of this iteration
     float *dbg_x;
     unsigned char *dbg_rho;
+    // adjoint capture of this iteration (twa_backward): n of every collision
+    // and wall factor that sends weight rho0 is appended to adj_pool
+    AdjRec *adj_pool;
+    unsigned *adj_cursor; // appends attempted (those at index >= adj_cap are dropped)
+    unsigned adj_cap;
+    unsigned *adj_offs;   // the node pass stores the final cursor here
+    unsigned char *dbg_l; // the node pass writes the new <-rho codes here, canonical [p][eta+1]
+    int *dbg_cnt;         // and the size of each node's mean set (its edges of the winning weight)
     long long e_energy, e_coll, e_wall; // canonical edge offsets
     long long f_energy, f_coll, f_wall; // canonical factor offsets
 };
@@ -92,6 +108,12 @@ struct twa_solver {
     twa_status latched = TWA_OK;
     float *dbg_x = nullptr;
     unsigned char *dbg_rho = nullptr;
+    twa_rt::AdjRec *adj_pool = nullptr; // adjoint capture of the next iteration
+    unsigned *adj_cursor = nullptr;
+    unsigned adj_cap = 0;
+    unsigned *adj_offs = nullptr;
+    unsigned char *dbg_l = nullptr;
+    int *dbg_cnt = nullptr;
     long long nblocks_stream = 0;
     int nblocks_queue = 0;
     // event timing (twa_iterate_timed): 1 = kernels launched now take a
@@ -115,6 +137,10 @@ struct twa_solver {
     float *origin_z = nullptr, *origin_u = nullptr;
     unsigned char *origin_l = nullptr;
     long long origin_iter = 0;
+    // twa_backward's buffers: allocated at its first call, grown when a
+    // later call needs more, kept until twa_destroy
+    void *adj_ws = nullptr, *adj_arena = nullptr, *adj_pool_mem = nullptr;
+    size_t adj_ws_bytes = 0, adj_arena_bytes = 0, adj_pool_bytes = 0;
 };
 
 namespace twa_rt {
@@ -128,6 +154,9 @@ float rho_at(const twa_solver *s, long long k);
 // replace the state (canonical device arrays) without touching the start
 // of the differentiated run
 twa_status import_state(twa_solver *s, const float *z, const float *u, const unsigned char *lrho, long long iter);
+// <-rho codes of the current node records, canonical [p][eta+1] (device
+// array); leaves a pending u update pending
+twa_status export_lrho(twa_solver *s, unsigned char *lrho);
 
 } // namespace twa_rt
 

@@ -270,9 +270,10 @@ __device__ __forceinline__ bool coll_factor(const Params &P, long long f, float 
             for (int k = 0; k < D; ++k) n[e * D + k] = zz[k] - u[e * D + k];
         }
         push_new = P.admm || coll_active<D>(n, R);
-        if (!push_new && P.dbg_x) {
+        if (!push_new && P.dbg_rho) {
             long long e0 = P.e_coll + 4 * f;
-            for (int k = 0; k < 4 * D; ++k) P.dbg_x[e0 * D + k] = n[k];
+            if (P.dbg_x)
+                for (int k = 0; k < 4 * D; ++k) P.dbg_x[e0 * D + k] = n[k];
             P.dbg_rho[P.f_coll + f] = W_ZERO;
         }
     }
@@ -469,10 +470,12 @@ __device__ __forceinline__ void wall_stream(const Params &P, const Rec &Z, long 
             float4 za = Z.cur[na], zb = Z.cur[nb];
             f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
             push_new = P.admm || segseg_sq(n0, n1, xa, xb) < r * r;
-            if (!push_new && P.dbg_x) {
+            if (!push_new && P.dbg_rho) {
                 long long e0 = P.e_wall + 2 * f;
-                P.dbg_x[e0 * 2 + 0] = n0.x, P.dbg_x[e0 * 2 + 1] = n0.y;
-                P.dbg_x[e0 * 2 + 2] = n1.x, P.dbg_x[e0 * 2 + 3] = n1.y;
+                if (P.dbg_x) {
+                    P.dbg_x[e0 * 2 + 0] = n0.x, P.dbg_x[e0 * 2 + 1] = n0.y;
+                    P.dbg_x[e0 * 2 + 2] = n1.x, P.dbg_x[e0 * 2 + 3] = n1.y;
+                }
                 P.dbg_rho[P.f_wall + f] = W_ZERO;
             }
         }
@@ -544,9 +547,10 @@ __device__ __forceinline__ void energy_stream(const Params &P, const Rec &Z, lon
         contribute(P, na, 0, m, D);
         contribute(P, nb, 0, m + D, D);
     }
-    if (P.dbg_x) {
+    if (P.dbg_rho) {
         long long e0 = P.e_energy + 2 * f;
-        for (int q = 0; q < 2 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
+        if (P.dbg_x)
+            for (int q = 0; q < 2 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
         P.dbg_rho[P.f_energy + f] = send ? W_STD : W_ZERO;
     }
 }
@@ -592,8 +596,9 @@ __device__ __forceinline__ void vo_goal_stream(const Params &P, const Rec &Z, lo
     vo_cost_prox<D>(xr, C, n, k, P.rho, x);
     for (int c = 0; c < D; ++c) m[c] = x[c] + u[c];
     contribute(P, nd, 0, m, D);
-    if (P.dbg_x) {
-        for (int c = 0; c < D; ++c) P.dbg_x[f * D + c] = x[c];
+    if (P.dbg_rho) {
+        if (P.dbg_x)
+            for (int c = 0; c < D; ++c) P.dbg_x[f * D + c] = x[c];
         P.dbg_rho[f] = W_STD;
     }
 }
@@ -629,8 +634,9 @@ __device__ __forceinline__ void fixed_stream(const Params &P, const Rec &Z, long
     for (int c = 0; c < D; ++c) m[c] = x[c] + u[c];
     contribute(P, nd, P.admm ? 0 : 1, m, D);
     if (!P.admm) P.inf_val[nd] = make_float4(m[0], m[1], D == 3 ? m[2] : 0.f, 0.f);
-    if (P.dbg_x) {
-        for (int c = 0; c < D; ++c) P.dbg_x[f * D + c] = x[c];
+    if (P.dbg_rho) {
+        if (P.dbg_x)
+            for (int c = 0; c < D; ++c) P.dbg_x[f * D + c] = x[c];
         P.dbg_rho[f] = P.admm ? W_STD : W_INF;
     }
 }
@@ -638,7 +644,7 @@ __device__ __forceinline__ void fixed_stream(const Params &P, const Rec &Z, long
 // Queued collision factor (entry e): deferred u update, full minimiser,
 // consensus contributions.
 template <int D, int MODE>
-__device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsigned e) {
+__device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsigned e, float *nout) {
     const bool dense = P.dense != 0;
     long long f = e & kIdx;
     bool prev = (e & kPrev) != 0;
@@ -676,6 +682,8 @@ __device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsign
         for (int q = 0; q < 4 * D; ++q) u[q] = 0.f;
     }
     for (int q = 0; q < 4 * D; ++q) n[q] = zc[q] - u[q];
+    if (P.adj_pool)
+        for (int q = 0; q < 4 * D; ++q) nout[q] = n[q];
     bool act = coll_active<D>(n, R);
     if (act) {
         for (int q = 0; q < 4; ++q) w[q] = wval(k[q], P.rho);
@@ -701,9 +709,10 @@ __device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsign
         }
     }
     if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) store_u_coll<D>(P, f, u);
-    if (P.dbg_x) {
+    if (P.dbg_rho) {
         long long e0 = P.e_coll + 4 * f;
-        for (int q = 0; q < 4 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
+        if (P.dbg_x)
+            for (int q = 0; q < 4 * D; ++q) P.dbg_x[e0 * D + q] = x[q];
         P.dbg_rho[P.f_coll + f] = (act || P.admm) ? W_STD : W_ZERO;
     }
     return act;
@@ -743,7 +752,7 @@ __device__ __forceinline__ void capsule_prox_pair(const Capsule C, f2 n0, f2 n1,
 // Queued wall factor (entry e).  piece < 0: one lane; 0 or 1: the two lanes
 // of a pair share the minimiser (capsule_prox_pair) and lane 0 writes.
 template <int MODE>
-__device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsigned e, int piece) {
+__device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsigned e, int piece, float *nout) {
     const bool writer = piece <= 0;
     const bool dense = P.dense != 0;
     long long f = e & kIdx;
@@ -779,6 +788,7 @@ __device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsign
         u = P.u_wall[f];
     }
     f2 n0 = mk(ca.x - u.x, ca.y - u.y), n1 = mk(cb.x - u.z, cb.y - u.w);
+    if (P.adj_pool) nout[0] = n0.x, nout[1] = n0.y, nout[2] = n1.x, nout[3] = n1.y;
     bool act = segseg_sq(n0, n1, Cw.a, Cw.b) < Cw.r * Cw.r;
     f2 x0 = n0, x1 = n1;
     if (act) {
@@ -800,10 +810,12 @@ __device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsign
         contribute(P, nb, 0, m1, 2);
     }
     if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) P.u_wall[f] = u;
-    if (P.dbg_x) {
+    if (P.dbg_rho) {
         long long e0 = P.e_wall + 2 * f;
-        P.dbg_x[e0 * 2 + 0] = x0.x, P.dbg_x[e0 * 2 + 1] = x0.y;
-        P.dbg_x[e0 * 2 + 2] = x1.x, P.dbg_x[e0 * 2 + 3] = x1.y;
+        if (P.dbg_x) {
+            P.dbg_x[e0 * 2 + 0] = x0.x, P.dbg_x[e0 * 2 + 1] = x0.y;
+            P.dbg_x[e0 * 2 + 2] = x1.x, P.dbg_x[e0 * 2 + 3] = x1.y;
+        }
         P.dbg_rho[P.f_wall + f] = (act || P.admm) ? W_STD : W_ZERO;
     }
     return act;
@@ -841,6 +853,11 @@ __device__ __forceinline__ void node_update(const Params &P, long long nd) {
     }
     P.zr_prev[nd] = cur;
     P.zr_cur[nd] = nw;
+    if (P.dbg_l) {
+        const long long i = nd % P.p, s = nd / P.p;
+        P.dbg_l[i * (P.eta + 1) + s] = (unsigned char)(int)nw.w;
+        P.dbg_cnt[i * (P.eta + 1) + s] = ci > 0 ? ci : cs;
+    }
     for (int kind = 0; kind < 2; ++kind) {
         for (int c = 0; c < D; ++c) P.acc[((long long)kind * D + c) * P.N + nd] = 0ull;
         P.cnt[(long long)kind * P.N + nd] = 0;
@@ -889,6 +906,26 @@ __global__ __launch_bounds__(kBlock) void k_stream(Params P) {
     stream_block<D, MODE, DENSE>(P, blockIdx.x);
 }
 
+// twa_backward's recompute: append (factor, n) of the lanes whose factor sent
+// weight rho0 from its minimiser, one atomic per wave.  All lanes call it.
+template <int D>
+__device__ __forceinline__ void adj_append(const Params &P, bool pred, unsigned f, bool wall, const float *n) {
+    const unsigned long long mask = __ballot(pred);
+    if (mask == 0ull) return;
+    const int lane = __lane_id(), leader = __ffsll((long long)mask) - 1;
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(P.adj_cursor, (unsigned)__popcll(mask));
+    base = __shfl(base, leader);
+    const unsigned idx = base + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+    if (pred && idx < P.adj_cap) {
+        twa_rt::AdjRec r;
+        r.f = f;
+        r.wall = wall ? 1u : 0u;
+        for (int q = 0; q < 8; ++q) r.n[q] = (wall && q >= 4) ? 0.f : n[q];
+        P.adj_pool[idx] = r;
+    }
+}
+
 // One queue entry per lane of a wave-uniform loop: collision entries first,
 // wall entries from the next multiple of 64 (a wave never mixes the two
 // minimisers, whose run times differ several-fold); piece: which lane of a
@@ -897,10 +934,12 @@ template <int D, int MODE>
 __device__ __forceinline__ void queue_entry(const Params &P, const Rec &Z, bool is_coll, bool is_wall, unsigned e,
                                             int piece) {
     bool ac = false, aw = false;
-    if (is_coll) ac = coll_queue<D, MODE>(P, Z, e);
-    else if (is_wall) aw = wall_queue<MODE>(P, Z, e, piece) && piece <= 0;
+    float n[4 * D];
+    if (is_coll) ac = coll_queue<D, MODE>(P, Z, e, n);
+    else if (is_wall) aw = wall_queue<MODE>(P, Z, e, piece, n) && piece <= 0;
     count_wave(&P.counters[2], ac);
     count_wave(&P.counters[3], aw);
+    if (P.adj_pool) adj_append<D>(P, ac || aw, e & kIdx, aw, n);
 }
 
 // One wave per workgroup: the few busy waves land on different compute
@@ -977,6 +1016,7 @@ __device__ __forceinline__ void close_counters_wave(const Params &P) {
         P.stats[1] = P.counters[3];
         P.stats[2] = v + P.counters[1];
         P.counters[1] = P.counters[2] = P.counters[3] = 0;
+        if (P.adj_offs) *P.adj_offs = *P.adj_cursor;
     }
 }
 
@@ -1462,9 +1502,19 @@ twa_status run_iteration(twa_solver *s, int mode, float rho, float rho_prev) {
     s->P.step_prev = s->alpha / rho_prev;
     s->P.dbg_x = (mode == M_FINAL) ? nullptr : s->dbg_x;
     s->P.dbg_rho = (mode == M_FINAL) ? nullptr : s->dbg_rho;
+    s->P.adj_pool = (mode == M_FINAL) ? nullptr : s->adj_pool;
+    s->P.adj_cursor = s->adj_cursor;
+    s->P.adj_cap = s->adj_cap;
+    s->P.adj_offs = (mode == M_FINAL) ? nullptr : s->adj_offs;
+    s->P.dbg_l = (mode == M_FINAL) ? nullptr : s->dbg_l;
+    s->P.dbg_cnt = s->dbg_cnt;
     twa_status st = s->dim == 2 ? launch_iteration<2>(s, mode) : launch_iteration<3>(s, mode);
     s->P.dbg_x = nullptr;
     s->P.dbg_rho = nullptr;
+    s->P.adj_pool = nullptr;
+    s->P.adj_offs = nullptr;
+    s->P.dbg_l = nullptr;
+    s->P.dbg_cnt = nullptr;
     return st;
 }
 
@@ -1550,12 +1600,12 @@ twa_status iterate_impl(twa_solver *s, int k, bool timed) {
     const int tail = timed ? std::min(k, kTimedTail) : 0;
     // (steady rho0 throughout, the previous iteration's weights included)
     const bool settled = s->iter >= s->n_warm && (!s->pending || s->iter - 1 >= s->n_warm);
-    if (s->tiny_params && k - tail > 0 && settled && !s->dbg_x) {
+    if (s->tiny_params && k - tail > 0 && settled && !s->dbg_rho && !s->adj_pool) {
         TRY(iterate_tiny(s, k - tail));
         k = tail;
     }
     while (k > 0) {
-        const bool steady = s->pending && s->iter - 1 >= s->n_warm && !s->dbg_x;
+        const bool steady = s->pending && s->iter - 1 >= s->n_warm && !s->dbg_rho && !s->adj_pool;
         if (steady && k - tail > 0 && capture_graphs(s)) {
             // the largest captured chunk that fits before the timed tail
             int b = twa_solver::kGraphSizes - 1;
@@ -1578,6 +1628,10 @@ twa_status iterate_impl(twa_solver *s, int k, bool timed) {
         k--;
         s->dbg_x = nullptr;
         s->dbg_rho = nullptr;
+        s->adj_pool = nullptr;
+        s->adj_offs = nullptr;
+        s->dbg_l = nullptr;
+        s->dbg_cnt = nullptr;
     }
     return TWA_OK;
 }
@@ -1672,6 +1726,14 @@ twa_status import_state(twa_solver *s, const float *z, const float *u, const uns
     return TWA_OK;
 }
 
+twa_status export_lrho(twa_solver *s, unsigned char *lrho) {
+    unsigned nb = (unsigned)((s->P.N + 255) / 256);
+    hipLaunchKernelGGL(k_z_export, dim3(nb), dim3(256), 0, s->stream, (const float4 *)s->P.zr_cur, (float *)nullptr,
+                       lrho, s->p, s->eta, s->dim);
+    HIP_TRY(s, hipGetLastError());
+    return TWA_OK;
+}
+
 } // namespace twa_rt
 
 extern "C" {
@@ -1687,6 +1749,8 @@ void twa_destroy(twa_solver *s) {
         if (e) (void)hipGraphExecDestroy(e);
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     for (void *p : s->allocs) (void)hipFree(p);
+    for (void *p : {s->adj_ws, s->adj_arena, s->adj_pool_mem})
+        if (p) (void)hipFree(p);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s;
 }
@@ -2424,7 +2488,7 @@ twa_status twa_batch_iterate(twa_batch *b, int k) {
             return bfail(b, TWA_E_DEVICE, "finalize: " + s->err);
         any_pending |= s->pending;
         all_pending &= s->pending;
-        dbg |= s->dbg_x != nullptr;
+        dbg |= s->dbg_rho != nullptr;
     }
     if (any_pending && !all_pending)
         for (twa_solver *s : b->solvers)

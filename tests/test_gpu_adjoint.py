@@ -3,8 +3,10 @@ against the FP64 reference adjoint, which is itself pinned to FP64 central
 differences of the unrolled map.
 
 Both sides receive the same seeded cotangent dL/dz^K (a linear loss), so the
-comparison is of J^T v for one v.  Bar: every output within 1e-3 of the
-reference relative to that output's largest magnitude."""
+comparison is of J^T v for one v.  Bar, element by element: |gpu - ref| <=
+1e-3 * max(|ref|, 0.1 * max|ref of that output|).  The floor: an entry far
+below its output's largest is a sum in which larger FP32 terms cancel, so its
+rounding error scales with the output's magnitude, not its own."""
 import numpy as np
 import pytest
 
@@ -14,6 +16,7 @@ from paper_1311_4527_amd import instances as I
 pytestmark = pytest.mark.gpu
 
 REL = 1e-3
+FLOOR = 0.1
 
 
 def _sub(seed=7, radius=None):
@@ -43,9 +46,11 @@ def _ref_grad(inst, K, v):
 def _compare(got, ref, names=("dx0", "dxT", "dr", "dz0")):
     for name, a, b in zip(names, got, ref):
         scale = max(np.abs(b).max(), 1e-12)
-        err = np.abs(a - b).max()
-        print(f"{name}: max|ref| {scale:.3e}  max err {err:.3e}  rel {err / scale:.2e}", flush=True)
-        assert err <= REL * scale, (name, err, scale)
+        tol = REL * np.maximum(np.abs(b), FLOOR * scale)
+        err = np.abs(a - b)
+        worst = float(np.max(err / tol))
+        print(f"{name}: max|ref| {scale:.3e}  max err {err.max():.3e}  worst err/tol {worst:.2f}", flush=True)
+        assert np.all(err <= tol), (name, np.argwhere(err > tol)[:5].ravel(), worst)
 
 
 @pytest.mark.parametrize("K", [1, 6, 40])
@@ -184,10 +189,10 @@ def test_full_size_adjoint_runs_and_is_linear():
 @pytest.mark.parametrize("case", ["swap100", "box64_walls", "swap8_tiny"])
 @pytest.mark.parametrize("flags", [0, 1])
 def test_reading_the_state_leaves_the_run_unchanged(case, flags):
-    """The reverse sweep recomputes each segment reading the state after every
-    iteration (twa_get_state settles the deferred u update, and the next
-    iteration starts afresh); the states it linearises about must be the
-    forward run's own, bit for bit."""
+    """The adjoint takes a checkpoint every ceil(sqrt(K)) iterations
+    (twa_get_state settles the deferred u update, and the next iteration
+    starts afresh) and recomputes each segment from it; the states it
+    linearises about must be the forward run's own, bit for bit."""
     import torch
     from paper_1311_4527_amd.twa import Solver
     inst = {"swap100": lambda: I.conf_swap100(0),
