@@ -259,6 +259,23 @@ twa_status twa_consensus_scale(int p, int n_walls, double coord_max, double *sca
 twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT, float *dL_dr,
                         float *dL_dz0);
 
+/*
+ * twa_backward for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid allocation): the same computation,
+ * arguments, results and errors, with every buffer taken from a static
+ * scratch array of 128 MiB that the library holds on each device it runs on
+ * (from its first use there until the process ends; its address is looked
+ * up when a TWA_F_TAPE solver is created).  Calls no hipMalloc / hipFree and
+ * captures no new HIP graph (graphs the solver already holds are replayed).
+ * A run whose checkpoints and captured records do not fit returns
+ * TWA_E_NOMEM with the sizes in twa_last_error; twa_backward has no such
+ * limit.  Every call on one device shares that device's scratch, which keeps
+ * the last call's contents: calls that overlap on one device (other host
+ * threads, other streams) race and must be serialised by the caller.
+ */
+twa_status twa_backward_noalloc(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT, float *dL_dr,
+                                float *dL_dz0);
+
 /* Text of the last error on this solver ("" if none). */
 const char *twa_last_error(const twa_solver *s);
 

@@ -33,6 +33,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -378,10 +379,23 @@ __global__ void k_fill_float(float *p, long long n) {
         p[t] = 0.f;
 }
 
+// ------------------------------------------------------------------ scratch
+// The library's static scratch for twa_backward_noalloc (callers that cannot
+// allocate): each device holds one copy, from the first load of the
+// library's code on it until the process ends.  Host code reaches it only
+// through the address looked up per device at solver creation (the array's
+// own name is a host-side stand-in).  Calls on one device share it.
+constexpr size_t kScratchBytes = 128ull << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
 // ------------------------------------------------------------------ workspace
-// Bump allocation of one call's buffers from a region (the solver's own,
-// allocated at its first call and kept).  With base == nullptr it only adds
-// up the sizes.
+// Bump allocation of one call's buffers from a region: the solver's own
+// (allocated at its first call and kept), or the library's static scratch.
+// With base == nullptr it only adds up the sizes.
 struct Region {
     char *base = nullptr;
     size_t cap = 0, used = 0;
@@ -695,6 +709,25 @@ twa_status ensure(twa_solver *s, void **buf, size_t *have, size_t want) {
 
 } // namespace
 
+namespace twa_rt {
+
+// the static scratch's address on the solver's device (set up at create)
+twa_status scratch_setup(twa_solver *s) {
+    if (s->device < 0 || s->device >= kMaxDevices) return fail(s, TWA_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[s->device]) return TWA_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(s, TWA_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[s->device] = p;
+    return TWA_OK;
+}
+
+} // namespace twa_rt
+
 extern "C" twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT, float *dL_dr,
                                    float *dL_dz0) {
     TRY(check_args(s, dL_dz, dL_dx0, dL_dxT, dL_dr));
@@ -730,4 +763,50 @@ extern "C" twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_
         want_arena = (size_t)need * sizeof(AdjRec) * 5 / 4 + 4096;
     }
     return twa_rt::fail(s, TWA_E_NOMEM, "twa_backward: record stores kept overflowing");
+}
+
+extern "C" twa_status twa_backward_noalloc(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT,
+                                           float *dL_dr, float *dL_dz0) {
+    using twa_rt::fail;
+    TRY(check_args(s, dL_dz, dL_dx0, dL_dxT, dL_dr));
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (s->device >= 0 && s->device < kMaxDevices) base = g_scratch_ptr[s->device];
+    }
+    if (!base) return fail(s, TWA_E_STATE, "twa_backward_noalloc: no scratch on the solver's device");
+    const Shape h = shape_of(s);
+    Region R;
+    R.base = static_cast<char *>(base);
+    R.cap = kScratchBytes;
+    Buffers B{};
+    if (!layout(R, h, B)) {
+        Region sz;
+        layout(sz, h, B);
+        return fail(s, TWA_E_NOMEM, "twa_backward_noalloc: the run needs more than the " +
+                                        std::to_string(kScratchBytes >> 20) + " MiB scratch (" +
+                                        std::to_string(sz.used >> 20) + " MiB before its records)");
+    }
+    // the rest of the scratch holds the records: half checkpoints, half capture
+    // (less two alignment pads)
+    const size_t left = R.cap - std::min(R.cap, ((R.used + 255) & ~(size_t)255) + 512);
+    const size_t rest = left / 2 / sizeof(AdjRec);
+    B.arena_cap = (unsigned)std::min<size_t>(rest, 0xffffffffu);
+    B.pool_cap = B.arena_cap;
+    B.arena = R.take<AdjRec>(B.arena_cap);
+    B.pool = R.take<AdjRec>(B.pool_cap);
+    if (!B.arena || !B.pool || B.arena_cap < 64)
+        return fail(s, TWA_E_NOMEM, "twa_backward_noalloc: no scratch left for the records");
+    const bool was = s->no_capture;
+    s->no_capture = true; // replay graphs already captured, capture none (that would allocate)
+    int outcome = kDone;
+    unsigned need = 0;
+    const twa_status st = run_once(s, h, B, dL_dz, dL_dx0, dL_dxT, dL_dr, dL_dz0, &outcome, &need, nullptr);
+    s->no_capture = was;
+    if (st != TWA_OK) return st;
+    if (outcome != kDone)
+        return fail(s, TWA_E_NOMEM, std::string("twa_backward_noalloc: the scratch holds ") +
+                                        std::to_string(B.arena_cap) + " records per store, the run needs " +
+                                        std::to_string(need));
+    return TWA_OK;
 }

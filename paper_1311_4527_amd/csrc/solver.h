@@ -128,6 +128,8 @@ struct twa_solver {
     bool graph_failed = false;
     long long graph_iters = 0;  // iterations run from graph replays
     hipStream_t own_stream = nullptr; // made at create when the caller passes the null stream
+    bool no_capture = false;          // inside a call that allocates nothing: capture no new graph
+    int device = 0;                   // the HIP device current at create
     // tiny instances: the persistent batched kernel on this one instance
     // (a device copy of the parameters and its one-bin layout)
     twa_rt::Params *tiny_params = nullptr;
@@ -157,6 +159,8 @@ twa_status import_state(twa_solver *s, const float *z, const float *u, const uns
 // <-rho codes of the current node records, canonical [p][eta+1] (device
 // array); leaves a pending u update pending
 twa_status export_lrho(twa_solver *s, unsigned char *lrho);
+// look up the static scratch of twa_backward_noalloc on the solver's device
+twa_status scratch_setup(twa_solver *s);
 
 } // namespace twa_rt
 

@@ -1606,7 +1606,9 @@ twa_status iterate_impl(twa_solver *s, int k, bool timed) {
     }
     while (k > 0) {
         const bool steady = s->pending && s->iter - 1 >= s->n_warm && !s->dbg_rho && !s->adj_pool;
-        if (steady && k - tail > 0 && capture_graphs(s)) {
+        // (a call that must not allocate replays graphs already captured but
+        // captures none: instantiating a graph allocates)
+        if (steady && k - tail > 0 && (s->graphs[0] || !s->no_capture) && capture_graphs(s)) {
             // the largest captured chunk that fits before the timed tail
             int b = twa_solver::kGraphSizes - 1;
             while ((1 << b) > k - tail) --b;
@@ -1808,6 +1810,11 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     }
     s->p = p, s->eta = eta, s->dim = dim, s->W = n_walls;
     s->rho0 = s->rho0_init = rho0, s->alpha = alpha, s->flags = flags;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(s, TWA_E_DEVICE, "hipGetDevice failed");
+        return bail(TWA_E_DEVICE);
+    }
     if (!s->stream) {
         // The null stream cannot be captured into graphs.  A stream made with
         // the default flags orders itself with the null stream both ways, so
@@ -2043,6 +2050,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         const twa_status st = prepare_tiny(s);
         if (st != TWA_OK) return bail(st);
     }
+    if ((flags & TWA_F_TAPE) && twa_rt::scratch_setup(s) != TWA_OK) return bail(TWA_E_DEVICE);
     if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(TWA_E_DEVICE);
     *out = s;
     return TWA_OK;

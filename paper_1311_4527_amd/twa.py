@@ -87,6 +87,8 @@ def load_library():
                                         ct.POINTER(ct.c_double)]
     lib.twa_backward.restype = ct.c_int
     lib.twa_backward.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+    lib.twa_backward_noalloc.restype = ct.c_int
+    lib.twa_backward_noalloc.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     lib.twa_last_error.restype = ct.c_char_p
     lib.twa_last_error.argtypes = [_vp]
     lib.twa_destroy.restype = None
@@ -256,6 +258,12 @@ class Solver:
         dz0 = torch.empty_like(dz) if want_dz0 else None
         self._check(load_library().twa_backward(self.h, _ptr(dz), _ptr(dx0), _ptr(dxT), _ptr(dr), _ptr(dz0)))
         return dx0, dxT, dr, dz0
+
+    def twa_backward_noalloc(self, dL_dz, dx0, dxT, dr, dz0=None):
+        """twa_backward into caller-provided device tensors, with the library's
+        static scratch instead of any allocation (see the header)."""
+        self._check(load_library().twa_backward_noalloc(self.h, _ptr(dL_dz), _ptr(dx0), _ptr(dxT), _ptr(dr),
+                                                        _ptr(dz0)))
 
     # -- convenience
     def step_debug(self):
