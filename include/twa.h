@@ -147,8 +147,11 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
  * replaced by the start and goal); resets u to 0 and <-rho to the default. */
 twa_status twa_set_init(twa_solver *s, const float *z);
 
-/* rho0 = rho0_init for the first n_warm iterations counted from 0, then the
- * create-time rho0 (Sec. 4 uses a small rho0 for 20 iterations). */
+/* Sec. 4's warm-up: the standard weight is rho0_init for the first n_warm
+ * iterations counted from 0, then the create-time rho0 (the paper uses
+ * eta p 1e-5 for 20 iterations).  The warm-up weight enters the minimisers;
+ * the u step of App. B step 7 stays alpha / rho0 with the create-time rho0
+ * (over the warm-up value the iterates diverge). */
 twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm);
 
 /* Run k >= 0 iterations (App. B steps 1-7), asynchronously.  Iterations at

@@ -984,6 +984,9 @@ long tor_num_factors(void *h) { return ((tor_t *)h)->F; }
 long tor_num_edges(void *h) { return ((tor_t *)h)->E; }
 long tor_iteration(void *h) { return ((tor_t *)h)->iter; }
 
+/* Sec. 4's warm-up: rho0 = rho0_init in the minimisers' weights for the
+ * first n_warm iterations (counted from 0), then the configuration's rho0.
+ * The u step stays alpha / rho0 of the configuration throughout (step 7). */
 void tor_set_schedule(void *h, double rho0_init, int n_warm) {
     tor_t *T = (tor_t *)h;
     T->rho0_init = rho0_init;
@@ -1183,8 +1186,12 @@ static void one_iteration(tor_t *T) {
         if (T->mode == TOR_MODE_ADMM) back = TOR_STD;
         for (long q = a; q < b; q++) T->rin[T->adj[q]] = back;
     }
-    /* 7. u update */
-    double step = T->alpha / rho;
+    /* 7. u update.  The step is alpha / rho0 with the configuration's rho0
+     * even while the warm-up's small rho0 is in force (Sec. 4): that small
+     * value enters the minimisers' weights only.  Over the warm-up value the
+     * step would be alpha / (eta p 1e-5), in the hundreds, and the iterates
+     * diverge (see the design notes). */
+    double step = T->alpha / T->rho0;
 #pragma omp parallel for schedule(static)
     for (long e = 0; e < E; e++) {
         if (T->rout[e] == TOR_STD && T->rin[e] == TOR_STD) {
@@ -1324,7 +1331,7 @@ void tor_backward(void *h, const double *dz, double *dx0, double *dxT, double *d
         const double *z = T->tape_z + t * N * dim, *u = T->tape_u + t * E * dim;
         const unsigned char *rin = T->tape_rin + t * E, *rout = T->tape_rout + t * E;
         const unsigned char *rin1 = (t + 1 < T->tape_len) ? T->tape_rin + (t + 1) * E : T->tape_rin_next;
-        double rho = T->tape_rho[t], s = T->alpha / rho;
+        double rho = T->tape_rho[t], s = T->alpha / T->rho0;
         for (long e = 0; e < E; e++)
             for (int k = 0; k < dim; k++) n[e * dim + k] = z[T->enode[e] * dim + k] - u[e * dim + k];
         /* step 7 */

@@ -58,7 +58,7 @@ struct Adj {
     const unsigned char *l;      // [N] <-rho^k
     const unsigned char *rout;   // [F] ->rho^k
     const unsigned char *lnext;  // [N] <-rho^{k+1}
-    float rho, step;             // rho0 of iteration k, alpha / rho0
+    float rho, step;             // weight rho0 of iteration k; u step alpha / (configuration's rho0)
     // cotangents
     const float *zb_in;  // [N][2] dL/dz^{k+1}
     float *zb_out;       // [N][2] dL/dz^k: zeroed, then accumulated
@@ -641,7 +641,7 @@ twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_d
             A.rout = B.rout + t * h.F;
             A.rout_prev = t > 0 ? B.rout + (t - 1) * h.F : nullptr;
             A.rho = twa_rt::rho_at(s, k0 + t);
-            A.step = s->alpha / A.rho;
+            A.step = s->alpha / s->rho0; // the u step ignores the warm-up's rho0
             const unsigned *offs = B.offs + t;
             // the step after this one belongs to the segment reversed before
             // (or is the loss): it could not accumulate this step's S

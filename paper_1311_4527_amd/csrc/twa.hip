@@ -1496,10 +1496,13 @@ twa_status launch_iteration(twa_solver *s, int mode) {
 }
 
 twa_status run_iteration(twa_solver *s, int mode, float rho, float rho_prev) {
+    // the warm-up's small rho0 enters the minimisers' weights only; the u
+    // step is alpha / rho0 of the configuration throughout (App. B step 7
+    // with Sec. 4's schedule: over the warm-up value it diverges)
     s->P.rho = rho;
-    s->P.step = s->alpha / rho;
+    s->P.step = s->alpha / s->rho0;
     s->P.rho_prev = rho_prev;
-    s->P.step_prev = s->alpha / rho_prev;
+    s->P.step_prev = s->alpha / s->rho0;
     s->P.dbg_x = (mode == M_FINAL) ? nullptr : s->dbg_x;
     s->P.dbg_rho = (mode == M_FINAL) ? nullptr : s->dbg_rho;
     s->P.adj_pool = (mode == M_FINAL) ? nullptr : s->adj_pool;

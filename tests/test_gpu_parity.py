@@ -221,37 +221,86 @@ def test_timed_iterations_match_untimed(k):
     assert sum(ms) <= 1.5 * wall_ms + 1.0
 
 
-def test_full_solve_small_swap():
-    """Collision-free and objective within 1e-3 of the reference after the
-    same number of iterations (p=8 circle swap)."""
-    inst = I.conf_small(0)
+def _objective(inst, z):
+    return float(np.sum(inst.C * np.sum(np.diff(z, axis=1) ** 2, axis=2)))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_full_solve_small_swap(seed):
+    """The 8-agent swap after its 2000 iterations: collision-free to 1e-6
+    (no clearance below -1e-6, Sec. 3.1's constraint) and the objective within
+    1e-3 of the reference's after the same iterations."""
+    inst = I.conf_small(seed)
     S = _solver(inst)
-    S.twa_iterate(4000)
+    S.twa_iterate(2000)
     zg = S.twa_get_trajectories().cpu().numpy().astype(np.float64)
     P = O.Planner(inst)
-    P.iterate(4000)
-    zr = P.trajectories()
-    assert O.min_clearance(inst.radii, zg) > -1e-5
-    Jg = float(np.sum(inst.C * np.sum(np.diff(zg, axis=1) ** 2, axis=2)))
-    Jr = P.objective()
-    assert abs(Jg - Jr) <= 1e-3 * Jr
+    P.iterate(2000)
+    assert P.min_clearance() >= -1e-6          # the reference meets the bar by then
+    assert O.min_clearance(inst.radii, zg) >= -1e-6
+    Jg, Jr = _objective(inst, zg), P.objective()
+    assert abs(Jg - Jr) <= 1e-3 * Jr, (Jg, Jr)
     assert np.array_equal(zg[:, 0], inst.x0.astype(np.float32).astype(np.float64))
 
 
 def test_full_solve_swap100():
+    """The 100-agent swap after its 5000 iterations: objective within 1e-3 of
+    the reference's.  Neither side is collision-free to 1e-6 yet (the
+    reference's clearance keeps oscillating between -3e-5 and -8e-7 up to
+    32,000 iterations while the agents slide along each other), so the GPU
+    run is held to the reference's clearance here and the bar itself to the
+    restarted solve below."""
     inst = I.conf_swap100(0)
     S = _solver(inst)
     S.twa_iterate(5000)
     zg = S.twa_get_trajectories().cpu().numpy().astype(np.float64)
     P = O.Planner(inst)
     P.iterate(5000)
-    cg = O.min_clearance(inst.radii, zg)
-    cr = P.min_clearance()
-    Jg = float(np.sum(inst.C * np.sum(np.diff(zg, axis=1) ** 2, axis=2)))
-    Jr = P.objective()
+    cg, cr = O.min_clearance(inst.radii, zg), P.min_clearance()
+    Jg, Jr = _objective(inst, zg), P.objective()
     assert abs(Jg - Jr) <= 1e-3 * Jr, (Jg, Jr)
-    # the GPU run is as clear as the reference run (both converge slowly to contact)
     assert cg > min(cr, 0.0) - 5e-5, (cg, cr)
+
+
+def test_full_solve_swap100_collision_free_after_restart():
+    """The 100-agent swap solved to the bar: its 5000 energy iterations, then
+    the feasibility problem restarted from that state (App. J: no anytime
+    guarantee, so a stopped run is made collision-free by re-solving
+    feasibility from where it stopped) until no clearance is below -1e-6.
+    Both sides do the same; the GPU plan is collision-free to 1e-6 and its
+    objective within 1e-3 of the reference's."""
+    import torch
+    from paper_1311_4527_amd.twa import Solver, TWA_F_COST_NONE
+    inst = I.conf_swap100(0)
+    S = _solver(inst)
+    S.twa_iterate(5000)
+    z, u, l, _ = S.twa_get_state()
+    F = Solver.from_instance(inst, flags=TWA_F_COST_NONE)
+    F.twa_set_state(z, u, l, 0)
+    kg = None
+    for k in range(1, 2001):
+        F.twa_iterate(1)
+        if F.twa_get_quality()["min_clearance"] >= -1e-6:
+            kg = k
+            break
+    assert kg is not None
+    zg = F.twa_get_trajectories().cpu().numpy().astype(np.float64)
+    assert O.min_clearance(inst.radii, zg) >= -1e-6
+    P = O.Planner(inst)
+    P.iterate(5000)
+    zr, ur, lr = P.get_state()
+    R = O.Planner(inst, cost=O.COST_NONE)
+    R.set_state(zr, ur, lr, 0)
+    kr = None
+    for k in range(1, 2001):
+        R.iterate(1)
+        if R.min_clearance() >= -1e-6:
+            kr = k
+            break
+    assert kr is not None
+    Jg, Jr = _objective(inst, zg), _objective(inst, R.trajectories())
+    print(f"restart: GPU {kg} iterations J {Jg:.8e}, reference {kr} iterations J {Jr:.8e}", flush=True)
+    assert abs(Jg - Jr) <= 1e-3 * Jr, (Jg, Jr)
 
 
 @pytest.mark.parametrize("flags", [1, 0])
@@ -282,3 +331,33 @@ def test_parity_many_agents_one_iteration(flags):
     z, u, lr = P.get_state()
     del P
     one_iteration_parity(inst, z, u, lr, 0, flags=flags)
+
+
+@pytest.mark.parametrize("case", ["swap8", "box24"])
+def test_parity_across_the_warm_up_switch(case):
+    """Sec. 4's schedule (rho0 = eta p 1e-5 for 20 iterations, then 1):
+    single iterations from reference states on both sides of the switch, and
+    40 fused iterations through it (each iteration's deferred u update uses
+    the previous iteration's weights) against the reference's 40."""
+    import torch
+    inst = I.conf_small(0) if case == "swap8" else I.random_box(24, 0.03, 6, n_walls=3, sigma=1e-2, seed=11,
+                                                                alpha=0.1, C=1 / 144)
+    sched = (inst.eta * inst.p * 1e-5, 20)
+    P = O.Planner(inst)
+    P.set_schedule(*sched)
+    done = 0
+    for k in (0, 10, 19, 20, 21, 40):
+        P.iterate(k - done)
+        done = k
+        z, u, lr = P.get_state()
+        one_iteration_parity(inst, z, u, lr, k, schedule=sched)
+    S = _solver(inst)
+    S.twa_set_schedule(*sched)
+    S.twa_iterate(40)
+    zg = S.twa_get_trajectories().cpu().numpy().astype(np.float64)
+    R = O.Planner(inst)
+    R.set_schedule(*sched)
+    R.iterate(40)
+    err = np.abs(zg - R.trajectories()).max()
+    print(f"warm-up run of 40: max |z_gpu - z_ref| {err:.2e}", flush=True)
+    assert err < 1e-4
