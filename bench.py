@@ -150,7 +150,7 @@ def run_batched(K, warmup):
     import numpy as np
     import torch
     from paper_1311_4527_amd import autotune, instances as I
-    from paper_1311_4527_amd.twa import Batch, Solver
+    from paper_1311_4527_amd.twa import Batch, Solver, TWA_F_DENSE
     insts = I.conf_batch()
     F = sum(i.counts()["factors"] for i in insts)
     tuner = Batch(insts)
@@ -181,11 +181,26 @@ def run_batched(K, warmup):
         S.close()
         Jb, Jp = objective(inst, zb[i]), objective(inst, zp)
         worst = max(worst, abs(Jb - Jp) / max(Jp, 1e-30))
+    # the literal dense form of the same batch in the phased launch: every
+    # edge's u read and written, so HBM-bound; its whole iterations (three
+    # phases) against the algorithmic bytes of all instances
+    D = Batch(insts, flags=TWA_F_DENSE)
+    D.twa_batch_config(0, 1)
+    D.twa_batch_iterate(warmup)
+    Kd = min(K, 500)
+    d_ms = D.twa_batch_iterate_timed(Kd)
+    D.close()
+    bytes_it = sum(algorithmic_bytes(i, True) for i in insts)
+    A = bytes_it / (d_ms * 1e-3 / Kd) / 1e9
+    dense = dict(iterations=Kd, device_ms=d_ms, us_per_iteration=d_ms * 1e3 / Kd, value=F * Kd / (d_ms * 1e-3),
+                 roofline=dict(bound="hbm", achieved=A, peak=HBM_PEAK_GBS, unit="GB/s", frac=A / HBM_PEAK_GBS,
+                               traffic=None, kernel="kp_stream + kp_queue + kp_nodes (whole iteration)",
+                               algorithmic_bytes_per_iteration=bytes_it))
     return dict(instances=len(insts), factors=F, iterations=K, warmup=warmup,
                 value=F * K / t_batch, unit="factor-updates/s", seconds=t_batch, device_ms=dev_ms,
                 plain_sequential=dict(value=F * K / t_plain, seconds=t_plain),
                 speedup=t_plain / t_batch, max_rel_objective_diff=worst,
-                autotune=dict(block=block, groups=groups, candidates=log))
+                autotune=dict(block=block, groups=groups, candidates=log), dense_phased=dense)
 
 
 def profile_batched(K, warmup=50, block=0, groups=1):
@@ -334,6 +349,7 @@ def run_vo(p=16, r=0.05):
         V.step()
         times.append(time.perf_counter() - t0)
         its.append(V.last_iterations)
+    V.close()
     t = np.array(times)
     conv = [n for n in its if n > 0]
     return dict(p=p, r=r, epochs=len(times), arrived=V.arrived(), epochs_at_cap=len(its) - len(conv),
@@ -380,11 +396,21 @@ def run_adjoint(K=500):
                 backward_s=t2 - t1, backward_over_forward=(t2 - t1) / t_fwd, finite=ok)
 
 
-def cpu_baseline(inst, budget_s=12.0):
-    """The FP64 reference, untouched, on this host's cores: one untimed
-    iteration, then iterations until about budget_s seconds have passed."""
-    import oracle as O
-    P = O.Planner(inst)
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_rate(P, budget_s):
+    """Reference iterations per second over about budget_s seconds (after one
+    untimed iteration)."""
     P.iterate(1)
     n = 0
     t0 = time.perf_counter()
@@ -393,14 +419,29 @@ def cpu_baseline(inst, budget_s=12.0):
         n += 1
         if time.perf_counter() - t0 >= budget_s:
             break
-    dt = time.perf_counter() - t0
-    F = inst.counts()["factors"]
+    return n, time.perf_counter() - t0
+
+
+def cpu_baseline(inst, budget_s=8.0):
+    """The FP64 reference, untouched, on this host's cores: all of the threads
+    it is given (OMP_NUM_THREADS), then one thread, each over about budget_s
+    seconds of iterations of the same instance from its straight-line start."""
+    import oracle as O
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    cores = min(cores, os.cpu_count() or cores)
+    cores = min(cores, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1))
+    F = inst.counts()["factors"]
+    O.set_threads(cores)
+    n, dt = _oracle_rate(O.Planner(inst), budget_s)
+    O.set_threads(1)
+    n1, dt1 = _oracle_rate(O.Planner(inst), budget_s)
+    O.set_threads(cores)
     out = dict(value=F * n / dt, unit="factor-updates/s", cores=cores, kind="oracle",
-               sample=f"{n} reference iterations (after 1 untimed) of the same p=1024, eta=16, 32-wall "
-                      f"instance from its straight-line start, {dt:.1f} s wall")
-    # the two small circle swaps, beside the GPU's small_workloads leg
+               sample=f"{n} reference iterations on {cores} threads (after 1 untimed) of the same p=1024, eta=16, "
+                      f"32-wall instance from its straight-line start, {dt:.1f} s wall; and {n1} iterations on "
+                      f"one thread, {dt1:.1f} s",
+               cpu_model=cpu_model(), single_thread=dict(value=F * n1 / dt1, unit="factor-updates/s", cores=1,
+                                                         iterations=n1, seconds=dt1))
+    # the two small circle swaps and one free agent, beside the GPU's small_workloads leg
     small = {}
     for name, K in (("swap8", 2000), ("swap100", 100), ("single1", 200)):
         si = workload(name)

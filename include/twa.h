@@ -147,6 +147,16 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
  * replaced by the start and goal); resets u to 0 and <-rho to the default. */
 twa_status twa_set_init(twa_solver *s, const float *z);
 
+/* New start and goal positions x0, xT [p][dim] (device) for the same
+ * problem shape, radii, walls, costs and flags -- e.g. the next epoch of the
+ * velocity-obstacle planner (Sec. 5), whose starts are the agents' current
+ * positions and whose goals are the new reference end positions.  Validated
+ * as at create (finite, feasible; TWA_E_INFEASIBLE otherwise), and within the
+ * coordinate range the solver was created for (TWA_E_INVALID otherwise: the
+ * consensus scale depends on it).  Resets the state to straight lines, u = 0,
+ * and the default <-rho, as twa_create does.  Synchronises the stream. */
+twa_status twa_set_endpoints(twa_solver *s, const float *x0, const float *xT);
+
 /* Sec. 4's warm-up: the standard weight is rho0_init for the first n_warm
  * iterations counted from 0, then the create-time rho0 (the paper uses
  * eta p 1e-5 for 20 iterations).  The warm-up weight enters the minimisers;

@@ -86,6 +86,12 @@ def _load():
     return lib
 
 
+def set_threads(n: int) -> None:
+    """Threads of the reference's OpenMP loops (the runtime it links)."""
+    _load()
+    ct.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
 def _d(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a, a.ctypes.data_as(_dp)

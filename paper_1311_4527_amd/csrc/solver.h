@@ -129,6 +129,10 @@ struct twa_solver {
     long long graph_iters = 0;  // iterations run from graph replays
     hipStream_t own_stream = nullptr; // made at create when the caller passes the null stream
     bool no_capture = false;          // inside a call that allocates nothing: capture no new graph
+    std::vector<float> h_radii, h_walls; // host copies for validating new end points
+    double coord_max = 1.0;            // the coordinate range the consensus scale was chosen for
+    float4 *xfix_dev = nullptr;        // the fixed factors' constants (P.xfix)
+    std::vector<float4> h_fix, h_z;    // staging of twa_set_endpoints (kept, so later calls reuse it)
     int device = 0;                   // the HIP device current at create
     // tiny instances: the persistent batched kernel on this one instance
     // (a device copy of the parameters and its one-bin layout)

@@ -1703,6 +1703,68 @@ void consensus_scale(int p, int n_walls, double coord_max, double *scale, double
     *limit = std::ldexp(1.0, 62) / ((double)deg * *scale);
 }
 
+// Feasibility of the fixed end points (Sec. 1: non-strict separation):
+// starts pairwise >= r_i + r_j apart and clear of every wall, goals too
+// (a velocity-obstacle epoch's reference ends are preferences, not
+// constraints).  FP32 positions left in contact may overlap by rounding: a
+// 1e-5 relative slack.
+twa_status check_ends(twa_solver *s, const std::vector<float> &h0, const std::vector<float> &hT) {
+    const int p = s->p, dim = s->dim, n_walls = s->W;
+    const std::vector<float> &hr = s->h_radii, &hw = s->h_walls;
+    for (int which = 0; which < ((s->flags & TWA_F_VO) ? 1 : 2); ++which) {
+        const std::vector<float> &X = which ? hT : h0;
+        for (int i = 0; i < p; ++i)
+            for (int j = i + 1; j < p; ++j) {
+                double d2 = 0;
+                for (int c = 0; c < dim; ++c) {
+                    double d = (double)X[i * dim + c] - X[j * dim + c];
+                    d2 += d * d;
+                }
+                double R = ((double)hr[i] + hr[j]) * (1.0 - 1e-5);
+                if (d2 < R * R)
+                    return fail(s, TWA_E_INFEASIBLE, std::string(which ? "goals " : "starts ") + std::to_string(i) +
+                                                         " and " + std::to_string(j) + " overlap");
+            }
+        for (int i = 0; i < p && n_walls > 0; ++i)
+            for (int w = 0; w < n_walls; ++w) {
+                double ax = hw[w * 4 + 0], ay = hw[w * 4 + 1], bx = hw[w * 4 + 2], by = hw[w * 4 + 3];
+                double qx = X[i * 2 + 0], qy = X[i * 2 + 1];
+                double dx = bx - ax, dy = by - ay, L2 = dx * dx + dy * dy, t = 0;
+                if (L2 > 0) t = std::min(1.0, std::max(0.0, ((qx - ax) * dx + (qy - ay) * dy) / L2));
+                double ex = ax + t * dx - qx, ey = ay + t * dy - qy;
+                if (ex * ex + ey * ey < (double)hr[i] * hr[i] * (1.0 - 2e-5))
+                    return fail(s, TWA_E_INFEASIBLE, std::string(which ? "goal " : "start ") + std::to_string(i) +
+                                                         " touches wall " + std::to_string(w));
+            }
+    }
+    return TWA_OK;
+}
+
+// The constants of the fixed factors (start i, goal i as float4) and the
+// straight-line state between them (<-rho infinity at certain ends, rho0
+// elsewhere), time-major node records.
+void build_ends(const twa_solver *s, const std::vector<float> &h0, const std::vector<float> &hT,
+                std::vector<float4> &hfix, std::vector<float4> &hz) {
+    const int p = s->p, eta = s->eta, dim = s->dim;
+    const bool admm = s->P.admm != 0, vo = s->P.vo != 0;
+    hfix.assign((size_t)2 * p, make_float4(0.f, 0.f, 0.f, 0.f));
+    for (int i = 0; i < p; ++i) {
+        hfix[2 * i] = make_float4(h0[i * dim], h0[i * dim + 1], dim == 3 ? h0[i * dim + 2] : 0.f, 0.f);
+        hfix[2 * i + 1] = make_float4(hT[i * dim], hT[i * dim + 1], dim == 3 ? hT[i * dim + 2] : 0.f, 0.f);
+    }
+    hz.assign((size_t)(eta + 1) * p, make_float4(0.f, 0.f, 0.f, 0.f));
+    for (int i = 0; i < p; ++i)
+        for (int s2 = 0; s2 <= eta; ++s2) {
+            float v[3] = {0.f, 0.f, 0.f};
+            for (int c = 0; c < dim; ++c) {
+                double a = h0[i * dim + c], b = hT[i * dim + c];
+                v[c] = (s2 == 0) ? (float)a : (s2 == eta) ? (float)b : (float)(a + (double)s2 / eta * (b - a));
+            }
+            hz[(size_t)s2 * p + i] =
+                make_float4(v[0], v[1], v[2], (float)(((s2 == 0 && !admm) || (s2 == eta && !admm && !vo)) ? W_INF : W_STD));
+        }
+}
+
 bool finite_all(const std::vector<float> &v) {
     for (float x : v)
         if (!std::isfinite(x)) return false;
@@ -1854,39 +1916,10 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     for (float v : h0) Lmax = std::max(Lmax, (double)std::fabs(v));
     for (float v : hT) Lmax = std::max(Lmax, (double)std::fabs(v));
     for (float v : hw) Lmax = std::max(Lmax, (double)std::fabs(v));
-    // feasibility of the fixed end points (Sec. 1: non-strict separation);
-    // a velocity-obstacle epoch's reference ends are preferences, not constraints
-    for (int which = 0; which < ((flags & TWA_F_VO) ? 1 : 2); ++which) {
-        const std::vector<float> &X = which ? hT : h0;
-        for (int i = 0; i < p; ++i)
-            for (int j = i + 1; j < p; ++j) {
-                double d2 = 0;
-                for (int c = 0; c < dim; ++c) {
-                    double d = (double)X[i * dim + c] - X[j * dim + c];
-                    d2 += d * d;
-                }
-                // FP32 positions in contact may overlap by rounding: 1e-5 relative slack
-                double R = ((double)hr[i] + hr[j]) * (1.0 - 1e-5);
-                if (d2 < R * R) {
-                    fail(s, TWA_E_INFEASIBLE, std::string(which ? "goals " : "starts ") + std::to_string(i) + " and " +
-                                                  std::to_string(j) + " overlap");
-                    return bail(TWA_E_INFEASIBLE);
-                }
-            }
-        for (int i = 0; i < p && n_walls > 0; ++i)
-            for (int w = 0; w < n_walls; ++w) {
-                double ax = hw[w * 4 + 0], ay = hw[w * 4 + 1], bx = hw[w * 4 + 2], by = hw[w * 4 + 3];
-                double qx = X[i * 2 + 0], qy = X[i * 2 + 1];
-                double dx = bx - ax, dy = by - ay, L2 = dx * dx + dy * dy, t = 0;
-                if (L2 > 0) t = std::min(1.0, std::max(0.0, ((qx - ax) * dx + (qy - ay) * dy) / L2));
-                double ex = ax + t * dx - qx, ey = ay + t * dy - qy;
-                if (ex * ex + ey * ey < (double)hr[i] * hr[i] * (1.0 - 2e-5)) {
-                    fail(s, TWA_E_INFEASIBLE, std::string(which ? "goal " : "start ") + std::to_string(i) +
-                                                  " touches wall " + std::to_string(w));
-                    return bail(TWA_E_INFEASIBLE);
-                }
-            }
-    }
+    s->h_radii = hr;
+    s->h_walls = hw;
+    s->coord_max = Lmax;
+    if (check_ends(s, h0, hT) != TWA_OK) return bail(TWA_E_INFEASIBLE);
     // --- device buffers
     Params &P = s->P;
     P.p = p, P.eta = eta, P.W = n_walls, P.dim = dim;
@@ -1999,25 +2032,11 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     P.rho = P.rho_prev = rho0;
     P.step = P.step_prev = alpha / rho0;
     // constants
-    std::vector<float4> hwall(std::max(1, n_walls)), hfix(Ff);
+    std::vector<float4> hwall(std::max(1, n_walls)), hfix, hz;
     for (int w = 0; w < n_walls; ++w) hwall[w] = make_float4(hw[w * 4 + 0], hw[w * 4 + 1], hw[w * 4 + 2], hw[w * 4 + 3]);
-    for (int i = 0; i < p; ++i) {
-        hfix[2 * i] = make_float4(h0[i * dim], h0[i * dim + 1], dim == 3 ? h0[i * dim + 2] : 0.f, 0.f);
-        hfix[2 * i + 1] = make_float4(hT[i * dim], hT[i * dim + 1], dim == 3 ? hT[i * dim + 2] : 0.f, 0.f);
-    }
     // initial state: straight lines, <-rho INF at the ends and STD inside
-    std::vector<float4> hz(P.N);
-    for (int i = 0; i < p; ++i)
-        for (int s2 = 0; s2 <= eta; ++s2) {
-            float v[3] = {0.f, 0.f, 0.f};
-            for (int c = 0; c < dim; ++c) {
-                double a = h0[i * dim + c], b = hT[i * dim + c];
-                v[c] = (s2 == 0) ? (float)a : (s2 == eta) ? (float)b : (float)(a + (double)s2 / eta * (b - a));
-            }
-            hz[(size_t)s2 * p + i] =
-                make_float4(v[0], v[1], v[2],
-                            (float)(((s2 == 0 && !P.admm) || (s2 == eta && !P.admm && !P.vo)) ? W_INF : W_STD));
-        }
+    build_ends(s, h0, hT, hfix, hz);
+    s->xfix_dev = xfix_d;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMemcpyAsync(radii_d, hr.data(), sizeof(float) * p, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
@@ -2077,6 +2096,30 @@ twa_status twa_set_init(twa_solver *s, const float *z) {
     TRY(reset_state_buffers(s));
     s->iter = 0;
     return save_origin(s);
+}
+
+twa_status twa_set_endpoints(twa_solver *s, const float *x0, const float *xT) {
+    TRY(check_alive(s));
+    if (!x0 || !xT) return fail(s, TWA_E_INVALID, "null x0 or xT");
+    std::vector<float> h0, hT;
+    TRY(to_host(s, h0, x0, (size_t)s->p * s->dim));
+    TRY(to_host(s, hT, xT, (size_t)s->p * s->dim));
+    if (!finite_all(h0) || !finite_all(hT)) return fail(s, TWA_E_INVALID, "non-finite end point");
+    for (const std::vector<float> *v : {&h0, &hT})
+        for (float c : *v)
+            if (std::fabs((double)c) > s->coord_max)
+                return fail(s, TWA_E_INVALID, "end point beyond the coordinate range the solver was created for");
+    TRY(check_ends(s, h0, hT));
+    build_ends(s, h0, hT, s->h_fix, s->h_z);
+    HIP_TRY(s, hipMemcpyAsync(s->xfix_dev, s->h_fix.data(), sizeof(float4) * s->h_fix.size(), hipMemcpyHostToDevice,
+                              s->stream));
+    HIP_TRY(s, hipMemcpyAsync(s->P.zr_cur, s->h_z.data(), sizeof(float4) * s->P.N, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(s, hipMemcpyAsync(s->P.zr_prev, s->h_z.data(), sizeof(float4) * s->P.N, hipMemcpyHostToDevice, s->stream));
+    TRY(reset_state_buffers(s));
+    s->iter = 0;
+    TRY(save_origin(s));
+    HIP_TRY(s, hipStreamSynchronize(s->stream)); // the sources are host memory of the solver, reused next call
+    return TWA_OK;
 }
 
 twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm) {

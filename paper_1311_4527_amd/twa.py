@@ -60,6 +60,8 @@ def load_library():
                                ct.c_float, ct.c_uint, _vp, ct.POINTER(_vp)]
     lib.twa_set_init.restype = ct.c_int
     lib.twa_set_init.argtypes = [_vp, _vp]
+    lib.twa_set_endpoints.restype = ct.c_int
+    lib.twa_set_endpoints.argtypes = [_vp, _vp, _vp]
     lib.twa_set_schedule.restype = ct.c_int
     lib.twa_set_schedule.argtypes = [_vp, ct.c_float, ct.c_int]
     lib.twa_iterate.restype = ct.c_int
@@ -191,6 +193,11 @@ class Solver:
         zt = _dev(z, device=self.device).reshape(self.p, self.eta + 1, self.dim)
         self._check(load_library().twa_set_init(self.h, _ptr(zt)))
         torch.cuda.current_stream(self.device).synchronize()
+
+    def twa_set_endpoints(self, x0, xT):
+        x0t = _dev(x0, device=self.device).reshape(self.p, self.dim)
+        xTt = _dev(xT, device=self.device).reshape(self.p, self.dim)
+        self._check(load_library().twa_set_endpoints(self.h, _ptr(x0t), _ptr(xTt)))
 
     def twa_set_schedule(self, rho0_init: float, n_warm: int):
         self._check(load_library().twa_set_schedule(self.h, float(rho0_init), int(n_warm)))

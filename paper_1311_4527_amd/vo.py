@@ -3,8 +3,11 @@ the joint problem of eq. rec_col_avoi_pos for new end positions x_i after a
 horizon tau, closest to the preferred ones x^ref_i = x_i(0) + v^ref_i tau
 without any two agents colliding while moving there at constant velocity
 (and without touching a wall); the agents then move a fraction of the way
-and the next epoch starts from there.  Each epoch is one solver created with
-TWA_F_VO (eta = 1); this module only drives the epochs.
+and the next epoch starts from there.  One solver created with TWA_F_VO
+(eta = 1) serves every epoch: each epoch loads its start and reference end
+positions (twa_set_endpoints) and iterates until the device's clearance
+measure (twa_get_quality) says the plan is collision-free; this module only
+drives the epochs.
 """
 from __future__ import annotations
 
@@ -13,7 +16,7 @@ from typing import Optional
 import numpy as np
 import torch
 
-from .twa import Solver, TWA_F_VO
+from .twa import Solver, TWAError, TWA_E_INVALID, TWA_F_VO
 
 
 class VOPlanner:
@@ -27,13 +30,14 @@ class VOPlanner:
     cost well below rho0 lets crowded epochs converge); iters: cap on the
     planner iterations of one epoch, which runs in blocks of `check`
     iterations until its plan is collision-free (the paper times each epoch
-    to convergence); margin: relative safety margin on the radii used for
+    to convergence; the check runs on the device); margin: relative safety
+    margin on the radii used for
     planning, so that a plan that is collision-free up to FP32 rounding
     keeps the agents strictly apart at their true radii."""
 
     def __init__(self, positions, goals, radii, walls=None, tau: float = 1.0, fraction: float = 0.5,
                  vmax: float = 0.25, cost=None, rho0: float = 1.0, alpha: float = 0.1, iters: int = 20000,
-                 check: int = 250, margin: float = 1e-3, device="cuda"):
+                 check: int = 50, margin: float = 1e-3, device="cuda"):
         self.pos = np.asarray(positions, dtype=np.float64).copy()
         self.goals = np.asarray(goals, dtype=np.float64).copy()
         self.radii = np.asarray(radii, dtype=np.float64)
@@ -45,6 +49,7 @@ class VOPlanner:
         self.iters, self.check = int(iters), max(1, int(check))
         self.plan_radii = self.radii * (1.0 + float(margin))
         self.last_iterations = 0     # iterations the last epoch took (0: cap reached)
+        self._S = None               # the epochs' solver
 
     def reference(self) -> np.ndarray:
         """x^ref: straight towards the goal at up to vmax for tau."""
@@ -79,26 +84,44 @@ class VOPlanner:
         # positions (relative 5e-6, inside what the solver accepts as starts)
         return self.clearance(self.pos, x, self.plan_radii * (1.0 - 5e-6)) >= 0.0
 
+    def _solver(self, xref: np.ndarray) -> Solver:
+        """The epochs' solver with this epoch's start and reference ends
+        (made at the first epoch, and again should an agent leave the
+        coordinate range it was made for)."""
+        if self._S is not None:
+            try:
+                self._S.twa_set_endpoints(self.pos, xref)
+                return self._S
+            except TWAError as e:
+                if e.status != TWA_E_INVALID:
+                    raise
+                self._S.close()
+        self._S = Solver(self.p, 1, self.dim, self.plan_radii, self.pos, xref, walls=self.walls,
+                         C=self.cost[:, None], rho0=self.rho0, alpha=self.alpha, flags=TWA_F_VO, device=self.device)
+        return self._S
+
     def solve_epoch(self, xref: Optional[np.ndarray] = None) -> np.ndarray:
         """End positions of one epoch (break-point 1 of the solver), iterated
         until collision-free or the iteration cap."""
         xref = self.reference() if xref is None else xref
-        S = Solver(self.p, 1, self.dim, self.plan_radii, self.pos, xref, walls=self.walls, C=self.cost[:, None],
-                   rho0=self.rho0, alpha=self.alpha, flags=TWA_F_VO, device=self.device)
-        try:
-            S.twa_set_init(np.stack([self.pos, xref], axis=1))
-            done, self.last_iterations = 0, 0
-            while done < self.iters:
-                n = min(self.check, self.iters - done)
-                S.twa_iterate(n)
-                done += n
-                x = S.twa_get_trajectories()[:, 1].cpu().numpy().astype(np.float64)
-                if self._plan_ok(x):
-                    self.last_iterations = done
-                    break
-        finally:
-            S.close()
-        return x
+        S = self._solver(xref)
+        # collision-free at the planning radii up to FP32 rounding of the
+        # positions (relative 5e-6, inside what the solver accepts as starts)
+        tol = -1e-5 * float(self.plan_radii.min())
+        done, self.last_iterations = 0, 0
+        while done < self.iters:
+            n = min(self.check, self.iters - done)
+            S.twa_iterate(n)
+            done += n
+            if S.twa_get_quality()["min_clearance"] >= tol:
+                self.last_iterations = done
+                break
+        return S.twa_get_trajectories()[:, 1].cpu().numpy().astype(np.float64)
+
+    def close(self):
+        if self._S is not None:
+            self._S.close()
+            self._S = None
 
     def step(self) -> np.ndarray:
         """Plan one epoch and move a fraction of the way; returns the new
