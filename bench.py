@@ -74,20 +74,26 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def algorithmic_bytes(inst, dense: bool):
+def algorithmic_bytes(inst, dense: bool, active=(0, 0)):
     """Bytes the factor-stream kernel must move per launch.
 
-    dense: u of every edge is read and written (8+8 B per edge in 2-D), both
-    node-record arrays are read once (16 B per node each), plus radii.
+    dense: u of every collision and wall edge is read (8 B per edge in 2-D);
+    it is written back only where it changes, i.e. where a factor that sent
+    weight rho0 in the previous iteration turns inactive and its u resets to
+    zero (at most active = (collision, wall) factors active in the last
+    iteration); energy and fixed edges' u read and written; both node-record
+    arrays read once (16 B per node each), plus radii.
     otherwise: one activity bit per collision/wall factor read and written,
     energy and fixed edges' u read and written, the current node records."""
     c = inst.counts()
     d = inst.dim
     N = c["nodes"]
-    if dense:
-        return 2 * 4 * d * c["edges"] + 2 * 16 * N + 4 * inst.p
-    bits = 2 * ((c["coll"] + 31) // 32 + (c["wall"] + 31) // 32) * 4
     small = 2 * 4 * d * (2 * c["energy"] + c["fixed"])
+    if dense:
+        reads = 4 * d * (4 * c["coll"] + 2 * c["wall"])
+        resets = 4 * d * (4 * active[0] + 2 * active[1])
+        return reads + resets + small + 2 * 16 * N + 4 * inst.p
+    bits = 2 * ((c["coll"] + 31) // 32 + (c["wall"] + 31) // 32) * 4
     return bits + small + 16 * N + 4 * inst.p
 
 
@@ -116,13 +122,14 @@ def run_gpu(inst, dense, steps, warmup):
                 min_clearance=q["min_clearance"], max_move=q["max_move"])
 
 
-def roofline(inst, variant, avg_ms):
+def roofline(inst, variant, avg_ms, stats):
     """Roofline object of the dominant kernel (avg_ms: per-launch device ms of
-    the three kernels)."""
+    the three kernels; stats: the solver's, for the active factor counts)."""
     dom = max(range(3), key=lambda k: avg_ms[k])
     dense = variant == "dense"
+    active = (stats["active_coll"], stats["active_wall"])
     if dom == 0 and dense:
-        A = algorithmic_bytes(inst, True) / (avg_ms[0] * 1e-3) / 1e9
+        A = algorithmic_bytes(inst, True, active) / (avg_ms[0] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=A, peak=HBM_PEAK_GBS, unit="GB/s", frac=A / HBM_PEAK_GBS,
                     traffic=measured_traffic("dense"))
     elif dom == 0:
@@ -133,7 +140,7 @@ def roofline(inst, variant, avg_ms):
         roof = dict(bound="alu", achieved=None, peak=FP32_VALU_TFLOPS, unit="TFLOP/s", frac=None, traffic=None)
     roof["kernel"] = KERNELS[dom]
     roof["avg_us"] = {KERNELS[k]: avg_ms[k] * 1e3 for k in range(3)}
-    roof["algorithmic_bytes_per_launch"] = algorithmic_bytes(inst, dense)
+    roof["algorithmic_bytes_per_launch"] = algorithmic_bytes(inst, dense, active)
     return roof
 
 
@@ -182,15 +189,16 @@ def run_batched(K, warmup):
         Jb, Jp = objective(inst, zb[i]), objective(inst, zp)
         worst = max(worst, abs(Jb - Jp) / max(Jp, 1e-30))
     # the literal dense form of the same batch in the phased launch: every
-    # edge's u read and written, so HBM-bound; its whole iterations (three
-    # phases) against the algorithmic bytes of all instances
+    # edge's u read, so HBM-bound; its whole iterations (three phases)
+    # against the algorithmic bytes of all instances
     D = Batch(insts, flags=TWA_F_DENSE)
     D.twa_batch_config(0, 1)
     D.twa_batch_iterate(warmup)
     Kd = min(K, 500)
     d_ms = D.twa_batch_iterate_timed(Kd)
+    act = [D.twa_batch_solver(i).twa_get_stats() for i in range(len(insts))]
     D.close()
-    bytes_it = sum(algorithmic_bytes(i, True) for i in insts)
+    bytes_it = sum(algorithmic_bytes(i, True, (a["active_coll"], a["active_wall"])) for i, a in zip(insts, act))
     A = bytes_it / (d_ms * 1e-3 / Kd) / 1e9
     dense = dict(iterations=Kd, device_ms=d_ms, us_per_iteration=d_ms * 1e3 / Kd, value=F * Kd / (d_ms * 1e-3),
                  roofline=dict(bound="hbm", achieved=A, peak=HBM_PEAK_GBS, unit="GB/s", frac=A / HBM_PEAK_GBS,
@@ -543,7 +551,7 @@ def main():
                                     f"r={float(inst.radii[0])}, FP32 ({c['coll']} collision + {c['wall']} wall + "
                                     f"{c['energy']} energy + {c['fixed']} fixed factors, {c['edges']} edges)",
                            variant=args.variant, iterations_per_s=args.steps / r["seconds"]),
-               roofline=roofline(inst, args.variant, avg),
+               roofline=roofline(inst, args.variant, avg, r["stats"]),
                active=r["stats"], objective=r["objective"], min_clearance=r["min_clearance"],
                max_move=r["max_move"])
     print(f"# main {args.variant}: {out['value']:.4g} factor-updates/s", file=sys.stderr, flush=True)
@@ -553,7 +561,7 @@ def main():
         avg2 = [m / args.steps for m in r2["kernel_ms"]]
         out["variants"] = {other: dict(value=F * args.steps / r2["seconds"],
                                        ms_per_step=1e3 * r2["seconds"] / args.steps,
-                                       roofline=roofline(inst, other, avg2), objective=r2["objective"])}
+                                       roofline=roofline(inst, other, avg2, r2["stats"]), objective=r2["objective"])}
         print(f"# variant {other}: {out['variants'][other]['value']:.4g}", file=sys.stderr, flush=True)
         out["batched"] = run_batched(args.batch_steps, 50)
         print(f"# batched: {out['batched']['value']:.4g} (x{out['batched']['speedup']:.1f} vs sequential)",

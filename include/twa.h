@@ -59,10 +59,12 @@ enum { TWA_W_ZERO = 0, TWA_W_STD = 1, TWA_W_INF = 2 };
 
 /* twa_create flags */
 enum {
-    /* Read and write u of every edge every iteration, the literal dense form
-     * of App. B step 7.  Without it an edge whose factor sent weight 0 keeps
-     * no u (it is zero by the update rule), and a bit per factor records
-     * which factors carry one.  Results are identical. */
+    /* Read u of every edge every iteration, the literal dense form of
+     * App. B step 7 (u is written where the update changes it: a u that
+     * the rule resets to zero and that is zero already is not stored
+     * again).  Without it an edge whose factor sent weight 0 keeps no u (it
+     * is zero by the update rule), and a bit per factor records which
+     * factors carry one.  Results are identical. */
     TWA_F_DENSE = 1u << 0,
     /* Make twa_backward available: the solver remembers the state each run
      * starts from (at create, twa_set_init and twa_set_state).  No cost per

@@ -248,8 +248,12 @@ __device__ __forceinline__ bool coll_factor(const Params &P, long long f, float 
             push_prev = true;
             check_cur = false;
         } else {
+            // zero weight resets u; a u that is zero already (the common
+            // case) is not written again, so the pass only reads u
+            unsigned nz = 0u;
+            for (int k = 0; k < 4 * D; ++k) nz |= __float_as_uint(u[k]);
             for (int k = 0; k < 4 * D; ++k) u[k] = 0.f;
-            store_u_coll<D>(P, f, u);
+            if (nz) store_u_coll<D>(P, f, u);
         }
     } else {
         if ((word >> lane) & 1ull) {
@@ -452,8 +456,10 @@ __device__ __forceinline__ void wall_stream(const Params &P, const Rec &Z, long 
                 push_prev = true;
                 check_cur = false;
             } else {
+                const unsigned nz = __float_as_uint(u.x) | __float_as_uint(u.y) | __float_as_uint(u.z) |
+                                    __float_as_uint(u.w);
                 u = make_float4(0.f, 0.f, 0.f, 0.f);
-                P.u_wall[f] = u;
+                if (nz) P.u_wall[f] = u;
             }
         } else {
             unsigned wd = P.bits_wall[f >> 5];
@@ -865,11 +871,12 @@ __device__ __forceinline__ void node_update(const Params &P, long long nd) {
 }
 
 // ------------------------------------------------------------------ plain kernels
-// DENSE: the literal dense form (u of every edge read and written); it
-// walks two break-point intervals per wave, the activity-bit form eight.
+// DENSE: the literal dense form (u of every edge read; written where it
+// changes); it walks four break-point intervals per wave, the activity-bit
+// form eight.
 template <int D, int MODE, bool DENSE>
 __device__ __forceinline__ void stream_block(const Params &P, long long b) {
-    constexpr int CPW = DENSE ? 2 : 8;
+    constexpr int CPW = DENSE ? 4 : 8;
     const bool clear_bits = MODE != M_FINAL && P.dense == 0;
     const Rec Z{P.zr_cur, P.zr_prev};
     if (b < P.nbc) {
@@ -1926,7 +1933,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
     P.Fc = Fc, P.Fw = Fw, P.Fe = Fe, P.Ff = Ff;
     P.N = (long long)p * (eta + 1);
     // break-point intervals per wave in k_stream (see k_stream)
-    P.cpw = (flags & (TWA_F_DENSE | TWA_F_ADMM)) ? 2 : 8; // as k_stream<..., DENSE> (ADMM runs dense)
+    P.cpw = (flags & (TWA_F_DENSE | TWA_F_ADMM)) ? 4 : 8; // as k_stream<..., DENSE> (ADMM runs dense)
     // rows of the pair triangle cut into chunks of 64: chunk (s, i, j0)
     std::vector<int> hrowchunk((size_t)p, 0);
     for (int i = 0; i + 1 < p; ++i) hrowchunk[i + 1] = hrowchunk[i] + (p - 1 - i + 63) / 64;
