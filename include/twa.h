@@ -115,6 +115,29 @@ typedef struct {
 } twa_stats;
 
 /*
+ * Device memory provider (boundary convention of this library; the paper
+ * has no such notion).  Every device buffer that a later twa_create,
+ * twa_batch_create or twa_backward allocates comes from
+ *   alloc(bytes, device, stream, ctx)      -> device pointer, NULL on failure
+ * and goes back through
+ *   release(ptr, bytes, device, stream, ctx)
+ * where device is the HIP device of the solver and stream its hipStream_t.
+ * The library calls release only once its own work on that memory is done
+ * (it synchronises the stream first), so a stream-ordered pool such as a
+ * caching allocator may hand the block out again at once.  A failed alloc
+ * makes the call fail with TWA_E_NOMEM.  alloc and release must both be
+ * NULL (restore hipMalloc / hipFree, the default) or both be set, else
+ * TWA_E_INVALID.  Process-wide; each solver and batch keeps the pair in
+ * effect when it was created for its whole life, so changing it does not
+ * affect existing ones.  The callbacks run on the calling thread, inside
+ * the library call that needs memory, and must not call into this library.
+ * twa_backward_noalloc never calls them.
+ */
+typedef void *(*twa_alloc_fn)(size_t bytes, int device, void *stream, void *ctx);
+typedef void (*twa_free_fn)(void *ptr, size_t bytes, int device, void *stream, void *ctx);
+twa_status twa_set_allocator(twa_alloc_fn alloc, twa_free_fn release, void *ctx);
+
+/*
  * Create a solver for one planning problem (Sec. 1 problem statement,
  * Sec. 3.1-3.2 formulation).
  *   p >= 1 agents, eta >= 1 segments (eta+1 break-points), dim 2 or 3.

@@ -695,14 +695,16 @@ twa_status grow_solver_pool(twa_solver *s, Buffers &B, unsigned need) {
 // grow-only device buffer owned by the solver
 twa_status ensure(twa_solver *s, void **buf, size_t *have, size_t want) {
     if (*have >= want) return TWA_OK;
-    if (*buf) (void)hipFree(*buf);
+    if (*buf) {
+        // the stream may still read the old buffer
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        s->mem.put(*buf, *have, s->stream);
+    }
     *buf = nullptr;
     *have = 0;
-    if (hipMalloc(buf, want) != hipSuccess) {
-        (void)hipGetLastError();
-        *buf = nullptr;
+    *buf = s->mem.get(want, s->stream);
+    if (!*buf)
         return twa_rt::fail(s, TWA_E_NOMEM, "twa_backward: allocation of " + std::to_string(want) + " bytes failed");
-    }
     *have = want;
     return TWA_OK;
 }

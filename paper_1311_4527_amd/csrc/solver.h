@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/twa.h"
@@ -87,6 +88,21 @@ struct Params {
     long long f_energy, f_coll, f_wall; // canonical factor offsets
 };
 
+// Device memory provider of one solver or batch: the process-wide pair of
+// twa_set_allocator in effect at its create, else hipMalloc / hipFree.
+struct Allocator {
+    twa_alloc_fn alloc = nullptr;
+    twa_free_fn release = nullptr;
+    void *ctx = nullptr;
+    int device = 0;
+    // nullptr on failure (a HIP error it caused is cleared)
+    void *get(size_t bytes, hipStream_t stream) const;
+    // the caller has synchronised stream (or never used the memory)
+    void put(void *ptr, size_t bytes, hipStream_t stream) const;
+};
+// the pair in effect now, for device
+Allocator current_allocator(int device);
+
 } // namespace twa_rt
 
 struct twa_solver {
@@ -103,7 +119,8 @@ struct twa_solver {
     unsigned *resid_dev = nullptr;  // residual of the last finalized iteration (float bits)
     bool resid_valid = false;       // resid_dev holds the last iteration's residual
     int *bad_dev = nullptr;
-    std::vector<void *> allocs;
+    twa_rt::Allocator mem;                           // where every buffer below comes from
+    std::vector<std::pair<void *, size_t>> allocs; // buffers of create (freed at destroy)
     std::string err;
     twa_status latched = TWA_OK;
     float *dbg_x = nullptr;

@@ -33,6 +33,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -42,6 +43,54 @@
 
 using namespace twa;
 using twa_rt::Params;
+
+// ------------------------------------------------------------------ device memory provider
+namespace twa_rt {
+
+namespace {
+std::mutex g_alloc_mutex;
+twa_alloc_fn g_alloc = nullptr;
+twa_free_fn g_release = nullptr;
+void *g_alloc_ctx = nullptr;
+} // namespace
+
+Allocator current_allocator(int device) {
+    std::lock_guard<std::mutex> lock(g_alloc_mutex);
+    Allocator a;
+    a.alloc = g_alloc;
+    a.release = g_release;
+    a.ctx = g_alloc_ctx;
+    a.device = device;
+    return a;
+}
+
+void *Allocator::get(size_t bytes, hipStream_t stream) const {
+    void *p = nullptr;
+    if (alloc) {
+        p = alloc(bytes, device, stream, ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    return p;
+}
+
+void Allocator::put(void *ptr, size_t bytes, hipStream_t stream) const {
+    if (!ptr) return;
+    if (release) release(ptr, bytes, device, stream, ctx);
+    else (void)hipFree(ptr);
+}
+
+} // namespace twa_rt
+
+extern "C" twa_status twa_set_allocator(twa_alloc_fn alloc, twa_free_fn release, void *ctx) {
+    if ((alloc == nullptr) != (release == nullptr)) return TWA_E_INVALID;
+    std::lock_guard<std::mutex> lock(twa_rt::g_alloc_mutex);
+    twa_rt::g_alloc = alloc;
+    twa_rt::g_release = release;
+    twa_rt::g_alloc_ctx = alloc ? ctx : nullptr;
+    return TWA_OK;
+}
 
 #define TWA_VERSION "twa-mi355x 0.1"
 
@@ -1064,11 +1113,12 @@ __device__ __forceinline__ const Params &params_lds(const Params *src, Params *d
 // lengths are workgroup-local counters.
 constexpr int kBatchLdsNodes = 4000; // 62.5 KiB of node records per workgroup
 
-template <int D, int MODE, int BLOCK>
+template <int D, int MODE, int BLOCK, bool RESIDENT = false>
 __device__ __forceinline__ void batch_instance(const Params &P, float4 *zs, int *len) {
     const bool clear_bits = P.dense == 0;
-    const bool stage = P.N <= kBatchLdsNodes;
-    const bool stage_prev = P.dense && MODE != M_FIRST && 2 * P.N <= kBatchLdsNodes;
+    // RESIDENT: P's node records already live in LDS (k_tiny)
+    const bool stage = !RESIDENT && P.N <= kBatchLdsNodes;
+    const bool stage_prev = !RESIDENT && P.dense && MODE != M_FIRST && 2 * P.N <= kBatchLdsNodes;
     if (stage)
         for (long long nd = threadIdx.x; nd < P.N; nd += BLOCK) zs[nd] = P.zr_cur[nd];
     if (stage_prev)
@@ -1153,6 +1203,90 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const Params *insts, const int 
                 else batch_instance<3, M_FUSED, BLOCK>(P, zs, len);
             }
         }
+    }
+}
+
+// ------------------------------------------------------------------ LDS-resident tiny instance
+// A tiny instance alone in one workgroup keeps its whole mutable state (node
+// records, u, x, activity bits, queues, consensus sums, counters) in LDS for
+// the K iterations of a launch: loaded at the start, written back at the
+// end.  Every access of an iteration then stays on the compute unit; the
+// per-factor code is batch_instance's, on a copy of the parameters whose
+// pointers are redirected into LDS (generic pointers reach LDS as well), so
+// the instance evolves bitwise as in the persistent batched kernel.
+enum TinyArr {
+    TA_ZPREV, TA_ZCUR, TA_UC, TA_XC, TA_UW, TA_XW, TA_UE, TA_UF, TA_BC, TA_BW, TA_CTR, TA_ACC, TA_CNT, TA_INF,
+    TA_QC, TA_QW, TA_QCNT, kTinyArrays
+};
+constexpr int kTinyCopied = TA_QC; // arrays before it are loaded and written back; the queues are scratch
+
+struct TinyLds {
+    unsigned off[kTinyArrays];   // byte offset in the dynamic LDS (16-aligned)
+    unsigned bytes[kTinyArrays]; // multiple of 4
+    unsigned total;
+};
+
+__device__ __forceinline__ void tiny_arrays(const Params &P, void **a) {
+    a[TA_ZPREV] = P.zr_prev, a[TA_ZCUR] = P.zr_cur, a[TA_UC] = P.u_coll, a[TA_XC] = P.x_coll;
+    a[TA_UW] = P.u_wall, a[TA_XW] = P.x_wall, a[TA_UE] = P.u_energy, a[TA_UF] = P.u_fixed;
+    a[TA_BC] = P.bits_coll, a[TA_BW] = P.bits_wall, a[TA_CTR] = P.counters, a[TA_ACC] = P.acc;
+    a[TA_CNT] = P.cnt, a[TA_INF] = P.inf_val, a[TA_QC] = P.qc, a[TA_QW] = P.qw, a[TA_QCNT] = P.qcnt;
+}
+
+__device__ __forceinline__ void tiny_redirect(Params &P, char *b, const TinyLds &L) {
+    P.zr_prev = reinterpret_cast<float4 *>(b + L.off[TA_ZPREV]);
+    P.zr_cur = reinterpret_cast<float4 *>(b + L.off[TA_ZCUR]);
+    P.u_coll = reinterpret_cast<float4 *>(b + L.off[TA_UC]);
+    P.x_coll = reinterpret_cast<float4 *>(b + L.off[TA_XC]);
+    P.u_wall = reinterpret_cast<float4 *>(b + L.off[TA_UW]);
+    P.x_wall = reinterpret_cast<float4 *>(b + L.off[TA_XW]);
+    P.u_energy = reinterpret_cast<float *>(b + L.off[TA_UE]);
+    P.u_fixed = reinterpret_cast<float *>(b + L.off[TA_UF]);
+    P.bits_coll = reinterpret_cast<unsigned long long *>(b + L.off[TA_BC]);
+    P.bits_wall = reinterpret_cast<unsigned *>(b + L.off[TA_BW]);
+    P.counters = reinterpret_cast<int *>(b + L.off[TA_CTR]);
+    P.acc = reinterpret_cast<unsigned long long *>(b + L.off[TA_ACC]);
+    P.cnt = reinterpret_cast<int *>(b + L.off[TA_CNT]);
+    P.inf_val = reinterpret_cast<float4 *>(b + L.off[TA_INF]);
+    P.qc = reinterpret_cast<unsigned *>(b + L.off[TA_QC]);
+    P.qw = reinterpret_cast<unsigned *>(b + L.off[TA_QW]);
+    P.qcnt = reinterpret_cast<int *>(b + L.off[TA_QCNT]);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_tiny(const Params *src, TinyLds L, int K, int first) {
+    extern __shared__ __align__(16) char lds[];
+    __shared__ Params sp;
+    __shared__ int len[2];
+    const Params &G = params_lds<BLOCK>(src, &sp); // (ends with a barrier)
+    void *ga[kTinyArrays];
+    tiny_arrays(G, ga);
+#pragma unroll
+    for (int a = 0; a < kTinyCopied; ++a) {
+        const unsigned *g = static_cast<const unsigned *>(ga[a]);
+        unsigned *d = reinterpret_cast<unsigned *>(lds + L.off[a]);
+        for (unsigned t = threadIdx.x; t < L.bytes[a] / 4; t += BLOCK) d[t] = g[t];
+    }
+    if (threadIdx.x == 0) reinterpret_cast<int *>(lds + L.off[TA_QCNT])[0] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) tiny_redirect(sp, lds, L);
+    __syncthreads();
+    for (int it = 0; it < K; ++it) {
+        const bool fst = first && it == 0;
+        if (sp.dim == 2) {
+            if (fst) batch_instance<2, M_FIRST, BLOCK, true>(sp, nullptr, len);
+            else batch_instance<2, M_FUSED, BLOCK, true>(sp, nullptr, len);
+        } else {
+            if (fst) batch_instance<3, M_FIRST, BLOCK, true>(sp, nullptr, len);
+            else batch_instance<3, M_FUSED, BLOCK, true>(sp, nullptr, len);
+        }
+    }
+    // (batch_instance ends with a barrier) write the state back
+#pragma unroll
+    for (int a = 0; a < kTinyCopied; ++a) {
+        const unsigned *d = reinterpret_cast<const unsigned *>(lds + L.off[a]);
+        unsigned *g = static_cast<unsigned *>(ga[a]);
+        for (unsigned t = threadIdx.x; t < L.bytes[a] / 4; t += BLOCK) g[t] = d[t];
     }
 }
 
@@ -1455,14 +1589,10 @@ void launch(twa_solver *s, Kern kernel, dim3 grid, dim3 block, Args... args) {
 
 template <class T>
 twa_status dev_alloc(twa_solver *s, T **ptr, size_t count) {
-    void *p = nullptr;
     size_t bytes = std::max<size_t>(count * sizeof(T), 16);
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(s, TWA_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-    }
-    s->allocs.push_back(p);
+    void *p = s->mem.get(bytes, s->stream);
+    if (!p) return fail(s, TWA_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    s->allocs.emplace_back(p, bytes);
     *ptr = static_cast<T *>(p);
     return TWA_OK;
 }
@@ -1570,6 +1700,39 @@ constexpr int kTinyBlock = 512, kTinyChunk = 4096; // iterations per launch at m
 
 bool tiny(const twa_solver *s) { return s->P.Fc + s->P.Fw <= kTinyFactors; }
 
+// LDS layout of a tiny instance's mutable state for k_tiny (the sizes of
+// its device arrays); false when it does not fit kTinyLdsMax.
+constexpr unsigned kTinyLdsMax = 56u << 10;
+
+bool tiny_layout(const twa_solver *s, TinyLds *L) {
+    const Params &P = s->P;
+    const long long d = s->dim, N = P.N;
+    long long bytes[kTinyArrays];
+    bytes[TA_ZPREV] = bytes[TA_ZCUR] = 16 * N;
+    bytes[TA_UC] = bytes[TA_XC] = 16 * std::max<long long>(1, d * P.Fc);
+    bytes[TA_UW] = bytes[TA_XW] = 16 * std::max<long long>(1, P.Fw);
+    bytes[TA_UE] = 4 * P.Fe * 2 * d;
+    bytes[TA_UF] = 4 * P.Ff * d;
+    bytes[TA_BC] = 8 * std::max<long long>(1, P.nch);
+    bytes[TA_BW] = 4 * std::max<long long>(1, (P.Fw + 31) / 32);
+    bytes[TA_CTR] = 4 * 8;
+    bytes[TA_ACC] = 8 * 2 * d * N;
+    bytes[TA_CNT] = 4 * 2 * N;
+    bytes[TA_INF] = 16 * N;
+    bytes[TA_QC] = 4 * std::max<long long>(1, P.Fc); // one entry per factor at most
+    bytes[TA_QW] = 4 * std::max<long long>(1, P.Fw);
+    bytes[TA_QCNT] = 4;
+    long long off = 0;
+    for (int a = 0; a < kTinyArrays; ++a) {
+        L->off[a] = (unsigned)off;
+        L->bytes[a] = (unsigned)bytes[a];
+        off += (bytes[a] + 15) & ~15LL;
+        if (off > (long long)kTinyLdsMax) return false;
+    }
+    L->total = (unsigned)off;
+    return true;
+}
+
 // The device copy of a tiny instance's parameters that the persistent kernel
 // reads (at the steady rho0, no debug capture) and its one-bin layout; made
 // at create, so that iterating allocates and uploads nothing.
@@ -1591,11 +1754,17 @@ twa_status prepare_tiny(twa_solver *s) {
 // k iterations of a tiny instance at the steady rho0 (bitwise the plain
 // iterations: the same per-factor code).
 twa_status iterate_tiny(twa_solver *s, int k) {
+    TinyLds L;
+    const bool resident = tiny_layout(s, &L);
     while (k > 0) {
         const int n = std::min(k, kTinyChunk);
-        hipLaunchKernelGGL(k_batch<kTinyBlock>, dim3(1), dim3(kTinyBlock), 0, s->stream,
-                           (const Params *)s->tiny_params, (const int *)s->tiny_bins, (const int *)s->tiny_bins + 2, n,
-                           s->pending ? 0 : 1);
+        if (resident)
+            hipLaunchKernelGGL(k_tiny<kTinyBlock>, dim3(1), dim3(kTinyBlock), L.total, s->stream,
+                               (const Params *)s->tiny_params, L, n, s->pending ? 0 : 1);
+        else
+            hipLaunchKernelGGL(k_batch<kTinyBlock>, dim3(1), dim3(kTinyBlock), 0, s->stream,
+                               (const Params *)s->tiny_params, (const int *)s->tiny_bins,
+                               (const int *)s->tiny_bins + 2, n, s->pending ? 0 : 1);
         HIP_TRY(s, hipGetLastError());
         s->pending = true;
         s->iter += n;
@@ -1822,9 +1991,10 @@ void twa_destroy(twa_solver *s) {
     for (hipGraphExec_t e : s->graphs)
         if (e) (void)hipGraphExecDestroy(e);
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
-    for (void *p : s->allocs) (void)hipFree(p);
-    for (void *p : {s->adj_ws, s->adj_arena, s->adj_pool_mem})
-        if (p) (void)hipFree(p);
+    for (auto &a : s->allocs) s->mem.put(a.first, a.second, s->stream);
+    s->mem.put(s->adj_ws, s->adj_ws_bytes, s->stream);
+    s->mem.put(s->adj_arena, s->adj_arena_bytes, s->stream);
+    s->mem.put(s->adj_pool_mem, s->adj_pool_bytes, s->stream);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s;
 }
@@ -1887,6 +2057,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         fail(s, TWA_E_DEVICE, "hipGetDevice failed");
         return bail(TWA_E_DEVICE);
     }
+    s->mem = twa_rt::current_allocator(s->device);
     if (!s->stream) {
         // The null stream cannot be captured into graphs.  A stream made with
         // the default flags orders itself with the null stream both ways, so
@@ -2317,6 +2488,8 @@ struct twa_batch {
     int g_k = -1, g_first = -1;
     std::vector<Params> hparams;       // host copy of insts_dev
     hipStream_t own_stream = nullptr;  // made when the caller passes the null stream
+    twa_rt::Allocator mem;             // where insts_dev, the bins and map_dev come from
+    size_t map_bytes = 0;
 };
 
 namespace {
@@ -2422,10 +2595,11 @@ void twa_batch_destroy(twa_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
     for (twa_solver *s : b->solvers) twa_destroy(s);
-    if (b->insts_dev) (void)hipFree(b->insts_dev);
-    if (b->bin_start_dev) (void)hipFree(b->bin_start_dev);
-    if (b->bin_items_dev) (void)hipFree(b->bin_items_dev);
-    if (b->map_dev) (void)hipFree(b->map_dev);
+    const size_t n = b->solvers.size();
+    b->mem.put(b->insts_dev, sizeof(Params) * n, b->stream);
+    b->mem.put(b->bin_start_dev, sizeof(int) * (n + 1), b->stream);
+    b->mem.put(b->bin_items_dev, sizeof(int) * n, b->stream);
+    b->mem.put(b->map_dev, b->map_bytes, b->stream);
     if (b->pexec) (void)hipGraphExecDestroy(b->pexec);
     if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
     delete b;
@@ -2437,6 +2611,13 @@ twa_status twa_batch_create(int n, const twa_instance *inst, unsigned flags, voi
     twa_batch *b = new (std::nothrow) twa_batch();
     if (!b) return TWA_E_NOMEM;
     b->stream = static_cast<hipStream_t>(hip_stream);
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return TWA_E_DEVICE;
+    }
+    b->mem = twa_rt::current_allocator(device);
     if (!b->stream) {
         // as twa_create: a capturable stream ordered with the null stream
         if (hipStreamCreate(&b->own_stream) != hipSuccess) {
@@ -2461,11 +2642,10 @@ twa_status twa_batch_create(int n, const twa_instance *inst, unsigned flags, voi
         }
         b->solvers.push_back(s);
     }
-    hipError_t e = hipMalloc(&b->insts_dev, sizeof(Params) * n);
-    if (e == hipSuccess) e = hipMalloc(&b->bin_start_dev, sizeof(int) * (n + 1));
-    if (e == hipSuccess) e = hipMalloc(&b->bin_items_dev, sizeof(int) * n);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
+    b->insts_dev = static_cast<Params *>(b->mem.get(sizeof(Params) * n, b->stream));
+    b->bin_start_dev = static_cast<int *>(b->mem.get(sizeof(int) * (n + 1), b->stream));
+    b->bin_items_dev = static_cast<int *>(b->mem.get(sizeof(int) * n, b->stream));
+    if (!b->insts_dev || !b->bin_start_dev || !b->bin_items_dev) {
         twa_batch_destroy(b);
         return TWA_E_NOMEM;
     }
@@ -2500,9 +2680,9 @@ twa_status twa_batch_create(int n, const twa_instance *inst, unsigned flags, voi
     b->n_nodes = (int)mn.size();
     ms.insert(ms.end(), mq.begin(), mq.end());
     ms.insert(ms.end(), mn.begin(), mn.end());
-    if (hipMalloc(&b->map_dev, sizeof(int2) * ms.size()) != hipSuccess) {
-        (void)hipGetLastError();
-        b->map_dev = nullptr;
+    b->map_bytes = sizeof(int2) * ms.size();
+    b->map_dev = static_cast<int2 *>(b->mem.get(b->map_bytes, b->stream));
+    if (!b->map_dev) {
         twa_batch_destroy(b);
         return TWA_E_NOMEM;
     }

@@ -2,14 +2,17 @@
 
 Every function of the library is exposed under the same name; ``Solver``
 wraps a ``twa_solver*`` and owns it.  PyTorch provides the device memory
-(CUDA tensors on the HIP device) and the stream.  Every step of the planner
-runs in the HIP kernels of ``libtwa.so``: if the library is missing this
-module raises, there is no fallback.
+(CUDA tensors on the HIP device; the solvers' own buffers come from torch's
+caching allocator through ``twa_set_allocator``) and the stream.  Every step
+of the planner runs in the HIP kernels of ``libtwa.so``: if the library is
+missing this module raises, there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as ct
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -45,6 +48,52 @@ class _Stats(ct.Structure):
 
 _lib = None
 _vp = ct.c_void_p
+_ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_int, ct.c_void_p, ct.c_void_p)
+_FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_size_t, ct.c_int, ct.c_void_p, ct.c_void_p)
+_live = weakref.WeakSet()   # solvers and batches that own library objects
+
+
+def _torch_alloc(nbytes, device, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(device), stream=int(stream or 0))
+    except Exception:  # NULL: the library call fails with TWA_E_NOMEM
+        return None
+
+
+def _torch_free(ptr, nbytes, device, stream, ctx):
+    try:
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+# kept alive for as long as the library may call them
+_torch_alloc_c = _ALLOC_FN(_torch_alloc)
+_torch_free_c = _FREE_FN(_torch_free)
+
+
+def twa_set_allocator(use_torch: bool = True):
+    """Where solvers and batches created from now on take their device
+    buffers: torch's caching allocator (the default, set when the library
+    is loaded) or plain hipMalloc/hipFree (use_torch=False)."""
+    lib = load_library()
+    if use_torch:
+        st = lib.twa_set_allocator(_torch_alloc_c, _torch_free_c, None)
+    else:
+        st = lib.twa_set_allocator(_ALLOC_FN(), _FREE_FN(), None)
+    if st != TWA_OK:
+        raise TWAError(st, "twa_set_allocator failed")
+
+
+@atexit.register
+def _close_all():
+    # destroy what is still alive while torch's allocator can take the
+    # memory back (before the interpreter tears the modules down)
+    for o in list(_live):
+        try:
+            o.close()
+        except Exception:
+            pass
 
 
 def load_library():
@@ -115,6 +164,10 @@ def load_library():
     lib.twa_batch_last_error.argtypes = [_vp]
     lib.twa_batch_destroy.restype = None
     lib.twa_batch_destroy.argtypes = [_vp]
+    lib.twa_set_allocator.restype = ct.c_int
+    lib.twa_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, _vp]
+    if lib.twa_set_allocator(_torch_alloc_c, _torch_free_c, None) != TWA_OK:
+        raise TWAError(TWA_E_INVALID, "twa_set_allocator failed")
     _lib = lib
     return lib
 
@@ -157,6 +210,7 @@ class Solver:
         if st != TWA_OK:
             raise TWAError(st, "twa_create failed")
         self.h = h
+        _live.add(self)
         self.n_walls = nw
         nf, ne = ct.c_longlong(), ct.c_longlong()
         lib.twa_sizes(self.h, ct.byref(nf), ct.byref(ne))
@@ -334,6 +388,7 @@ class Batch:
         if st != TWA_OK:
             raise TWAError(st, "twa_batch_create failed")
         self.h = h
+        _live.add(self)
         self.stream.synchronize()
 
     def _check(self, st):

@@ -1,10 +1,11 @@
 """Instances of at most 256 collision + wall factors: untimed iterations run
-in the persistent one-workgroup kernel, all iterations of a call in one
-launch.  The per-factor code is the plain kernels', so the state after any
-mix of such calls and plain iterations must equal, bit for bit, the state
-after plain iterations alone (twa_iterate_timed launches its last four
-iterations on their own, through the plain kernels, so calls of four timed
-iterations run plain throughout)."""
+in one workgroup, all iterations of a call in one launch, with the whole
+state held in LDS when it fits (else in the persistent batched kernel).
+The per-factor code is the plain kernels', so the state after any mix of
+such calls and plain iterations must equal, bit for bit, the state after
+plain iterations alone (twa_iterate_timed launches its last two iterations
+on their own, through the plain kernels, so calls of two timed iterations
+run plain throughout)."""
 import pytest
 
 from paper_1311_4527_amd import instances as I
@@ -17,6 +18,8 @@ CASES = {
     "swap8_2d": lambda: I.conf_small(0),                                # 112 collision factors
     "swap6_3d": lambda: I.circle_swap(6, 0.05, 4, dim=3, seed=3),       # 60
     "box8_walls": lambda: I.conf_box1024(seed=5, p=8, eta=4, n_walls=4),  # 112 + 128 wall factors
+    # 250 collision factors over 251 break-points: too large for the LDS copy
+    "pair_eta250": lambda: I.circle_swap(2, 0.05, 250, seed=4),
 }
 
 
@@ -28,9 +31,9 @@ def _state(S):
 
 
 def _plain(S, k):
-    assert k % 4 == 0
-    for _ in range(k // 4):
-        S.twa_iterate_timed(4)
+    assert k % 2 == 0
+    for _ in range(k // 2):
+        S.twa_iterate_timed(2)
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
@@ -93,6 +96,23 @@ def test_tiny_long_call_spans_launches():
     za, ua, la, ia = _state(A)
     zb, ub, lb, ib = _state(B)
     assert ia == ib == 5000
+    assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb)
+    A.close()
+    B.close()
+
+
+def test_tiny_vo_epoch_equals_plain():
+    """A velocity-obstacle epoch (eta = 1) in the LDS-resident kernel."""
+    import torch
+    from paper_1311_4527_amd.twa import Solver, TWA_F_VO
+    inst = I.circle_swap(12, 0.05, 1, seed=5, alpha=0.1, C=0.05)
+    A = Solver.from_instance(inst, flags=TWA_F_VO)
+    B = Solver.from_instance(inst, flags=TWA_F_VO)
+    A.twa_iterate(149)
+    A.twa_iterate(1)
+    _plain(B, 150)
+    za, ua, la, _ = _state(A)
+    zb, ub, lb, _ = _state(B)
     assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb)
     A.close()
     B.close()

@@ -158,3 +158,16 @@ def test_consensus_scale_rejects_bad_arguments(lib):
     sc, lim = ct.c_double(), ct.c_double()
     for args in ((0, 0, 1.0), (4, -1, 1.0), (4, 0, 0.5), (4, 0, float("nan"))):
         assert lib.twa_consensus_scale(*args, ct.byref(sc), ct.byref(lim)) == 1
+
+
+def test_set_allocator_takes_both_callbacks_or_none(lib):
+    fn_a = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_int, ct.c_void_p, ct.c_void_p)
+    fn_f = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_size_t, ct.c_int, ct.c_void_p, ct.c_void_p)
+    lib.twa_set_allocator.restype = ct.c_int
+    lib.twa_set_allocator.argtypes = [fn_a, fn_f, ct.c_void_p]
+    a = fn_a(lambda n, d, s, c: None)
+    f = fn_f(lambda p, n, d, s, c: None)
+    assert lib.twa_set_allocator(a, fn_f(), None) == 1
+    assert lib.twa_set_allocator(fn_a(), f, None) == 1
+    assert lib.twa_set_allocator(a, f, None) == 0
+    assert lib.twa_set_allocator(fn_a(), fn_f(), None) == 0
