@@ -57,8 +57,11 @@ def test_solver_and_backward_buffers_come_from_the_callbacks():
         assert torch.equal(z, z_ref)
         g = S.twa_backward(torch.ones_like(z))
         assert C.calls > n_create        # the adjoint's buffers
+        # (the adjoint sums cotangents with float atomics: equal up to the
+        # rounding of their order)
         for a, b in zip(g, g_ref):
-            assert torch.equal(a, b)
+            scale = float(b.abs().max())
+            assert torch.allclose(a, b, rtol=1e-5, atol=1e-6 * scale), float((a - b).abs().max())
         S.close()
         assert not C.live                # everything went back through release
     finally:
