@@ -288,11 +288,13 @@ twa_status twa_consensus_scale(int p, int n_walls, double coord_max, double *sca
  * collision and wall factors sparse, as it is zero on every factor that sent
  * weight 0) and recomputes one segment at a time, the factor kernels
  * capturing each iteration's weights and the minimiser inputs of the
- * factors that sent rho0.  Its buffers are allocated at the first call and
- * kept, grown when a later call needs more, until twa_destroy (TWA_E_NOMEM
- * if they do not fit).  The solver's forward state is the same afterwards.
- * dim == 2 only (TWA_E_INVALID otherwise); TWA_E_STATE without TWA_F_TAPE.
- * Synchronises the stream.
+ * factors that sent rho0.  A segment's reverse steps run on a second stream
+ * that the solver makes at create (TWA_F_TAPE), while the segment before it
+ * is recomputed on the solver's stream.  Its buffers are allocated at the
+ * first call and kept, grown when a later call needs more, until
+ * twa_destroy (TWA_E_NOMEM if they do not fit).  The solver's forward state
+ * is the same afterwards.  dim == 2 only (TWA_E_INVALID otherwise);
+ * TWA_E_STATE without TWA_F_TAPE.  Synchronises both streams.
  */
 twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT, float *dL_dr,
                         float *dL_dz0);

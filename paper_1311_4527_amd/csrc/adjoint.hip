@@ -129,12 +129,31 @@ __global__ __launch_bounds__(256) void k_adj_accum(Adj A, float *S, const AdjRec
     }
 }
 
-// per node: the class of its mean (infinite edges if any, else rho0 edges:
-// the <-rho code the node pass gave it) and g = (dz' - s * sum of du' over
-// kept edges) / |mean set|
-__global__ __launch_bounds__(256) void k_adj_select(Adj A) {
+// Blocks [0, nb_nodes), per node: the class of its mean (infinite edges if
+// any, else rho0 edges: the <-rho code the node pass gave it) and g = (dz' -
+// s * sum of du' over kept edges) / |mean set|; and the node's entries of
+// this step's output sums cleared.  The other blocks clear the output's u
+// cotangents of the collision / wall factors captured two steps later (in
+// forward order; records [clr[0], clr[1])), the last ones written there, so
+// that only this step's writes remain.  Every fixed and energy edge is
+// written at every step.
+__global__ __launch_bounds__(256) void k_adj_select(Adj A, unsigned nb_nodes, const AdjRec *pool, const unsigned *clr,
+                                                    unsigned cap) {
+    if (blockIdx.x >= nb_nodes) {
+        if (!clr) return;
+        const unsigned b = clr[0], e = min(clr[1], cap), nblk = gridDim.x - nb_nodes;
+        for (unsigned q = b + (blockIdx.x - nb_nodes) * blockDim.x + threadIdx.x; q < e; q += nblk * blockDim.x) {
+            const AdjRec rec = pool[q];
+            const long long e0 = rec.wall ? A.e_wall + 2 * (long long)rec.f : A.e_coll + 4 * (long long)rec.f;
+            const int ne = rec.wall ? 2 : 4;
+            for (int k = 0; k < ne; ++k) A.ub_out[2 * (e0 + k)] = A.ub_out[2 * (e0 + k) + 1] = 0.f;
+        }
+        return;
+    }
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= A.N) return;
+    A.zb_out[2 * t] = A.zb_out[2 * t + 1] = 0.f;
+    A.S_next[2 * t] = A.S_next[2 * t + 1] = 0.f;
     const int i = (int)(t / (A.eta + 1)), s = (int)(t % (A.eta + 1));
     const bool keep_node = A.lnext[t] == W_STD;
     float sx = A.S_in[2 * t], sy = A.S_in[2 * t + 1];
@@ -435,20 +454,27 @@ struct Buffers {
     unsigned *ck_first, *ck_end;  // [ncp]
     float *u_tmp;                 // [E][2] dense u of a state being packed or unpacked
     // two cotangent sets, alternately a reverse step's input and its output
-    // (the output is cleared in one memset): dL/du [E][2], dL/dz [N][2], and
-    // the per-node sum S [N][2] that the step after it reads
+    // (the output is cleared where the step before last wrote it, or whole
+    // at a segment's first two steps): dL/du [E][2], dL/dz [N][2], and the
+    // per-node sum S [N][2] that the step after it reads
     char *set[2];
     size_t set_bytes;
     float *g;                     // [N][2]
     unsigned char *cls;           // [N]
     double *drd;                  // [p]
-    unsigned *arena_cursor, *pool_cursor;
-    unsigned *offs;               // [len_max + 1] pool cursor before each iteration of a segment
-    unsigned char *rout;          // [len_max][F] ->rho of each iteration of a segment
-    unsigned char *lseg;          // [len_max + 1][N] <-rho before each iteration, and after the last
-    int *cntseg;                  // [len_max][N] size of each node's mean set in each iteration
-    AdjRec *arena, *pool;
-    unsigned arena_cap, pool_cap;
+    unsigned *arena_cursor;
+    // What a segment's recompute captures, twice: segment c uses copy c & 1,
+    // so that one segment is recomputed while the one after it is reversed.
+    unsigned *pool_cursor[2];
+    unsigned *offs[2];            // [len_max + 1] pool cursor before each iteration of a segment
+    unsigned char *rout[2];       // [len_max][F] ->rho of each iteration of a segment
+    unsigned char *lseg[2];       // [len_max + 1][N] <-rho before each iteration, and after the last
+    int *cntseg[2];               // [len_max][N] size of each node's mean set in each iteration
+    AdjRec *arena, *pool[2];
+    unsigned arena_cap, pool_cap; // pool_cap: records of each of the two pools
+    // pools_follow: the arena and the pools share one store of arena_cap
+    // records; the pools take what the checkpoints leave (set after pass 1)
+    bool pools_follow;
 };
 
 // Carve one cotangent set (see Buffers) from base; returns its size.
@@ -483,14 +509,17 @@ bool layout(Region &R, const Shape &h, Buffers &B) {
     B.cls = R.take<unsigned char>((size_t)h.N);
     B.drd = R.take<double>((size_t)h.p);
     B.arena_cursor = R.take<unsigned>(1);
-    B.pool_cursor = R.take<unsigned>(1);
-    B.offs = R.take<unsigned>((size_t)h.len_max + 1);
-    B.rout = R.take<unsigned char>((size_t)h.len_max * h.F);
-    B.lseg = R.take<unsigned char>((size_t)(h.len_max + 1) * h.N);
-    B.cntseg = R.take<int>((size_t)h.len_max * h.N);
-    return B.cur.z && B.cur.l && B.cur.u_small && B.cur.first && B.cur.end && B.ck_z && B.ck_us && B.ck_l &&
-           B.ck_first && B.ck_end && B.u_tmp && B.set[0] && B.set[1] && B.g && B.cls && B.drd && B.arena_cursor &&
-           B.pool_cursor && B.offs && B.rout && B.lseg && B.cntseg;
+    bool ok = true;
+    for (int b = 0; b < 2; ++b) {
+        B.pool_cursor[b] = R.take<unsigned>(1);
+        B.offs[b] = R.take<unsigned>((size_t)h.len_max + 1);
+        B.rout[b] = R.take<unsigned char>((size_t)h.len_max * h.F);
+        B.lseg[b] = R.take<unsigned char>((size_t)(h.len_max + 1) * h.N);
+        B.cntseg[b] = R.take<int>((size_t)h.len_max * h.N);
+        ok = ok && B.pool_cursor[b] && B.offs[b] && B.rout[b] && B.lseg[b] && B.cntseg[b];
+    }
+    return ok && B.cur.z && B.cur.l && B.cur.u_small && B.cur.first && B.cur.end && B.ck_z && B.ck_us && B.ck_l &&
+           B.ck_first && B.ck_end && B.u_tmp && B.set[0] && B.set[1] && B.g && B.cls && B.drd && B.arena_cursor;
 }
 
 Sparse ckpt(const Buffers &B, const Shape &h, long long c) {
@@ -550,6 +579,13 @@ twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_d
     hipStream_t st = s->stream;
     *outcome = kDone;
     *need = 0;
+    if (!s->adj_stream || !s->adj_used)
+        return twa_rt::fail(s, TWA_E_STATE, "twa_backward: the solver has no reverse stream");
+    // whatever way this returns, the reverse stream's work on B is over
+    struct Join {
+        hipStream_t rs;
+        ~Join() { (void)hipStreamSynchronize(rs); }
+    } join{s->adj_stream};
     HIP_TRY(s, hipMemsetAsync(B.arena_cursor, 0, sizeof(unsigned), st));
     const long long cur_iter = s->iter, it0 = s->origin_iter;
     TRY(pack(s, h, B, B.cur));
@@ -575,6 +611,14 @@ twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_d
         *need = used;
         return unpack(s, h, B, B.cur, cur_iter);
     }
+    if (B.pools_follow) {
+        // nothing is appended to the arena after pass 1
+        const unsigned start = (used + 63u) & ~63u;
+        B.pool_cap = start < B.arena_cap ? (B.arena_cap - start) / 2 : 0u;
+        B.pool[0] = B.arena + start;
+        B.pool[1] = B.pool[0] + B.pool_cap;
+        B.arena_cap = used;
+    }
 
     Adj A{};
     A.p = s->p, A.eta = s->eta, A.W = s->W;
@@ -595,66 +639,97 @@ twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_d
     HIP_TRY(s, hipMemsetAsync(B.drd, 0, sizeof(double) * s->p, st));
     const unsigned nb_nodes = (unsigned)((h.N + 255) / 256), nb_small = (unsigned)((P.f_coll + 255) / 256);
     const unsigned nb_rec = 256; // blocks striding over the captured records
+    const unsigned nb_clr = 64;  // blocks clearing a step's output sparsely
 
-    // pass 2: segments in reverse; recompute each capturing its decisions,
-    // then run it backwards
-    for (long long c = h.ncp - 1; c >= 0; --c) {
+    // pass 2: segments in reverse, software-pipelined over two streams: a
+    // segment is recomputed on the solver's stream, capturing its decisions
+    // into capture copy c & 1, while the segment after it runs backwards on
+    // the reverse stream.  Events: adj_ev[b] recomputed into copy b,
+    // adj_ev[2 + b] copy b reversed (free for the next recompute).
+    hipStream_t rs = s->adj_stream;
+    HIP_TRY(s, hipEventRecord(s->adj_ev[2], st));
+    HIP_TRY(s, hipStreamWaitEvent(rs, s->adj_ev[2], 0)); // the cotangent sets are set up
+    auto recompute = [&](long long c) -> twa_status {
         const long long k0 = it0 + c * h.L, len = std::min(h.L, h.K - c * h.L);
-    recompute:
+        const int b = (int)(c & 1);
+        // the reverse of segment c + 2 read this copy
+        if (c + 2 < h.ncp) HIP_TRY(s, hipStreamWaitEvent(st, s->adj_ev[2 + b], 0));
         TRY(unpack(s, h, B, ckpt(B, h, c), k0));
-        HIP_TRY(s, hipMemsetAsync(B.pool_cursor, 0, sizeof(unsigned), st));
-        HIP_TRY(s, hipMemsetAsync(B.offs, 0, sizeof(unsigned), st));
-        TRY(twa_rt::export_lrho(s, B.lseg));
+        HIP_TRY(s, hipMemsetAsync(B.pool_cursor[b], 0, sizeof(unsigned), st));
+        HIP_TRY(s, hipMemsetAsync(B.offs[b], 0, sizeof(unsigned), st));
+        TRY(twa_rt::export_lrho(s, B.lseg[b]));
         for (long long t = 0; t < len; ++t) {
             // the iteration's weights, its captured factors, and (from its
             // node pass) the new <-rho codes, the mean-set sizes and the
             // capture cursor
-            s->dbg_rho = B.rout + t * h.F;
-            s->adj_pool = B.pool;
-            s->adj_cursor = B.pool_cursor;
+            s->dbg_rho = B.rout[b] + t * h.F;
+            s->adj_pool = B.pool[b];
+            s->adj_cursor = B.pool_cursor[b];
             s->adj_cap = B.pool_cap;
-            s->adj_offs = B.offs + t + 1;
-            s->dbg_l = B.lseg + (t + 1) * h.N;
-            s->dbg_cnt = B.cntseg + t * h.N;
+            s->adj_offs = B.offs[b] + t + 1;
+            s->dbg_l = B.lseg[b] + (t + 1) * h.N;
+            s->dbg_cnt = B.cntseg[b] + t * h.N;
             TRY(twa_iterate(s, 1));
         }
-        HIP_TRY(s, hipMemcpyAsync(&used, B.pool_cursor, sizeof(unsigned), hipMemcpyDeviceToHost, st));
-        HIP_TRY(s, hipStreamSynchronize(st));
-        if (used > B.pool_cap) {
-            if (grow_pool) {
-                TRY(grow_pool(s, B, used));
-                goto recompute;
+        HIP_TRY(s, hipMemcpyAsync(s->adj_used + b, B.pool_cursor[b], sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        HIP_TRY(s, hipEventRecord(s->adj_ev[b], st));
+        return TWA_OK;
+    };
+    if (h.ncp > 0) TRY(recompute(h.ncp - 1));
+    for (long long c = h.ncp - 1; c >= 0; --c) {
+        const long long k0 = it0 + c * h.L, len = std::min(h.L, h.K - c * h.L);
+        const int b = (int)(c & 1);
+        // segment c is recomputed (and nothing after it is queued on st)
+        HIP_TRY(s, hipEventSynchronize(s->adj_ev[b]));
+        while (s->adj_used[b] > B.pool_cap) {
+            if (!grow_pool) {
+                *outcome = kPoolFull;
+                *need = s->adj_used[b];
+                return unpack(s, h, B, B.cur, cur_iter);
             }
-            *outcome = kPoolFull;
-            *need = used;
-            return unpack(s, h, B, B.cur, cur_iter);
+            // (the segment being reversed reads the other pool)
+            HIP_TRY(s, hipStreamSynchronize(rs));
+            TRY(grow_pool(s, B, s->adj_used[b]));
+            TRY(recompute(c));
+            HIP_TRY(s, hipEventSynchronize(s->adj_ev[b]));
         }
+        // the segment before it goes on the solver's stream first, so that
+        // the two run together
+        if (c > 0) TRY(recompute(c - 1));
+        HIP_TRY(s, hipStreamWaitEvent(rs, s->adj_ev[b], 0));
         for (long long t = len - 1; t >= 0; --t) {
             float *ub_in, *zb_in, *S_in, *ub_out, *zb_out, *S_out;
             set_layout(h, B.set[in], &ub_in, &zb_in, &S_in);
             set_layout(h, B.set[1 - in], &ub_out, &zb_out, &S_out);
             A.ub_in = ub_in, A.zb_in = zb_in, A.S_in = S_in;
             A.ub_out = ub_out, A.zb_out = zb_out, A.S_next = S_out;
-            A.l = B.lseg + t * h.N;
-            A.lnext = B.lseg + (t + 1) * h.N;
-            A.cnt = B.cntseg + t * h.N;
-            A.rout = B.rout + t * h.F;
-            A.rout_prev = t > 0 ? B.rout + (t - 1) * h.F : nullptr;
+            A.l = B.lseg[b] + t * h.N;
+            A.lnext = B.lseg[b] + (t + 1) * h.N;
+            A.cnt = B.cntseg[b] + t * h.N;
+            A.rout = B.rout[b] + t * h.F;
+            A.rout_prev = t > 0 ? B.rout[b] + (t - 1) * h.F : nullptr;
             A.rho = twa_rt::rho_at(s, k0 + t);
             A.step = s->alpha / s->rho0; // the u step ignores the warm-up's rho0
-            const unsigned *offs = B.offs + t;
+            const unsigned *offs = B.offs[b] + t;
             // the step after this one belongs to the segment reversed before
             // (or is the loss): it could not accumulate this step's S
             if (t == len - 1)
-                hipLaunchKernelGGL(k_adj_accum, dim3(nb_rec), dim3(256), 0, st, A, S_in, (const AdjRec *)B.pool, offs,
-                                   B.pool_cap);
-            HIP_TRY(s, hipMemsetAsync(B.set[1 - in], 0, B.set_bytes, st));
-            hipLaunchKernelGGL(k_adj_select, dim3(nb_nodes), dim3(256), 0, st, A);
-            hipLaunchKernelGGL(k_adj_factors, dim3(nb_small + nb_rec), dim3(256), 0, st, A, nb_small,
-                               (const AdjRec *)B.pool, offs, B.pool_cap);
+                hipLaunchKernelGGL(k_adj_accum, dim3(nb_rec), dim3(256), 0, rs, A, S_in, (const AdjRec *)B.pool[b],
+                                   offs, B.pool_cap);
+            // The output set holds what step t + 2 wrote.  Its records are in
+            // this segment's pool if it belongs to the segment; otherwise
+            // (it was reversed before, its pool is being refilled) the whole
+            // set is cleared.
+            const bool sparse = t + 2 < len;
+            if (!sparse) HIP_TRY(s, hipMemsetAsync(B.set[1 - in], 0, B.set_bytes, rs));
+            hipLaunchKernelGGL(k_adj_select, dim3(nb_nodes + (sparse ? nb_clr : 0u)), dim3(256), 0, rs, A, nb_nodes,
+                               (const AdjRec *)B.pool[b], sparse ? B.offs[b] + t + 2 : nullptr, B.pool_cap);
+            hipLaunchKernelGGL(k_adj_factors, dim3(nb_small + nb_rec), dim3(256), 0, rs, A, nb_small,
+                               (const AdjRec *)B.pool[b], offs, B.pool_cap);
             HIP_TRY(s, hipGetLastError());
             in = 1 - in;
         }
+        HIP_TRY(s, hipEventRecord(s->adj_ev[2 + b], rs));
     }
     {
         float *ub, *zb, *S;
@@ -662,9 +737,10 @@ twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_d
         A.zb_in = zb;
     }
     const long long nfin = std::max<long long>(h.N, s->p);
-    hipLaunchKernelGGL(k_adj_finish, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, st, A, dL_dz0, dL_dr);
+    hipLaunchKernelGGL(k_adj_finish, dim3((unsigned)((nfin + 255) / 256)), dim3(256), 0, rs, A, dL_dz0, dL_dr);
     HIP_TRY(s, hipGetLastError());
     TRY(unpack(s, h, B, B.cur, cur_iter));
+    HIP_TRY(s, hipStreamSynchronize(rs));
     HIP_TRY(s, hipStreamSynchronize(st));
     return TWA_OK;
 }
@@ -683,12 +759,18 @@ twa_status check_args(twa_solver *s, const float *dL_dz, float *dL_dx0, float *d
 
 twa_status ensure(twa_solver *s, void **buf, size_t *have, size_t want);
 
+// the two capture pools, halves of one buffer
+void set_pools(Buffers &B, void *mem, size_t bytes) {
+    B.pool_cap = (unsigned)std::min<size_t>(bytes / 2 / sizeof(AdjRec), 0xffffffffu);
+    B.pool[0] = static_cast<AdjRec *>(mem);
+    B.pool[1] = B.pool[0] + B.pool_cap;
+}
+
 // the allocating path's pool growth (a quarter to spare)
 twa_status grow_solver_pool(twa_solver *s, Buffers &B, unsigned need) {
     const size_t want = std::min<size_t>((size_t)need * 5 / 4 + 1024, 0xffffffffu) * sizeof(AdjRec);
-    TRY(ensure(s, &s->adj_pool_mem, &s->adj_pool_bytes, want));
-    B.pool = static_cast<AdjRec *>(s->adj_pool_mem);
-    B.pool_cap = (unsigned)std::min<size_t>(s->adj_pool_bytes / sizeof(AdjRec), 0xffffffffu);
+    TRY(ensure(s, &s->adj_pool_mem, &s->adj_pool_bytes, 2 * want));
+    set_pools(B, s->adj_pool_mem, s->adj_pool_bytes);
     return TWA_OK;
 }
 
@@ -713,9 +795,27 @@ twa_status ensure(twa_solver *s, void **buf, size_t *have, size_t want) {
 
 namespace twa_rt {
 
-// the static scratch's address on the solver's device (set up at create)
-twa_status scratch_setup(twa_solver *s) {
+// the static scratch's address on the solver's device, the reverse stream
+// and its events (set up at create)
+twa_status tape_setup(twa_solver *s) {
     if (s->device < 0 || s->device >= kMaxDevices) return fail(s, TWA_E_DEVICE, "device index out of range");
+    if (hipStreamCreate(&s->adj_stream) != hipSuccess) {
+        (void)hipGetLastError();
+        s->adj_stream = nullptr;
+        return fail(s, TWA_E_DEVICE, "hipStreamCreate failed");
+    }
+    for (hipEvent_t &ev : s->adj_ev)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            ev = nullptr;
+            return fail(s, TWA_E_DEVICE, "hipEventCreate failed");
+        }
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->adj_used), 2 * sizeof(unsigned), hipHostMallocDefault) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        s->adj_used = nullptr;
+        return fail(s, TWA_E_DEVICE, "hipHostMalloc failed");
+    }
     std::lock_guard<std::mutex> lock(g_scratch_mu);
     if (g_scratch_ptr[s->device]) return TWA_OK;
     void *p = nullptr;
@@ -748,15 +848,14 @@ extern "C" twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const size_t per = 2 * (size_t)std::max(queued, 0) + 1024;
     size_t want_arena = std::max<size_t>(s->adj_arena_bytes, (size_t)(h.ncp + 1) * per * sizeof(AdjRec));
-    size_t want_pool = std::max<size_t>(s->adj_pool_bytes, (size_t)h.len_max * per * sizeof(AdjRec));
+    size_t want_pool = std::max<size_t>(s->adj_pool_bytes, 2 * (size_t)h.len_max * per * sizeof(AdjRec));
     for (int attempt = 0; attempt < 3; ++attempt) {
         const size_t cap_recs = (size_t)0xffffffffu * sizeof(AdjRec);
         TRY(ensure(s, &s->adj_arena, &s->adj_arena_bytes, std::min(want_arena, cap_recs)));
         TRY(ensure(s, &s->adj_pool_mem, &s->adj_pool_bytes, std::min(want_pool, cap_recs)));
         B.arena = static_cast<AdjRec *>(s->adj_arena);
         B.arena_cap = (unsigned)(s->adj_arena_bytes / sizeof(AdjRec));
-        B.pool = static_cast<AdjRec *>(s->adj_pool_mem);
-        B.pool_cap = (unsigned)(s->adj_pool_bytes / sizeof(AdjRec));
+        set_pools(B, s->adj_pool_mem, s->adj_pool_bytes);
         int outcome = kDone;
         unsigned need = 0;
         TRY(run_once(s, h, B, dL_dz, dL_dx0, dL_dxT, dL_dr, dL_dz0, &outcome, &need, grow_solver_pool));
@@ -789,15 +888,14 @@ extern "C" twa_status twa_backward_noalloc(twa_solver *s, const float *dL_dz, fl
                                         std::to_string(kScratchBytes >> 20) + " MiB scratch (" +
                                         std::to_string(sz.used >> 20) + " MiB before its records)");
     }
-    // the rest of the scratch holds the records: half checkpoints, half capture
-    // (less two alignment pads)
-    const size_t left = R.cap - std::min(R.cap, ((R.used + 255) & ~(size_t)255) + 512);
-    const size_t rest = left / 2 / sizeof(AdjRec);
-    B.arena_cap = (unsigned)std::min<size_t>(rest, 0xffffffffu);
-    B.pool_cap = B.arena_cap;
+    // the rest of the scratch holds the records: the checkpoints' first, the
+    // two capture pools share what they leave (less an alignment pad)
+    const size_t left = R.cap - std::min(R.cap, ((R.used + 255) & ~(size_t)255) + 256);
+    B.arena_cap = (unsigned)std::min<size_t>(left / sizeof(AdjRec), 0xffffffffu);
     B.arena = R.take<AdjRec>(B.arena_cap);
-    B.pool = R.take<AdjRec>(B.pool_cap);
-    if (!B.arena || !B.pool || B.arena_cap < 64)
+    B.pools_follow = true;
+    const unsigned total = B.arena_cap;
+    if (!B.arena || B.arena_cap < 256)
         return fail(s, TWA_E_NOMEM, "twa_backward_noalloc: no scratch left for the records");
     const bool was = s->no_capture;
     s->no_capture = true; // replay graphs already captured, capture none (that would allocate)
@@ -806,9 +904,12 @@ extern "C" twa_status twa_backward_noalloc(twa_solver *s, const float *dL_dz, fl
     const twa_status st = run_once(s, h, B, dL_dz, dL_dx0, dL_dxT, dL_dr, dL_dz0, &outcome, &need, nullptr);
     s->no_capture = was;
     if (st != TWA_OK) return st;
+    if (outcome == kArenaFull)
+        return fail(s, TWA_E_NOMEM, "twa_backward_noalloc: the scratch holds " + std::to_string(total) +
+                                        " records, the checkpoints need " + std::to_string(need));
     if (outcome != kDone)
-        return fail(s, TWA_E_NOMEM, std::string("twa_backward_noalloc: the scratch holds ") +
-                                        std::to_string(B.arena_cap) + " records per store, the run needs " +
+        return fail(s, TWA_E_NOMEM, "twa_backward_noalloc: the checkpoints leave " + std::to_string(B.pool_cap) +
+                                        " records of scratch to each capture pool, a segment needs " +
                                         std::to_string(need));
     return TWA_OK;
 }

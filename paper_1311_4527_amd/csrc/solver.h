@@ -164,6 +164,12 @@ struct twa_solver {
     // later call needs more, kept until twa_destroy
     void *adj_ws = nullptr, *adj_arena = nullptr, *adj_pool_mem = nullptr;
     size_t adj_ws_bytes = 0, adj_arena_bytes = 0, adj_pool_bytes = 0;
+    // twa_backward's second stream (a segment's reverse steps run on it while
+    // the segment before it is recomputed on `stream`) and the events that
+    // order the two: recomputed into, and reversed from, each capture copy
+    hipStream_t adj_stream = nullptr;
+    hipEvent_t adj_ev[4] = {};
+    unsigned *adj_used = nullptr; // pinned host [2]: records each recompute wanted
 };
 
 namespace twa_rt {
@@ -180,8 +186,9 @@ twa_status import_state(twa_solver *s, const float *z, const float *u, const uns
 // <-rho codes of the current node records, canonical [p][eta+1] (device
 // array); leaves a pending u update pending
 twa_status export_lrho(twa_solver *s, unsigned char *lrho);
-// look up the static scratch of twa_backward_noalloc on the solver's device
-twa_status scratch_setup(twa_solver *s);
+// TWA_F_TAPE at create: look up the static scratch of twa_backward_noalloc
+// on the solver's device, make twa_backward's second stream and its events
+twa_status tape_setup(twa_solver *s);
 
 } // namespace twa_rt
 

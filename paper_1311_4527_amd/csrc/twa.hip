@@ -1995,6 +1995,13 @@ void twa_destroy(twa_solver *s) {
     s->mem.put(s->adj_ws, s->adj_ws_bytes, s->stream);
     s->mem.put(s->adj_arena, s->adj_arena_bytes, s->stream);
     s->mem.put(s->adj_pool_mem, s->adj_pool_bytes, s->stream);
+    if (s->adj_stream) {
+        (void)hipStreamSynchronize(s->adj_stream);
+        (void)hipStreamDestroy(s->adj_stream);
+    }
+    for (hipEvent_t e : s->adj_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->adj_used) (void)hipHostFree(s->adj_used);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s;
 }
@@ -2250,7 +2257,7 @@ twa_status twa_create(int p, int eta, int dim, const float *radii, const float *
         const twa_status st = prepare_tiny(s);
         if (st != TWA_OK) return bail(st);
     }
-    if ((flags & TWA_F_TAPE) && twa_rt::scratch_setup(s) != TWA_OK) return bail(TWA_E_DEVICE);
+    if ((flags & TWA_F_TAPE) && twa_rt::tape_setup(s) != TWA_OK) return bail(TWA_E_DEVICE);
     if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(TWA_E_DEVICE);
     *out = s;
     return TWA_OK;
