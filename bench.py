@@ -29,8 +29,8 @@ KERNELS = ("k_stream", "k_queue", "k_nodes")
 # by the same counters over a 512 MiB device copy (read x2.000, write
 # x1.000).  Valid only for the kernel sources they were taken on.
 MEASURED_TRAFFIC = {
-    "dense": dict(fetch_kib=143242.3, write_kib=272373.3, sources="ce1758257f437cd6"),
-    "skip": dict(fetch_kib=4348.9, write_kib=2340.0, sources="ce1758257f437cd6"),
+    "dense": dict(fetch_kib=142748.4, write_kib=1224.0, sources="5b0348ad9f8d8699"),
+    "skip": dict(fetch_kib=4343.6, write_kib=2366.2, sources="5b0348ad9f8d8699"),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 KERNEL_SOURCES = ("paper_1311_4527_amd/csrc/twa.hip", "paper_1311_4527_amd/csrc/prox.h",
@@ -513,7 +513,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (for hardware-counter scaling)")
-    ap.add_argument("--leg", choices=["batched", "adjoint"], default=None,
+    ap.add_argument("--leg", choices=["batched", "adjoint", "vo"], default=None,
                     help="only run one side leg, without its comparison runs (for profiling)")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -537,6 +537,9 @@ def main():
         return
     if args.leg == "adjoint":
         print(json.dumps(run_adjoint(500)), flush=True)
+        return
+    if args.leg == "vo":
+        print(json.dumps(run_vo()), flush=True)
         return
     inst = workload(args.workload)
     c = inst.counts()
