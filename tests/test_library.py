@@ -68,6 +68,21 @@ def test_create_rejects_bad_scalars(lib):
         assert st == 1
 
 
+@pytest.mark.parametrize("p,eta,nw", [(65537, 1, 0), (50000, 2, 0), (8, 1 << 16, 0), (4096, 16, 1 << 15),
+                                       (4, 4, 1 << 24)])
+def test_create_rejects_problems_past_the_index_range(lib, p, eta, nw):
+    """Factor indices are 31-bit in the queues (collision or wall factors per
+    kind < 2^31), break-point intervals < 2^16, walls < 2^24: larger problems
+    are refused before any device work."""
+    lib.twa_create.restype = ct.c_int
+    lib.twa_last_error.restype = ct.c_char_p
+    out = ct.c_void_p()
+    dummy = ct.c_void_p(16)
+    st = lib.twa_create(p, eta, 2, dummy, dummy, dummy, nw, dummy if nw else None, dummy, ct.c_float(1.0),
+                        ct.c_float(0.1), 0, None, ct.byref(out))
+    assert st == 1 and not out.value
+
+
 def test_null_solver_calls(lib):
     lib.twa_iterate.restype = ct.c_int
     lib.twa_last_error.restype = ct.c_char_p
