@@ -18,7 +18,9 @@ CASES = {
     "swap8_2d": lambda: I.conf_small(0),                                # 112 collision factors
     "swap6_3d": lambda: I.circle_swap(6, 0.05, 4, dim=3, seed=3),       # 60
     "box8_walls": lambda: I.conf_box1024(seed=5, p=8, eta=4, n_walls=4),  # 112 + 128 wall factors
-    # 250 collision factors over 251 break-points: too large for the LDS copy
+    # 190 collision factors over 191 break-points: 54 KiB of state in LDS, near
+    # the bound; 250 over 251: too large for the LDS copy
+    "pair_eta190": lambda: I.circle_swap(2, 0.05, 190, seed=4),
     "pair_eta250": lambda: I.circle_swap(2, 0.05, 250, seed=4),
 }
 
