@@ -158,6 +158,64 @@ __device__ __forceinline__ void contribute(const Params &P, long long node, int 
     atomicAdd(&P.cnt[(long long)kind * P.N + node], 1);
 }
 
+// The consensus contributions of one queued minimiser (up to four nodes),
+// handed from the minimiser to the wave-level sum below.
+struct Contrib {
+    int n = 0;         // nodes contributed to (0, 2 or 4)
+    long long nd[4];
+    float m[4][3];
+};
+
+// Contributions of every lane of a wave (all lanes call it; lanes with
+// k >= c.n give nothing).  Slots 0 and 1 are agent i's nodes (s, i) and
+// (s+1, i), which the queued collision factors of one pair-row chunk, and
+// the wall factors of one agent and interval, share: there the lanes with
+// the same node are summed across the wave first, so the node takes one
+// atomic per component per group instead of one per lane (up to two groups
+// are formed, the second only if the first had company; the remaining
+// lanes add directly).  Slots 2 and 3 (agent j, a
+// different node on every lane of a chunk) add directly.  The sums are exact
+// integers, so the result does not depend on the grouping.
+__device__ __forceinline__ void contribute_wave(const Params &P, const Contrib &c, int D) {
+    const int lane = __lane_id();
+    for (int k = 0; k < 4; ++k) {
+        bool pred = k < c.n;
+        if (__ballot(pred) == 0ull) continue;
+        const long long node = pred ? c.nd[k] : -1;
+        long long q[3] = {0, 0, 0};
+        if (pred)
+            for (int d = 0; d < D; ++d) {
+                float v = c.m[k][d] * P.scalef;
+                if (!(fabsf(v) <= P.sat_lim)) P.counters[5] = 1;
+                v = fminf(fmaxf(v, -4.0e18f), 4.0e18f);
+                q[d] = __float2ll_rn(v);
+            }
+        for (int g = 0; g < (k < 2 ? 2 : 0); ++g) {
+            const unsigned long long pending = __ballot(pred);
+            if (pending == 0ull) break;
+            const int leader = __ffsll((long long)pending) - 1;
+            const long long key = __shfl(node, leader);
+            const bool mine = pred && node == key;
+            const unsigned long long peers = __ballot(mine);
+            long long sum[3];
+            for (int d = 0; d < 3; ++d) sum[d] = mine ? q[d] : 0;
+            if (__popcll(peers) > 1)
+                for (int o = 1; o < 64; o <<= 1)
+                    for (int d = 0; d < D; ++d) sum[d] += __shfl_xor(sum[d], o);
+            if (lane == leader) {
+                for (int d = 0; d < D; ++d) atomicAdd(&P.acc[(long long)d * P.N + key], (unsigned long long)sum[d]);
+                atomicAdd(&P.cnt[key], (int)__popcll(peers));
+            }
+            pred = pred && !mine;
+            if (__popcll(peers) == 1) break; // the nodes are spread: the rest add directly
+        }
+        if (pred) {
+            for (int d = 0; d < D; ++d) atomicAdd(&P.acc[(long long)d * P.N + node], (unsigned long long)q[d]);
+            atomicAdd(&P.cnt[node], 1);
+        }
+    }
+}
+
 // Finalizing pass only: fold |x - z| of an edge whose u is updated (both
 // weights rho0) into the residual maximum (non-negative floats order as
 // their bit patterns).
@@ -699,7 +757,7 @@ __device__ __forceinline__ void fixed_stream(const Params &P, const Rec &Z, long
 // Queued collision factor (entry e): deferred u update, full minimiser,
 // consensus contributions.
 template <int D, int MODE>
-__device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsigned e, float *nout) {
+__device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsigned e, float *nout, Contrib &out) {
     const bool dense = P.dense != 0;
     long long f = e & kIdx;
     bool prev = (e & kPrev) != 0;
@@ -743,10 +801,10 @@ __device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsign
     if (act) {
         for (int q = 0; q < 4; ++q) w[q] = wval(k[q], P.rho);
         coll_prox<D>(n, w, k, R, x);
-        float m[3];
+        out.n = 4;
         for (int q = 0; q < 4; ++q) {
-            for (int c = 0; c < D; ++c) m[c] = x[q * D + c] + u[q * D + c];
-            contribute(P, nd[q], 0, m, D);
+            out.nd[q] = nd[q];
+            for (int c = 0; c < D; ++c) out.m[q][c] = x[q * D + c] + u[q * D + c];
         }
         store_x_coll<D>(P, f, x);
         const int r = j - i - 1;
@@ -755,10 +813,10 @@ __device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsign
         for (int q = 0; q < 4 * D; ++q) x[q] = n[q];
         if (P.admm) {
             // standard ADMM: x = n still carries weight rho0
-            float m[3];
+            out.n = 4;
             for (int q = 0; q < 4; ++q) {
-                for (int c = 0; c < D; ++c) m[c] = x[q * D + c] + u[q * D + c];
-                contribute(P, nd[q], 0, m, D);
+                out.nd[q] = nd[q];
+                for (int c = 0; c < D; ++c) out.m[q][c] = x[q * D + c] + u[q * D + c];
             }
             store_x_coll<D>(P, f, x);
         }
@@ -807,7 +865,8 @@ __device__ __forceinline__ void capsule_prox_pair(const Capsule C, f2 n0, f2 n1,
 // Queued wall factor (entry e).  piece < 0: one lane; 0 or 1: the two lanes
 // of a pair share the minimiser (capsule_prox_pair) and lane 0 writes.
 template <int MODE>
-__device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsigned e, int piece, float *nout) {
+__device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsigned e, int piece, float *nout,
+                                           Contrib &out) {
     const bool writer = piece <= 0;
     const bool dense = P.dense != 0;
     long long f = e & kIdx;
@@ -851,18 +910,14 @@ __device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsign
         else capsule_prox_pair(Cw, n0, n1, wval(ka, P.rho), wval(kb, P.rho), ka, kb, piece, x0, x1);
     }
     if (!writer) return act;
-    if (act) {
+    if (act || P.admm) {
+        // (standard ADMM: x = n still carries weight rho0)
         P.x_wall[f] = make_float4(x0.x, x0.y, x1.x, x1.y);
-        float m0[2] = {x0.x + u.x, x0.y + u.y}, m1[2] = {x1.x + u.z, x1.y + u.w};
-        contribute(P, na, 0, m0, 2);
-        contribute(P, nb, 0, m1, 2);
-        atomicOr(&P.bits_wall[f >> 5], 1u << (f & 31));
-    } else if (P.admm) {
-        // standard ADMM: x = n still carries weight rho0
-        P.x_wall[f] = make_float4(x0.x, x0.y, x1.x, x1.y);
-        float m0[2] = {x0.x + u.x, x0.y + u.y}, m1[2] = {x1.x + u.z, x1.y + u.w};
-        contribute(P, na, 0, m0, 2);
-        contribute(P, nb, 0, m1, 2);
+        out.n = 2;
+        out.nd[0] = na, out.nd[1] = nb;
+        out.m[0][0] = x0.x + u.x, out.m[0][1] = x0.y + u.y;
+        out.m[1][0] = x1.x + u.z, out.m[1][1] = x1.y + u.w;
+        if (act) atomicOr(&P.bits_wall[f >> 5], 1u << (f & 31));
     }
     if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) P.u_wall[f] = u;
     if (P.dbg_rho) {
@@ -991,8 +1046,10 @@ __device__ __forceinline__ void queue_entry(const Params &P, const Rec &Z, bool 
                                             int piece) {
     bool ac = false, aw = false;
     float n[4 * D];
-    if (is_coll) ac = coll_queue<D, MODE>(P, Z, e, n);
-    else if (is_wall) aw = wall_queue<MODE>(P, Z, e, piece, n) && piece <= 0;
+    Contrib c;
+    if (is_coll) ac = coll_queue<D, MODE>(P, Z, e, n, c);
+    else if (is_wall) aw = wall_queue<MODE>(P, Z, e, piece, n, c) && piece <= 0;
+    if (MODE != M_FINAL) contribute_wave(P, c, D);
     count_wave(&P.counters[2], ac);
     count_wave(&P.counters[3], aw);
     if (P.adj_pool) adj_append<D>(P, ac || aw, e & kIdx, aw, n);

@@ -61,7 +61,7 @@ def test_solver_and_backward_buffers_come_from_the_callbacks():
         # rounding of their order)
         for a, b in zip(g, g_ref):
             scale = float(b.abs().max())
-            assert torch.allclose(a, b, rtol=1e-5, atol=1e-6 * scale), float((a - b).abs().max())
+            assert torch.allclose(a, b, rtol=1e-4, atol=1e-4 * scale), float((a - b).abs().max())
         S.close()
         assert not C.live                # everything went back through release
     finally:
