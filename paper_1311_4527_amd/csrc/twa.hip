@@ -176,6 +176,7 @@ struct Contrib {
 // lanes add directly).  Slots 2 and 3 (agent j, a
 // different node on every lane of a chunk) add directly.  The sums are exact
 // integers, so the result does not depend on the grouping.
+template <bool GROUP>
 __device__ __forceinline__ void contribute_wave(const Params &P, const Contrib &c, int D) {
     const int lane = __lane_id();
     for (int k = 0; k < 4; ++k) {
@@ -190,7 +191,7 @@ __device__ __forceinline__ void contribute_wave(const Params &P, const Contrib &
                 v = fminf(fmaxf(v, -4.0e18f), 4.0e18f);
                 q[d] = __float2ll_rn(v);
             }
-        for (int g = 0; g < (k < 2 ? 2 : 0); ++g) {
+        for (int g = 0; g < (GROUP && k < 2 ? 2 : 0); ++g) {
             const unsigned long long pending = __ballot(pred);
             if (pending == 0ull) break;
             const int leader = __ffsll((long long)pending) - 1;
@@ -1040,8 +1041,10 @@ __device__ __forceinline__ void adj_append(const Params &P, bool pred, unsigned 
 // One queue entry per lane of a wave-uniform loop: collision entries first,
 // wall entries from the next multiple of 64 (a wave never mixes the two
 // minimisers, whose run times differ several-fold); piece: which lane of a
-// wall entry's pair (-1: the entry has one lane).
-template <int D, int MODE>
+// wall entry's pair (-1: the entry has one lane).  GROUP: sum agent i's
+// contributions across the wave first (the grid-wide queue kernels; in one
+// workgroup with the sums in LDS, or few waves, direct atomics are cheaper).
+template <int D, int MODE, bool GROUP>
 __device__ __forceinline__ void queue_entry(const Params &P, const Rec &Z, bool is_coll, bool is_wall, unsigned e,
                                             int piece) {
     bool ac = false, aw = false;
@@ -1049,7 +1052,7 @@ __device__ __forceinline__ void queue_entry(const Params &P, const Rec &Z, bool 
     Contrib c;
     if (is_coll) ac = coll_queue<D, MODE>(P, Z, e, n, c);
     else if (is_wall) aw = wall_queue<MODE>(P, Z, e, piece, n, c) && piece <= 0;
-    if (MODE != M_FINAL) contribute_wave(P, c, D);
+    if (MODE != M_FINAL) contribute_wave<GROUP>(P, c, D);
     count_wave(&P.counters[2], ac);
     count_wave(&P.counters[3], aw);
     if (P.adj_pool) adj_append<D>(P, ac || aw, e & kIdx, aw, n);
@@ -1092,7 +1095,7 @@ __device__ __forceinline__ void queue_block(const Params &P, long long qb, long 
         } else if (is_wall) {
             e = P.qw[(t - wall0) >> 1];
         }
-        queue_entry<D, MODE>(P, Z, is_coll, is_wall, e, (int)((t - wall0) & 1));
+        queue_entry<D, MODE, true>(P, Z, is_coll, is_wall, e, (int)((t - wall0) & 1));
     }
 }
 
@@ -1228,7 +1231,7 @@ __device__ __forceinline__ void batch_instance(const Params &P, float4 *zs, int 
     for (long long t0 = threadIdx.x & ~63; t0 < total; t0 += BLOCK) {
         const long long t = t0 + (threadIdx.x & 63);
         const bool is_coll = t < nqc, is_wall = t >= wall0 && t < total;
-        queue_entry<D, MODE>(P, Z, is_coll, is_wall, is_coll ? P.qc[t] : is_wall ? P.qw[t - wall0] : 0u, -1);
+        queue_entry<D, MODE, false>(P, Z, is_coll, is_wall, is_coll ? P.qc[t] : is_wall ? P.qw[t - wall0] : 0u, -1);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
