@@ -658,19 +658,20 @@ twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_d
         HIP_TRY(s, hipMemsetAsync(B.pool_cursor[b], 0, sizeof(unsigned), st));
         HIP_TRY(s, hipMemsetAsync(B.offs[b], 0, sizeof(unsigned), st));
         TRY(twa_rt::export_lrho(s, B.lseg[b]));
-        for (long long t = 0; t < len; ++t) {
-            // the iteration's weights, its captured factors, and (from its
-            // node pass) the new <-rho codes, the mean-set sizes and the
-            // capture cursor
-            s->dbg_rho = B.rout[b] + t * h.F;
-            s->adj_pool = B.pool[b];
-            s->adj_cursor = B.pool_cursor[b];
-            s->adj_cap = B.pool_cap;
-            s->adj_offs = B.offs[b] + t + 1;
-            s->dbg_l = B.lseg[b] + (t + 1) * h.N;
-            s->dbg_cnt = B.cntseg[b] + t * h.N;
-            TRY(twa_iterate(s, 1));
-        }
+        // each iteration's weights, its captured factors, and (from its node
+        // pass) the new <-rho codes, the mean-set sizes and the capture
+        // cursor; a full-length segment replays the graph kept for copy b
+        twa_rt::SegCapture cap;
+        cap.rout = B.rout[b];
+        cap.pool = B.pool[b];
+        cap.cursor = B.pool_cursor[b];
+        cap.cap = B.pool_cap;
+        cap.offs = B.offs[b];
+        cap.lseg = B.lseg[b];
+        cap.cntseg = B.cntseg[b];
+        cap.F = h.F;
+        cap.N = h.N;
+        TRY(twa_rt::run_segment(s, len, cap, len == h.L ? b : -1));
         HIP_TRY(s, hipMemcpyAsync(s->adj_used + b, B.pool_cursor[b], sizeof(unsigned), hipMemcpyDeviceToHost, st));
         HIP_TRY(s, hipEventRecord(s->adj_ev[b], st));
         return TWA_OK;

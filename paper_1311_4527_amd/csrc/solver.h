@@ -88,6 +88,22 @@ struct Params {
     long long f_energy, f_coll, f_wall; // canonical factor offsets
 };
 
+// What the iterations of a segment recomputed by twa_backward capture:
+// iteration t writes its ->rho to rout + t*F, appends a record per factor
+// that sent rho0 to pool (cursor, cap), stores the cursor after it to
+// offs[t + 1], and (node pass) the new <-rho codes to lseg + (t+1)*N and the
+// mean-set sizes to cntseg + t*N.
+struct SegCapture {
+    unsigned char *rout;
+    AdjRec *pool;
+    unsigned *cursor;
+    unsigned cap;
+    unsigned *offs;
+    unsigned char *lseg;
+    int *cntseg;
+    long long F, N;
+};
+
 // Device memory provider of one solver or batch: the process-wide pair of
 // twa_set_allocator in effect at its create, else hipMalloc / hipFree.
 struct Allocator {
@@ -169,6 +185,12 @@ struct twa_solver {
     // order the two: recomputed into, and reversed from, each capture copy
     hipStream_t adj_stream = nullptr;
     hipEvent_t adj_ev[4] = {};
+    // graphs of a whole recomputed segment, one per capture copy, with the
+    // segment length and capture buffers they were captured for
+    hipGraphExec_t seg_graph[2] = {};
+    twa_rt::SegCapture seg_key[2] = {};
+    long long seg_len[2] = {0, 0};
+    bool seg_failed = false;
     unsigned *adj_used = nullptr; // pinned host [2]: records each recompute wanted
 };
 
@@ -186,6 +208,12 @@ twa_status import_state(twa_solver *s, const float *z, const float *u, const uns
 // <-rho codes of the current node records, canonical [p][eta+1] (device
 // array); leaves a pending u update pending
 twa_status export_lrho(twa_solver *s, unsigned char *lrho);
+// len iterations from a state just imported (no update pending), each
+// capturing as c describes; replayed from the graph kept for capture copy
+// `slot` (0 or 1; -1: no graph) when every iteration runs at the
+// configuration's rho0 and the graph fits (captured now unless no_capture),
+// else launched one by one
+twa_status run_segment(twa_solver *s, long long len, const SegCapture &c, int slot);
 // TWA_F_TAPE at create: look up the static scratch of twa_backward_noalloc
 // on the solver's device, make twa_backward's second stream and its events
 twa_status tape_setup(twa_solver *s);

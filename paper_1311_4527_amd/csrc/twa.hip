@@ -1877,6 +1877,11 @@ twa_status iterate_impl(twa_solver *s, int k, bool timed) {
     return TWA_OK;
 }
 
+bool same_capture(const twa_rt::SegCapture &a, const twa_rt::SegCapture &b) {
+    return a.rout == b.rout && a.pool == b.pool && a.cursor == b.cursor && a.cap == b.cap && a.offs == b.offs &&
+           a.lseg == b.lseg && a.cntseg == b.cntseg && a.F == b.F && a.N == b.N;
+}
+
 // pending -> canonical: materialise u^k
 twa_status finalize(twa_solver *s) {
     if (!s->pending) return TWA_OK;
@@ -2029,6 +2034,66 @@ twa_status import_state(twa_solver *s, const float *z, const float *u, const uns
     return TWA_OK;
 }
 
+twa_status run_segment(twa_solver *s, long long len, const SegCapture &c, int slot) {
+    auto capture_into = [&](long long t) {
+        s->dbg_x = nullptr;
+        s->dbg_rho = c.rout + t * c.F;
+        s->adj_pool = c.pool;
+        s->adj_cursor = c.cursor;
+        s->adj_cap = c.cap;
+        s->adj_offs = c.offs + t + 1;
+        s->dbg_l = c.lseg + (t + 1) * c.N;
+        s->dbg_cnt = c.cntseg + t * c.N;
+    };
+    auto capture_none = [&]() {
+        s->dbg_rho = nullptr;
+        s->adj_pool = nullptr;
+        s->adj_offs = nullptr;
+        s->dbg_l = nullptr;
+        s->dbg_cnt = nullptr;
+    };
+    // every iteration at the configuration's rho0, the first from a settled state
+    const bool steady = slot >= 0 && !s->pending && s->iter >= s->n_warm && len > 0;
+    bool fits = steady && s->seg_graph[slot] && s->seg_len[slot] == len && same_capture(s->seg_key[slot], c);
+    if (steady && !fits && !s->no_capture && !s->seg_failed) {
+        if (s->seg_graph[slot]) (void)hipGraphExecDestroy(s->seg_graph[slot]);
+        s->seg_graph[slot] = nullptr;
+        hipGraph_t g = nullptr;
+        bool ok = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        s->timing = 0;
+        for (long long t = 0; t < len && ok; ++t) {
+            capture_into(t);
+            ok = run_iteration(s, t == 0 ? M_FIRST : M_FUSED, s->rho0, s->rho0) == TWA_OK;
+        }
+        capture_none();
+        ok = (hipStreamEndCapture(s->stream, &g) == hipSuccess) && ok && g != nullptr;
+        if (ok) ok = hipGraphInstantiate(&s->seg_graph[slot], g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (ok) {
+            s->seg_key[slot] = c;
+            s->seg_len[slot] = len;
+            fits = true;
+        } else {
+            (void)hipGetLastError();
+            s->seg_graph[slot] = nullptr;
+            s->seg_failed = true;
+            s->err.clear();
+            s->latched = TWA_OK;
+        }
+    }
+    if (steady && fits) {
+        HIP_TRY(s, hipGraphLaunch(s->seg_graph[slot], s->stream));
+        s->iter += len;
+        s->pending = true;
+        return TWA_OK;
+    }
+    for (long long t = 0; t < len; ++t) {
+        capture_into(t);
+        TRY(iterate_impl(s, 1, false)); // (clears the capture pointers)
+    }
+    return TWA_OK;
+}
+
 twa_status export_lrho(twa_solver *s, unsigned char *lrho) {
     unsigned nb = (unsigned)((s->P.N + 255) / 256);
     hipLaunchKernelGGL(k_z_export, dim3(nb), dim3(256), 0, s->stream, (const float4 *)s->P.zr_cur, (float *)nullptr,
@@ -2059,6 +2124,8 @@ void twa_destroy(twa_solver *s) {
         (void)hipStreamSynchronize(s->adj_stream);
         (void)hipStreamDestroy(s->adj_stream);
     }
+    for (hipGraphExec_t e : s->seg_graph)
+        if (e) (void)hipGraphExecDestroy(e);
     for (hipEvent_t e : s->adj_ev)
         if (e) (void)hipEventDestroy(e);
     if (s->adj_used) (void)hipHostFree(s->adj_used);
