@@ -112,6 +112,9 @@ typedef struct {
     double objective;        /* energy objective of z, as twa_get_quality */
     double min_clearance;    /* smallest clearance of z, as twa_get_quality */
     long long graph_iterations; /* iterations run so far from replayed HIP graphs */
+    long long tape_checkpoints; /* checkpoints of the current run on the forward tape
+                                   (TWA_F_TAPE: made by the first twa_backward, it records
+                                   from the next start of a run; see twa_backward) */
 } twa_stats;
 
 /*
@@ -290,7 +293,14 @@ twa_status twa_consensus_scale(int p, int n_walls, double coord_max, double *sca
  * capturing each iteration's weights and the minimiser inputs of the
  * factors that sent rho0.  A segment's reverse steps run on a second stream
  * that the solver makes at create (TWA_F_TAPE), while the segment before it
- * is recomputed on the solver's stream.  Its buffers are allocated at the
+ * is recomputed on the solver's stream.  The first call also sizes and
+ * allocates a forward tape: from the next start of a run (twa_set_init,
+ * twa_set_state, twa_set_endpoints) twa_iterate packs the state every 32
+ * iterations into it (64 checkpoints, runs of up to 2,048 iterations), and
+ * a call over a run the tape covers takes its checkpoints from there instead
+ * of re-running the forward (segments a multiple of 32 near sqrt(K));
+ * otherwise it re-runs the forward as the first call did.  The results are
+ * the same either way (the forward is bitwise unchanged by recording).  Its buffers are allocated at the
  * first call and kept, grown when a later call needs more, until
  * twa_destroy (TWA_E_NOMEM if they do not fit).  The solver's forward state
  * is the same afterwards.  dim == 2 only (TWA_E_INVALID otherwise);

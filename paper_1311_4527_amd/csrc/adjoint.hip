@@ -342,6 +342,8 @@ struct Sparse {
     unsigned char *l;  // [N]
     float *u_small;    // [e_coll][2]: the fixed and energy edges
     unsigned *first, *end; // device
+    AdjRec *arena;     // the record store [first, end) index (cap records)
+    unsigned cap;
 };
 
 // canonical dense u -> arena records of the collision / wall factors with a
@@ -433,13 +435,19 @@ struct Shape {
     int p;
 };
 
-Shape shape_of(const twa_solver *s) {
+// tape_every > 0: the forward tape holds the checkpoints every tape_every
+// iterations, and segments are a multiple of that near sqrt(K)
+Shape shape_of(const twa_solver *s, int tape_every = 0) {
     const twa_rt::Params &P = s->P;
     Shape h;
     h.N = P.N, h.E = P.e_wall + 2 * P.Fw, h.F = P.Ff + P.Fe + P.Fc + P.Fw, h.p = s->p;
     h.e_small = P.e_coll, h.nfac = P.Fc + P.Fw;
     h.K = s->iter - s->origin_iter;
-    h.L = std::max<long long>(1, (long long)std::ceil(std::sqrt((double)std::max<long long>(h.K, 0))));
+    const double root = std::sqrt((double)std::max<long long>(h.K, 0));
+    if (tape_every > 0)
+        h.L = tape_every * std::max<long long>(1, std::llround(root / tape_every));
+    else
+        h.L = std::max<long long>(1, (long long)std::ceil(root));
     h.ncp = h.K > 0 ? (h.K + h.L - 1) / h.L : 0;
     h.len_max = std::min(h.L, std::max<long long>(h.K, 1));
     return h;
@@ -529,25 +537,47 @@ Sparse ckpt(const Buffers &B, const Shape &h, long long c) {
     q.u_small = B.ck_us + c * h.e_small * 2;
     q.first = B.ck_first + c;
     q.end = B.ck_end + c;
+    q.arena = B.arena;
+    q.cap = B.arena_cap;
+    return q;
+}
+
+// checkpoint c of the solver's forward tape
+Sparse tape_slot(const twa_solver *s, long long c) {
+    const twa_solver::Tape &T = s->tape;
+    const long long N = s->P.N, es = s->P.e_coll;
+    Sparse q;
+    q.z = T.z + c * N * 2;
+    q.l = T.l + c * N;
+    q.u_small = T.us + c * es * 2;
+    q.first = T.first + c;
+    q.end = T.end + c;
+    q.arena = T.arena;
+    q.cap = T.arena_cap;
     return q;
 }
 
 unsigned grid_for(unsigned long long n) { return (unsigned)std::max<unsigned long long>(1, std::min<unsigned long long>((n + 255) / 256, 1024)); }
 
 // the solver's current state into q: z and <-rho, the fixed and energy u
-// dense, the collision / wall u as arena records
-twa_status pack(twa_solver *s, const Shape &h, Buffers &B, const Sparse &q) {
+// dense, the collision / wall u as records appended to q's store at *cursor
+// (u_tmp: [E][2] scratch)
+twa_status pack_state(twa_solver *s, float *u_tmp, unsigned *cursor, const Sparse &q) {
+    const long long e_small = s->P.e_coll, nfac = s->P.Fc + s->P.Fw;
     long long it = 0;
-    TRY(twa_get_state(s, q.z, B.u_tmp, q.l, &it)); // settles the pending u update
-    HIP_TRY(s, hipMemcpyAsync(q.u_small, B.u_tmp, sizeof(float) * 2 * h.e_small, hipMemcpyDeviceToDevice, s->stream));
-    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s->stream, q.first, (const unsigned *)B.arena_cursor);
-    if (h.nfac > 0)
-        hipLaunchKernelGGL(k_pack, dim3((unsigned)((h.nfac + 255) / 256)), dim3(256), 0, s->stream,
-                           (const float *)B.u_tmp, s->P.f_coll, h.nfac, h.e_small, s->P.Fc, B.arena, B.arena_cap,
-                           B.arena_cursor);
-    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s->stream, q.end, (const unsigned *)B.arena_cursor);
+    TRY(twa_get_state(s, q.z, u_tmp, q.l, &it)); // settles the pending u update
+    HIP_TRY(s, hipMemcpyAsync(q.u_small, u_tmp, sizeof(float) * 2 * e_small, hipMemcpyDeviceToDevice, s->stream));
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s->stream, q.first, (const unsigned *)cursor);
+    if (nfac > 0)
+        hipLaunchKernelGGL(k_pack, dim3((unsigned)((nfac + 255) / 256)), dim3(256), 0, s->stream,
+                           (const float *)u_tmp, s->P.f_coll, nfac, e_small, s->P.Fc, q.arena, q.cap, cursor);
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s->stream, q.end, (const unsigned *)cursor);
     HIP_TRY(s, hipGetLastError());
     return TWA_OK;
+}
+
+twa_status pack(twa_solver *s, const Shape &, Buffers &B, const Sparse &q) {
+    return pack_state(s, B.u_tmp, B.arena_cursor, q);
 }
 
 // state q into the solver, at iteration k
@@ -555,9 +585,9 @@ twa_status unpack(twa_solver *s, const Shape &h, Buffers &B, const Sparse &q, lo
     hipLaunchKernelGGL(k_fill_float, dim3(grid_for((unsigned long long)h.E * 2)), dim3(256), 0, s->stream, B.u_tmp,
                        h.E * 2);
     HIP_TRY(s, hipMemcpyAsync(B.u_tmp, q.u_small, sizeof(float) * 2 * h.e_small, hipMemcpyDeviceToDevice, s->stream));
-    hipLaunchKernelGGL(k_unpack, dim3(grid_for(B.arena_cap)), dim3(256), 0, s->stream, B.u_tmp, s->P.f_coll,
-                       h.e_small, s->P.Fc, (const AdjRec *)B.arena, (const unsigned *)q.first,
-                       (const unsigned *)q.end, B.arena_cap);
+    hipLaunchKernelGGL(k_unpack, dim3(grid_for(q.cap)), dim3(256), 0, s->stream, B.u_tmp, s->P.f_coll,
+                       h.e_small, s->P.Fc, (const AdjRec *)q.arena, (const unsigned *)q.first,
+                       (const unsigned *)q.end, q.cap);
     HIP_TRY(s, hipGetLastError());
     return twa_rt::import_state(s, q.z, B.u_tmp, q.l, k);
 }
@@ -574,7 +604,8 @@ enum { kDone = 0, kArenaFull = 1, kPoolFull = 2 };
 using GrowPool = twa_status (*)(twa_solver *s, Buffers &B, unsigned need);
 
 twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_dz, float *dL_dx0, float *dL_dxT,
-                    float *dL_dr, float *dL_dz0, int *outcome, unsigned *need, GrowPool grow_pool) {
+                    float *dL_dr, float *dL_dz0, int *outcome, unsigned *need, GrowPool grow_pool, bool use_tape,
+                    unsigned *arena_used) {
     const twa_rt::Params &P = s->P;
     hipStream_t st = s->stream;
     *outcome = kDone;
@@ -588,6 +619,12 @@ twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_d
     } join{s->adj_stream};
     HIP_TRY(s, hipMemsetAsync(B.arena_cursor, 0, sizeof(unsigned), st));
     const long long cur_iter = s->iter, it0 = s->origin_iter;
+    B.cur.arena = B.arena;
+    B.cur.cap = B.arena_cap;
+    // checkpoint c: from the forward tape (every h.L / interval-th of its
+    // checkpoints), or packed by pass 1
+    const long long tape_step = use_tape ? h.L / s->tape.interval : 0;
+    auto checkpoint = [&](long long c) { return use_tape ? tape_slot(s, c * tape_step) : ckpt(B, h, c); };
     TRY(pack(s, h, B, B.cur));
     unsigned used = 0;
     HIP_TRY(s, hipMemcpyAsync(&used, B.arena_cursor, sizeof(unsigned), hipMemcpyDeviceToHost, st));
@@ -598,11 +635,14 @@ twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_d
         *need = used;
         return TWA_OK;
     }
-    // pass 1: checkpoints every L iterations from the run's start
-    if (h.K > 0) TRY(twa_rt::import_state(s, s->origin_z, s->origin_u, s->origin_l, it0));
-    for (long long c = 0; c < h.ncp; ++c) {
-        TRY(pack(s, h, B, ckpt(B, h, c)));
-        if (c + 1 < h.ncp) TRY(twa_iterate(s, (int)h.L));
+    // pass 1: checkpoints every L iterations from the run's start (the tape
+    // holds them already when it covers the run)
+    if (!use_tape) {
+        if (h.K > 0) TRY(twa_rt::import_state(s, s->origin_z, s->origin_u, s->origin_l, it0));
+        for (long long c = 0; c < h.ncp; ++c) {
+            TRY(pack(s, h, B, ckpt(B, h, c)));
+            if (c + 1 < h.ncp) TRY(twa_iterate(s, (int)h.L));
+        }
     }
     HIP_TRY(s, hipMemcpyAsync(&used, B.arena_cursor, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     HIP_TRY(s, hipStreamSynchronize(st));
@@ -611,6 +651,7 @@ twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_d
         *need = used;
         return unpack(s, h, B, B.cur, cur_iter);
     }
+    if (arena_used) *arena_used = used;
     if (B.pools_follow) {
         // nothing is appended to the arena after pass 1
         const unsigned start = (used + 63u) & ~63u;
@@ -654,7 +695,7 @@ twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_d
         const int b = (int)(c & 1);
         // the reverse of segment c + 2 read this copy
         if (c + 2 < h.ncp) HIP_TRY(s, hipStreamWaitEvent(st, s->adj_ev[2 + b], 0));
-        TRY(unpack(s, h, B, ckpt(B, h, c), k0));
+        TRY(unpack(s, h, B, checkpoint(c), k0));
         HIP_TRY(s, hipMemsetAsync(B.pool_cursor[b], 0, sizeof(unsigned), st));
         HIP_TRY(s, hipMemsetAsync(B.offs[b], 0, sizeof(unsigned), st));
         TRY(twa_rt::export_lrho(s, B.lseg[b]));
@@ -746,6 +787,65 @@ twa_status run_once(twa_solver *s, const Shape &h, Buffers &B, const float *dL_d
     return TWA_OK;
 }
 
+// Does the forward tape hold every checkpoint of the current run (one at
+// each multiple of its interval below K, none of their records dropped)?
+// Synchronises the stream when it has to read the record count.
+bool tape_covers(twa_solver *s) {
+    const twa_solver::Tape &T = s->tape;
+    const long long K = s->iter - s->origin_iter;
+    if (!T.mem || !T.ok || K <= 0) return false;
+    if (T.count < (K + T.interval - 1) / T.interval) return false;
+    unsigned used = ~0u;
+    if (hipMemcpyAsync(&used, T.cursor, sizeof(unsigned), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return used <= T.arena_cap;
+}
+
+// Allocate the forward tape after an allocating twa_backward, for runs like
+// the one just differentiated: 64 checkpoints of every 32 iterations (runs
+// up to 2,048 iterations), each with room for twice the records a
+// checkpoint of this run held.  It records from the next start of a run.
+twa_status tape_alloc(twa_solver *s, unsigned records_per_checkpoint) {
+    twa_solver::Tape &T = s->tape;
+    if (T.mem) return TWA_OK;
+    const long long N = s->P.N, es = s->P.e_coll, E = s->P.e_wall + 2 * s->P.Fw;
+    const int cap = 64;
+    const size_t per = 2 * (size_t)records_per_checkpoint + 1024;
+    const size_t recs = std::min<size_t>((size_t)cap * per, 0x7fffffffu);
+    for (int pass = 0; pass < 2; ++pass) {
+        Region R;
+        if (pass == 1) {
+            R.base = static_cast<char *>(T.mem);
+            R.cap = T.bytes;
+        }
+        float *z = R.take<float>((size_t)cap * N * 2);
+        unsigned char *l = R.take<unsigned char>((size_t)cap * N);
+        float *us = R.take<float>((size_t)cap * es * 2);
+        unsigned *first = R.take<unsigned>(cap), *end = R.take<unsigned>(cap), *cursor = R.take<unsigned>(1);
+        float *u_tmp = R.take<float>((size_t)E * 2);
+        AdjRec *arena = R.take<AdjRec>(recs);
+        if (pass == 0) {
+            T.bytes = R.used;
+            T.mem = s->mem.get(T.bytes, s->stream);
+            if (!T.mem) {
+                T.bytes = 0;
+                return TWA_OK; // no tape: later calls re-run the forward as this one did
+            }
+        } else {
+            T.z = z, T.l = l, T.us = us, T.first = first, T.end = end, T.cursor = cursor, T.u_tmp = u_tmp;
+            T.arena = arena;
+            T.arena_cap = (unsigned)recs;
+        }
+    }
+    T.cap = cap;
+    T.count = 0;
+    T.ok = false; // the run just differentiated was not recorded
+    return TWA_OK;
+}
+
 twa_status check_args(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT, float *dL_dr) {
     using twa_rt::fail;
     TRY(twa_rt::check_alive(s));
@@ -796,6 +896,24 @@ twa_status ensure(twa_solver *s, void **buf, size_t *have, size_t want) {
 
 namespace twa_rt {
 
+twa_status tape_take(twa_solver *s) {
+    twa_solver::Tape &T = s->tape;
+    if (!T.ok || s->dbg_rho || s->adj_pool) return TWA_OK;
+    const long long since = s->iter - s->origin_iter;
+    if (since > (long long)T.count * T.interval) {
+        T.ok = false; // iterations ran past a checkpoint (not through twa_iterate)
+        return TWA_OK;
+    }
+    if (since % T.interval != 0 || since / T.interval != T.count) return TWA_OK;
+    if (T.count >= T.cap) {
+        T.ok = false; // the run outgrew the tape
+        return TWA_OK;
+    }
+    TRY(pack_state(s, T.u_tmp, T.cursor, tape_slot(s, T.count)));
+    ++T.count;
+    return TWA_OK;
+}
+
 // the static scratch's address on the solver's device, the reverse stream
 // and its events (set up at create)
 twa_status tape_setup(twa_solver *s) {
@@ -834,7 +952,8 @@ twa_status tape_setup(twa_solver *s) {
 extern "C" twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_dx0, float *dL_dxT, float *dL_dr,
                                    float *dL_dz0) {
     TRY(check_args(s, dL_dz, dL_dx0, dL_dxT, dL_dr));
-    const Shape h = shape_of(s);
+    const bool use_tape = tape_covers(s);
+    const Shape h = shape_of(s, use_tape ? s->tape.interval : 0);
     Region sz;
     Buffers B{};
     layout(sz, h, B);
@@ -848,7 +967,8 @@ extern "C" twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_
     HIP_TRY(s, hipMemcpyAsync(&queued, s->stats_dev + 2, sizeof(int), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const size_t per = 2 * (size_t)std::max(queued, 0) + 1024;
-    size_t want_arena = std::max<size_t>(s->adj_arena_bytes, (size_t)(h.ncp + 1) * per * sizeof(AdjRec));
+    const size_t packed = use_tape ? 1 : (size_t)h.ncp + 1; // checkpoints the arena takes
+    size_t want_arena = std::max<size_t>(s->adj_arena_bytes, packed * per * sizeof(AdjRec));
     size_t want_pool = std::max<size_t>(s->adj_pool_bytes, 2 * (size_t)h.len_max * per * sizeof(AdjRec));
     for (int attempt = 0; attempt < 3; ++attempt) {
         const size_t cap_recs = (size_t)0xffffffffu * sizeof(AdjRec);
@@ -858,9 +978,11 @@ extern "C" twa_status twa_backward(twa_solver *s, const float *dL_dz, float *dL_
         B.arena_cap = (unsigned)(s->adj_arena_bytes / sizeof(AdjRec));
         set_pools(B, s->adj_pool_mem, s->adj_pool_bytes);
         int outcome = kDone;
-        unsigned need = 0;
-        TRY(run_once(s, h, B, dL_dz, dL_dx0, dL_dxT, dL_dr, dL_dz0, &outcome, &need, grow_solver_pool));
-        if (outcome == kDone) return TWA_OK;
+        unsigned need = 0, used = 0;
+        TRY(run_once(s, h, B, dL_dz, dL_dx0, dL_dxT, dL_dr, dL_dz0, &outcome, &need, grow_solver_pool, use_tape,
+                     &used));
+        if (outcome == kDone)
+            return use_tape ? TWA_OK : tape_alloc(s, (unsigned)(used / std::max<long long>(1, h.ncp + 1)));
         // the arena's need is exact (every checkpoint was counted): one more attempt
         want_arena = (size_t)need * sizeof(AdjRec) * 5 / 4 + 4096;
     }
@@ -877,7 +999,8 @@ extern "C" twa_status twa_backward_noalloc(twa_solver *s, const float *dL_dz, fl
         if (s->device >= 0 && s->device < kMaxDevices) base = g_scratch_ptr[s->device];
     }
     if (!base) return fail(s, TWA_E_STATE, "twa_backward_noalloc: no scratch on the solver's device");
-    const Shape h = shape_of(s);
+    const bool use_tape = tape_covers(s);
+    const Shape h = shape_of(s, use_tape ? s->tape.interval : 0);
     Region R;
     R.base = static_cast<char *>(base);
     R.cap = kScratchBytes;
@@ -902,7 +1025,8 @@ extern "C" twa_status twa_backward_noalloc(twa_solver *s, const float *dL_dz, fl
     s->no_capture = true; // replay graphs already captured, capture none (that would allocate)
     int outcome = kDone;
     unsigned need = 0;
-    const twa_status st = run_once(s, h, B, dL_dz, dL_dx0, dL_dxT, dL_dr, dL_dz0, &outcome, &need, nullptr);
+    const twa_status st =
+        run_once(s, h, B, dL_dz, dL_dx0, dL_dxT, dL_dr, dL_dz0, &outcome, &need, nullptr, use_tape, nullptr);
     s->no_capture = was;
     if (st != TWA_OK) return st;
     if (outcome == kArenaFull)

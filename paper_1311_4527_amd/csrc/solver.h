@@ -191,6 +191,28 @@ struct twa_solver {
     twa_rt::SegCapture seg_key[2] = {};
     long long seg_len[2] = {0, 0};
     bool seg_failed = false;
+    // Forward-time checkpoints for twa_backward (sized and allocated by its
+    // first allocating call): from the next start of a differentiated run,
+    // the state at every `interval` iterations since it is packed as
+    // twa_backward packs its own checkpoints (z and <-rho dense, the fixed
+    // and energy u dense, the collision/wall u as records), so a backward
+    // call over a run the tape covers skips re-running the forward.
+    struct Tape {
+        int interval = 32;     // iterations between checkpoints
+        int cap = 0;           // checkpoints it holds
+        int count = 0;         // checkpoints taken since the run's start
+        bool ok = false;       // recording (the run started after allocation, nothing lost)
+        float *z = nullptr;    // [cap][N][2]
+        unsigned char *l = nullptr; // [cap][N]
+        float *us = nullptr;   // [cap][fixed + energy edges][2]
+        unsigned *first = nullptr, *end = nullptr; // [cap] record ranges
+        unsigned *cursor = nullptr;                // records appended (device)
+        twa_rt::AdjRec *arena = nullptr;
+        unsigned arena_cap = 0;
+        float *u_tmp = nullptr; // [E][2] dense u of the state being packed
+        void *mem = nullptr;
+        size_t bytes = 0;
+    } tape;
     unsigned *adj_used = nullptr; // pinned host [2]: records each recompute wanted
 };
 
@@ -214,6 +236,10 @@ twa_status export_lrho(twa_solver *s, unsigned char *lrho);
 // configuration's rho0 and the graph fits (captured now unless no_capture),
 // else launched one by one
 twa_status run_segment(twa_solver *s, long long len, const SegCapture &c, int slot);
+// At a checkpoint iteration of a recording tape, pack the current state
+// into it (twa_iterate calls it at multiples of the interval since the run's
+// start); a no-op otherwise
+twa_status tape_take(twa_solver *s);
 // TWA_F_TAPE at create: look up the static scratch of twa_backward_noalloc
 // on the solver's device, make twa_backward's second stream and its events
 twa_status tape_setup(twa_solver *s);

@@ -1835,7 +1835,7 @@ twa_status iterate_tiny(twa_solver *s, int k) {
 
 // Run k iterations; graph replays where possible.  timed: the last
 // kTimedTail iterations are launched on their own, with events.
-twa_status iterate_impl(twa_solver *s, int k, bool timed) {
+twa_status iterate_core(twa_solver *s, int k, bool timed) {
     const int tail = timed ? std::min(k, kTimedTail) : 0;
     // (steady rho0 throughout, the previous iteration's weights included)
     const bool settled = s->iter >= s->n_warm && (!s->pending || s->iter - 1 >= s->n_warm);
@@ -1873,6 +1873,21 @@ twa_status iterate_impl(twa_solver *s, int k, bool timed) {
         s->adj_offs = nullptr;
         s->dbg_l = nullptr;
         s->dbg_cnt = nullptr;
+    }
+    return TWA_OK;
+}
+
+// Run k iterations; with a recording forward tape the call is cut at the
+// tape's checkpoint iterations, each packed before the run goes on (only the
+// last piece carries the timed tail).
+twa_status iterate_impl(twa_solver *s, int k, bool timed) {
+    if (!s->tape.ok || s->dbg_rho || s->adj_pool) return iterate_core(s, k, timed);
+    while (k > 0) {
+        TRY(twa_rt::tape_take(s));
+        const long long since = s->iter - s->origin_iter;
+        const int n = (int)std::min<long long>(k, s->tape.interval - since % s->tape.interval);
+        TRY(iterate_core(s, n, timed && n == k));
+        k -= n;
     }
     return TWA_OK;
 }
@@ -1927,6 +1942,12 @@ twa_status save_origin(twa_solver *s) {
                        s->dim, 1);
     HIP_TRY(s, hipGetLastError());
     s->origin_iter = s->iter;
+    // a new run: the forward tape (if twa_backward made one) records it
+    if (s->tape.mem) {
+        HIP_TRY(s, hipMemsetAsync(s->tape.cursor, 0, sizeof(unsigned), s->stream));
+        s->tape.count = 0;
+        s->tape.ok = true;
+    }
     return TWA_OK;
 }
 
@@ -2120,6 +2141,7 @@ void twa_destroy(twa_solver *s) {
     s->mem.put(s->adj_ws, s->adj_ws_bytes, s->stream);
     s->mem.put(s->adj_arena, s->adj_arena_bytes, s->stream);
     s->mem.put(s->adj_pool_mem, s->adj_pool_bytes, s->stream);
+    s->mem.put(s->tape.mem, s->tape.bytes, s->stream);
     if (s->adj_stream) {
         (void)hipStreamSynchronize(s->adj_stream);
         (void)hipStreamDestroy(s->adj_stream);
@@ -2530,6 +2552,7 @@ twa_status twa_get_stats(twa_solver *s, twa_stats *out) {
     out->active_coll = h[0];
     out->active_wall = h[1];
     out->queued = h[2];
+    out->tape_checkpoints = s->tape.ok ? s->tape.count : 0;
     float rf;
     std::memcpy(&rf, &r, sizeof(rf));
     out->residual = s->resid_valid ? (double)rf : 0.0;

@@ -43,7 +43,8 @@ class TWAError(RuntimeError):
 class _Stats(ct.Structure):
     _fields_ = [("iter", ct.c_longlong), ("active_coll", ct.c_longlong), ("active_wall", ct.c_longlong),
                 ("queued", ct.c_longlong), ("residual", ct.c_double), ("objective", ct.c_double),
-                ("min_clearance", ct.c_double), ("graph_iterations", ct.c_longlong)]
+                ("min_clearance", ct.c_double), ("graph_iterations", ct.c_longlong),
+                ("tape_checkpoints", ct.c_longlong)]
 
 
 _lib = None
@@ -296,7 +297,7 @@ class Solver:
         self._check(load_library().twa_get_stats(self.h, ct.byref(s)))
         return dict(iter=s.iter, active_coll=s.active_coll, active_wall=s.active_wall, queued=s.queued,
                     residual=s.residual, objective=s.objective, min_clearance=s.min_clearance,
-                    graph_iterations=s.graph_iterations)
+                    graph_iterations=s.graph_iterations, tape_checkpoints=s.tape_checkpoints)
 
     def twa_get_quality(self) -> dict:
         """Energy objective, smallest clearance and largest last move of the

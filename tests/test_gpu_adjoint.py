@@ -211,3 +211,70 @@ def test_reading_the_state_leaves_the_run_unchanged(case, flags):
     assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb)
     A.close()
     B.close()
+
+
+def _tape_solver(inst, K, v):
+    """A TAPE solver whose first backward made the forward tape, restarted
+    from the initial state and run K iterations again (recorded)."""
+    import torch
+    from paper_1311_4527_amd.twa import Solver, TWA_F_TAPE
+    S = Solver.from_instance(inst, flags=TWA_F_TAPE)
+    S.twa_iterate(K)
+    first = [t.cpu().numpy().astype(np.float64) for t in S.twa_backward(torch.from_numpy(v.astype(np.float32)))]
+    S.twa_set_init(inst.z0)
+    S.twa_iterate(K)
+    return S, first
+
+
+@pytest.mark.parametrize("K", [40, 500])
+def test_forward_tape_matches_reference(K):
+    """The second backward reads its checkpoints from the tape the forward
+    recorded (no re-run of the forward): the same gradient as the reference
+    and as the first call, the forward itself bitwise the untaped one, and
+    the run continues bitwise afterwards."""
+    import torch
+    from paper_1311_4527_amd.twa import Solver
+    inst = _sub(radius=0.3) if K == 40 else _sub()
+    v = np.random.default_rng(11 + K).normal(size=inst.z0.shape)
+    S, first = _tape_solver(inst, K, v)
+    assert S.twa_get_stats()["tape_checkpoints"] == (K + 31) // 32
+    R = Solver.from_instance(inst)
+    R.twa_iterate(K)
+    assert torch.equal(S.twa_get_trajectories(), R.twa_get_trajectories())
+    got = [t.cpu().numpy().astype(np.float64) for t in S.twa_backward(torch.from_numpy(v.astype(np.float32)))]
+    g_ref, _ = _ref_grad(inst, K, v)
+    _compare(got, g_ref)
+    for name, a, b in zip(("dx0", "dxT", "dr", "dz0"), got, first):
+        scale = max(np.abs(b).max(), 1e-30)
+        assert np.allclose(a, b, rtol=1e-4, atol=1e-4 * scale), (name, np.abs(a - b).max(), scale)
+    assert torch.equal(S.twa_get_trajectories(), R.twa_get_trajectories())
+    S.twa_iterate(9)
+    R.twa_iterate(9)
+    assert torch.equal(S.twa_get_trajectories(), R.twa_get_trajectories())
+    S.close()
+    R.close()
+
+
+def test_forward_tape_outgrown_falls_back():
+    """A run longer than the tape holds (64 checkpoints of 32 iterations) is
+    differentiated by re-running the forward, with the same result as a
+    solver that never had a tape."""
+    import torch
+    from paper_1311_4527_amd.twa import Solver, TWA_F_TAPE
+    inst = _sub()
+    K = 2100
+    v = np.random.default_rng(3).normal(size=inst.z0.shape)
+    S, _ = _tape_solver(inst, 40, v)
+    S.twa_set_init(inst.z0)
+    S.twa_iterate(K)
+    assert S.twa_get_stats()["tape_checkpoints"] == 0   # outgrown: no longer recording
+    got = [t.cpu().numpy().astype(np.float64) for t in S.twa_backward(torch.from_numpy(v.astype(np.float32)))]
+    F = Solver.from_instance(inst, flags=TWA_F_TAPE)
+    F.twa_iterate(K)
+    want = [t.cpu().numpy().astype(np.float64) for t in F.twa_backward(torch.from_numpy(v.astype(np.float32)))]
+    for name, a, b in zip(("dx0", "dxT", "dr", "dz0"), got, want):
+        assert np.all(np.isfinite(a)), name
+        scale = max(np.abs(b).max(), 1e-30)
+        assert np.allclose(a, b, rtol=1e-4, atol=1e-4 * scale), (name, np.abs(a - b).max(), scale)
+    S.close()
+    F.close()
