@@ -541,7 +541,8 @@ __device__ __forceinline__ void wall_stream(const Params &P, const Rec &Z, long 
     const bool dense = P.dense != 0;
     bool push_prev = false, push_new = false;
     int fw = __builtin_amdgcn_readfirstlane((int)f);
-    unsigned long long pk = P.wbase_wall[fw >> 6];
+    // (a wave whose first factor is past the end has no valid lane)
+    unsigned long long pk = fw < P.Fw ? P.wbase_wall[fw >> 6] : 0ull;
     int s = (int)(pk >> 48), i = (int)((pk >> 24) & 0xffffffull), w = (int)(pk & 0xffffffull);
     if (valid) {
         advance_wall(P.p, P.W, (int)(f - fw), s, i, w);
@@ -1210,15 +1211,27 @@ __device__ __forceinline__ void batch_instance(const Params &P, float4 *zs, int 
         for (long long base = 0; base < P.Fc; base += 2 * BLOCK)
             coll_flat<D, MODE, 2>(P, Z, base + threadIdx.x, BLOCK, &len[0]);
     }
+    // The wall, energy and fixed factors start at the first wave the kinds
+    // before them leave idle in their first round (whole waves, so each wave
+    // still takes consecutive factors): in a small instance the kinds run
+    // side by side instead of one after another on the first waves.
+    auto round64 = [](long long n) { return (int)((std::min<long long>(n, BLOCK) + 63) / 64 * 64); };
+    const long long lanes_c =
+        P.p >= 64 ? 64LL * P.cps * (P.dense ? (P.eta + 1) / 2 : (P.eta + 3) / 4) : P.Fc;
+    const int shift_w = round64(lanes_c) % BLOCK;
+    const int shift_e = (shift_w + round64(P.Fw)) % BLOCK;
+    const int shift_f = (shift_e + round64(P.Fe)) % BLOCK;
+    const int tw = (threadIdx.x + BLOCK - shift_w) % BLOCK, te = (threadIdx.x + BLOCK - shift_e) % BLOCK,
+              tf = (threadIdx.x + BLOCK - shift_f) % BLOCK;
     for (long long base = 0; base < P.Fw; base += BLOCK) {
-        long long f = base + threadIdx.x;
+        long long f = base + tw;
         bool valid = f < P.Fw, q;
         unsigned val;
         wall_stream<MODE>(P, Z, f, valid, &q, &val);
         push(P.qw, &len[1], q, val);
     }
-    for (long long f = threadIdx.x; f < P.Fe; f += BLOCK) energy_stream<D, MODE>(P, Z, f);
-    for (long long f = threadIdx.x; f < P.Ff; f += BLOCK) fixed_stream<D, MODE>(P, Z, f);
+    for (long long f = te; f < P.Fe; f += BLOCK) energy_stream<D, MODE>(P, Z, f);
+    for (long long f = tf; f < P.Ff; f += BLOCK) fixed_stream<D, MODE>(P, Z, f);
     __syncthreads();
     if (clear_bits) {
         // every factor has read its activity bit: clear the words for the queue
