@@ -534,69 +534,93 @@ __device__ __forceinline__ void coll_flat(const Params &P, const Rec &Z, long lo
     for (int k = 0; k < U; ++k) push(P.qc, qlen, q[k], val[k]);
 }
 
-// Wall factor f: activity test (segment distance) and queue decision.
+// Where wall factor f sits: (s, i, wall), its two node records.
+struct WallAt {
+    long long f;
+    int s, i, w;
+    long long na, nb;
+};
+
+__device__ __forceinline__ WallAt wall_at(const Params &P, long long f, unsigned long long pk, int k) {
+    WallAt a;
+    a.f = f;
+    a.s = (int)(pk >> 48), a.i = (int)((pk >> 24) & 0xffffffull), a.w = (int)(pk & 0xffffffull);
+    advance_wall(P.p, P.W, k, a.s, a.i, a.w);
+    a.na = (long long)a.s * P.p + a.i;
+    a.nb = a.na + P.p;
+    return a;
+}
+
+// Wall factor a: activity test (segment distance) and queue decision.  bit:
+// the factor's activity bit (read only in the activity-bit form after the
+// first iteration).
+template <int MODE>
+__device__ __forceinline__ bool wall_test(const Params &P, const Rec &Z, const WallAt &a, bool bit, unsigned *val) {
+    const bool dense = P.dense != 0;
+    const long long f = a.f;
+    bool push_prev = false, push_new = false;
+    float4 wl = P.walls[a.w];
+    f2 xa = mk(wl.x, wl.y), xb = mk(wl.z, wl.w);
+    float r = P.radii[a.i];
+    float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+    bool check_cur = true;
+    if (MODE == M_FIRST) {
+        u = P.u_wall[f];
+    } else if (dense && P.admm) {
+        push_prev = true;
+        check_cur = false;
+    } else if (dense) {
+        u = P.u_wall[f];
+        float4 za = Z.prev[a.na], zb = Z.prev[a.nb];
+        f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
+        if (segseg_sq(n0, n1, xa, xb) < r * r) {
+            push_prev = true;
+            check_cur = false;
+        } else {
+            const unsigned nz = __float_as_uint(u.x) | __float_as_uint(u.y) | __float_as_uint(u.z) |
+                                __float_as_uint(u.w);
+            u = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (nz) P.u_wall[f] = u;
+        }
+    } else if (bit) {
+        push_prev = true;
+        check_cur = false;
+    }
+    if (MODE == M_FINAL) {
+        check_cur = false;
+        if (!dense && !push_prev) P.u_wall[f] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (check_cur) {
+        float4 za = Z.cur[a.na], zb = Z.cur[a.nb];
+        f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
+        push_new = P.admm || segseg_sq(n0, n1, xa, xb) < r * r;
+        if (!push_new && P.dbg_rho) {
+            long long e0 = P.e_wall + 2 * f;
+            if (P.dbg_x) {
+                P.dbg_x[e0 * 2 + 0] = n0.x, P.dbg_x[e0 * 2 + 1] = n0.y;
+                P.dbg_x[e0 * 2 + 2] = n1.x, P.dbg_x[e0 * 2 + 3] = n1.y;
+            }
+            P.dbg_rho[P.f_wall + f] = W_ZERO;
+        }
+    }
+    *val = (unsigned)f | (push_prev ? kPrev : 0u);
+    return push_prev || push_new;
+}
+
+// Wall factor f of the stream (lanes of a wave take consecutive factors).
 template <int MODE>
 __device__ __forceinline__ void wall_stream(const Params &P, const Rec &Z, long long f, bool valid, bool *q,
                                             unsigned *val) {
-    const bool dense = P.dense != 0;
-    bool push_prev = false, push_new = false;
     int fw = __builtin_amdgcn_readfirstlane((int)f);
     // (a wave whose first factor is past the end has no valid lane)
     unsigned long long pk = fw < P.Fw ? P.wbase_wall[fw >> 6] : 0ull;
-    int s = (int)(pk >> 48), i = (int)((pk >> 24) & 0xffffffull), w = (int)(pk & 0xffffffull);
+    *q = false;
+    *val = (unsigned)f;
     if (valid) {
-        advance_wall(P.p, P.W, (int)(f - fw), s, i, w);
-        long long na = (long long)s * P.p + i, nb = na + P.p;
-        float4 wl = P.walls[w];
-        f2 xa = mk(wl.x, wl.y), xb = mk(wl.z, wl.w);
-        float r = P.radii[i];
-        float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
-        bool check_cur = true;
-        if (MODE == M_FIRST) {
-            u = P.u_wall[f];
-        } else if (dense && P.admm) {
-            push_prev = true;
-            check_cur = false;
-        } else if (dense) {
-            u = P.u_wall[f];
-            float4 za = Z.prev[na], zb = Z.prev[nb];
-            f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
-            if (segseg_sq(n0, n1, xa, xb) < r * r) {
-                push_prev = true;
-                check_cur = false;
-            } else {
-                const unsigned nz = __float_as_uint(u.x) | __float_as_uint(u.y) | __float_as_uint(u.z) |
-                                    __float_as_uint(u.w);
-                u = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (nz) P.u_wall[f] = u;
-            }
-        } else {
-            unsigned wd = P.bits_wall[f >> 5];
-            if ((wd >> (f & 31)) & 1u) {
-                push_prev = true;
-                check_cur = false;
-            }
-        }
-        if (MODE == M_FINAL) {
-            check_cur = false;
-            if (!dense && !push_prev) P.u_wall[f] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        if (check_cur) {
-            float4 za = Z.cur[na], zb = Z.cur[nb];
-            f2 n0 = mk(za.x - u.x, za.y - u.y), n1 = mk(zb.x - u.z, zb.y - u.w);
-            push_new = P.admm || segseg_sq(n0, n1, xa, xb) < r * r;
-            if (!push_new && P.dbg_rho) {
-                long long e0 = P.e_wall + 2 * f;
-                if (P.dbg_x) {
-                    P.dbg_x[e0 * 2 + 0] = n0.x, P.dbg_x[e0 * 2 + 1] = n0.y;
-                    P.dbg_x[e0 * 2 + 2] = n1.x, P.dbg_x[e0 * 2 + 3] = n1.y;
-                }
-                P.dbg_rho[P.f_wall + f] = W_ZERO;
-            }
-        }
+        const WallAt a = wall_at(P, f, pk, (int)(f - fw));
+        const bool bit = P.dense == 0 && MODE != M_FIRST && ((P.bits_wall[f >> 5] >> (f & 31)) & 1u);
+        *q = wall_test<MODE>(P, Z, a, bit, val);
     }
-    *q = push_prev || push_new;
-    *val = (unsigned)f | (push_prev ? kPrev : 0u);
 }
 
 // Per-segment factor of agent i between break-points s and s+1: the energy
@@ -756,19 +780,37 @@ __device__ __forceinline__ void fixed_stream(const Params &P, const Rec &Z, long
     }
 }
 
-// Queued collision factor (entry e): deferred u update, full minimiser,
-// consensus contributions.
-template <int D, int MODE>
-__device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsigned e, float *nout, Contrib &out) {
-    const bool dense = P.dense != 0;
-    long long f = e & kIdx;
-    bool prev = (e & kPrev) != 0;
-    unsigned long long pk = P.wbase_coll[f >> 6];
-    int s = (int)(pk >> 48), i = (int)((pk >> 24) & 0xffffffull), j = (int)(pk & 0xffffffull);
-    advance_pair(P.p, (int)(f & 63), s, i, j);
+// Where collision factor f sits: (s, i, j), its four node records and the
+// radius sum.
+struct CollAt {
+    long long f;
+    int s, i, j;
     long long nd[4];
-    coll_nodes(P, s, i, j, nd);
-    float R = P.radii[i] + P.radii[j];
+    float R;
+};
+
+__device__ __forceinline__ CollAt coll_at(const Params &P, long long f) {
+    CollAt c;
+    c.f = f;
+    unsigned long long pk = P.wbase_coll[f >> 6];
+    c.s = (int)(pk >> 48), c.i = (int)((pk >> 24) & 0xffffffull), c.j = (int)(pk & 0xffffffull);
+    advance_pair(P.p, (int)(f & 63), c.s, c.i, c.j);
+    coll_nodes(P, c.s, c.i, c.j, c.nd);
+    c.R = P.radii[c.i] + P.radii[c.j];
+    return c;
+}
+
+// Collision factor c taken from the queue (prev: it was active last
+// iteration): deferred u update, full minimiser, consensus contributions.
+// SET_BITS: mark the factor active in its chunk's activity word.
+template <int D, int MODE, bool SET_BITS = true>
+__device__ __forceinline__ bool coll_minimise(const Params &P, const Rec &Z, const CollAt &c, bool prev, float *nout,
+                                              Contrib &out) {
+    const bool dense = P.dense != 0;
+    const long long f = c.f;
+    const int s = c.s, i = c.i, j = c.j;
+    const long long *nd = c.nd;
+    const float R = c.R;
     float u[4 * D], zc[4 * D], n[4 * D], x[4 * D], w[4];
     int k[4];
     float4 rc[4];
@@ -809,8 +851,10 @@ __device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsign
             for (int c = 0; c < D; ++c) out.m[q][c] = x[q * D + c] + u[q * D + c];
         }
         store_x_coll<D>(P, f, x);
-        const int r = j - i - 1;
-        atomicOr(&P.bits_coll[(long long)s * P.cps + P.rowchunk[i] + (r >> 6)], 1ull << (r & 63));
+        if (SET_BITS) {
+            const int r = j - i - 1;
+            atomicOr(&P.bits_coll[(long long)s * P.cps + P.rowchunk[i] + (r >> 6)], 1ull << (r & 63));
+        }
     } else {
         for (int q = 0; q < 4 * D; ++q) x[q] = n[q];
         if (P.admm) {
@@ -831,6 +875,12 @@ __device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsign
         P.dbg_rho[P.f_coll + f] = (act || P.admm) ? W_STD : W_ZERO;
     }
     return act;
+}
+
+// Queued collision factor (entry e)
+template <int D, int MODE>
+__device__ __forceinline__ bool coll_queue(const Params &P, const Rec &Z, unsigned e, float *nout, Contrib &out) {
+    return coll_minimise<D, MODE>(P, Z, coll_at(P, e & kIdx), (e & kPrev) != 0, nout, out);
 }
 
 // The same minimiser on two lanes (lanes 2k and 2k+1 hold the same factor,
@@ -864,21 +914,18 @@ __device__ __forceinline__ void capsule_prox_pair(const Capsule C, f2 n0, f2 n1,
     capsule_finish(C, n0, n1, w0, w1, d, L2, seg, sw, bb, x0, x1, nullptr);
 }
 
-// Queued wall factor (entry e).  piece < 0: one lane; 0 or 1: the two lanes
-// of a pair share the minimiser (capsule_prox_pair) and lane 0 writes.
-template <int MODE>
-__device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsigned e, int piece, float *nout,
-                                           Contrib &out) {
+// Wall factor a taken from the queue (prev: it was active last iteration).
+// piece < 0: one lane; 0 or 1: the two lanes of a pair share the minimiser
+// (capsule_prox_pair) and lane 0 writes.  SET_BITS: mark the factor active in
+// its activity word.
+template <int MODE, bool SET_BITS = true>
+__device__ __forceinline__ bool wall_minimise(const Params &P, const Rec &Z, const WallAt &a, bool prev, int piece,
+                                              float *nout, Contrib &out) {
     const bool writer = piece <= 0;
     const bool dense = P.dense != 0;
-    long long f = e & kIdx;
-    bool prev = (e & kPrev) != 0;
-    unsigned long long pk = P.wbase_wall[f >> 6];
-    int s = (int)(pk >> 48), i = (int)((pk >> 24) & 0xffffffull), wi = (int)(pk & 0xffffffull);
-    advance_wall(P.p, P.W, (int)(f & 63), s, i, wi);
-    long long na = (long long)s * P.p + i, nb = na + P.p;
-    float4 wl = P.walls[wi];
-    Capsule Cw{mk(wl.x, wl.y), mk(wl.z, wl.w), P.radii[i]};
+    const long long f = a.f, na = a.na, nb = a.nb;
+    float4 wl = P.walls[a.w];
+    Capsule Cw{mk(wl.x, wl.y), mk(wl.z, wl.w), P.radii[a.i]};
     float4 ca = Z.cur[na], cb = Z.cur[nb];
     int ka = wcode(ca), kb = wcode(cb);
     float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -919,7 +966,7 @@ __device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsign
         out.nd[0] = na, out.nd[1] = nb;
         out.m[0][0] = x0.x + u.x, out.m[0][1] = x0.y + u.y;
         out.m[1][0] = x1.x + u.z, out.m[1][1] = x1.y + u.w;
-        if (act) atomicOr(&P.bits_wall[f >> 5], 1u << (f & 31));
+        if (SET_BITS && act) atomicOr(&P.bits_wall[f >> 5], 1u << (f & 31));
     }
     if (MODE == M_FUSED && ((prev && (dense || act)) || (!prev && !dense))) P.u_wall[f] = u;
     if (P.dbg_rho) {
@@ -931,6 +978,15 @@ __device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsign
         P.dbg_rho[P.f_wall + f] = (act || P.admm) ? W_STD : W_ZERO;
     }
     return act;
+}
+
+// Queued wall factor (entry e)
+template <int MODE>
+__device__ __forceinline__ bool wall_queue(const Params &P, const Rec &Z, unsigned e, int piece, float *nout,
+                                           Contrib &out) {
+    const long long f = e & kIdx;
+    return wall_minimise<MODE>(P, Z, wall_at(P, f, P.wbase_wall[f >> 6], (int)(f & 63)), (e & kPrev) != 0, piece,
+                               nout, out);
 }
 
 // Node nd: z and <-rho of the next iteration, shift records, clear sums.
@@ -1174,12 +1230,11 @@ __device__ __forceinline__ const Params &params_lds(const Params *src, Params *d
 // lengths are workgroup-local counters.
 constexpr int kBatchLdsNodes = 4000; // 62.5 KiB of node records per workgroup
 
-template <int D, int MODE, int BLOCK, bool RESIDENT = false>
+template <int D, int MODE, int BLOCK>
 __device__ __forceinline__ void batch_instance(const Params &P, float4 *zs, int *len) {
     const bool clear_bits = P.dense == 0;
-    // RESIDENT: P's node records already live in LDS (k_tiny)
-    const bool stage = !RESIDENT && P.N <= kBatchLdsNodes;
-    const bool stage_prev = !RESIDENT && P.dense && MODE != M_FIRST && 2 * P.N <= kBatchLdsNodes;
+    const bool stage = P.N <= kBatchLdsNodes;
+    const bool stage_prev = P.dense && MODE != M_FIRST && 2 * P.N <= kBatchLdsNodes;
     if (stage)
         for (long long nd = threadIdx.x; nd < P.N; nd += BLOCK) zs[nd] = P.zr_cur[nd];
     if (stage_prev)
@@ -1281,17 +1336,16 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const Params *insts, const int 
 
 // ------------------------------------------------------------------ LDS-resident tiny instance
 // A tiny instance alone in one workgroup keeps its whole mutable state (node
-// records, u, x, activity bits, queues, consensus sums, counters) in LDS for
-// the K iterations of a launch: loaded at the start, written back at the
-// end.  Every access of an iteration then stays on the compute unit; the
-// per-factor code is batch_instance's, on a copy of the parameters whose
-// pointers are redirected into LDS (generic pointers reach LDS as well), so
-// the instance evolves bitwise as in the persistent batched kernel.
+// records, u, x, activity bits, consensus sums, counters) in LDS for the K
+// iterations of a launch: loaded at the start, written back at the end.
+// Every access of an iteration then stays on the compute unit.  Each lane
+// owns one collision or wall factor for the whole launch (tiny_iteration),
+// on a copy of the parameters whose pointers are redirected into LDS.
 enum TinyArr {
     TA_ZPREV, TA_ZCUR, TA_UC, TA_XC, TA_UW, TA_XW, TA_UE, TA_UF, TA_BC, TA_BW, TA_CTR, TA_ACC, TA_CNT, TA_INF,
     TA_QC, TA_QW, TA_QCNT, kTinyArrays
 };
-constexpr int kTinyCopied = TA_QC; // arrays before it are loaded and written back; the queues are scratch
+constexpr int kTinyCopied = TA_QC; // arrays before it are loaded and written back; the rest is scratch
 
 struct TinyLds {
     unsigned off[kTinyArrays];   // byte offset in the dynamic LDS (16-aligned)
@@ -1326,12 +1380,110 @@ __device__ __forceinline__ void tiny_redirect(Params &P, char *b, const TinyLds 
     P.qcnt = reinterpret_cast<int *>(b + L.off[TA_QCNT]);
 }
 
+// The factors a lane of k_tiny owns for the whole launch: collision factor
+// t (lane t < Fc) and wall factor t - c0 (c0 = Fc rounded up to whole waves),
+// decoded once; act: the factor was active in the last iteration (its
+// activity bit, kept in a register between iterations), ever: active in some
+// iteration of the launch.
+struct TinyOwn {
+    CollAt c;
+    WallAt w;
+    bool act_c = false, act_w = false, ever_c = false, ever_w = false;
+};
+
+// One iteration of an LDS-resident tiny instance.  Every lane runs its own
+// factors through the same per-factor code as the plain kernels (activity
+// test, then the minimiser where the factor is queued) with no queue in
+// between, so the iteration has two barriers: factors, then nodes.  The
+// consensus sums are exact integers, so the order in which lanes add to them
+// does not matter and the instance evolves bitwise as in the plain solver.
+// The activity words are not read or written here: the owner lanes keep the
+// bits (tiny_bits writes them back at the end of the launch).
+template <int D, int MODE, int BLOCK>
+__device__ __forceinline__ void tiny_iteration(const Params &P, int *len, TinyOwn &o) {
+    const Rec Z{P.zr_cur, P.zr_prev};
+    const bool dense = P.dense != 0;
+    {
+        bool q = false, act = false;
+        Contrib out;
+        if (o.c.f >= 0) {
+            float4 rc[4], rp[4];
+            float u[4 * D], n[4 * D];
+            for (int k = 0; k < 4 * D; ++k) u[k] = 0.f;
+            for (int e = 0; e < 4; ++e) rc[e] = Z.cur[o.c.nd[e]];
+            for (int e = 0; e < 4; ++e) rp[e] = rc[e];
+            if (dense || MODE == M_FIRST) load_u_coll<D>(P, o.c.f, u);
+            if (dense && MODE != M_FIRST)
+                for (int e = 0; e < 4; ++e) rp[e] = Z.prev[o.c.nd[e]];
+            unsigned val;
+            if (dense) q = coll_factor<D, MODE, true>(P, o.c.f, o.c.R, rc, rp, u, 0ull, 0, &val);
+            else q = coll_factor<D, MODE, false>(P, o.c.f, o.c.R, rc, rp, u, o.act_c ? 1ull : 0ull, 0, &val);
+            if (q) act = coll_minimise<D, MODE, false>(P, Z, o.c, (val & kPrev) != 0, n, out);
+        }
+        count_wave(&len[0], q);
+        contribute_wave<false>(P, out, D);
+        count_wave(&P.counters[2], act);
+        o.act_c = act;
+        o.ever_c = o.ever_c || act;
+    }
+    if (P.Fw > 0) {
+        bool q = false, act = false;
+        Contrib out;
+        if (o.w.f >= 0) {
+            unsigned val;
+            q = wall_test<MODE>(P, Z, o.w, o.act_w, &val);
+            float n[4];
+            if (q) act = wall_minimise<MODE, false>(P, Z, o.w, (val & kPrev) != 0, -1, n, out);
+        }
+        count_wave(&len[1], q);
+        contribute_wave<false>(P, out, D);
+        count_wave(&P.counters[3], act);
+        o.act_w = act;
+        o.ever_w = o.ever_w || act;
+    }
+    // per-segment and fixed factors on the waves after the owners'
+    auto round64 = [](long long n) { return (int)((std::min<long long>(n, BLOCK) + 63) / 64 * 64); };
+    const int shift_e = (round64(P.Fc) + round64(P.Fw)) % BLOCK, shift_f = (shift_e + round64(P.Fe)) % BLOCK;
+    const int te = (threadIdx.x + BLOCK - shift_e) % BLOCK, tf = (threadIdx.x + BLOCK - shift_f) % BLOCK;
+    for (long long f = te; f < P.Fe; f += BLOCK) energy_stream<D, MODE>(P, Z, f);
+    for (long long f = tf; f < P.Ff; f += BLOCK) fixed_stream<D, MODE>(P, Z, f);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        P.qcnt[0] = len[0];
+        P.counters[1] = len[1];
+        close_counters(P, 1);
+        len[0] = len[1] = 0;
+    }
+    for (long long nd = threadIdx.x; nd < P.N; nd += BLOCK) node_update<D>(P, nd);
+    __syncthreads();
+}
+
+// Activity words at the end of a launch: in the activity-bit form the factors
+// active in the last iteration (every word cleared first), in the dense form
+// (where the words only accumulate) those active in any iteration added.
+__device__ __forceinline__ void tiny_bits(const Params &P, const TinyOwn &o, int block) {
+    const bool dense = P.dense != 0;
+    if (!dense) {
+        for (long long w = threadIdx.x; w < P.nch; w += block) P.bits_coll[w] = 0ull;
+        for (long long w = threadIdx.x; w < (P.Fw + 31) / 32; w += block) P.bits_wall[w] = 0u;
+        __syncthreads();
+    }
+    if (o.c.f >= 0 && (dense ? o.ever_c : o.act_c)) {
+        const int r = o.c.j - o.c.i - 1;
+        atomicOr(&P.bits_coll[(long long)o.c.s * P.cps + P.rowchunk[o.c.i] + (r >> 6)], 1ull << (r & 63));
+    }
+    if (o.w.f >= 0 && (dense ? o.ever_w : o.act_w)) atomicOr(&P.bits_wall[o.w.f >> 5], 1u << (o.w.f & 31));
+    __syncthreads();
+}
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_tiny(const Params *src, TinyLds L, int K, int first) {
     extern __shared__ __align__(16) char lds[];
-    __shared__ Params sp;
     __shared__ int len[2];
-    const Params &G = params_lds<BLOCK>(src, &sp); // (ends with a barrier)
+    // The parameters live in registers, their state pointers redirected into
+    // LDS: the compiler then sees those pointers address LDS and accesses
+    // them with LDS instructions.
+    const Params &G = *src;
     void *ga[kTinyArrays];
     tiny_arrays(G, ga);
 #pragma unroll
@@ -1340,21 +1492,37 @@ __global__ __launch_bounds__(BLOCK) void k_tiny(const Params *src, TinyLds L, in
         unsigned *d = reinterpret_cast<unsigned *>(lds + L.off[a]);
         for (unsigned t = threadIdx.x; t < L.bytes[a] / 4; t += BLOCK) d[t] = g[t];
     }
-    if (threadIdx.x == 0) reinterpret_cast<int *>(lds + L.off[TA_QCNT])[0] = 0;
+    if (threadIdx.x == 0) {
+        reinterpret_cast<int *>(lds + L.off[TA_QCNT])[0] = 0;
+        len[0] = len[1] = 0;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) tiny_redirect(sp, lds, L);
-    __syncthreads();
+    Params sp = G;
+    tiny_redirect(sp, lds, L);
+    TinyOwn o;
+    o.c.f = o.w.f = -1;
+    const long long c0 = ((long long)sp.Fc + 63) & ~63LL;
+    if (threadIdx.x < sp.Fc) {
+        o.c = coll_at(sp, threadIdx.x);
+        const int r = o.c.j - o.c.i - 1;
+        o.act_c = (sp.bits_coll[(long long)o.c.s * sp.cps + sp.rowchunk[o.c.i] + (r >> 6)] >> (r & 63)) & 1ull;
+    } else if (threadIdx.x >= c0 && threadIdx.x - c0 < sp.Fw) {
+        const long long f = threadIdx.x - c0;
+        o.w = wall_at(sp, f, sp.wbase_wall[f >> 6], (int)(f & 63));
+        o.act_w = (sp.bits_wall[f >> 5] >> (f & 31)) & 1u;
+    }
     for (int it = 0; it < K; ++it) {
         const bool fst = first && it == 0;
         if (sp.dim == 2) {
-            if (fst) batch_instance<2, M_FIRST, BLOCK, true>(sp, nullptr, len);
-            else batch_instance<2, M_FUSED, BLOCK, true>(sp, nullptr, len);
+            if (fst) tiny_iteration<2, M_FIRST, BLOCK>(sp, len, o);
+            else tiny_iteration<2, M_FUSED, BLOCK>(sp, len, o);
         } else {
-            if (fst) batch_instance<3, M_FIRST, BLOCK, true>(sp, nullptr, len);
-            else batch_instance<3, M_FUSED, BLOCK, true>(sp, nullptr, len);
+            if (fst) tiny_iteration<3, M_FIRST, BLOCK>(sp, len, o);
+            else tiny_iteration<3, M_FUSED, BLOCK>(sp, len, o);
         }
     }
-    // (batch_instance ends with a barrier) write the state back
+    tiny_bits(sp, o, BLOCK);
+    // write the state back
 #pragma unroll
     for (int a = 0; a < kTinyCopied; ++a) {
         const unsigned *d = reinterpret_cast<const unsigned *>(lds + L.off[a]);
@@ -1792,8 +1960,7 @@ bool tiny_layout(const twa_solver *s, TinyLds *L) {
     bytes[TA_ACC] = 8 * 2 * d * N;
     bytes[TA_CNT] = 4 * 2 * N;
     bytes[TA_INF] = 16 * N;
-    bytes[TA_QC] = 4 * std::max<long long>(1, P.Fc); // one entry per factor at most
-    bytes[TA_QW] = 4 * std::max<long long>(1, P.Fw);
+    bytes[TA_QC] = bytes[TA_QW] = 4; // (no queues: each lane runs its own factors)
     bytes[TA_QCNT] = 4;
     long long off = 0;
     for (int a = 0; a < kTinyArrays; ++a) {
