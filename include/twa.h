@@ -199,6 +199,21 @@ twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm);
  * single-workgroup launch instead (bitwise the same iterations). */
 twa_status twa_iterate(twa_solver *s, int k);
 
+/* Iterate until the plan is collision-free: up to max_iter >= 0 iterations
+ * in blocks of every >= 1, with the smallest clearance that twa_get_quality
+ * reports (Sec. 2 pairs, Sec. 3.2 walls) taken after each block and after
+ * the last iteration; stops after the first block whose clearance is
+ * >= min_clearance (the stopping rule of a velocity-obstacle epoch, Sec. 5).
+ * Writes the iterations run to *done (host int) and 1 to *met (host int) if
+ * the bar was met, else 0.  The iterations and the clearance are those of
+ * twa_iterate followed by twa_get_quality, bitwise.  A tiny instance (at most
+ * 256 collision + wall factors, state within 56 KiB of LDS, at the steady
+ * rho0, no forward tape) runs the whole call on the device, the clearance
+ * taken inside the persistent launch, and synchronises once; otherwise each
+ * block is launched and checked from the host.  TWA_E_INVALID for a null
+ * out-pointer, max_iter < 0, every < 1 or a NaN bar. */
+twa_status twa_iterate_until(twa_solver *s, int max_iter, int every, double min_clearance, int *done, int *met);
+
 /* As twa_iterate, and times the kernels with HIP events on the solver's
  * stream; synchronises and writes the device time in milliseconds of each
  * kernel summed over the k iterations to kernel_ms (host array of 3: factor

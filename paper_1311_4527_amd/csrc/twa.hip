@@ -1334,6 +1334,50 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const Params *insts, const int 
     }
 }
 
+// ------------------------------------------------------------------ clearance measures
+// squared distance from q to the segment [a, b] (planar)
+__device__ __forceinline__ double pt_seg2(double qx, double qy, double ax, double ay, double bx, double by) {
+    const double ex = bx - ax, ey = by - ay, ee = ex * ex + ey * ey;
+    double t = 0.0;
+    if (ee > 0.0) t = fmin(fmax(((qx - ax) * ex + (qy - ay) * ey) / ee, 0.0), 1.0);
+    const double vx = qx - (ax + t * ex), vy = qy - (ay + t * ey);
+    return vx * vx + vy * vy;
+}
+
+// twice the signed area of (a, b, c)
+__device__ __forceinline__ double cross3(double ax, double ay, double bx, double by, double cx, double cy) {
+    return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
+}
+
+// Clearance of agents i and j over one interval: closest approach of the two
+// constant-velocity motions a -> b minus ri + rj (Sec. 2).
+__device__ __forceinline__ double pair_clearance(float4 ai, float4 bi, float4 aj, float4 bj, double ri, double rj) {
+    // relative position at the interval's ends; closest approach over the interval
+    const double d0x = (double)aj.x - ai.x, d0y = (double)aj.y - ai.y, d0z = (double)aj.z - ai.z;
+    const double ex = ((double)bj.x - bi.x) - d0x, ey = ((double)bj.y - bi.y) - d0y, ez = ((double)bj.z - bi.z) - d0z;
+    const double ee = ex * ex + ey * ey + ez * ez;
+    double a = 0.0;
+    if (ee > 0.0) a = fmin(fmax(-(d0x * ex + d0y * ey + d0z * ez) / ee, 0.0), 1.0);
+    const double vx = d0x + a * ex, vy = d0y + a * ey, vz = d0z + a * ez;
+    return sqrt(vx * vx + vy * vy + vz * vz) - (ri + rj);
+}
+
+// Clearance of agent i's interval a -> b from a wall (planar): segment
+// distance minus ri (Sec. 3.2).
+__device__ __forceinline__ double wall_clearance(float4 ai, float4 bi, float4 wl, double ri) {
+    const double px = ai.x, py = ai.y, qx = bi.x, qy = bi.y;
+    const double o1 = cross3(px, py, qx, qy, wl.x, wl.y), o2 = cross3(px, py, qx, qy, wl.z, wl.w);
+    const double o3 = cross3(wl.x, wl.y, wl.z, wl.w, px, py), o4 = cross3(wl.x, wl.y, wl.z, wl.w, qx, qy);
+    double d2;
+    if (o1 * o2 < 0.0 && o3 * o4 < 0.0) {
+        d2 = 0.0; // proper crossing
+    } else {
+        d2 = fmin(fmin(pt_seg2(px, py, wl.x, wl.y, wl.z, wl.w), pt_seg2(qx, qy, wl.x, wl.y, wl.z, wl.w)),
+                  fmin(pt_seg2(wl.x, wl.y, px, py, qx, qy), pt_seg2(wl.z, wl.w, px, py, qx, qy)));
+    }
+    return sqrt(d2) - ri;
+}
+
 // ------------------------------------------------------------------ LDS-resident tiny instance
 // A tiny instance alone in one workgroup keeps its whole mutable state (node
 // records, u, x, activity bits, consensus sums, counters) in LDS for the K
@@ -1476,10 +1520,19 @@ __device__ __forceinline__ void tiny_bits(const Params &P, const TinyOwn &o, int
     __syncthreads();
 }
 
+// every > 0: after every `every` iterations and after the last one, the
+// smallest clearance of the current break-points (the measure of
+// twa_get_quality, from the same functions) is taken over the workgroup; the
+// launch stops after the first check that reaches bar.  ctl[0] accumulates
+// the iterations run, ctl[1] is set once the bar is met (later launches of
+// the same call then do nothing).
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_tiny(const Params *src, TinyLds L, int K, int first) {
+__global__ __launch_bounds__(BLOCK) void k_tiny(const Params *src, TinyLds L, int K, int first, int every, double bar,
+                                                int *ctl) {
+    if (ctl && ctl[1]) return;
     extern __shared__ __align__(16) char lds[];
     __shared__ int len[2];
+    __shared__ double wmin[BLOCK / 64];
     // The parameters live in registers, their state pointers redirected into
     // LDS: the compiler then sees those pointers address LDS and accesses
     // them with LDS instructions.
@@ -1511,6 +1564,8 @@ __global__ __launch_bounds__(BLOCK) void k_tiny(const Params *src, TinyLds L, in
         o.w = wall_at(sp, f, sp.wbase_wall[f >> 6], (int)(f & 63));
         o.act_w = (sp.bits_wall[f >> 5] >> (f & 31)) & 1u;
     }
+    int ran = K;
+    bool met = false;
     for (int it = 0; it < K; ++it) {
         const bool fst = first && it == 0;
         if (sp.dim == 2) {
@@ -1520,6 +1575,31 @@ __global__ __launch_bounds__(BLOCK) void k_tiny(const Params *src, TinyLds L, in
             if (fst) tiny_iteration<3, M_FIRST, BLOCK>(sp, len, o);
             else tiny_iteration<3, M_FUSED, BLOCK>(sp, len, o);
         }
+        if (every > 0 && ((it + 1) % every == 0 || it + 1 == K)) {
+            // (the iteration ended with a barrier: the records are complete)
+            const float4 *z = sp.zr_cur;
+            double best = INFINITY;
+            if (o.c.f >= 0)
+                best = pair_clearance(z[o.c.nd[0]], z[o.c.nd[1]], z[o.c.nd[2]], z[o.c.nd[3]], (double)sp.radii[o.c.i],
+                                      (double)sp.radii[o.c.j]);
+            if (o.w.f >= 0 && sp.dim == 2)
+                best = fmin(best, wall_clearance(z[o.w.na], z[o.w.nb], sp.walls[o.w.w], (double)sp.radii[o.w.i]));
+            for (int d = 32; d >= 1; d >>= 1) best = fmin(best, __shfl_xor(best, d));
+            if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = best;
+            __syncthreads();
+            double m = wmin[0];
+            for (int w = 1; w < BLOCK / 64; ++w) m = fmin(m, wmin[w]);
+            // (wmin is written again only after the next iteration's barriers)
+            if (m >= bar) {
+                ran = it + 1;
+                met = true;
+                break;
+            }
+        }
+    }
+    if (ctl && threadIdx.x == 0) {
+        ctl[0] += ran;
+        if (met) ctl[1] = 1;
     }
     tiny_bits(sp, o, BLOCK);
     // write the state back
@@ -1649,20 +1729,6 @@ __global__ __launch_bounds__(1024) void k_quality_sums(const float4 *zr, const f
     }
 }
 
-// squared distance from q to the segment [a, b] (planar)
-__device__ __forceinline__ double pt_seg2(double qx, double qy, double ax, double ay, double bx, double by) {
-    const double ex = bx - ax, ey = by - ay, ee = ex * ex + ey * ey;
-    double t = 0.0;
-    if (ee > 0.0) t = fmin(fmax(((qx - ax) * ex + (qy - ay) * ey) / ee, 0.0), 1.0);
-    const double vx = qx - (ax + t * ex), vy = qy - (ay + t * ey);
-    return vx * vx + vy * vy;
-}
-
-// twice the signed area of (a, b, c)
-__device__ __forceinline__ double cross3(double ax, double ay, double bx, double by, double cx, double cy) {
-    return (bx - ax) * (cy - ay) - (by - ay) * (cx - ax);
-}
-
 // rows (s, i) of the pair triangle, one per workgroup pass; lanes over j > i
 // and over the walls; one atomicMin per workgroup
 __global__ __launch_bounds__(256) void k_quality_clearance(const float4 *zr, const float *radii, const float4 *walls,
@@ -1675,34 +1741,11 @@ __global__ __launch_bounds__(256) void k_quality_clearance(const float4 *zr, con
         const int s = (int)(row / p), i = (int)(row % p);
         const float4 ai = zr[(long long)s * p + i], bi = zr[(long long)(s + 1) * p + i];
         const double ri = radii[i];
-        for (int j = i + 1 + (int)threadIdx.x; j < p; j += 256) {
-            const float4 aj = zr[(long long)s * p + j], bj = zr[(long long)(s + 1) * p + j];
-            // relative position at the interval's ends; closest approach over the interval
-            const double d0x = (double)aj.x - ai.x, d0y = (double)aj.y - ai.y, d0z = (double)aj.z - ai.z;
-            const double ex = ((double)bj.x - bi.x) - d0x, ey = ((double)bj.y - bi.y) - d0y,
-                         ez = ((double)bj.z - bi.z) - d0z;
-            const double ee = ex * ex + ey * ey + ez * ez;
-            double a = 0.0;
-            if (ee > 0.0) a = fmin(fmax(-(d0x * ex + d0y * ey + d0z * ez) / ee, 0.0), 1.0);
-            const double vx = d0x + a * ex, vy = d0y + a * ey, vz = d0z + a * ez;
-            best = fmin(best, sqrt(vx * vx + vy * vy + vz * vz) - (ri + (double)radii[j]));
-        }
-        if (dim == 2) {
-            for (int w = (int)threadIdx.x; w < W; w += 256) {
-                const float4 wl = walls[w];
-                const double px = ai.x, py = ai.y, qx = bi.x, qy = bi.y;
-                const double o1 = cross3(px, py, qx, qy, wl.x, wl.y), o2 = cross3(px, py, qx, qy, wl.z, wl.w);
-                const double o3 = cross3(wl.x, wl.y, wl.z, wl.w, px, py), o4 = cross3(wl.x, wl.y, wl.z, wl.w, qx, qy);
-                double d2;
-                if (o1 * o2 < 0.0 && o3 * o4 < 0.0) {
-                    d2 = 0.0; // proper crossing
-                } else {
-                    d2 = fmin(fmin(pt_seg2(px, py, wl.x, wl.y, wl.z, wl.w), pt_seg2(qx, qy, wl.x, wl.y, wl.z, wl.w)),
-                              fmin(pt_seg2(wl.x, wl.y, px, py, qx, qy), pt_seg2(wl.z, wl.w, px, py, qx, qy)));
-                }
-                best = fmin(best, sqrt(d2) - ri);
-            }
-        }
+        for (int j = i + 1 + (int)threadIdx.x; j < p; j += 256)
+            best = fmin(best, pair_clearance(ai, bi, zr[(long long)s * p + j], zr[(long long)(s + 1) * p + j], ri,
+                                             (double)radii[j]));
+        if (dim == 2)
+            for (int w = (int)threadIdx.x; w < W; w += 256) best = fmin(best, wall_clearance(ai, bi, walls[w], ri));
     }
     for (int d = 32; d >= 1; d >>= 1) best = fmin(best, __shfl_xor(best, d));
     if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = best;
@@ -1982,9 +2025,11 @@ twa_status prepare_tiny(twa_solver *s) {
     c.step = c.step_prev = s->alpha / s->rho0;
     c.dbg_x = nullptr;
     c.dbg_rho = nullptr;
-    const int bins[3] = {0, 1, 0}; // bin_start {0, 1}, bin_items {0}
+    // bin_start {0, 1}, bin_items {0}; then the two control words of k_tiny's
+    // clearance check (twa_iterate_until)
+    const int bins[5] = {0, 1, 0, 0, 0};
     TRY(dev_alloc(s, &s->tiny_params, 1));
-    TRY(dev_alloc(s, &s->tiny_bins, 3));
+    TRY(dev_alloc(s, &s->tiny_bins, 5));
     HIP_TRY(s, hipMemcpyAsync(s->tiny_params, &c, sizeof(Params), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(s, hipMemcpyAsync(s->tiny_bins, bins, sizeof(bins), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(s, hipStreamSynchronize(s->stream)); // the sources are on this stack
@@ -2000,7 +2045,7 @@ twa_status iterate_tiny(twa_solver *s, int k) {
         const int n = std::min(k, kTinyChunk);
         if (resident)
             hipLaunchKernelGGL(k_tiny<kTinyBlock>, dim3(1), dim3(kTinyBlock), L.total, s->stream,
-                               (const Params *)s->tiny_params, L, n, s->pending ? 0 : 1);
+                               (const Params *)s->tiny_params, L, n, s->pending ? 0 : 1, 0, 0.0, (int *)nullptr);
         else
             hipLaunchKernelGGL(k_batch<kTinyBlock>, dim3(1), dim3(kTinyBlock), 0, s->stream,
                                (const Params *)s->tiny_params, (const int *)s->tiny_bins,
@@ -2648,6 +2693,53 @@ twa_status twa_iterate(twa_solver *s, int k) {
     TRY(check_alive(s));
     if (k < 0) return fail(s, TWA_E_INVALID, "k must be >= 0");
     return iterate_impl(s, k, false);
+}
+
+twa_status twa_iterate_until(twa_solver *s, int max_iter, int every, double min_clearance, int *done, int *met) {
+    TRY(check_alive(s));
+    if (!done || !met) return fail(s, TWA_E_INVALID, "null done or met");
+    *done = 0;
+    *met = 0;
+    if (max_iter < 0 || every < 1 || std::isnan(min_clearance))
+        return fail(s, TWA_E_INVALID, "max_iter >= 0, every >= 1 and a clearance bar required");
+    if (max_iter == 0) return TWA_OK;
+    TinyLds L;
+    const bool settled = s->iter >= s->n_warm && (!s->pending || s->iter - 1 >= s->n_warm);
+    if (s->tiny_params && settled && !s->dbg_rho && !s->adj_pool && !s->tape.ok && every <= kTinyChunk &&
+        tiny_layout(s, &L)) {
+        // the whole call on the device: launches of whole blocks of `every`
+        // iterations, each stopping at the first check that meets the bar
+        int *ctl = s->tiny_bins + 3;
+        HIP_TRY(s, hipMemsetAsync(ctl, 0, 2 * sizeof(int), s->stream));
+        const int chunk = kTinyChunk / every * every;
+        for (int left = max_iter, first = s->pending ? 0 : 1; left > 0; first = 0) {
+            const int n = std::min(left, chunk);
+            hipLaunchKernelGGL(k_tiny<kTinyBlock>, dim3(1), dim3(kTinyBlock), L.total, s->stream,
+                               (const Params *)s->tiny_params, L, n, first, every, min_clearance, ctl);
+            HIP_TRY(s, hipGetLastError());
+            left -= n;
+        }
+        int h[2];
+        HIP_TRY(s, hipMemcpyAsync(h, ctl, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(s, hipStreamSynchronize(s->stream));
+        s->iter += h[0];
+        s->pending = true;
+        *done = h[0];
+        *met = h[1];
+        return TWA_OK;
+    }
+    while (*done < max_iter) {
+        const int n = std::min(every, max_iter - *done);
+        TRY(iterate_impl(s, n, false));
+        *done += n;
+        double clr;
+        TRY(twa_get_quality(s, nullptr, &clr, nullptr));
+        if (clr >= min_clearance) {
+            *met = 1;
+            break;
+        }
+    }
+    return TWA_OK;
 }
 
 twa_status twa_iterate_timed(twa_solver *s, int k, double *kernel_ms) {

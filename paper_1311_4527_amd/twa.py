@@ -116,6 +116,9 @@ def load_library():
     lib.twa_set_schedule.argtypes = [_vp, ct.c_float, ct.c_int]
     lib.twa_iterate.restype = ct.c_int
     lib.twa_iterate.argtypes = [_vp, ct.c_int]
+    lib.twa_iterate_until.restype = ct.c_int
+    lib.twa_iterate_until.argtypes = [_vp, ct.c_int, ct.c_int, ct.c_double, ct.POINTER(ct.c_int),
+                                      ct.POINTER(ct.c_int)]
     lib.twa_iterate_timed.restype = ct.c_int
     lib.twa_iterate_timed.argtypes = [_vp, ct.c_int, ct.POINTER(ct.c_double)]
     lib.twa_get_trajectories.restype = ct.c_int
@@ -259,6 +262,15 @@ class Solver:
 
     def twa_iterate(self, k: int):
         self._check(load_library().twa_iterate(self.h, int(k)))
+
+    def twa_iterate_until(self, max_iter: int, every: int, min_clearance: float):
+        """Up to max_iter iterations in blocks of `every`, stopping after the
+        first block whose smallest clearance is >= min_clearance; returns
+        (iterations run, whether the bar was met)."""
+        done, met = ct.c_int(), ct.c_int()
+        self._check(load_library().twa_iterate_until(self.h, int(max_iter), int(every), float(min_clearance),
+                                                     ct.byref(done), ct.byref(met)))
+        return done.value, bool(met.value)
 
     def twa_iterate_timed(self, k: int):
         """k iterations with HIP events around each launch; returns the summed

@@ -6,8 +6,9 @@ without any two agents colliding while moving there at constant velocity
 and the next epoch starts from there.  One solver created with TWA_F_VO
 (eta = 1) serves every epoch: each epoch loads its start and reference end
 positions (twa_set_endpoints) and iterates until the device's clearance
-measure (twa_get_quality) says the plan is collision-free; this module only
-drives the epochs.
+measure says the plan is collision-free (twa_iterate_until: for a small
+instance the whole epoch, checks included, is one persistent launch); this
+module only drives the epochs.
 """
 from __future__ import annotations
 
@@ -108,14 +109,8 @@ class VOPlanner:
         # collision-free at the planning radii up to FP32 rounding of the
         # positions (relative 5e-6, inside what the solver accepts as starts)
         tol = -1e-5 * float(self.plan_radii.min())
-        done, self.last_iterations = 0, 0
-        while done < self.iters:
-            n = min(self.check, self.iters - done)
-            S.twa_iterate(n)
-            done += n
-            if S.twa_get_quality()["min_clearance"] >= tol:
-                self.last_iterations = done
-                break
+        done, met = S.twa_iterate_until(self.iters, self.check, tol)
+        self.last_iterations = done if met else 0
         return S.twa_get_trajectories()[:, 1].cpu().numpy().astype(np.float64)
 
     def close(self):

@@ -118,3 +118,69 @@ def test_tiny_vo_epoch_equals_plain():
     assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb)
     A.close()
     B.close()
+
+
+def _until_by_blocks(S, max_iter, every, bar):
+    """The stopping rule of twa_iterate_until, from the host."""
+    done = 0
+    while done < max_iter:
+        n = min(every, max_iter - done)
+        S.twa_iterate(n)
+        done += n
+        if S.twa_get_quality()["min_clearance"] >= bar:
+            return done, True
+    return done, False
+
+
+def _vo12():
+    return I.circle_swap(12, 0.05, 1, seed=5, alpha=0.1, C=0.05)
+
+
+UNTIL = [
+    # (instance, flags, every, max_iter, bar): a VO epoch (stops partway), the
+    # bar met at the first check, never met, a call longer than one launch
+    # (4096 iterations) with a short last block, walls, an instance whose state
+    # does not fit in LDS (host-driven blocks) and one too large for the
+    # one-workgroup path
+    ("vo12", "vo", 50, 20000, -5e-7),
+    ("swap8_2d", 0, 30, 700, -float("inf")),
+    ("swap8_2d", 0, 30, 700, float("inf")),
+    ("swap8_2d", 0, 50, 5010, float("inf")),
+    ("box8_walls", 0, 25, 1000, -1e-6),
+    ("pair_eta250", 0, 40, 300, -1e-6),
+    ("box16", 0, 20, 200, -1e-6),
+]
+
+
+@pytest.mark.parametrize("case,flags,every,max_iter,bar", UNTIL)
+def test_iterate_until_equals_host_blocks(case, flags, every, max_iter, bar):
+    import torch
+    from paper_1311_4527_amd.twa import Solver, TWA_F_VO
+    make = {"vo12": _vo12, "box16": lambda: I.conf_box1024(seed=6, p=16, eta=4, n_walls=4), **CASES}[case]
+    fl = TWA_F_VO if flags == "vo" else flags
+    inst = make()
+    A = Solver.from_instance(inst, flags=fl)
+    B = Solver.from_instance(inst, flags=fl)
+    A.twa_iterate(7)  # a pending state carried into the call
+    B.twa_iterate(7)
+    got = A.twa_iterate_until(max_iter, every, bar)
+    want = _until_by_blocks(B, max_iter, every, bar)
+    print(case, got, want, flush=True)
+    assert got == want
+    za, ua, la, ia = _state(A)
+    zb, ub, lb, ib = _state(B)
+    assert ia == ib == 7 + got[0]
+    assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb)
+    assert A.twa_get_stats() == B.twa_get_stats()
+    A.close()
+    B.close()
+
+
+def test_iterate_until_rejects_bad_arguments():
+    from paper_1311_4527_amd.twa import Solver, TWAError
+    S = Solver.from_instance(I.conf_small(0))
+    for args in [(-1, 10, 0.0), (10, 0, 0.0), (10, 5, float("nan"))]:
+        with pytest.raises(TWAError):
+            S.twa_iterate_until(*args)
+    assert S.twa_iterate_until(0, 5, 0.0) == (0, False)
+    S.close()
