@@ -1424,11 +1424,10 @@ __device__ __forceinline__ void tiny_redirect(Params &P, char *b, const TinyLds 
     P.qcnt = reinterpret_cast<int *>(b + L.off[TA_QCNT]);
 }
 
-// The factors a lane of k_tiny owns for the whole launch: collision factor
-// t (lane t < Fc) and wall factor t - c0 (c0 = Fc rounded up to whole waves),
-// decoded once; act: the factor was active in the last iteration (its
-// activity bit, kept in a register between iterations), ever: active in some
-// iteration of the launch.
+// The factors a lane of k_tiny owns for the whole launch (a collision factor
+// on waves 0-3, a wall factor on waves 4-7), decoded once; act: the factor
+// was active in the last iteration (its activity bit, kept in a register
+// between iterations), ever: active in some iteration of the launch.
 struct TinyOwn {
     CollAt c;
     WallAt w;
@@ -1485,9 +1484,9 @@ __device__ __forceinline__ void tiny_iteration(const Params &P, int *len, TinyOw
         o.act_w = act;
         o.ever_w = o.ever_w || act;
     }
-    // per-segment and fixed factors on the waves after the owners'
+    // per-segment and fixed factors from wave 4 on (beside the collision owners)
     auto round64 = [](long long n) { return (int)((std::min<long long>(n, BLOCK) + 63) / 64 * 64); };
-    const int shift_e = (round64(P.Fc) + round64(P.Fw)) % BLOCK, shift_f = (shift_e + round64(P.Fe)) % BLOCK;
+    const int shift_e = 256 % BLOCK, shift_f = (shift_e + round64(P.Fe)) % BLOCK;
     const int te = (threadIdx.x + BLOCK - shift_e) % BLOCK, tf = (threadIdx.x + BLOCK - shift_f) % BLOCK;
     for (long long f = te; f < P.Fe; f += BLOCK) energy_stream<D, MODE>(P, Z, f);
     for (long long f = tf; f < P.Ff; f += BLOCK) fixed_stream<D, MODE>(P, Z, f);
@@ -1529,6 +1528,7 @@ __device__ __forceinline__ void tiny_bits(const Params &P, const TinyOwn &o, int
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_tiny(const Params *src, TinyLds L, int K, int first, int every, double bar,
                                                 int *ctl) {
+    static_assert(BLOCK == 512, "the owner lanes take waves 0-3 and 4-7");
     if (ctl && ctl[1]) return;
     extern __shared__ __align__(16) char lds[];
     __shared__ int len[2];
@@ -1554,13 +1554,16 @@ __global__ __launch_bounds__(BLOCK) void k_tiny(const Params *src, TinyLds L, in
     tiny_redirect(sp, lds, L);
     TinyOwn o;
     o.c.f = o.w.f = -1;
-    const long long c0 = ((long long)sp.Fc + 63) & ~63LL;
-    if (threadIdx.x < sp.Fc) {
-        o.c = coll_at(sp, threadIdx.x);
+    // collision factors spread over waves 0-3 (one per SIMD), wall factors
+    // over waves 4-7, ceil(F / 4) lanes of each (F <= 256)
+    const int wv = (int)(threadIdx.x >> 6), ln = (int)(threadIdx.x & 63);
+    const int per_c = (int)((sp.Fc + 3) / 4), per_w = (int)((sp.Fw + 3) / 4);
+    if (wv < 4 && ln < per_c && wv * per_c + ln < sp.Fc) {
+        o.c = coll_at(sp, wv * per_c + ln);
         const int r = o.c.j - o.c.i - 1;
         o.act_c = (sp.bits_coll[(long long)o.c.s * sp.cps + sp.rowchunk[o.c.i] + (r >> 6)] >> (r & 63)) & 1ull;
-    } else if (threadIdx.x >= c0 && threadIdx.x - c0 < sp.Fw) {
-        const long long f = threadIdx.x - c0;
+    } else if (wv >= 4 && ln < per_w && (wv - 4) * per_w + ln < sp.Fw) {
+        const long long f = (wv - 4) * per_w + ln;
         o.w = wall_at(sp, f, sp.wbase_wall[f >> 6], (int)(f & 63));
         o.act_w = (sp.bits_wall[f >> 5] >> (f & 31)) & 1u;
     }
