@@ -348,6 +348,7 @@ def run_vo(p=16, r=0.05):
     pos = np.stack([np.cos(ang), np.sin(ang)], 1)
     V = VOPlanner(pos, -pos, np.full(p, r), tau=1.0, fraction=0.5, vmax=0.25)
     V.solve_epoch()  # warm
+    warm = V.last_iterations
     times, its = [], []
     for _ in range(200):
         if V.arrived():
@@ -361,7 +362,8 @@ def run_vo(p=16, r=0.05):
     t = np.array(times)
     conv = [n for n in its if n > 0]
     return dict(p=p, r=r, epochs=len(times), arrived=V.arrived(), epochs_at_cap=len(its) - len(conv),
-                iterations_median=float(np.median(conv)) if conv else None,
+                iterations_median=float(np.median(conv)) if conv else None, iterations_total=int(sum(conv)),
+                warm_iterations=int(warm),
                 epoch_ms_median=float(np.median(t) * 1e3), epoch_ms_p90=float(np.percentile(t, 90) * 1e3),
                 epoch_ms_max=float(t.max() * 1e3))
 
