@@ -2712,19 +2712,24 @@ twa_status twa_iterate_until(twa_solver *s, int max_iter, int every, double min_
         tiny_layout(s, &L)) {
         // the whole call on the device: launches of whole blocks of `every`
         // iterations, each stopping at the first check that meets the bar
+        // (a launch after that returns at once); the host reads the outcome
+        // after every 8 launches, so a large max_iter queues no more launches
+        // than that beyond the one that met the bar
         int *ctl = s->tiny_bins + 3;
         HIP_TRY(s, hipMemsetAsync(ctl, 0, 2 * sizeof(int), s->stream));
         const int chunk = kTinyChunk / every * every;
-        for (int left = max_iter, first = s->pending ? 0 : 1; left > 0; first = 0) {
-            const int n = std::min(left, chunk);
-            hipLaunchKernelGGL(k_tiny<kTinyBlock>, dim3(1), dim3(kTinyBlock), L.total, s->stream,
-                               (const Params *)s->tiny_params, L, n, first, every, min_clearance, ctl);
-            HIP_TRY(s, hipGetLastError());
-            left -= n;
+        int left = max_iter, first = s->pending ? 0 : 1, h[2] = {0, 0};
+        while (left > 0 && !h[1]) {
+            for (int l = 0; l < 8 && left > 0; ++l, first = 0) {
+                const int n = std::min(left, chunk);
+                hipLaunchKernelGGL(k_tiny<kTinyBlock>, dim3(1), dim3(kTinyBlock), L.total, s->stream,
+                                   (const Params *)s->tiny_params, L, n, first, every, min_clearance, ctl);
+                HIP_TRY(s, hipGetLastError());
+                left -= n;
+            }
+            HIP_TRY(s, hipMemcpyAsync(h, ctl, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+            HIP_TRY(s, hipStreamSynchronize(s->stream));
         }
-        int h[2];
-        HIP_TRY(s, hipMemcpyAsync(h, ctl, sizeof(h), hipMemcpyDeviceToHost, s->stream));
-        HIP_TRY(s, hipStreamSynchronize(s->stream));
         s->iter += h[0];
         s->pending = true;
         *done = h[0];

@@ -146,6 +146,7 @@ UNTIL = [
     ("swap8_2d", 0, 30, 700, -float("inf")),
     ("swap8_2d", 0, 30, 700, float("inf")),
     ("swap8_2d", 0, 50, 5010, float("inf")),
+    ("swap8_2d", 0, 1000, 40000, float("inf")),  # more than one group of 8 launches
     ("box8_walls", 0, 25, 1000, -1e-6),
     ("pair_eta250", 0, 40, 300, -1e-6),
     ("box16", 0, 20, 200, -1e-6),
