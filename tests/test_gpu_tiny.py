@@ -148,6 +148,8 @@ UNTIL = [
     ("swap8_2d", 0, 50, 5010, float("inf")),
     ("swap8_2d", 0, 1000, 40000, float("inf")),  # more than one group of 8 launches
     ("box8_walls", 0, 25, 1000, -1e-6),
+    ("swap6_3d", 0, 30, 900, -1e-6),
+    ("swap8_2d", 1, 40, 2000, -1e-6),  # dense form
     ("pair_eta250", 0, 40, 300, -1e-6),
     ("box16", 0, 20, 200, -1e-6),
 ]
