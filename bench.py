@@ -368,6 +368,31 @@ def run_vo(p=16, r=0.05):
                 epoch_ms_max=float(t.max() * 1e3))
 
 
+def run_sizes(sizes=(256, 512, 1024, 2048), steps=200, warmup=300):
+    """The benchmark's random box (eta = 16, 32 walls, r = 0.005) at other
+    agent counts: whole-iteration throughput, dense and activity bits, in the
+    steady state (warmup iterations first), with the dominant kernel's
+    roofline fraction (algorithmic bytes or operations of that size; the
+    counter traffic is measured for 1024 agents only)."""
+    from paper_1311_4527_amd import instances as I
+    out = []
+    for p in sizes:
+        inst = I.conf_box1024(p=p)
+        F = inst.counts()["factors"]
+        row = dict(p=p, factors=F)
+        for variant in ("dense", "skip"):
+            r = run_gpu(inst, variant == "dense", steps, warmup)
+            avg = [m / steps for m in r["kernel_ms"]]
+            roof = roofline(inst, variant, avg, r["stats"])
+            row[variant] = dict(value=F * steps / r["seconds"], ms_per_step=1e3 * r["seconds"] / steps,
+                                kernel=roof["kernel"], bound=roof["bound"], frac=roof["frac"],
+                                avg_us=roof["avg_us"])
+        print(f"# p={p}: dense {row['dense']['value']:.4g}, skip {row['skip']['value']:.4g} factor-updates/s",
+              file=sys.stderr, flush=True)
+        out.append(row)
+    return out
+
+
 def run_adjoint(K=500):
     """Forward K iterations alone, then forward with the start remembered plus
     the adjoint on the p=256, eta=8 swap.  The TAPE solver's first backward
@@ -521,7 +546,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (for hardware-counter scaling)")
-    ap.add_argument("--leg", choices=["batched", "adjoint", "vo"], default=None,
+    ap.add_argument("--leg", choices=["batched", "adjoint", "vo", "sizes"], default=None,
                     help="only run one side leg, without its comparison runs (for profiling)")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -548,6 +573,9 @@ def main():
         return
     if args.leg == "vo":
         print(json.dumps(run_vo()), flush=True)
+        return
+    if args.leg == "sizes":
+        print(json.dumps(run_sizes()), flush=True)
         return
     inst = workload(args.workload)
     c = inst.counts()
