@@ -480,7 +480,7 @@ def cpu_baseline(inst, budget_s=8.0):
                sample=f"{n} reference iterations on {cores} threads (after 1 untimed) of the same p=1024, eta=16, "
                       f"32-wall instance from its straight-line start, {dt:.1f} s wall; and {n1} iterations on "
                       f"one thread, {dt1:.1f} s",
-               cpu_model=cpu_model(), single_thread=dict(value=F * n1 / dt1, unit="factor-updates/s", cores=1,
+               cpu_model=cpu_model(), host_threads=os.cpu_count(), single_thread=dict(value=F * n1 / dt1, unit="factor-updates/s", cores=1,
                                                          iterations=n1, seconds=dt1))
     # the two small circle swaps and one free agent, beside the GPU's small_workloads leg
     small = {}

@@ -278,3 +278,31 @@ def test_forward_tape_outgrown_falls_back():
         assert np.allclose(a, b, rtol=1e-4, atol=1e-4 * scale), (name, np.abs(a - b).max(), scale)
     S.close()
     F.close()
+
+
+def test_iterate_until_with_a_forward_tape():
+    """twa_iterate_until on a solver that records a forward tape runs its
+    blocks through the taped iteration (checkpoints every 32 iterations
+    across blocks of 25), and the backward over that run equals the one of a
+    plain run of the same length."""
+    import torch
+    from paper_1311_4527_amd.twa import Solver, TWA_F_TAPE
+    inst = _sub(radius=0.3)
+    v = np.random.default_rng(5).normal(size=inst.z0.shape)
+    S, _ = _tape_solver(inst, 40, v)
+    S.twa_set_init(inst.z0)
+    done, met = S.twa_iterate_until(400, 25, -1e-6)
+    print("until", done, met, flush=True)
+    assert 0 < done <= 400 and (met or done == 400)
+    assert S.twa_get_stats()["tape_checkpoints"] == (done + 31) // 32
+    F = Solver.from_instance(inst, flags=TWA_F_TAPE)
+    F.twa_iterate(done)
+    assert torch.equal(S.twa_get_trajectories(), F.twa_get_trajectories())
+    vt = torch.from_numpy(v.astype(np.float32))
+    got = [t.cpu().numpy().astype(np.float64) for t in S.twa_backward(vt)]
+    want = [t.cpu().numpy().astype(np.float64) for t in F.twa_backward(vt)]
+    for name, a, b in zip(("dx0", "dxT", "dr", "dz0"), got, want):
+        scale = max(np.abs(b).max(), 1e-30)
+        assert np.allclose(a, b, rtol=1e-4, atol=1e-4 * scale), (name, np.abs(a - b).max(), scale)
+    S.close()
+    F.close()
