@@ -162,12 +162,23 @@ __device__ __forceinline__ void contribute(const Params &P, long long node, int 
 // handed from the minimiser to the wave-level sum below.
 struct Contrib {
     int n = 0;         // nodes contributed to (0, 2 or 4)
+    unsigned skip = 0; // slot k is left out where bit k is set (fixed_node)
     long long nd[4];
     float m[4][3];
 };
 
+// Break-point s of every agent is a fixed start or goal: its fixed factor
+// sends weight infinity in every iteration (App. B step 5 then takes z from
+// that edge alone), so an ordinary (rho0) contribution to such a node never
+// enters z, its <-rho or the adjoint's mean sets and is not made.  Standard
+// ADMM sends rho0 from the fixed factors too; a VO epoch's reference end is
+// soft.
+__device__ __forceinline__ bool fixed_node(const Params &P, int s) {
+    return !P.admm && (s == 0 || (s == P.eta && !P.vo));
+}
+
 // Contributions of every lane of a wave (all lanes call it; lanes with
-// k >= c.n give nothing).  Slots 0 and 1 are agent i's nodes (s, i) and
+// k >= c.n, or with slot k skipped, give nothing).  Slots 0 and 1 are agent i's nodes (s, i) and
 // (s+1, i), which the queued collision factors of one pair-row chunk, and
 // the wall factors of one agent and interval, share: there the lanes with
 // the same node are summed across the wave first, so the node takes one
@@ -180,7 +191,7 @@ template <bool GROUP>
 __device__ __forceinline__ void contribute_wave(const Params &P, const Contrib &c, int D) {
     const int lane = __lane_id();
     for (int k = 0; k < 4; ++k) {
-        bool pred = k < c.n;
+        bool pred = k < c.n && !((c.skip >> k) & 1u);
         if (__ballot(pred) == 0ull) continue;
         const long long node = pred ? c.nd[k] : -1;
         long long q[3] = {0, 0, 0};
@@ -683,8 +694,8 @@ __device__ __forceinline__ void energy_stream(const Params &P, const Rec &Z, lon
     const bool send = segment_prox<D>(P, C, n, ka, kb, P.rho, x);
     if (send) {
         for (int q = 0; q < 2 * D; ++q) m[q] = x[q] + u[q];
-        contribute(P, na, 0, m, D);
-        contribute(P, nb, 0, m + D, D);
+        if (!fixed_node(P, s)) contribute(P, na, 0, m, D);
+        if (!fixed_node(P, s + 1)) contribute(P, nb, 0, m + D, D);
     }
     if (P.dbg_rho) {
         long long e0 = P.e_energy + 2 * f;
@@ -846,6 +857,7 @@ __device__ __forceinline__ bool coll_minimise(const Params &P, const Rec &Z, con
         for (int q = 0; q < 4; ++q) w[q] = wval(k[q], P.rho);
         coll_prox<D>(n, w, k, R, x);
         out.n = 4;
+        out.skip = (fixed_node(P, s) ? 5u : 0u) | (fixed_node(P, s + 1) ? 10u : 0u);
         for (int q = 0; q < 4; ++q) {
             out.nd[q] = nd[q];
             for (int c = 0; c < D; ++c) out.m[q][c] = x[q * D + c] + u[q * D + c];
@@ -858,7 +870,7 @@ __device__ __forceinline__ bool coll_minimise(const Params &P, const Rec &Z, con
     } else {
         for (int q = 0; q < 4 * D; ++q) x[q] = n[q];
         if (P.admm) {
-            // standard ADMM: x = n still carries weight rho0
+            // standard ADMM: x = n still carries weight rho0 (no fixed nodes)
             out.n = 4;
             for (int q = 0; q < 4; ++q) {
                 out.nd[q] = nd[q];
@@ -963,6 +975,7 @@ __device__ __forceinline__ bool wall_minimise(const Params &P, const Rec &Z, con
         // (standard ADMM: x = n still carries weight rho0)
         P.x_wall[f] = make_float4(x0.x, x0.y, x1.x, x1.y);
         out.n = 2;
+        out.skip = (fixed_node(P, a.s) ? 1u : 0u) | (fixed_node(P, a.s + 1) ? 2u : 0u);
         out.nd[0] = na, out.nd[1] = nb;
         out.m[0][0] = x0.x + u.x, out.m[0][1] = x0.y + u.y;
         out.m[1][0] = x1.x + u.z, out.m[1][1] = x1.y + u.w;
