@@ -545,11 +545,14 @@ __device__ __forceinline__ void coll_flat(const Params &P, const Rec &Z, long lo
     for (int k = 0; k < U; ++k) push(P.qc, qlen, q[k], val[k]);
 }
 
-// Where wall factor f sits: (s, i, wall), its two node records.
+// Where wall factor f sits: (s, i, wall), its two node records, the wall's
+// end points and agent i's radius.
 struct WallAt {
     long long f;
     int s, i, w;
     long long na, nb;
+    float4 wl;
+    float r;
 };
 
 __device__ __forceinline__ WallAt wall_at(const Params &P, long long f, unsigned long long pk, int k) {
@@ -559,6 +562,8 @@ __device__ __forceinline__ WallAt wall_at(const Params &P, long long f, unsigned
     advance_wall(P.p, P.W, k, a.s, a.i, a.w);
     a.na = (long long)a.s * P.p + a.i;
     a.nb = a.na + P.p;
+    a.wl = P.walls[a.w];
+    a.r = P.radii[a.i];
     return a;
 }
 
@@ -570,9 +575,9 @@ __device__ __forceinline__ bool wall_test(const Params &P, const Rec &Z, const W
     const bool dense = P.dense != 0;
     const long long f = a.f;
     bool push_prev = false, push_new = false;
-    float4 wl = P.walls[a.w];
+    const float4 wl = a.wl;
     f2 xa = mk(wl.x, wl.y), xb = mk(wl.z, wl.w);
-    float r = P.radii[a.i];
+    const float r = a.r;
     float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
     bool check_cur = true;
     if (MODE == M_FIRST) {
@@ -816,7 +821,7 @@ __device__ __forceinline__ CollAt coll_at(const Params &P, long long f) {
 // SET_BITS: mark the factor active in its chunk's activity word.
 template <int D, int MODE, bool SET_BITS = true>
 __device__ __forceinline__ bool coll_minimise(const Params &P, const Rec &Z, const CollAt &c, bool prev, float *nout,
-                                              Contrib &out) {
+                                              Contrib &out, const float4 *rc_in = nullptr) {
     const bool dense = P.dense != 0;
     const long long f = c.f;
     const int s = c.s, i = c.i, j = c.j;
@@ -825,8 +830,9 @@ __device__ __forceinline__ bool coll_minimise(const Params &P, const Rec &Z, con
     float u[4 * D], zc[4 * D], n[4 * D], x[4 * D], w[4];
     int k[4];
     float4 rc[4];
+    // rc_in: the four current records as the caller already loaded them
     for (int q = 0; q < 4; ++q) {
-        rc[q] = Z.cur[nd[q]];
+        rc[q] = rc_in ? rc_in[q] : Z.cur[nd[q]];
         node_xyz(rc[q], zc + q * D, D);
         k[q] = wcode(rc[q]);
     }
@@ -936,8 +942,8 @@ __device__ __forceinline__ bool wall_minimise(const Params &P, const Rec &Z, con
     const bool writer = piece <= 0;
     const bool dense = P.dense != 0;
     const long long f = a.f, na = a.na, nb = a.nb;
-    float4 wl = P.walls[a.w];
-    Capsule Cw{mk(wl.x, wl.y), mk(wl.z, wl.w), P.radii[a.i]};
+    const float4 wl = a.wl;
+    Capsule Cw{mk(wl.x, wl.y), mk(wl.z, wl.w), a.r};
     float4 ca = Z.cur[na], cb = Z.cur[nb];
     int ka = wcode(ca), kb = wcode(cb);
     float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1474,7 +1480,7 @@ __device__ __forceinline__ void tiny_iteration(const Params &P, int *len, TinyOw
             unsigned val;
             if (dense) q = coll_factor<D, MODE, true>(P, o.c.f, o.c.R, rc, rp, u, 0ull, 0, &val);
             else q = coll_factor<D, MODE, false>(P, o.c.f, o.c.R, rc, rp, u, o.act_c ? 1ull : 0ull, 0, &val);
-            if (q) act = coll_minimise<D, MODE, false>(P, Z, o.c, (val & kPrev) != 0, n, out);
+            if (q) act = coll_minimise<D, MODE, false>(P, Z, o.c, (val & kPrev) != 0, n, out, rc);
         }
         count_wave(&len[0], q);
         contribute_wave<false>(P, out, D);
@@ -1599,7 +1605,7 @@ __global__ __launch_bounds__(BLOCK) void k_tiny(const Params *src, TinyLds L, in
                 best = pair_clearance(z[o.c.nd[0]], z[o.c.nd[1]], z[o.c.nd[2]], z[o.c.nd[3]], (double)sp.radii[o.c.i],
                                       (double)sp.radii[o.c.j]);
             if (o.w.f >= 0 && sp.dim == 2)
-                best = fmin(best, wall_clearance(z[o.w.na], z[o.w.nb], sp.walls[o.w.w], (double)sp.radii[o.w.i]));
+                best = fmin(best, wall_clearance(z[o.w.na], z[o.w.nb], o.w.wl, (double)o.w.r));
             for (int d = 32; d >= 1; d >>= 1) best = fmin(best, __shfl_xor(best, d));
             if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = best;
             __syncthreads();
