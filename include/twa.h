@@ -195,8 +195,9 @@ twa_status twa_set_schedule(twa_solver *s, float rho0_init, int n_warm);
 /* Run k >= 0 iterations (App. B steps 1-7), asynchronously.  Iterations at
  * the steady rho0 are replayed from HIP graphs of 32, 16, ..., 1 iterations
  * (captured together the first time, so any k replays); an instance of at
- * most 256 collision + wall factors runs them in one persistent
- * single-workgroup launch instead (bitwise the same iterations). */
+ * most 256 collision + wall factors (or 512 collision factors and no walls)
+ * runs them in one persistent single-workgroup launch instead (bitwise the
+ * same iterations). */
 twa_status twa_iterate(twa_solver *s, int k);
 
 /* Iterate until the plan is collision-free: up to max_iter >= 0 iterations
@@ -206,8 +207,8 @@ twa_status twa_iterate(twa_solver *s, int k);
  * >= min_clearance (the stopping rule of a velocity-obstacle epoch, Sec. 5).
  * Writes the iterations run to *done (host int) and 1 to *met (host int) if
  * the bar was met, else 0.  The iterations and the clearance are those of
- * twa_iterate followed by twa_get_quality, bitwise.  A tiny instance (at most
- * 256 collision + wall factors, state within 56 KiB of LDS, at the steady
+ * twa_iterate followed by twa_get_quality, bitwise.  A tiny instance (as for
+ * twa_iterate's single-workgroup launch, state within 56 KiB of LDS, at the steady
  * rho0, no forward tape) runs the whole call on the device, the clearance
  * taken inside the persistent launch, and synchronises once; otherwise each
  * block is launched and checked from the host.  TWA_E_INVALID for a null

@@ -1444,7 +1444,8 @@ __device__ __forceinline__ void tiny_redirect(Params &P, char *b, const TinyLds 
 }
 
 // The factors a lane of k_tiny owns for the whole launch (a collision factor
-// on waves 0-3, a wall factor on waves 4-7), decoded once; act: the factor
+// on waves 0-3, or 0-7 for more than 256 of them, a wall factor on waves
+// 4-7), decoded once; act: the factor
 // was active in the last iteration (its activity bit, kept in a register
 // between iterations), ever: active in some iteration of the launch.
 struct TinyOwn {
@@ -1574,10 +1575,12 @@ __global__ __launch_bounds__(BLOCK) void k_tiny(const Params *src, TinyLds L, in
     TinyOwn o;
     o.c.f = o.w.f = -1;
     // collision factors spread over waves 0-3 (one per SIMD), wall factors
-    // over waves 4-7, ceil(F / 4) lanes of each (F <= 256)
+    // over waves 4-7, ceil(F / 4) lanes of each (F <= 256); more than 256
+    // collision factors (no walls then) over all eight waves
     const int wv = (int)(threadIdx.x >> 6), ln = (int)(threadIdx.x & 63);
-    const int per_c = (int)((sp.Fc + 3) / 4), per_w = (int)((sp.Fw + 3) / 4);
-    if (wv < 4 && ln < per_c && wv * per_c + ln < sp.Fc) {
+    const int wc = sp.Fc > 256 ? 8 : 4;
+    const int per_c = (int)((sp.Fc + wc - 1) / wc), per_w = (int)((sp.Fw + 3) / 4);
+    if (wv < wc && ln < per_c && wv * per_c + ln < sp.Fc) {
         o.c = coll_at(sp, wv * per_c + ln);
         const int r = o.c.j - o.c.i - 1;
         o.act_c = (sp.bits_coll[(long long)o.c.s * sp.cps + sp.rowchunk[o.c.i] + (r >> 6)] >> (r & 63)) & 1ull;
@@ -1998,13 +2001,17 @@ bool capture_graphs(twa_solver *s) {
     return ok;
 }
 
-// Instances this small (collision + wall factors) run untimed iterations
-// in the persistent batched kernel, one workgroup, all iterations of a call
-// in one launch: three launches per iteration would cost more than the work.
+// Instances this small (at most 256 collision + wall factors, or 512
+// collision factors and no walls: one factor per lane of a 512-lane
+// workgroup) run untimed iterations in one workgroup, all iterations of a
+// call in one launch: three launches per iteration would cost more than the
+// work.
 constexpr long long kTinyFactors = 256;
 constexpr int kTinyBlock = 512, kTinyChunk = 4096; // iterations per launch at most
 
-bool tiny(const twa_solver *s) { return s->P.Fc + s->P.Fw <= kTinyFactors; }
+bool tiny(const twa_solver *s) {
+    return s->P.Fc + s->P.Fw <= kTinyFactors || (s->P.Fw == 0 && s->P.Fc <= 2 * kTinyFactors);
+}
 
 // LDS layout of a tiny instance's mutable state for k_tiny (the sizes of
 // its device arrays); false when it does not fit kTinyLdsMax.
