@@ -1,6 +1,7 @@
-"""Instances of at most 256 collision + wall factors: untimed iterations run
-in one workgroup, all iterations of a call in one launch, with the whole
-state held in LDS when it fits (else in the persistent batched kernel).
+"""Instances of at most 256 collision + wall factors (or 512 collision
+factors and no walls): untimed iterations run in one workgroup, all
+iterations of a call in one launch, with the whole state held in LDS when it
+fits (else in the persistent batched kernel).
 The per-factor code is the plain kernels', so the state after any mix of
 such calls and plain iterations must equal, bit for bit, the state after
 plain iterations alone (twa_iterate_timed launches its last two iterations
