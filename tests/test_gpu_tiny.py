@@ -197,3 +197,24 @@ def test_iterate_until_rejects_bad_arguments():
             S.twa_iterate_until(*args)
     assert S.twa_iterate_until(0, 5, 0.0) == (0, False)
     S.close()
+
+
+def test_iterate_until_through_a_warm_up_schedule():
+    """Blocks that start inside a rho0 warm-up run from the host (plain
+    iterations at the warm-up value); the result equals the host loop."""
+    import torch
+    from paper_1311_4527_amd.twa import Solver
+    inst = I.conf_small(1)
+    A = Solver.from_instance(inst)
+    B = Solver.from_instance(inst)
+    for S in (A, B):
+        S.twa_set_schedule(0.25, 30)
+    got = A.twa_iterate_until(400, 25, -1e-6)
+    want = _until_by_blocks(B, 400, 25, -1e-6)
+    assert got == want
+    za, ua, la, ia = _state(A)
+    zb, ub, lb, ib = _state(B)
+    assert ia == ib
+    assert torch.equal(za, zb) and torch.equal(ua, ub) and torch.equal(la, lb)
+    A.close()
+    B.close()
